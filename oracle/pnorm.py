@@ -1,0 +1,221 @@
+"""Oracle: exact (max, x) matrix product and its p-norm ring estimate, FP64 on CPU.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): never imported by the
+product path.
+
+Paper: Serang, arXiv 1511.05690.
+  * Alg. 2 (Sec. 2.2): the naive (x, max) product R_ij = max_k X_ik * Y_kj.
+  * Alg. 3 (Sec. 2.2): the same loops with + in place of max (an ordinary
+    matrix product); numpy's BLAS matmul stands in for it, which Sec. 2.1
+    allows for any H that returns the same numbers as G.
+  * Sec. 1 (max via the Chebyshev norm): max_k u_k = lim_p ||u||_p, and
+    ||u||_p^p of u_k = A_ik B_kj is (A^p B^p)_ij because (ab)^p = a^p b^p
+    (Sec. 2.1, distributivity argument).
+  * Sec. 2.1, scaled call H'(I, p): inputs are divided by their maximum
+    before the power so that the only numerical hazard left is underflow.
+  * Sec. 1 and Alg. 5: the family P = {1, 2, 4, ...}; at every output index
+    only the p whose ring result is >= tau count as stable, and the estimate
+    is taken from that stable sequence.
+  * Sec. 1, error bound: ||u||_inf <= ||u||_p <= len(u)^(1/p) ||u||_inf; and
+    the optional division by len(u)^(1/p) that centres the error.
+
+Readings where the paper is silent or garbled (each is also listed in the
+design notes of the repository):
+  R1  Scaling: the printed H' multiplies the ring result by one global max
+      and never takes its 1/p root.  Read as: per-row max r_i of A and
+      per-column max c_j of B; the estimate is r_i c_j S_p^(1/p).  The p-norm
+      is positively homogeneous, so this is the same number with less
+      underflow.
+  R2  estimateMaxFromNormPowerSequence is the plain rule: the stable entry
+      with the largest p, rooted: S_{p*}^(1/p*).
+  R3  Stability is S_p >= tau (not >).
+  R4  No stable p at all: use the smallest p of the family and mark the
+      entry with index PSTAR_NONE (255).  If every term is 0 the estimate
+      is exactly 0.
+  R5  A zero row of A (zero column of B) has r = 0 (c = 0); its scaled row
+      is 0 and its outputs are 0.  An empty inner dimension (k = 0) gives
+      all-zero output with index PSTAR_NONE.
+"""
+
+import numpy as np
+
+PSTAR_NONE = 255
+
+
+def _f64(x):
+    return np.asarray(x, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# O-1: exact product (Alg. 2)
+# --------------------------------------------------------------------------
+def exact_maxtimes(A, B):
+    """Alg. 2: R_ij = max_k A_ik * B_kj with R starting at 0 (the identity of
+    max on nonnegative reals).  Batched over leading dimensions.
+
+    The loop over k is kept (ascending, as in Alg. 2); i and j are
+    vectorised.  max is exact, so the result does not depend on any order.
+    """
+    A = _f64(A)
+    B = _f64(B)
+    m, k = A.shape[-2:]
+    k2, n = B.shape[-2:]
+    if k != k2:
+        raise ValueError("inner dimensions differ")
+    batch = np.broadcast_shapes(A.shape[:-2], B.shape[:-2])
+    R = np.zeros(batch + (m, n))
+    for kk in range(k):
+        R = np.maximum(R, A[..., :, kk:kk + 1] * B[..., kk:kk + 1, :])
+    return R
+
+
+def exact_maxtimes_loops(A, B):
+    """Alg. 2 written as its three nested loops in pure Python (tiny inputs
+    only).  A second, independent formulation of exact_maxtimes."""
+    A = _f64(A)
+    B = _f64(B)
+    m, k = A.shape
+    n = B.shape[1]
+    R = [[0.0] * n for _ in range(m)]
+    for i in range(m):
+        for j in range(n):
+            for kk in range(k):
+                R[i][j] = max(R[i][j], float(A[i, kk]) * float(B[kk, j]))
+    return np.array(R, dtype=np.float64).reshape(m, n)
+
+
+# --------------------------------------------------------------------------
+# O-2 .. O-6: the p-norm estimate (Alg. 5 with the scaled call H')
+# --------------------------------------------------------------------------
+def scale_factors(A, B):
+    """Reading R1 of Sec. 2.1's H': r_i = max_k A_ik, c_j = max_k B_kj."""
+    A = _f64(A)
+    B = _f64(B)
+    r = np.max(A, axis=-1, initial=0.0)
+    c = np.max(B, axis=-2, initial=0.0)
+    return r, c
+
+
+def _scaled(A, B):
+    r, c = scale_factors(A, B)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Ap = np.where(r[..., :, None] > 0, A / r[..., :, None], 0.0)
+        Bp = np.where(c[..., None, :] > 0, B / c[..., None, :], 0.0)
+    return Ap, Bp, r, c
+
+
+def norm_power_sequence(A, B, P):
+    """First loop of Alg. 5: for every p in P, raise the scaled inputs to p
+    and call the ring product (Alg. 3) on them.
+
+    Returns S (len(P), ..., m, n) with S[q] = (A'^p) @ (B'^p), p = P[q],
+    i.e. S[q]_ij = ||u||_p^p for u_k = A'_ik B'_kj; plus r and c.
+    """
+    A = _f64(A)
+    B = _f64(B)
+    Ap, Bp, r, c = _scaled(A, B)
+    S = [np.power(Ap, p) @ np.power(Bp, p) for p in P]
+    return np.stack(S), r, c
+
+
+def select_pstar(S, tau):
+    """Alg. 5, second loop, with readings R2-R4: the index q of the largest
+    p whose ring result is >= tau; PSTAR_NONE where no p qualifies.
+    P is ascending, so the last qualifying q seen is the largest p."""
+    idx = np.full(S.shape[1:], PSTAR_NONE, dtype=np.uint8)
+    for q in range(S.shape[0]):
+        idx[S[q] >= tau] = q
+    return idx
+
+
+def _root(S, P, idx):
+    """S_{p*}^(1/p*) per entry (the 1/p root of Sec. 1), with the smallest
+    p of the family where idx is PSTAR_NONE (R4); 0 where S is 0."""
+    P = np.asarray(P, dtype=np.int64)
+    q = np.where(idx == PSTAR_NONE, 0, idx).astype(np.int64)
+    Ssel = np.take_along_axis(S, q[None], axis=0)[0]
+    psel = P[q].astype(np.float64)
+    root = np.where(Ssel > 0, np.power(np.where(Ssel > 0, Ssel, 1.0), 1.0 / psel), 0.0)
+    return root, psel, Ssel
+
+
+def pnorm_estimate(A, B, P, tau, norm_correct=False):
+    """The p-norm estimate of the (max, x) product (Alg. 5, Sec. 2.1-2.2).
+
+    C_ij = r_i c_j S_{p*}^(1/p*), p* = max{p in P : S_p[i, j] >= tau}.
+    With norm_correct, C is divided by k^(1/p*) (Sec. 1, centred error).
+
+    Returns a dict: C, pstar_idx (uint8, index into P, 255 = none stable),
+    r, c, S (the whole norm power sequence), pstar (the p used per entry).
+    """
+    P = [int(p) for p in P]
+    if any(p <= 0 for p in P) or any(P[i] >= P[i + 1] for i in range(len(P) - 1)):
+        raise ValueError("P must be strictly ascending positive integers")
+    A = _f64(A)
+    B = _f64(B)
+    k = A.shape[-1]
+    S, r, c = norm_power_sequence(A, B, P)
+    idx = select_pstar(S, tau)
+    root, psel, _ = _root(S, P, idx)
+    C = r[..., :, None] * c[..., None, :] * root
+    if norm_correct and k > 0:
+        C = C / np.power(float(k), 1.0 / psel)
+    return {"C": C, "pstar_idx": idx, "pstar": psel, "r": r, "c": c, "S": S}
+
+
+def pnorm_estimate_rows(A, B, P, tau, rows, norm_correct=False):
+    """The estimate restricted to output rows ``rows``: row i of C depends
+    only on row i of A (through r_i and A'_i) and on all of B, so this is
+    pnorm_estimate(A[rows], B)."""
+    A = _f64(A)
+    return pnorm_estimate(A[..., rows, :], B, P, tau, norm_correct=norm_correct)
+
+
+def pnorm_forward_fixed(A, B, P, pstar_idx):
+    """C_ij = (sum_k A_ik^p B_kj^p)^(1/p) with p = P[pstar_idx[i, j]] given
+    per entry (PSTAR_NONE -> P[0]); the forward with p* frozen, for finite
+    differences of the gradient."""
+    S, r, c = norm_power_sequence(A, B, P)
+    root, _, _ = _root(S, P, np.asarray(pstar_idx, dtype=np.uint8))
+    return r[..., :, None] * c[..., None, :] * root
+
+
+# --------------------------------------------------------------------------
+# O-10: analytic gradient with p* frozen
+# --------------------------------------------------------------------------
+def pnorm_grad(A, B, G, P, pstar_idx):
+    """Gradient of L = sum(G * C) for the estimate with p = p*_ij frozen per
+    entry.  The paper only notes that the p-norm rings are continuous and
+    differentiable (Sec. 4); the derivative follows from
+    C_ij = (sum_k A_ik^p B_kj^p)^(1/p):
+        dC_ij/dA_ik = C_ij^(1-p) A_ik^(p-1) B_kj^p
+    Written with the scaled quantities A' = A/r, B' = B/c, C' = C/(r_i c_j)
+    the powers of r and c cancel and nothing overflows:
+        dL/dA_ik = sum_p A'_ik^(p-1) sum_{j: p*_ij = p} G_ij c_j C'_ij^(1-p) B'_kj^p
+        dL/dB_kj = sum_p B'_kj^(p-1) sum_{i: p*_ij = p} A'_ik^p G_ij r_i C'_ij^(1-p)
+    Entries whose S is 0 contribute nothing.
+    """
+    A = _f64(A)
+    B = _f64(B)
+    G = _f64(G)
+    P = [int(p) for p in P]
+    Ap, Bp, r, c = _scaled(A, B)
+    idx = np.asarray(pstar_idx, dtype=np.uint8)
+    q_used = np.where(idx == PSTAR_NONE, 0, idx)
+    S = np.stack([np.power(Ap, p) @ np.power(Bp, p) for p in P])
+    root, psel, Ssel = _root(S, P, idx)  # root = C'
+    dA = np.zeros(np.broadcast_shapes(A.shape, G.shape[:-1] + (A.shape[-1],)))
+    dB = np.zeros(np.broadcast_shapes(B.shape, G.shape[:-2] + B.shape[-2:]))
+    for q, p in enumerate(P):
+        mask = (q_used == q) & (root > 0)
+        if not mask.any():
+            continue
+        with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
+            w = np.where(mask, np.power(np.where(mask, root, 1.0), 1.0 - p), 0.0)
+        GtA = G * c[..., None, :] * w
+        GtB = G * r[..., :, None] * w
+        Bpp = np.power(Bp, p)
+        App = np.power(Ap, p)
+        dA = dA + np.power(Ap, p - 1) * (GtA @ np.swapaxes(Bpp, -1, -2))
+        dB = dB + np.power(Bp, p - 1) * (np.swapaxes(App, -1, -2) @ GtB)
+    return dA, dB
