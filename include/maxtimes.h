@@ -1,0 +1,185 @@
+/*
+ * maxtimes.h -- C ABI of the MI355X (gfx950) p-norm (max, x) product library.
+ *
+ * The operation (Serang, "Fast Computation on Semirings Isomorphic to
+ * (x, max) on R+", arXiv 1511.05690):
+ *
+ *   Exact product (Alg. 2, Sec. 2.2):   E_ij = max_k A_ik B_kj,  A, B >= 0.
+ *   Estimate (Alg. 5 with the scaled ring call H' of Sec. 2.1):
+ *       r_i = max_k A_ik,  c_j = max_k B_kj,  A' = A / r,  B' = B / c
+ *       S_p = (A'^p) (B'^p)            one ordinary matrix product per p in P
+ *       p*_ij = max{ p in P : S_p[i,j] >= tau }   (the highest stable p, Sec. 1)
+ *       C_ij = r_i c_j S_{p*}[i,j]^(1/p*)          (the 1/p root of Sec. 1)
+ *   It satisfies E <= C <= k^(1/p*) E (the error bound of Sec. 1).
+ *   If no p is stable the smallest p of the family is used and p* is
+ *   recorded as MT_PSTAR_NONE.  A zero row of A or column of B gives 0.
+ *
+ *   APSP (Sec. 2.2): X = exp(-s W) (no edge = +inf -> 0, diagonal -> 1),
+ *   T squarings X <- est(X, X) each followed by X_ii <- 1 and X <- min(X, 1),
+ *   then D = -log(X) / s (X = 0 -> +inf).  T defaults to ceil(log2 n)
+ *   (the log n products of Sec. 1 and Sec. 2.2).
+ *
+ * Paths (mt_options.path):
+ *   MT_PATH_FP64        powers, ring products and root in FP64 (FP64 MFMA).
+ *   MT_PATH_BF16_SPLIT  powers in FP32, ring products as BF16 MFMA with FP32
+ *                       accumulation; for p <= split_max_p each power is split
+ *                       x = hi + lo (both BF16, round-to-nearest-even) and
+ *                       S_p = hi.hi + hi.lo + lo.hi.  The stability test is
+ *                       done in FP64 against tau.
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is a DEVICE pointer owned by the caller, row-major
+ *     and contiguous, batch-major for batched operands.  A: b x m x k,
+ *     B: b x k x n, C and p_star: b x m x n.  W and D: n x n.
+ *   - mt_options and p_family are HOST memory read during the call only.
+ *   - The library never allocates device memory: the caller passes a device
+ *     workspace of at least the size returned by the matching *_workspace_size
+ *     call (256-byte aligned).  Its contents on entry do not matter.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = null stream).
+ *     Outputs are valid once the stream has reached the end of the call.
+ *   - Argument errors are detected before anything is enqueued and returned
+ *     synchronously (MT_ERR_INVALID_ARG, MT_ERR_WORKSPACE, MT_ERR_UNSUPPORTED);
+ *     nothing is written.  The message is available from maxtimes_last_error().
+ *   - Domain errors (negative, NaN or +inf entries of A/B; negative or NaN
+ *     weights of W) are detected on the device.  They are reported as
+ *     MT_ERR_DOMAIN only when MT_FLAG_VALIDATE is set, which makes the call
+ *     wait for the device; otherwise outputs for such inputs are unspecified.
+ *   - Launch failures return MT_ERR_DEVICE.
+ *   - Calls on different streams may run concurrently only with distinct
+ *     workspaces and outputs.
+ */
+#ifndef MAXTIMES_H
+#define MAXTIMES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MT_OK = 0,
+    MT_ERR_INVALID_ARG = 1,
+    MT_ERR_DOMAIN = 2,
+    MT_ERR_WORKSPACE = 3,
+    MT_ERR_DEVICE = 4,
+    MT_ERR_UNSUPPORTED = 5
+} mt_status;
+
+/* Element type of A, B, C, G, dA, dB (and of D for apsp_estimate). */
+typedef enum { MT_F32 = 0, MT_F64 = 1 } mt_dtype;
+
+typedef enum { MT_PATH_FP64 = 0, MT_PATH_BF16_SPLIT = 1 } mt_path;
+
+/* Flags (mt_options.flags). */
+#define MT_FLAG_VALIDATE     1u  /* check the input domain on the device and wait for it */
+#define MT_FLAG_NORM_CORRECT 2u  /* divide C by k^(1/p*): centred error (Sec. 1) */
+#define MT_FLAG_CLAMP        4u  /* clamp C to <= 1 (always on inside apsp_estimate) */
+#define MT_FLAG_RAW_OUTPUT   8u  /* apsp_estimate: write X (the (x,max) matrix) instead of D */
+
+#define MT_PSTAR_NONE 255  /* p_star value when no p of the family was stable */
+#define MT_MAX_P 32        /* largest family size */
+#define MT_MAX_POWER 4096  /* largest p accepted */
+
+/* Default stability thresholds (used when tau <= 0).  A ring product of
+ * nonnegative terms has no cancellation, so tau only has to rule out
+ * underflow: 1e-290 in FP64, 1e-30 for the BF16/FP32 exponent range. */
+#define MT_TAU_FP64_DEFAULT 1e-290
+#define MT_TAU_BF16_DEFAULT 1e-30
+
+typedef struct {
+    const int32_t* p_family; /* host; n_p entries, strictly ascending, 1..MT_MAX_POWER */
+    int32_t n_p;             /* 1..MT_MAX_P; n_p = 1 selects that p everywhere */
+    int32_t path;            /* mt_path */
+    double tau;              /* stability threshold; <= 0 -> the path default */
+    int32_t split_max_p;     /* BF16 path: split p <= split_max_p; < 0 -> 4 */
+    uint32_t flags;          /* MT_FLAG_* */
+} mt_options;
+
+/* Workspace bytes needed by maxtimes_estimate for these sizes and options. */
+mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
+                                  const mt_options* opt, size_t* bytes);
+
+/*
+ * The estimate C of the (max, x) product of A and B (Alg. 5, Sec. 2.1-2.2).
+ *   A      b x m x k, dtype, entries >= 0 and finite.
+ *   B      b x k x n, dtype, entries >= 0 and finite.
+ *   C      b x m x n, dtype (output).
+ *   p_star b x m x n uint8 (output, nullable): index into p_family of the p
+ *          used per entry, MT_PSTAR_NONE if none was stable.
+ * b, m, n >= 1; k >= 0 (k = 0 gives C = 0 and p_star = MT_PSTAR_NONE).
+ * FP32 inputs are converted exactly on load for the FP64 path.
+ */
+mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype,
+                            int64_t b, int64_t m, int64_t k, int64_t n,
+                            const mt_options* opt, void* C, uint8_t* p_star,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by maxtimes_estimate_backward. */
+mt_status maxtimes_backward_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
+                                           const mt_options* opt, size_t* bytes);
+
+/*
+ * Gradient of L = sum(G .* C) with respect to A and B for the estimate with
+ * p* held fixed per entry (the paper notes the p-norm rings are continuous
+ * and differentiable, Sec. 4).  With C' = C / (r_i c_j):
+ *   dL/dA = sum_p A'^(p-1) .* ((Gt_p) (B'^p)^T),   Gt_p = [p* = p] G c_j C'^(1-p)
+ *   dL/dB = sum_p B'^(p-1) .* ((A'^p)^T (Gt'_p)),  Gt'_p = [p* = p] G r_i C'^(1-p)
+ *   A, B, C, p_star  the inputs and outputs of the forward call (same options).
+ *   G                b x m x n, dtype.
+ *   dA, dB           b x m x k and b x k x n, dtype (outputs, each nullable).
+ * Entries whose C is 0 contribute nothing.  MT_FLAG_NORM_CORRECT is not
+ * supported here (MT_ERR_UNSUPPORTED).  The BF16 path splits every power
+ * and every Gt into hi + lo, because G has mixed signs.
+ */
+mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G,
+                                     const void* C, const uint8_t* p_star, mt_dtype dtype,
+                                     int64_t b, int64_t m, int64_t k, int64_t n,
+                                     const mt_options* opt, void* dA, void* dB,
+                                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by apsp_estimate. */
+mt_status apsp_workspace_size(int64_t n, const mt_options* opt, size_t* bytes);
+
+/*
+ * Estimated all-pairs shortest distances of a directed graph (Sec. 2.2).
+ *   W            n x n FP32 weights, >= 0, +inf = no edge; the diagonal is
+ *                ignored (a vertex reaches itself at distance 0).
+ *   s            > 0, the transform exp(-s w); s = 1 is the paper's.
+ *   n_squarings  T; < 0 -> ceil(log2 n); 0 returns the transformed W
+ *                itself (direct edges only).
+ *   D            n x n of d_dtype (output): distances (+inf = unreachable),
+ *                or with MT_FLAG_RAW_OUTPUT the (x, max) matrix X.
+ *   p_star_last  n x n uint8 (nullable): p* index of the last squaring.
+ * MT_FLAG_CLAMP is implied.
+ */
+mt_status apsp_estimate(const float* W, int64_t n, double s, int32_t n_squarings,
+                        const mt_options* opt, void* D, mt_dtype d_dtype,
+                        uint8_t* p_star_last, void* workspace, size_t ws_bytes,
+                        void* stream);
+
+/* Static description of a status code. */
+const char* maxtimes_status_string(mt_status status);
+
+/* Message of the last error returned on the calling thread ("" if none). */
+const char* maxtimes_last_error(void);
+
+/*
+ * Per-kernel timing with HIP events recorded around every launch on the
+ * launch stream (off by default).  maxtimes_timing_read waits for the
+ * recorded events and returns the summed milliseconds and launch count of
+ * every kernel whose name starts with `prefix` since the last reset.
+ */
+mt_status maxtimes_timing_enable(int on);
+mt_status maxtimes_timing_reset(void);
+mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* launches);
+
+/* Library version string. */
+const char* maxtimes_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAXTIMES_H */

@@ -1,0 +1,296 @@
+"""MI355X (gfx950) p-norm (max, x) product and APSP estimate.
+
+A thin binding over ``libmaxtimes.so`` (C ABI in ``include/maxtimes.h``):
+argument marshalling only.  Every step of the computation runs in the
+library's HIP kernels; PyTorch supplies device memory and the stream.
+There is no CPU fallback: when the library is missing, every call raises.
+
+Method: Serang, "Fast Computation on Semirings Isomorphic to (x, max) on R+"
+(arXiv 1511.05690) -- Alg. 5 with the scaled ring call of Sec. 2.1 for the
+product, Sec. 2.2 for all-pairs shortest paths.
+
+    C = estimate(A, B, P=(1, 2, 4, ..., 64), path="bf16")   # C ~ max_k A_ik B_kj
+    D = apsp(W, s=1.0, P=..., path="fp64")                  # shortest distances
+"""
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
+    "workspace_size", "backward_workspace_size", "apsp_workspace_size", "timing_enable",
+    "timing_reset", "timing_read", "pfamily", "PSTAR_NONE", "PATHS",
+]
+
+PSTAR_NONE = 255
+MAX_P = 32
+PATHS = {"fp64": 0, "bf16": 1}
+F32, F64 = 0, 1
+FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT = 1, 2, 4, 8
+STATUS = {0: "MT_OK", 1: "MT_ERR_INVALID_ARG", 2: "MT_ERR_DOMAIN", 3: "MT_ERR_WORKSPACE",
+          4: "MT_ERR_DEVICE", 5: "MT_ERR_UNSUPPORTED"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmaxtimes.so")
+_lib = None
+
+
+class MaxTimesError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("p_family", ctypes.POINTER(ctypes.c_int32)),
+        ("n_p", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("split_max_p", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libmaxtimes.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise MaxTimesError(-1, f"{_LIB_PATH} is missing: build it with "
+                                "`python -m paper_1511_05690_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, vp, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    opt = ctypes.POINTER(_Options)
+    sig = {
+        "maxtimes_workspace_size": [i64, i64, i64, i64, opt, ctypes.POINTER(sz)],
+        "maxtimes_estimate": [vp, vp, ctypes.c_int, i64, i64, i64, i64, opt, vp, vp, vp, sz, vp],
+        "maxtimes_backward_workspace_size": [i64, i64, i64, i64, opt, ctypes.POINTER(sz)],
+        "maxtimes_estimate_backward": [vp, vp, vp, vp, vp, ctypes.c_int, i64, i64, i64, i64, opt,
+                                       vp, vp, vp, sz, vp],
+        "apsp_workspace_size": [i64, opt, ctypes.POINTER(sz)],
+        "apsp_estimate": [vp, i64, ctypes.c_double, ctypes.c_int32, opt, vp, ctypes.c_int, vp, vp,
+                          sz, vp],
+        "maxtimes_timing_enable": [ctypes.c_int],
+        "maxtimes_timing_reset": [],
+        "maxtimes_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(i64)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    for name in ("maxtimes_status_string", "maxtimes_last_error", "maxtimes_version"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_char_p
+    lib.maxtimes_status_string.argtypes = [ctypes.c_int]
+    lib.maxtimes_last_error.argtypes = []
+    lib.maxtimes_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        msg = _lib.maxtimes_last_error().decode()
+        raise MaxTimesError(status, msg)
+
+
+def pfamily(pmax):
+    """The powers of two 1, 2, 4, ..., pmax."""
+    out, p = [], 1
+    while p <= pmax:
+        out.append(p)
+        p *= 2
+    return out
+
+
+def _options(P, path, tau, split_max_p, flags):
+    P = [int(p) for p in P]
+    arr = (ctypes.c_int32 * max(1, len(P)))(*P)
+    o = _Options()
+    o.p_family = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    o.n_p = len(P)
+    o.path = PATHS[path] if isinstance(path, str) else int(path)
+    o.tau = -1.0 if tau is None else float(tau)
+    o.split_max_p = -1 if split_max_p is None else int(split_max_p)
+    o.flags = int(flags)
+    o._keep = arr  # keep the array alive with the struct
+    return o
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _shape3(A, B):
+    if A.dim() == 2 and B.dim() == 2:
+        return 1, A.shape[0], A.shape[1], B.shape[1], False
+    if A.dim() == 3 and B.dim() == 3 and A.shape[0] == B.shape[0]:
+        return A.shape[0], A.shape[1], A.shape[2], B.shape[2], True
+    raise ValueError("A and B must both be 2-D, or 3-D with the same batch size")
+
+
+def workspace_size(b, m, k, n, P, path="bf16", tau=None, split_max_p=None, flags=0):
+    lib = load_library()
+    o = _options(P, path, tau, split_max_p, flags)
+    out = ctypes.c_size_t(0)
+    _check(lib.maxtimes_workspace_size(b, m, k, n, ctypes.byref(o), ctypes.byref(out)))
+    return out.value
+
+
+def backward_workspace_size(b, m, k, n, P, path="bf16", tau=None, split_max_p=None, flags=0):
+    lib = load_library()
+    o = _options(P, path, tau, split_max_p, flags)
+    out = ctypes.c_size_t(0)
+    _check(lib.maxtimes_backward_workspace_size(b, m, k, n, ctypes.byref(o), ctypes.byref(out)))
+    return out.value
+
+
+def apsp_workspace_size(n, P, path="fp64", tau=None, split_max_p=None, flags=0):
+    lib = load_library()
+    o = _options(P, path, tau, split_max_p, flags)
+    out = ctypes.c_size_t(0)
+    _check(lib.apsp_workspace_size(n, ctypes.byref(o), ctypes.byref(out)))
+    return out.value
+
+
+def _workspace(nbytes, device, workspace):
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise MaxTimesError(3, "workspace tensor too small")
+        return workspace
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def _forward(A, B, P, path, tau, split_max_p, flags, want_pstar, workspace=None):
+    lib = load_library()
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("A and B must be device tensors")
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    A = A.contiguous()
+    B = B.contiguous()
+    b, m, k, n, batched = _shape3(A, B)
+    o = _options(P, path, tau, split_max_p, flags)
+    need = ctypes.c_size_t(0)
+    _check(lib.maxtimes_workspace_size(b, m, k, n, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, A.device, workspace)
+    shape = (b, m, n) if batched else (m, n)
+    C = torch.empty(shape, dtype=A.dtype, device=A.device)
+    ps = torch.empty(shape, dtype=torch.uint8, device=A.device) if want_pstar else None
+    _check(lib.maxtimes_estimate(_ptr(A), _ptr(B), _dtype_code(A), b, m, k, n, ctypes.byref(o),
+                                 _ptr(C), _ptr(ps), _ptr(ws), need.value, _stream(A.device)))
+    return C, ps
+
+
+def estimate_backward(A, B, G, C, p_star, P, path="bf16", tau=None, split_max_p=None,
+                      need_dA=True, need_dB=True, flags=0):
+    """Gradient of sum(G * C) for the estimate with p* held fixed."""
+    lib = load_library()
+    A, B, G, C, p_star = (t.contiguous() for t in (A, B, G, C, p_star))
+    b, m, k, n, batched = _shape3(A, B)
+    o = _options(P, path, tau, split_max_p, flags)
+    need = ctypes.c_size_t(0)
+    _check(lib.maxtimes_backward_workspace_size(b, m, k, n, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, A.device, None)
+    dA = torch.empty_like(A) if need_dA else None
+    dB = torch.empty_like(B) if need_dB else None
+    _check(lib.maxtimes_estimate_backward(_ptr(A), _ptr(B), _ptr(G), _ptr(C), _ptr(p_star),
+                                          _dtype_code(A), b, m, k, n, ctypes.byref(o), _ptr(dA),
+                                          _ptr(dB), _ptr(ws), need.value, _stream(A.device)))
+    return dA, dB
+
+
+class _EstimateFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A, B, P, path, tau, split_max_p, flags):
+        C, ps = _forward(A, B, P, path, tau, split_max_p, flags, True)
+        ctx.save_for_backward(A, B, C, ps)
+        ctx.cfg = (tuple(P), path, tau, split_max_p, flags)
+        ctx.mark_non_differentiable(ps)
+        return C, ps
+
+    @staticmethod
+    def backward(ctx, gC, gps):
+        A, B, C, ps = ctx.saved_tensors
+        P, path, tau, split_max_p, flags = ctx.cfg
+        dA, dB = estimate_backward(A, B, gC, C, ps, P, path, tau, split_max_p,
+                                   ctx.needs_input_grad[0], ctx.needs_input_grad[1], flags)
+        return dA, dB, None, None, None, None, None
+
+
+def estimate(A, B, P=(1, 2, 4, 8, 16, 32, 64), tau=None, path="bf16", split_max_p=None,
+             norm_correct=False, clamp=False, validate=False, return_pstar=False, workspace=None):
+    """Estimate C_ij = max_k A_ik B_kj for nonnegative A (.., m, k), B (.., k, n).
+
+    path "bf16": BF16 MFMA ring products with hi/lo split for p <= split_max_p;
+    path "fp64": FP64 MFMA ring products.  tau None = the path default.
+    Differentiable (p* held fixed) when A or B requires grad.
+    """
+    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_NORM_CORRECT if norm_correct else 0) | \
+        (FLAG_CLAMP if clamp else 0)
+    if torch.is_grad_enabled() and (A.requires_grad or B.requires_grad):
+        C, ps = _EstimateFn.apply(A, B, list(P), path, tau, split_max_p, flags)
+    else:
+        C, ps = _forward(A, B, P, path, tau, split_max_p, flags, return_pstar, workspace)
+    return (C, ps) if return_pstar else C
+
+
+def apsp(W, s=1.0, P=None, path="fp64", n_squarings=-1, tau=None, split_max_p=None,
+         out_dtype=torch.float32, raw=False, validate=False, return_pstar=False, workspace=None):
+    """Estimated all-pairs shortest distances of the n x n FP32 weight matrix W
+    (+inf = no edge).  raw=True returns the (x, max) matrix X instead."""
+    lib = load_library()
+    if P is None:
+        P = pfamily(512 if path == "fp64" else 128)
+    if W.dtype != torch.float32 or W.dim() != 2 or W.shape[0] != W.shape[1] or not W.is_cuda:
+        raise ValueError("W must be a square FP32 device tensor")
+    W = W.contiguous()
+    n = W.shape[0]
+    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_RAW_OUTPUT if raw else 0)
+    o = _options(P, path, tau, split_max_p, flags)
+    need = ctypes.c_size_t(0)
+    _check(lib.apsp_workspace_size(n, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, W.device, workspace)
+    D = torch.empty((n, n), dtype=out_dtype, device=W.device)
+    ps = torch.empty((n, n), dtype=torch.uint8, device=W.device) if return_pstar else None
+    _check(lib.apsp_estimate(_ptr(W), n, float(s), int(n_squarings), ctypes.byref(o), _ptr(D),
+                             _dtype_code(D), _ptr(ps), _ptr(ws), need.value, _stream(W.device)))
+    return (D, ps) if return_pstar else D
+
+
+def timing_enable(on=True):
+    _check(load_library().maxtimes_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load_library().maxtimes_timing_reset())
+
+
+def timing_read(prefix):
+    """(total milliseconds, launches) of the library's kernels whose name
+    starts with ``prefix``, from HIP events recorded on the launch stream."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(load_library().maxtimes_timing_read(prefix.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

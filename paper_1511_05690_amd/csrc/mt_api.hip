@@ -1,0 +1,480 @@
+// C ABI of libmaxtimes (include/maxtimes.h): argument checks, workspace
+// layout, the launch sequence of the p-norm (max, x) estimate (Alg. 5 with
+// the scaled ring call H' of Sec. 2.1) and of the APSP driver (Sec. 2.2),
+// and per-kernel event timing.  Host code only; kernels live in
+// mt_elementwise.hip, mt_gemm_bf16.hip, mt_gemm_f64.hip and mt_backward.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mt_internal.h"
+
+namespace mt {
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_last_error;
+
+mt_status fail(mt_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+mt_status device_fail(hipError_t e, const char* what) {
+    return fail(MT_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define MT_TRY(call, what)                                 \
+    do {                                                   \
+        hipError_t _e = (call);                            \
+        if (_e != hipSuccess) return device_fail(_e, what); \
+    } while (0)
+
+// ------------------------------------------------------------------ timing
+struct TimedLaunch {
+    const char* name;
+    hipEvent_t start;
+    hipEvent_t stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_launches;
+}  // namespace
+
+void timing_before(const char* name, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return;
+    TimedLaunch t{name, nullptr, nullptr};
+    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
+    (void)hipEventRecord(t.start, st);
+    g_launches.push_back(t);
+}
+
+void timing_after(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing || g_launches.empty()) return;
+    TimedLaunch& t = g_launches.back();
+    if (t.stop) (void)hipEventRecord(t.stop, st);
+}
+
+namespace {
+
+// ------------------------------------------------------------------ options
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct Family {
+    int32_t n;
+    int32_t p[MT_MAX_P];
+    bool bf16;
+    double tau;
+    int32_t split_max_p;
+    uint32_t flags;
+};
+
+mt_status parse_options(const mt_options* opt, Family* f) {
+    if (!opt) return fail(MT_ERR_INVALID_ARG, "options pointer is NULL");
+    if (!opt->p_family) return fail(MT_ERR_INVALID_ARG, "p_family is NULL");
+    if (opt->n_p < 1 || opt->n_p > MT_MAX_P)
+        return fail(MT_ERR_INVALID_ARG, "n_p = %d outside 1..%d", opt->n_p, MT_MAX_P);
+    if (opt->path != MT_PATH_FP64 && opt->path != MT_PATH_BF16_SPLIT)
+        return fail(MT_ERR_INVALID_ARG, "unknown path %d", opt->path);
+    const uint32_t known = MT_FLAG_VALIDATE | MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT;
+    if (opt->flags & ~known) return fail(MT_ERR_INVALID_ARG, "unknown flag bits 0x%x", opt->flags & ~known);
+    if (!(opt->tau <= 0.0 || (opt->tau > 0.0 && std::isfinite(opt->tau))))
+        return fail(MT_ERR_INVALID_ARG, "tau must be finite");
+    f->n = opt->n_p;
+    for (int q = 0; q < opt->n_p; ++q) {
+        const int32_t p = opt->p_family[q];
+        if (p < 1 || p > MT_MAX_POWER)
+            return fail(MT_ERR_INVALID_ARG, "p_family[%d] = %d outside 1..%d", q, p, MT_MAX_POWER);
+        if (q > 0 && p <= opt->p_family[q - 1])
+            return fail(MT_ERR_INVALID_ARG, "p_family is not strictly ascending at index %d", q);
+        f->p[q] = p;
+    }
+    f->bf16 = opt->path == MT_PATH_BF16_SPLIT;
+    f->tau = opt->tau > 0.0 ? opt->tau : (f->bf16 ? MT_TAU_BF16_DEFAULT : MT_TAU_FP64_DEFAULT);
+    f->split_max_p = opt->split_max_p < 0 ? 4 : opt->split_max_p;
+    f->flags = opt->flags;
+    return MT_OK;
+}
+
+// Planes of one operand: one per p (FP64), or hi (+ lo when split) per p (BF16).
+PlaneSpec plane_spec(const Family& f) {
+    PlaneSpec s;
+    memset(&s, 0, sizeof s);
+    s.n_p = f.n;
+    int pl = 0;
+    for (int q = 0; q < f.n; ++q) {
+        s.p[q] = f.p[q];
+        s.split[q] = f.bf16 && f.p[q] <= f.split_max_p;
+        s.first_plane[q] = pl;
+        pl += s.split[q] ? 2 : 1;
+    }
+    s.n_planes = pl;
+    return s;
+}
+
+float round_up_to_float(double tau) {
+    float f = (float)tau;
+    if ((double)f < tau) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+// Largest p first; a split p runs (hi,hi), (hi,lo), (lo,hi).
+FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
+    FamilyPlan plan;
+    memset(&plan, 0, sizeof plan);
+    plan.n = f.n;
+    plan.tau = f.tau;
+    plan.tau_f = round_up_to_float(f.tau);
+    for (int e = 0; e < f.n; ++e) {
+        const int q = f.n - 1 - e;
+        PlanEntry& pe = plan.e[e];
+        pe.pidx = q;
+        pe.p = f.p[q];
+        pe.inv_p = 1.0f / (float)f.p[q];
+        pe.corr = (f.flags & MT_FLAG_NORM_CORRECT) && k > 0 ? (float)std::pow((double)k, -1.0 / f.p[q]) : 1.0f;
+        const int hi = ps.first_plane[q];
+        if (ps.split[q]) {
+            pe.nseg = 3;
+            pe.a_plane[0] = hi; pe.b_plane[0] = hi;
+            pe.a_plane[1] = hi; pe.b_plane[1] = hi + 1;
+            pe.a_plane[2] = hi + 1; pe.b_plane[2] = hi;
+        } else {
+            pe.nseg = 1;
+            pe.a_plane[0] = hi;
+            pe.b_plane[0] = hi;
+        }
+    }
+    return plan;
+}
+
+RootSpec root_spec(const Family& f, int64_t k, int mode, int clamp) {
+    RootSpec r;
+    memset(&r, 0, sizeof r);
+    for (int q = 0; q < f.n; ++q) {
+        r.p[q] = f.p[q];
+        r.corr[q] = (f.flags & MT_FLAG_NORM_CORRECT) && k > 0 ? std::pow((double)k, -1.0 / f.p[q]) : 1.0;
+    }
+    r.mode = mode;
+    r.clamp = clamp;
+    return r;
+}
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int64_t mp, np, kp;  // padded sizes of the planes
+    int bm;              // FP64 tile (128 or 64); 256 for BF16
+    size_t esize;        // plane element bytes
+};
+
+Geom product_geom(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
+    Geom g;
+    if (f.bf16) {
+        g.bm = kBf16BM;
+        g.kp = round_up(k, kBf16BK);
+        g.esize = 2;
+    } else {
+        // 128-wide tiles when they give at least two workgroups per CU.
+        const int64_t tiles128 = b * ((m + 127) / 128) * ((n + 127) / 128);
+        g.bm = tiles128 >= 512 ? 128 : 64;
+        g.kp = round_up(k, kF64BK);
+        g.esize = 8;
+    }
+    g.mp = round_up(m, g.bm);
+    g.np = round_up(n, g.bm);
+    return g;
+}
+
+struct Layout {
+    size_t hdr, r, c, ap, bp, s, code, x, total;
+};
+
+// The workspace of one product (plus an APSP X buffer when x_bytes > 0).
+Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64_t b, int64_t m,
+                      int64_t n, size_t x_bytes) {
+    Layout L;
+    size_t off = 0;
+    L.hdr = off; off += align_up(sizeof(WsHeader));
+    L.r = off;   off += align_up((size_t)(b * m) * 8);
+    L.c = off;   off += align_up((size_t)(b * n) * 8);
+    L.ap = off;  off += align_up((size_t)b * ps.n_planes * g.mp * g.kp * g.esize);
+    L.bp = off;  off += align_up((size_t)b * ps.n_planes * g.np * g.kp * g.esize);
+    if (!f.bf16) {
+        L.s = off;    off += align_up((size_t)(b * m * n) * 8);
+        L.code = off; off += align_up((size_t)(b * m * n));
+    } else {
+        L.s = L.code = 0;
+    }
+    L.x = off;
+    off += align_up(x_bytes);
+    L.total = off;
+    return L;
+}
+
+mt_status check_dims(int64_t b, int64_t m, int64_t k, int64_t n) {
+    if (b < 0 || m < 0 || k < 0 || n < 0)
+        return fail(MT_ERR_INVALID_ARG, "negative size (b=%lld m=%lld k=%lld n=%lld)", (long long)b,
+                    (long long)m, (long long)k, (long long)n);
+    const int64_t lim = (int64_t)1 << 24;
+    if (m > lim || n > lim || k > lim || b > lim)
+        return fail(MT_ERR_UNSUPPORTED, "a size exceeds 2^24");
+    return MT_OK;
+}
+
+mt_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (ws_bytes < need)
+        return fail(MT_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    if (need > 0 && !ws) return fail(MT_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(MT_ERR_INVALID_ARG, "workspace is not 256-byte aligned");
+    return MT_OK;
+}
+
+mt_status read_domain_flag(const uint8_t* ws, hipStream_t st) {
+    int32_t flag = 0;
+    MT_TRY(hipMemcpyAsync(&flag, ws, sizeof flag, hipMemcpyDeviceToHost, st), "domain flag copy");
+    MT_TRY(hipStreamSynchronize(st), "domain flag sync");
+    if (flag) return fail(MT_ERR_DOMAIN, "input has negative, NaN or infinite entries");
+    return MT_OK;
+}
+
+// The product pipeline on already-validated arguments.  X-mode (APSP):
+// A = B = X (n x n, r = c = 1 by construction), the output goes back to X.
+mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64_t m, int64_t k,
+                      int64_t n, const Family& f, const PlaneSpec& ps, const Geom& g,
+                      const Layout& L, uint8_t* ws, bool scale, int mode, int clamp, void* out,
+                      int out_f64, uint8_t* pstar, hipStream_t st) {
+    double* r = scale ? (double*)(ws + L.r) : nullptr;
+    double* c = scale ? (double*)(ws + L.c) : nullptr;
+    void* ap = ws + L.ap;
+    void* bp = ws + L.bp;
+    MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, ps, f.bf16, ap, st), "power planes (A)");
+    MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, ps, f.bf16, bp, st), "power planes (B)");
+    const FamilyPlan plan = family_plan(f, ps, k);
+    EpiArgs epi;
+    memset(&epi, 0, sizeof epi);
+    epi.r = r;
+    epi.c = c;
+    if (f.bf16) {
+        epi.mode = mode;
+        epi.clamp = clamp;
+        epi.out = out;
+        epi.out_f64 = out_f64;
+        epi.pstar = pstar;
+        MT_TRY(launch_pfamily_gemm_bf16((const uint16_t*)ap, (const uint16_t*)bp, b, m, n, g.mp, g.np,
+                                        g.kp, ps.n_planes, plan, epi, st),
+               "p-family GEMM (BF16)");
+    } else {
+        epi.mode = EPI_PLAIN;
+        epi.out = ws + L.s;
+        epi.out_f64 = 1;
+        epi.pstar = ws + L.code;
+        MT_TRY(launch_pfamily_gemm_f64((const double*)ap, (const double*)bp, b, m, n, g.mp, g.np, g.kp,
+                                       ps.n_planes, g.bm, plan, epi, st),
+               "p-family GEMM (FP64)");
+        const RootSpec rsp = root_spec(f, k, mode, clamp);
+        MT_TRY(launch_select_root_f64((const double*)(ws + L.s), ws + L.code, b, m, n, r, c, rsp, out,
+                                      out_f64, pstar, st),
+               "select root (FP64)");
+    }
+    return MT_OK;
+}
+
+}  // namespace
+}  // namespace mt
+
+using namespace mt;
+
+extern "C" {
+
+const char* maxtimes_version(void) { return "maxtimes-gfx950 0.1"; }
+
+const char* maxtimes_status_string(mt_status s) {
+    switch (s) {
+        case MT_OK: return "ok";
+        case MT_ERR_INVALID_ARG: return "invalid argument";
+        case MT_ERR_DOMAIN: return "input outside the domain (negative, NaN or infinite)";
+        case MT_ERR_WORKSPACE: return "workspace too small";
+        case MT_ERR_DEVICE: return "device or launch failure";
+        case MT_ERR_UNSUPPORTED: return "unsupported argument combination";
+    }
+    return "unknown status";
+}
+
+const char* maxtimes_last_error(void) { return g_last_error.c_str(); }
+
+mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n, const mt_options* opt,
+                                  size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    const PlaneSpec ps = plane_spec(f);
+    const Geom g = product_geom(f, b, m, k, n);
+    *bytes = product_layout(f, ps, g, b, m, n, 0).total;
+    return MT_OK;
+}
+
+mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,
+                            int64_t k, int64_t n, const mt_options* opt, void* C, uint8_t* p_star,
+                            void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if (f.flags & MT_FLAG_RAW_OUTPUT) return fail(MT_ERR_INVALID_ARG, "MT_FLAG_RAW_OUTPUT is for apsp_estimate");
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    if (b == 0 || m == 0 || n == 0) return MT_OK;
+    if (!C) return fail(MT_ERR_INVALID_ARG, "C is NULL");
+    if (k > 0 && (!A || !B)) return fail(MT_ERR_INVALID_ARG, "A or B is NULL");
+    const PlaneSpec ps = plane_spec(f);
+    const Geom g = product_geom(f, b, m, k, n);
+    const Layout L = product_layout(f, ps, g, b, m, n, 0);
+    if ((s = check_ws(workspace, ws_bytes, L.total)) != MT_OK) return s;
+
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)workspace;
+    const int f64 = dtype == MT_F64;
+    int32_t* flag = (int32_t*)(ws + L.hdr);
+    MT_TRY(launch_fill_zero_u32(ws + L.hdr, sizeof(WsHeader) / 4, st), "clear header");
+    MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
+    MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st), "column max");
+    if (f.flags & MT_FLAG_VALIDATE) {
+        if ((s = read_domain_flag(ws + L.hdr, st)) != MT_OK) return s;
+    }
+    return run_product(A, B, f64, b, m, k, n, f, ps, g, L, ws, true, EPI_PLAIN,
+                       (f.flags & MT_FLAG_CLAMP) ? 1 : 0, C, f64, p_star, st);
+}
+
+mt_status apsp_workspace_size(int64_t n, const mt_options* opt, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if ((s = check_dims(1, n, n, n)) != MT_OK) return s;
+    const PlaneSpec ps = plane_spec(f);
+    const Geom g = product_geom(f, 1, n, n, n);
+    *bytes = product_layout(f, ps, g, 1, n, n, (size_t)(n * n) * (f.bf16 ? 4 : 8)).total;
+    return MT_OK;
+}
+
+mt_status apsp_estimate(const float* W, int64_t n, double s_scale, int32_t n_squarings,
+                        const mt_options* opt, void* D, mt_dtype d_dtype, uint8_t* p_star_last,
+                        void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if (f.flags & MT_FLAG_NORM_CORRECT) return fail(MT_ERR_UNSUPPORTED, "MT_FLAG_NORM_CORRECT is not defined for APSP");
+    if (d_dtype != MT_F32 && d_dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)d_dtype);
+    if ((s = check_dims(1, n, n, n)) != MT_OK) return s;
+    if (!(s_scale > 0.0) || !std::isfinite(s_scale)) return fail(MT_ERR_INVALID_ARG, "s must be finite and > 0");
+    if (n == 0) return MT_OK;
+    if (!W || !D) return fail(MT_ERR_INVALID_ARG, "W or D is NULL");
+    int T = n_squarings;
+    if (T < 0) {
+        T = 0;
+        while (((int64_t)1 << T) < n) ++T;
+    }
+    if (T > 64) return fail(MT_ERR_INVALID_ARG, "n_squarings = %d is too large", T);
+    const PlaneSpec ps = plane_spec(f);
+    const Geom g = product_geom(f, 1, n, n, n);
+    const int x_f64 = f.bf16 ? 0 : 1;
+    const Layout L = product_layout(f, ps, g, 1, n, n, (size_t)(n * n) * (x_f64 ? 8 : 4));
+    if ((s = check_ws(workspace, ws_bytes, L.total)) != MT_OK) return s;
+
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)workspace;
+    void* X = ws + L.x;
+    int32_t* flag = (int32_t*)(ws + L.hdr);
+    MT_TRY(launch_fill_zero_u32(ws + L.hdr, sizeof(WsHeader) / 4, st), "clear header");
+    MT_TRY(launch_apsp_transform(W, n, s_scale, X, x_f64, flag, st), "exp transform");
+    if (f.flags & MT_FLAG_VALIDATE) {
+        if ((s = read_domain_flag(ws + L.hdr, st)) != MT_OK) return s;
+    }
+    // X has X_ii = 1 and X <= 1 after the transform and after every squaring,
+    // so its row and column maxima are 1: the scaled call needs no scaling.
+    for (int t = 0; t < T; ++t) {
+        s = run_product(X, X, x_f64, 1, n, n, n, f, ps, g, L, ws, false, EPI_APSP_X, 1, X, x_f64,
+                        t == T - 1 ? p_star_last : nullptr, st);
+        if (s != MT_OK) return s;
+    }
+    MT_TRY(launch_apsp_to_dist(X, x_f64, n, s_scale, D, d_dtype == MT_F64,
+                               (f.flags & MT_FLAG_RAW_OUTPUT) ? 1 : 0, st),
+           "log transform");
+    return MT_OK;
+}
+
+mt_status maxtimes_backward_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
+                                           const mt_options* opt, size_t* bytes) {
+    g_last_error.clear();
+    (void)b; (void)m; (void)k; (void)n; (void)opt; (void)bytes;
+    return fail(MT_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G, const void* C,
+                                     const uint8_t* p_star, mt_dtype dtype, int64_t b, int64_t m,
+                                     int64_t k, int64_t n, const mt_options* opt, void* dA, void* dB,
+                                     void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    (void)A; (void)B; (void)G; (void)C; (void)p_star; (void)dtype; (void)b; (void)m; (void)k; (void)n;
+    (void)opt; (void)dA; (void)dB; (void)workspace; (void)ws_bytes; (void)stream;
+    return fail(MT_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+mt_status maxtimes_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return MT_OK;
+}
+
+mt_status maxtimes_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto& t : g_launches) {
+        if (t.start) (void)hipEventDestroy(t.start);
+        if (t.stop) (void)hipEventDestroy(t.stop);
+    }
+    g_launches.clear();
+    return MT_OK;
+}
+
+mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* launches) {
+    g_last_error.clear();
+    if (!prefix || !total_ms || !launches) return fail(MT_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    double ms = 0.0;
+    int64_t cnt = 0;
+    const size_t pl = strlen(prefix);
+    for (auto& t : g_launches) {
+        if (strncmp(t.name, prefix, pl) != 0 || !t.stop) continue;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e != hipSuccess) return device_fail(e, "event sync");
+        float x = 0.f;
+        e = hipEventElapsedTime(&x, t.start, t.stop);
+        if (e != hipSuccess) return device_fail(e, "event elapsed");
+        ms += x;
+        ++cnt;
+    }
+    *total_ms = ms;
+    *launches = cnt;
+    return MT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,394 @@
+// HBM-bound kernels of the p-norm (max, x) path on gfx950:
+//   * row / column maxima of the inputs with the domain check (the scaled
+//     ring call H' of Sec. 2.1: inputs divided by their maximum);
+//   * power planes: (A/r)^p and (B/c)^p for every p of the family, written
+//     once in the layout the MFMA GEMM reads (K contiguous, zero padded),
+//     as BF16 hi/lo pairs or FP64 (the powered inputs of Alg. 5);
+//   * the (+, min) <-> (x, max) transforms of Sec. 2.2.
+#include <cfloat>
+#include <cmath>
+
+#include "mt_internal.h"
+
+namespace mt {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline uint16_t bf16_rne(float x) {
+    // Round to nearest even on the bit pattern; x is finite and >= 0 here.
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <typename T>
+__device__ inline bool bad_value(T x) {
+    // negative, NaN or +inf
+    return !(x >= T(0)) || !(x <= (T)(sizeof(T) == 8 ? DBL_MAX : FLT_MAX));
+}
+
+__device__ inline double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void fill_zero_u32_kernel(uint32_t* p, int64_t words) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride) p[i] = 0u;
+}
+
+// One wave per row: r[row] = max_k A[row, k]; flags invalid entries.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict__ A, int64_t rows,
+                                                             int64_t k, double* __restrict__ r,
+                                                             int32_t* __restrict__ flag) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (row >= rows) return;
+    const T* a = A + row * k;
+    double mx = 0.0;
+    bool bad = false;
+    int64_t j = lane;
+    for (; j + 192 < k; j += 256) {
+        T v0 = a[j], v1 = a[j + 64], v2 = a[j + 128], v3 = a[j + 192];
+        bad |= bad_value(v0) | bad_value(v1) | bad_value(v2) | bad_value(v3);
+        mx = fmax(mx, fmax(fmax((double)v0, (double)v1), fmax((double)v2, (double)v3)));
+    }
+    for (; j < k; j += 64) {
+        T v = a[j];
+        bad |= bad_value(v);
+        mx = fmax(mx, (double)v);
+    }
+    mx = wave_max(mx);
+    if (lane == 0) r[row] = mx;
+    if (bad) atomicOr(flag, 1);
+}
+
+// c[b, j] = max_k B[b, k, j]: lanes across j (coalesced), 64 rows per block,
+// combined with an integer atomic max on the bit pattern (exact for >= 0).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mt_colmax_kernel(const T* __restrict__ B, int64_t k,
+                                                             int64_t n, double* __restrict__ c,
+                                                             int32_t* __restrict__ flag) {
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.y * 64;
+    const int64_t bi = blockIdx.z;
+    if (j >= n) return;
+    const T* bb = B + bi * k * n + j;
+    double mx = 0.0;
+    bool bad = false;
+    const int64_t k1 = k0 + 64 < k ? k0 + 64 : k;
+    for (int64_t kk = k0; kk < k1; ++kk) {
+        T v = bb[kk * n];
+        bad |= bad_value(v);
+        mx = fmax(mx, (double)v);
+    }
+    if (bad) atomicOr(flag, 1);
+    if (mx > 0.0 || mx != mx)
+        atomicMax((unsigned long long*)(c + bi * n + j), (unsigned long long)__double_as_longlong(mx));
+}
+
+template <typename T>
+__device__ inline T ipow(T x, int p) {
+    T r = T(1);
+    while (p) {
+        if (p & 1) r *= x;
+        x *= x;
+        p >>= 1;
+    }
+    return r;
+}
+
+// Power planes.  Tile: 64 plane rows x 64 plane columns per block.
+//   transpose == 0: plane row t = src row t (src is rows x cols)
+//   transpose == 1: plane row t = src column t (src is cols x rows)
+// Every thread produces 8 consecutive plane columns (one 16-byte BF16 chunk)
+// of two plane rows.
+template <typename TS, bool kBf16, bool kTranspose>
+__global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
+    const TS* __restrict__ src, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
+    const double* __restrict__ scale, PlaneSpec spec, void* __restrict__ planes) {
+    __shared__ TS tile[64][64 + 1];
+    const int64_t bi = blockIdx.z;
+    const int64_t t0 = (int64_t)blockIdx.y * 64;  // plane row
+    const int64_t u0 = (int64_t)blockIdx.x * 64;  // plane column
+    const TS* s = src + bi * rows * cols;
+
+    if (kTranspose) {
+        // src[u][t]: read 64 (u) x 64 (t) coalesced along t.
+        for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
+            const int uu = e >> 6, tt = e & 63;
+            const int64_t u = u0 + uu, t = t0 + tt;
+            tile[tt][uu] = (u < cols && t < rows) ? s[u * rows + t] : TS(0);
+        }
+        __syncthreads();
+    }
+
+    typedef typename std::conditional<kBf16, float, double>::type TC;
+    const int64_t plane_elems = rows_pad * cols_pad;
+    for (int rep = 0; rep < 2; ++rep) {
+        const int task = threadIdx.x + rep * kThreads;  // 0..511
+        const int tt = task >> 3, ch = task & 7;
+        const int64_t t = t0 + tt;
+        const int64_t u = u0 + ch * 8;
+        if (t >= rows_pad || u >= cols_pad) continue;
+        TC x[8];
+        double sc = 1.0;
+        if (scale != nullptr && t < rows) sc = scale[bi * rows + t];
+        const bool zero_row = (t >= rows) || (sc == 0.0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double v = 0.0;
+            if (!zero_row && u + i < cols) {
+                v = kTranspose ? (double)tile[tt][ch * 8 + i] : (double)s[t * cols + u + i];
+                if (scale != nullptr) v = v / sc;
+            }
+            x[i] = (TC)v;
+        }
+        TC pw[8];
+        int prev = 0;
+        for (int q = 0; q < spec.n_p; ++q) {
+            const int p = spec.p[q];
+            if (prev > 0 && p == 2 * prev) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) pw[i] = pw[i] * pw[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) pw[i] = ipow(x[i], p);
+            }
+            prev = p;
+            const int64_t pl = spec.first_plane[q];
+            if (kBf16) {
+                uint16_t* base = (uint16_t*)planes;
+                u32x4 hi, lo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint16_t h0 = bf16_rne((float)pw[2 * i]), h1 = bf16_rne((float)pw[2 * i + 1]);
+                    hi[i] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                    if (spec.split[q]) {
+                        const uint16_t l0 = bf16_rne((float)pw[2 * i] - bf16_to_float(h0));
+                        const uint16_t l1 = bf16_rne((float)pw[2 * i + 1] - bf16_to_float(h1));
+                        lo[i] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+                    }
+                }
+                const int64_t off = ((bi * spec.n_planes + pl) * plane_elems) + t * cols_pad + u;
+                *(u32x4*)(base + off) = hi;
+                if (spec.split[q]) *(u32x4*)(base + off + plane_elems) = lo;
+            } else {
+                double* base = (double*)planes;
+                const int64_t off = ((bi * spec.n_planes + pl) * plane_elems) + t * cols_pad + u;
+#pragma unroll
+                for (int i = 0; i < 8; i += 2) {
+                    double2 v2;
+                    v2.x = (double)pw[i];
+                    v2.y = (double)pw[i + 1];
+                    *(double2*)(base + off + i) = v2;
+                }
+            }
+        }
+    }
+}
+
+// X = exp(-s W) in FP64; +inf -> 0; diagonal -> 1.
+template <typename TX>
+__global__ __launch_bounds__(kThreads) void mt_apsp_transform_kernel(const float* __restrict__ W,
+                                                                     int64_t n, double s,
+                                                                     TX* __restrict__ X,
+                                                                     int32_t* __restrict__ flag) {
+    const int64_t total = n * n;
+    bool bad = false;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = e / n, j = e - (e / n) * n;
+        const float w = W[e];
+        double x;
+        if (i == j) {
+            x = 1.0;
+        } else {
+            if (!(w >= 0.0f)) bad = true;  // negative or NaN
+            x = exp(-s * (double)w);      // +inf -> 0
+        }
+        X[e] = (TX)x;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// D = -log(X) / s in FP64; X = 0 -> +inf.
+// raw != 0: D = X (the (x, max) matrix itself, converted to D's type).
+template <typename TX, typename TD>
+__global__ __launch_bounds__(kThreads) void mt_apsp_to_dist_kernel(const TX* __restrict__ X,
+                                                                   int64_t total, double s_inv,
+                                                                   int raw, TD* __restrict__ D) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kThreads) {
+        const double x = (double)X[e];
+        D[e] = raw ? (TD)x : (TD)(x > 0.0 ? -log(x) * s_inv + 0.0 : HUGE_VAL);
+    }
+}
+
+// FP64 path, after the GEMM's selection: C = r_i c_j S^(1/p*) (the 1/p root of
+// Sec. 1 with the restored row / column scale), optional clamp, APSP diagonal.
+template <typename TO>
+__global__ __launch_bounds__(kThreads) void mt_select_root_f64_kernel(
+    const double* __restrict__ S, const uint8_t* __restrict__ code, int64_t rows, int64_t m,
+    int64_t n, const double* __restrict__ r, const double* __restrict__ c, RootSpec spec,
+    TO* __restrict__ out, uint8_t* __restrict__ pstar_out) {
+    for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int64_t bi = row / m;
+        const int64_t i = row - bi * m;
+        const double ri = r ? r[row] : 1.0;
+        for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n;
+             j += (int64_t)gridDim.x * kThreads) {
+            const int64_t e = row * n + j;
+            const uint8_t q = code[e];
+            const int qi = q == MT_PSTAR_NONE ? 0 : q;
+            const int p = spec.p[qi];
+            const double s = S[e];
+            const double root = p == 1 ? s : (s > 0.0 ? exp(log(s) / (double)p) : 0.0);
+            double v = ri * (c ? c[bi * n + j] : 1.0) * root * spec.corr[qi];
+            if (spec.mode == EPI_APSP_X || spec.clamp) v = fmin(v, 1.0);
+            if (spec.mode == EPI_APSP_X && i == j) v = 1.0;
+            out[e] = (TO)v;
+            if (pstar_out) pstar_out[e] = q;
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = 65535 * 8) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st) {
+    if (words <= 0) return hipSuccess;
+    timing_before("mt_fill_zero", st);
+    hipLaunchKernelGGL(fill_zero_u32_kernel, dim3(grid_for(words, kThreads * 4, 4096)),
+                       dim3(kThreads), 0, st, (uint32_t*)p, words);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r, int32_t* flag,
+                         hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((rows + 3) / 4));
+    timing_before("mt_rowmax", st);
+    if (f64)
+        hipLaunchKernelGGL(mt_rowmax_kernel<double>, grid, dim3(kThreads), 0, st, (const double*)A,
+                           rows, k, r, flag);
+    else
+        hipLaunchKernelGGL(mt_rowmax_kernel<float>, grid, dim3(kThreads), 0, st, (const float*)A,
+                           rows, k, r, flag);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n, double* c,
+                         int32_t* flag, hipStream_t st) {
+    hipError_t e = launch_fill_zero_u32(c, b * n * 2, st);
+    if (e != hipSuccess || k <= 0) return e;
+    const dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)((k + 63) / 64), (unsigned)b);
+    timing_before("mt_colmax", st);
+    if (f64)
+        hipLaunchKernelGGL(mt_colmax_kernel<double>, grid, dim3(kThreads), 0, st, (const double*)B,
+                           k, n, c, flag);
+    else
+        hipLaunchKernelGGL(mt_colmax_kernel<float>, grid, dim3(kThreads), 0, st, (const float*)B, k,
+                           n, c, flag);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int64_t b, int64_t rows,
+                               int64_t cols, int64_t rows_pad, int64_t cols_pad,
+                               const double* scale, const PlaneSpec& spec, int bf16, void* planes,
+                               hipStream_t st) {
+    if (rows_pad <= 0 || cols_pad <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((cols_pad + 63) / 64), (unsigned)((rows_pad + 63) / 64), (unsigned)b);
+#define MT_PLANES(TS, BF, TR)                                                                   \
+    hipLaunchKernelGGL((mt_power_planes_kernel<TS, BF, TR>), grid, dim3(kThreads), 0, st,      \
+                       (const TS*)src, rows, cols, rows_pad, cols_pad, scale, spec, planes)
+    timing_before(bf16 ? "mt_power_planes_bf16" : "mt_power_planes_f64", st);
+    if (src_f64) {
+        if (bf16) {
+            if (transpose) MT_PLANES(double, true, true); else MT_PLANES(double, true, false);
+        } else {
+            if (transpose) MT_PLANES(double, false, true); else MT_PLANES(double, false, false);
+        }
+    } else {
+        if (bf16) {
+            if (transpose) MT_PLANES(float, true, true); else MT_PLANES(float, true, false);
+        } else {
+            if (transpose) MT_PLANES(float, false, true); else MT_PLANES(float, false, false);
+        }
+    }
+#undef MT_PLANES
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_apsp_transform(const float* W, int64_t n, double s, void* X, int x_f64,
+                                 int32_t* flag, hipStream_t st) {
+    const dim3 grid(grid_for(n * n, kThreads * 8, 1 << 16));
+    timing_before("mt_apsp_transform", st);
+    if (x_f64)
+        hipLaunchKernelGGL(mt_apsp_transform_kernel<double>, grid, dim3(kThreads), 0, st, W, n, s,
+                           (double*)X, flag);
+    else
+        hipLaunchKernelGGL(mt_apsp_transform_kernel<float>, grid, dim3(kThreads), 0, st, W, n, s,
+                           (float*)X, flag);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_apsp_to_dist(const void* X, int x_f64, int64_t n, double s, void* D, int d_f64,
+                               int raw, hipStream_t st) {
+    const dim3 grid(grid_for(n * n, kThreads * 8, 1 << 16));
+    const double s_inv = 1.0 / s;
+    timing_before("mt_apsp_to_dist", st);
+    if (x_f64) {
+        if (d_f64)
+            hipLaunchKernelGGL((mt_apsp_to_dist_kernel<double, double>), grid, dim3(kThreads), 0, st,
+                               (const double*)X, n * n, s_inv, raw, (double*)D);
+        else
+            hipLaunchKernelGGL((mt_apsp_to_dist_kernel<double, float>), grid, dim3(kThreads), 0, st,
+                               (const double*)X, n * n, s_inv, raw, (float*)D);
+    } else {
+        if (d_f64)
+            hipLaunchKernelGGL((mt_apsp_to_dist_kernel<float, double>), grid, dim3(kThreads), 0, st,
+                               (const float*)X, n * n, s_inv, raw, (double*)D);
+        else
+            hipLaunchKernelGGL((mt_apsp_to_dist_kernel<float, float>), grid, dim3(kThreads), 0, st,
+                               (const float*)X, n * n, s_inv, raw, (float*)D);
+    }
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_root_f64(const double* S, const uint8_t* code, int64_t b, int64_t m,
+                                  int64_t n, const double* r, const double* c, const RootSpec& spec,
+                                  void* out, int out_f64, uint8_t* pstar_out, hipStream_t st) {
+    const int64_t rows = b * m;
+    if (rows <= 0 || n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)(rows < 65535 ? rows : 65535));
+    timing_before("mt_select_root_f64", st);
+    if (out_f64)
+        hipLaunchKernelGGL(mt_select_root_f64_kernel<double>, grid, dim3(kThreads), 0, st, S, code,
+                           rows, m, n, r, c, spec, (double*)out, pstar_out);
+    else
+        hipLaunchKernelGGL(mt_select_root_f64_kernel<float>, grid, dim3(kThreads), 0, st, S, code,
+                           rows, m, n, r, c, spec, (float*)out, pstar_out);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+}  // namespace mt

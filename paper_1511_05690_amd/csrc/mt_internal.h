@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP translation units of libmaxtimes.
+// Not part of the public ABI (include/maxtimes.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "maxtimes.h"
+
+namespace mt {
+
+// ---------------------------------------------------------------- vector types
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void glb_cvoid;
+
+// ---------------------------------------------------------------- tiling
+// BF16 p-family GEMM: 256 x 256 output tile per workgroup, K step 64.
+constexpr int kBf16BM = 256;
+constexpr int kBf16BN = 256;
+constexpr int kBf16BK = 64;
+// FP64 p-family GEMM: BM x BM output tile (BM = 128 or 64), K step 16.
+constexpr int kF64BK = 16;
+
+// Workspace header: domain flag word and p* histogram.
+struct WsHeader {
+    int32_t domain_flag;
+    int32_t pad[7];
+    int32_t hist[MT_MAX_P + 1];
+};
+
+// Processing plan of the p family for one fused GEMM launch.  Entries are in
+// processing order (largest p first); `pidx` maps back to the family index.
+// For a split p the three segments are (hi,hi), (hi,lo), (lo,hi).
+struct PlanEntry {
+    int32_t pidx;       // index into the family (what p_star records)
+    int32_t p;          // the power
+    int32_t nseg;       // 1 or 3
+    int32_t a_plane[3]; // plane index per segment (A side)
+    int32_t b_plane[3]; // plane index per segment (B side)
+    float inv_p;        // 1 / p
+    float corr;         // k^(-1/p) with MT_FLAG_NORM_CORRECT, else 1
+};
+
+struct FamilyPlan {
+    int32_t n;  // entries
+    double tau;
+    float tau_f;  // smallest FP32 value >= tau (exact FP32 form of S >= tau)
+    PlanEntry e[MT_MAX_P];
+};
+
+// Output modes of the fused epilogue.
+enum EpiMode : int32_t {
+    EPI_PLAIN = 0,      // C = r c S^(1/p)   (optional clamp <= 1)
+    EPI_APSP_X = 1,     // X = min(C, 1), X_ii = 1
+};
+
+struct EpiArgs {
+    int32_t mode;
+    int32_t clamp;       // EPI_PLAIN only
+    void* out;           // C (b x m x n) of out dtype
+    int32_t out_f64;     // 1: out is double, 0: float
+    uint8_t* pstar;      // nullable
+    int32_t* hist;       // nullable: per-family-index counts (+ [MT_MAX_P] = none)
+    const double* r;     // b x m (nullable: all ones)
+    const double* c;     // b x n (nullable: all ones)
+};
+
+// ---------------------------------------------------------------- launchers
+// Every launcher returns hipSuccess or the launch error.
+hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st);
+hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r,
+                         int32_t* flag, hipStream_t st);
+hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n, double* c,
+                         int32_t* flag, hipStream_t st);
+hipError_t launch_apsp_transform(const float* W, int64_t n, double s, void* X, int x_f64,
+                                 int32_t* flag, hipStream_t st);
+hipError_t launch_apsp_to_dist(const void* X, int x_f64, int64_t n, double s, void* D,
+                               int d_f64, int raw, hipStream_t st);
+
+// Power planes.  src is b x rows x cols (row-major, element f64 ? double :
+// float) when !transpose, or b x cols x rows when transpose (then planes hold
+// the transpose).  Output planes: [b][plane][rows_pad][cols_pad] of bf16
+// (bf16 != 0) or double.  scale (nullable) is b x rows: plane row t is
+// (src row t) / scale[t].  powers: ascending list; split[q] says whether
+// power q gets a hi/lo pair (bf16 only).
+struct PlaneSpec {
+    int32_t n_p;
+    int32_t p[MT_MAX_P];
+    int32_t split[MT_MAX_P];
+    int32_t first_plane[MT_MAX_P];  // plane index of power q (hi plane if split)
+    int32_t n_planes;
+};
+hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int64_t b,
+                               int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
+                               const double* scale, const PlaneSpec& spec, int bf16, void* planes,
+                               hipStream_t st);
+
+// Fused p-family GEMM + selection epilogue.
+hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m,
+                                    int64_t n, int64_t mp, int64_t np, int64_t kp, int32_t n_planes,
+                                    const FamilyPlan& plan, const EpiArgs& epi, hipStream_t st);
+hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b, int64_t m,
+                                   int64_t n, int64_t mp, int64_t np, int64_t kp, int32_t n_planes,
+                                   int bm, const FamilyPlan& plan, const EpiArgs& epi,
+                                   hipStream_t st);
+
+// FP64 path: C = r c S^(1/p*) from the GEMM's recorded S and p* index.
+struct RootSpec {
+    int32_t p[MT_MAX_P];
+    double corr[MT_MAX_P];
+    int32_t mode;   // EpiMode
+    int32_t clamp;
+};
+hipError_t launch_select_root_f64(const double* S, const uint8_t* code, int64_t b, int64_t m,
+                                  int64_t n, const double* r, const double* c, const RootSpec& spec,
+                                  void* out, int out_f64, uint8_t* pstar_out, hipStream_t st);
+
+// Per-kernel event timing (api.cpp).
+void timing_before(const char* name, hipStream_t st);
+void timing_after(hipStream_t st);
+
+}  // namespace mt

@@ -1,0 +1,79 @@
+"""Comparison of the GPU estimate with the oracle (test infrastructure).
+
+Parity bar (floating point, from the precision of each path):
+  * FP64 path:       relative error <= 1e-5 where both sides chose the same p*.
+  * BF16-split path: relative error <= 2e-3 where both sides chose the same p*.
+Where the two sides chose different p* (the ring result of the disputed p
+sits on the threshold tau, and the two sides round differently), the entry
+passes only if the oracle's S at the disputed p is within the path's
+precision band of tau, and the GPU value then matches the oracle's estimate
+evaluated at the GPU's p*.  Bands: 1e-10 (FP64), 1e-3 (BF16 split p),
+1.2e-2 (BF16 unsplit p).  Entries where no p was stable on both sides are
+below the precision either path guarantees; they must agree in being tiny.
+"""
+
+import numpy as np
+
+import oracle
+
+TOL = {"fp64": 1e-5, "bf16": 2e-3}
+BAND = {"fp64": 1e-10, "bf16_split": 1e-3, "bf16": 1.2e-2}
+TAU = {"fp64": 1e-290, "bf16": 1e-30}
+
+
+def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, max_flip_frac=0.01):
+    """Check GPU (C, p*) against the oracle dict ``ref`` (pnorm_estimate
+    output).  Returns a dict of statistics."""
+    P = np.asarray(P)
+    tol = TOL[path]
+    tau = TAU[path] if "tau" not in ref else ref["tau"]
+    C_gpu = np.asarray(C_gpu, dtype=np.float64)
+    ps_gpu = np.asarray(ps_gpu)
+    C_ref = ref["C"]
+    q_ref = ref["pstar_idx"]
+    S = ref["S"]
+    r, c = ref["r"], ref["c"]
+    rc = r[..., :, None] * c[..., None, :]
+    none_g = ps_gpu == oracle.PSTAR_NONE
+    none_r = q_ref == oracle.PSTAR_NONE
+
+    same = (ps_gpu == q_ref) & ~none_g
+    denom = np.maximum(np.abs(C_ref), 1e-300)
+    rel = np.abs(C_gpu - C_ref) / denom
+    bad = same & (rel > tol)
+    assert not bad.any(), f"{bad.sum()} entries exceed rel tol {tol}: max {rel[same].max():.3e}"
+
+    flips = (ps_gpu != q_ref)
+    n_flip = int(flips.sum())
+    if n_flip:
+        qg = np.where(none_g, -1, ps_gpu.astype(np.int64))
+        qr = np.where(none_r, -1, q_ref.astype(np.int64))
+        qd = np.maximum(qg, qr)[flips]
+        Sd = np.take_along_axis(S, np.maximum(np.maximum(qg, qr), 0)[None], 0)[0][flips]
+        if path == "fp64":
+            band = np.full(qd.shape, BAND["fp64"])
+        else:
+            band = np.where(P[qd] <= split_max_p, BAND["bf16_split"], BAND["bf16"])
+        ok_band = np.abs(Sd / tau - 1.0) <= band
+        assert ok_band.all(), f"{(~ok_band).sum()} p* flips away from tau (S/tau-1 up to {np.abs(Sd / tau - 1).max():.3e})"
+        # GPU value against the oracle evaluated at the GPU's p*
+        qg_used = np.where(qg < 0, 0, qg)[flips]
+        S_at = np.take_along_axis(S, np.where(qg < 0, 0, qg)[None], 0)[0][flips]
+        C_at = rc[flips] * np.power(S_at, 1.0 / P[qg_used])
+        if norm_k is not None:
+            C_at = C_at / np.power(float(norm_k), 1.0 / P[qg_used])
+        rel_at = np.abs(C_gpu[flips] - C_at) / np.maximum(np.abs(C_at), 1e-300)
+        stable_g = ~none_g[flips]
+        assert (rel_at[stable_g] <= tol).all(), f"flip entries off by {rel_at[stable_g].max():.3e}"
+        assert n_flip <= max_flip_frac * C_ref.size + 2, f"too many p* flips: {n_flip} of {C_ref.size}"
+
+    both_none = none_g & none_r
+    if both_none.any():
+        # below tau neither side is accurate; both must be at most the value the threshold allows
+        cap = rc * np.power(tau * (1 + 1e-2), 1.0 / P[0]) * 1.01
+        if norm_k is not None:
+            cap = cap / np.power(float(norm_k), 1.0 / P[0])
+        assert (C_gpu[both_none] <= cap[both_none] + 1e-300).all()
+        assert (C_gpu[both_none] >= 0).all()
+    return {"max_rel": float(rel[same].max()) if same.any() else 0.0,
+            "flips": n_flip, "none": int(both_none.sum()), "n": int(C_ref.size)}

@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/maxtimes.h declares, and rejects bad arguments synchronously (before
+anything touches the device).  No compute call is made here."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1511_05690_amd as mt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "maxtimes.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(mt.library_path()),
+                                reason="libmaxtimes.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = mt.load_library()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version():
+    lib = mt.load_library()
+    for code in range(6):
+        assert lib.maxtimes_status_string(code)
+    assert lib.maxtimes_version().startswith(b"maxtimes")
+
+
+def _ws(P, path="bf16", b=1, m=64, k=64, n=64, **kw):
+    return mt.workspace_size(b, m, k, n, P, path=path, **kw)
+
+
+def test_workspace_sizes_scale_with_family_and_path():
+    small = _ws([1, 2])
+    big = _ws(mt.pfamily(128))
+    assert 0 < small < big
+    # BF16: 11 planes of 256x64 (padded) per operand for {1..128} with split p <= 4
+    planes = 11 * 256 * 64 * 2
+    assert big >= 2 * planes
+    f64 = _ws(mt.pfamily(128), path="fp64")
+    assert f64 > 0
+    assert mt.apsp_workspace_size(100, mt.pfamily(64), path="fp64") > 0
+
+
+@pytest.mark.parametrize("P,err", [([], 1), ([2, 1], 1), ([0, 1], 1), ([1, 5000], 1),
+                                   ([1, 1], 1), (list(range(1, 40)), 1)])
+def test_bad_family_rejected(P, err):
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws(P)
+    assert e.value.status == err
+
+
+def test_bad_path_flags_and_sizes_rejected():
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([1, 2], path=7)
+    assert e.value.status == 1
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([1, 2], flags=64)
+    assert e.value.status == 1
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([1, 2], m=-1)
+    assert e.value.status == 1
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([1, 2], n=1 << 25)
+    assert e.value.status == 5
+
+
+def _opts(P, path=1, flags=0):
+    return mt._options(P, path, None, None, flags)
+
+
+def test_null_pointers_and_small_workspace_rejected_before_launch():
+    lib = mt.load_library()
+    o = _opts([1, 2, 4])
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: every call fails validation first
+    null = ctypes.c_void_p(0)
+    st = lib.maxtimes_estimate(fake, fake, 0, 1, 8, 8, 8, None, fake, null, fake, 1 << 30, null)
+    assert st == 1
+    st = lib.maxtimes_estimate(fake, fake, 0, 1, 8, 8, 8, ctypes.byref(o), null, null, fake, 1 << 30, null)
+    assert st == 1 and b"C is NULL" in lib.maxtimes_last_error()
+    st = lib.maxtimes_estimate(null, fake, 0, 1, 8, 8, 8, ctypes.byref(o), fake, null, fake, 1 << 30, null)
+    assert st == 1
+    st = lib.maxtimes_estimate(fake, fake, 9, 1, 8, 8, 8, ctypes.byref(o), fake, null, fake, 1 << 30, null)
+    assert st == 1
+    st = lib.maxtimes_estimate(fake, fake, 0, 1, 8, 8, 8, ctypes.byref(o), fake, null, fake, 16, null)
+    assert st == 3 and b"workspace" in lib.maxtimes_last_error()
+    st = lib.maxtimes_estimate(fake, fake, 0, 1, 8, 8, 8, ctypes.byref(o), fake, null, null, 1 << 30, null)
+    assert st == 1
+    misaligned = ctypes.c_void_p(0x100004)
+    st = lib.maxtimes_estimate(fake, fake, 0, 1, 8, 8, 8, ctypes.byref(o), fake, null, misaligned, 1 << 30, null)
+    assert st == 1
+    # empty output: nothing to do, nothing touched
+    st = lib.maxtimes_estimate(null, null, 0, 1, 0, 8, 8, ctypes.byref(o), null, null, null, 0, null)
+    assert st == 0
+    # raw output is an APSP-only flag
+    o2 = _opts([1, 2], flags=8)
+    st = lib.maxtimes_estimate(fake, fake, 0, 1, 8, 8, 8, ctypes.byref(o2), fake, null, fake, 1 << 30, null)
+    assert st == 1
+
+
+def test_apsp_argument_errors():
+    lib = mt.load_library()
+    o = _opts([1, 2, 4], path=0)
+    fake = ctypes.c_void_p(0x100000)
+    null = ctypes.c_void_p(0)
+    assert lib.apsp_estimate(fake, 8, 0.0, -1, ctypes.byref(o), fake, 0, null, fake, 1 << 30, null) == 1
+    assert lib.apsp_estimate(fake, 8, float("inf"), -1, ctypes.byref(o), fake, 0, null, fake, 1 << 30, null) == 1
+    assert lib.apsp_estimate(null, 8, 1.0, -1, ctypes.byref(o), fake, 0, null, fake, 1 << 30, null) == 1
+    assert lib.apsp_estimate(fake, 8, 1.0, -1, ctypes.byref(o), fake, 0, null, fake, 8, null) == 3
+    assert lib.apsp_estimate(fake, 8, 1.0, 100, ctypes.byref(o), fake, 0, null, fake, 1 << 30, null) == 1
+    o2 = _opts([1, 2], path=0, flags=2)
+    assert lib.apsp_estimate(fake, 8, 1.0, -1, ctypes.byref(o2), fake, 0, null, fake, 1 << 30, null) == 5
+    assert lib.apsp_estimate(null, 0, 1.0, -1, ctypes.byref(o), null, 0, null, null, 0, null) == 0
+
+
+def test_timing_read_without_launches():
+    mt.timing_reset()
+    assert mt.timing_read("mt_") == (0.0, 0)
