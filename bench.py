@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the p-norm (max, x) product estimate on one MI355X.
+
+Workload (the configuration the metric compares the BF16 and FP64 paths
+on): C ~ max_k A_ik B_kj for A, B of 8192 x 8192, entries exp(N(0, 2^2))
+clipped to (0, 1e6], stored FP32; family P = {1, 2, ..., 128}; BF16 MFMA
+ring products with FP32 accumulation and hi/lo split for p <= 4.  A step is
+one maxtimes_estimate call (row/column maxima, power planes, fused p-family
+GEMM with the per-entry selection and root) on inputs resident in HBM.
+
+value = n^3 / t_step (effective max-times ops/s).  The FP64 path is timed on
+the same inputs; both are checked against the exact product (computed on
+the GPU by the library's exact kernel) on 256 sampled rows.  The oracle is
+timed on the host on a bounded row sample (cpu_baseline).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective max-times ops/s (n³/t) BF16 vs FP64 path; max rel. err vs exact"
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 matrix
+HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pfamily_gemm_bf16_8192_pmc.md")
+GEMM_SRC = os.path.join(ROOT, "paper_1511_05690_amd", "csrc", "mt_gemm_bf16.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the BF16 GEMM from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != source_hash(GEMM_SRC):
+        return None
+    return float(m_bytes.group(1))
+
+
+def gemm_segments(P, split_max_p=4):
+    return sum(3 if p <= split_max_p else 1 for p in P)
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / steps, wall
+
+
+def cpu_baseline(A, B, P, tau, rows):
+    """The oracle as it stands, on a bounded sample of output rows."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.pnorm_estimate_rows(A, B, P, tau, rows)
+    dt = time.perf_counter() - t0
+    n = B.shape[1]
+    k = A.shape[1]
+    blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+    threads = max([p.get("num_threads", 1) for p in blas] or [1])
+    return {
+        "value": len(rows) * k * n / dt,
+        "unit": "max-times ops/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"{len(rows)} of {A.shape[0]} output rows of the same 8192^2 workload "
+                   f"(FP64 numpy: powers of all of B, {len(P)} BLAS GEMMs of {len(rows)}x{k}x{n}); "
+                   f"{dt:.1f} s; elementwise numpy steps run on 1 thread, BLAS on {threads}; "
+                   f"host logical CPUs {os.cpu_count()}"),
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--only", choices=["bf16", "fp64"], default=None,
+                    help="time one path only (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=128)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the p-norm "
+              "product is measured on one MI355X; the multi-GPU sharding is a design, not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.calib_copy_mib:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": nbytes, "launches": 3}))
+        return
+
+    import paper_1511_05690_amd as mt
+    from workloads import config
+
+    mt.load_library()
+    log("[bench] generating the 8192^2 log-normal workload")
+    cfg = config(3)
+    A, B, P = cfg["A"], cfg["B"], cfg["P"]
+    n = A.shape[0]
+    Ad = torch.from_numpy(A).cuda()
+    Bd = torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    ops = float(n) ** 3
+
+    out = {}
+    res = {}
+    paths = [args.only] if args.only else ["bf16", "fp64"]
+    for path in paths:
+        steps = args.steps if path == "bf16" else args.fp64_steps
+        warm = args.warmup if path == "bf16" else 1
+        ws = torch.empty(mt.workspace_size(1, n, n, n, P, path=path), dtype=torch.uint8, device="cuda")
+        holder = {}
+
+        def step():
+            holder["C"] = mt.estimate(Ad, Bd, P=P, path=path, workspace=ws)
+
+        for _ in range(warm):
+            step()
+        torch.cuda.synchronize()
+        mt.timing_reset()
+        mt.timing_enable(True)
+        log(f"[bench] timing {path}: {steps} steps")
+        ms, wall = time_steps(step, steps, 0, torch)
+        mt.timing_enable(False)
+        kname = "mt_pfamily_gemm_" + ("bf16" if path == "bf16" else "f64")
+        gemm_ms, gemm_n = mt.timing_read(kname)
+        kern = {}
+        for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_pfamily_gemm", "mt_select_root",
+                   "mt_fill_zero"):
+            t, c = mt.timing_read(kn)
+            if c:
+                kern[kn] = round(t / steps, 4)
+        mt.timing_reset()
+        res[path] = {"ms_per_step": ms, "wall_s": wall, "gemm_ms": gemm_ms / max(gemm_n, 1),
+                     "gemm_launches": gemm_n, "kernel_ms_per_step": kern, "C": holder["C"]}
+        del ws
+        log(f"[bench] {path}: {ms:.3f} ms/step, GEMM {gemm_ms / max(gemm_n, 1):.3f} ms")
+
+    # error against the exact product on sampled rows (exact kernel on the GPU)
+    rows = np.sort(np.random.default_rng(3003).choice(n, 256, replace=False))
+    ri = torch.from_numpy(rows).cuda()
+    Asub = Ad[ri].contiguous()
+    E = mt.exact(Asub, Bd)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    E = mt.exact(Asub, Bd)
+    ev1.record()
+    torch.cuda.synchronize()
+    exact_ms = ev0.elapsed_time(ev1)
+    E64 = E.double()
+    errs = {}
+    for path in res:
+        rel = (res[path]["C"][ri].double() / E64 - 1.0).abs()
+        errs[path] = {"max": float(rel.max()), "median": float(rel.median())}
+        del res[path]["C"]
+
+    bf = res.get("bf16") or res[paths[0]]
+    main_path = "bf16" if "bf16" in res else paths[0]
+    seg = gemm_segments(P) if main_path == "bf16" else len(P)
+    flop = 2.0 * n * n * n * seg
+    achieved = flop / (bf["gemm_ms"] / 1e3) / 1e12
+    peak = BF16_PEAK_TFLOPS if main_path == "bf16" else FP64_PEAK_TFLOPS
+    traffic = traffic_from_profile() if main_path == "bf16" else None
+
+    value = ops / (bf["ms_per_step"] / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "max-times ops/s",
+        "n_gpus": 1,
+        "steps": args.steps if main_path == "bf16" else args.fp64_steps,
+        "warmup": args.warmup if main_path == "bf16" else 1,
+        "ms_per_step": bf["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if main_path == "bf16" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "8192^2 max-times product estimate, A,B = exp(N(0,2^2)) clipped to (0,1e6] "
+                        "FP32, P={1..128}, " + ("BF16 MFMA + FP32 accumulation, hi/lo split p<=4"
+                                                if main_path == "bf16" else "FP64 MFMA"),
+            "n": n, "p_family": P, "path": main_path,
+            "tau": 1e-30 if main_path == "bf16" else 1e-290,
+        },
+        "roofline": {
+            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic,
+            "kernel": "mt_pfamily_gemm_" + ("bf16" if main_path == "bf16" else "f64"),
+            "flop_per_launch": flop,
+            "avg_launch_ms": bf["gemm_ms"],
+        },
+        "kernel_ms_per_step": bf["kernel_ms_per_step"],
+        "max_rel_err_vs_exact": errs,
+        "exact_valu": {"rows": len(rows), "ms": exact_ms,
+                       "ops_per_s": len(rows) * float(n) * n / (exact_ms / 1e3)},
+    }
+    if "fp64" in res and main_path == "bf16":
+        f = res["fp64"]
+        fval = ops / (f["ms_per_step"] / 1e3)
+        out["fp64_path"] = {
+            "value": fval, "ms_per_step": f["ms_per_step"], "steps": args.fp64_steps,
+            "gemm_ms": f["gemm_ms"],
+            "gemm_tflops": 2.0 * n ** 3 * len(P) / (f["gemm_ms"] / 1e3) / 1e12,
+            "gemm_frac_of_fp64_peak": 2.0 * n ** 3 * len(P) / (f["gemm_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+            "kernel_ms_per_step": f["kernel_ms_per_step"],
+        }
+        out["bf16_over_fp64"] = value / fval
+
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_rows} rows")
+        out["cpu_baseline"] = cpu_baseline(A, B, P, 1e-30, rows[:args.cpu_rows])
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

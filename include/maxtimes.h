@@ -159,6 +159,16 @@ mt_status apsp_estimate(const float* W, int64_t n, double s, int32_t n_squarings
                         uint8_t* p_star_last, void* workspace, size_t ws_bytes,
                         void* stream);
 
+/*
+ * The exact (max, x) product E_ij = max_k A_ik B_kj (Alg. 2, Sec. 2.2), E
+ * starting at 0, on the vector ALUs: products in the input precision (one
+ * rounding), exact max.  A b x m x k, B b x k x n, E b x m x n, all of dtype,
+ * device memory; no workspace.  For measuring the estimate's error and as
+ * the exact-product throughput beside it.
+ */
+mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,
+                         int64_t k, int64_t n, void* E, void* stream);
+
 /* Static description of a status code. */
 const char* maxtimes_status_string(mt_status status);
 

@@ -20,7 +20,7 @@ import torch
 
 __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
-    "workspace_size", "backward_workspace_size", "apsp_workspace_size", "timing_enable",
+    "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
     "timing_reset", "timing_read", "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
@@ -78,6 +78,7 @@ def load_library():
         "apsp_workspace_size": [i64, opt, ctypes.POINTER(sz)],
         "apsp_estimate": [vp, i64, ctypes.c_double, ctypes.c_int32, opt, vp, ctypes.c_int, vp, vp,
                           sz, vp],
+        "maxtimes_exact": [vp, vp, ctypes.c_int, i64, i64, i64, i64, vp, vp],
         "maxtimes_timing_enable": [ctypes.c_int],
         "maxtimes_timing_reset": [],
         "maxtimes_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -277,6 +278,20 @@ def apsp(W, s=1.0, P=None, path="fp64", n_squarings=-1, tau=None, split_max_p=No
     _check(lib.apsp_estimate(_ptr(W), n, float(s), int(n_squarings), ctypes.byref(o), _ptr(D),
                              _dtype_code(D), _ptr(ps), _ptr(ws), need.value, _stream(W.device)))
     return (D, ps) if return_pstar else D
+
+
+def exact(A, B):
+    """The exact (max, x) product max_k A_ik B_kj on the GPU's vector ALUs
+    (products rounded once in the input precision)."""
+    lib = load_library()
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    A = A.contiguous()
+    B = B.contiguous()
+    b, m, k, n, batched = _shape3(A, B)
+    E = torch.empty((b, m, n) if batched else (m, n), dtype=A.dtype, device=A.device)
+    _check(lib.maxtimes_exact(_ptr(A), _ptr(B), _dtype_code(A), b, m, k, n, _ptr(E), _stream(A.device)))
+    return E
 
 
 def timing_enable(on=True):

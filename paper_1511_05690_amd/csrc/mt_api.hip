@@ -439,6 +439,20 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
     return fail(MT_ERR_UNSUPPORTED, "backward not built yet");
 }
 
+mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,
+                         int64_t k, int64_t n, void* E, void* stream) {
+    g_last_error.clear();
+    mt_status s = check_dims(b, m, k, n);
+    if (s != MT_OK) return s;
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (b == 0 || m == 0 || n == 0) return MT_OK;
+    if (!E) return fail(MT_ERR_INVALID_ARG, "E is NULL");
+    if (k > 0 && (!A || !B)) return fail(MT_ERR_INVALID_ARG, "A or B is NULL");
+    if (b > 65535 || m > ((int64_t)65535 * 64)) return fail(MT_ERR_UNSUPPORTED, "b or m too large for the exact kernel");
+    MT_TRY(launch_exact_maxtimes(A, B, dtype == MT_F64, b, m, k, n, E, (hipStream_t)stream), "exact product");
+    return MT_OK;
+}
+
 mt_status maxtimes_timing_enable(int on) {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_timing = on != 0;

@@ -121,6 +121,10 @@ hipError_t launch_select_root_f64(const double* S, const uint8_t* code, int64_t 
                                   int64_t n, const double* r, const double* c, const RootSpec& spec,
                                   void* out, int out_f64, uint8_t* pstar_out, hipStream_t st);
 
+// Exact (max, x) product on the vector ALUs.
+hipError_t launch_exact_maxtimes(const void* A, const void* B, int f64, int64_t b, int64_t m,
+                                 int64_t k, int64_t n, void* E, hipStream_t st);
+
 // Per-kernel event timing (api.cpp).
 void timing_before(const char* name, hipStream_t st);
 void timing_after(hipStream_t st);

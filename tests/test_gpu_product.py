@@ -183,3 +183,19 @@ def test_timing_facility_sees_kernels(gpu_lib):
         gpu_lib.timing_enable(False)
         gpu_lib.timing_reset()
     assert n == 1 and ms > 0
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (70, 33, 130), (3, 200, 64, 90)])
+def test_exact_kernel_matches_oracle(gpu_lib, shape):
+    """The exact (max, x) product kernel (Alg. 2) against the oracle."""
+    import torch
+
+    if len(shape) == 3:
+        A, B = uniform_product(*shape, seed=21)
+    else:
+        A, B = uniform_product(*shape[1:], seed=21, batch=shape[0])
+    for dt, tol in ((np.float64, 0.0), (np.float32, 6e-8)):
+        Ad, Bd = torch.from_numpy(A.astype(dt)).cuda(), torch.from_numpy(B.astype(dt)).cuda()
+        E = gpu_lib.exact(Ad, Bd).cpu().numpy().astype(np.float64)
+        ref = oracle.exact_maxtimes(A.astype(dt), B.astype(dt))
+        np.testing.assert_allclose(E, ref, rtol=tol, atol=0)
