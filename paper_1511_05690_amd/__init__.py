@@ -222,10 +222,17 @@ def estimate_backward(A, B, G, C, p_star, P, path="bf16", tau=None, split_max_p=
     return dA, dB
 
 
+# On the BF16 path the differentiable forward splits every power into hi + lo:
+# the adjoint raises C' to the power 1 - p, which carries the forward's
+# relative error in S undamped, so S must be accurate to about 1e-5.
+SPLIT_ALL = 4096
+
+
 class _EstimateFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, A, B, P, path, tau, split_max_p, flags):
-        C, ps = _forward(A, B, P, path, tau, split_max_p, flags, True)
+        fwd_split = SPLIT_ALL if (path == "bf16" and split_max_p is None) else split_max_p
+        C, ps = _forward(A, B, P, path, tau, fwd_split, flags, True)
         ctx.save_for_backward(A, B, C, ps)
         ctx.cfg = (tuple(P), path, tau, split_max_p, flags)
         ctx.mark_non_differentiable(ps)

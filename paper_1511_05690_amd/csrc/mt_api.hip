@@ -251,6 +251,39 @@ mt_status read_domain_flag(const uint8_t* ws, hipStream_t st) {
     return MT_OK;
 }
 
+// Backward workspace: adjoint planes of both gradient products and the
+// power planes they multiply (every power split on the BF16 path).
+struct BwdLayout {
+    int64_t m_out, k_out, n_out;  // output rows / cols padded to the adjoint tile
+    int64_t m_in, n_in;           // inner lengths padded to the K step
+    int32_t g_planes;             // adjoint planes per batch item
+    size_t hdr, r, c, xa, yb, pa, pb, total;
+};
+
+BwdLayout backward_layout(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
+    BwdLayout L;
+    const int64_t bm = f.bf16 ? kAdjBM : kAdjF64BM;
+    const int64_t ks = f.bf16 ? kBf16BK : kF64BK;
+    const size_t es = f.bf16 ? 2 : 8;
+    L.m_out = round_up(m, bm);
+    L.k_out = round_up(k, bm);
+    L.n_out = round_up(n, bm);
+    L.m_in = round_up(m, ks);
+    L.n_in = round_up(n, ks);
+    L.g_planes = f.bf16 ? 2 * f.n : f.n;
+    const int64_t pw_planes = f.bf16 ? 2 * f.n : f.n;
+    size_t off = 0;
+    L.hdr = off; off += align_up(sizeof(WsHeader));
+    L.r = off;   off += align_up((size_t)(b * m) * 8);
+    L.c = off;   off += align_up((size_t)(b * n) * 8);
+    L.xa = off;  off += align_up((size_t)b * L.g_planes * L.m_out * L.n_in * es);
+    L.yb = off;  off += align_up((size_t)b * L.g_planes * L.n_out * L.m_in * es);
+    L.pa = off;  off += align_up((size_t)b * pw_planes * L.k_out * L.n_in * es);
+    L.pb = off;  off += align_up((size_t)b * pw_planes * L.k_out * L.m_in * es);
+    L.total = off;
+    return L;
+}
+
 // The product pipeline on already-validated arguments.  X-mode (APSP):
 // A = B = X (n x n, r = c = 1 by construction), the output goes back to X.
 mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64_t m, int64_t k,
@@ -261,8 +294,10 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     double* c = scale ? (double*)(ws + L.c) : nullptr;
     void* ap = ws + L.ap;
     void* bp = ws + L.bp;
-    MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, ps, f.bf16, ap, st), "power planes (A)");
-    MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, ps, f.bf16, bp, st), "power planes (B)");
+    MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps, f.bf16, ap, st),
+           "power planes (A)");
+    MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, nullptr, ps, f.bf16, bp, st),
+           "power planes (B)");
     const FamilyPlan plan = family_plan(f, ps, k);
     EpiArgs epi;
     memset(&epi, 0, sizeof epi);
@@ -425,8 +460,13 @@ mt_status apsp_estimate(const float* W, int64_t n, double s_scale, int32_t n_squ
 mt_status maxtimes_backward_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
                                            const mt_options* opt, size_t* bytes) {
     g_last_error.clear();
-    (void)b; (void)m; (void)k; (void)n; (void)opt; (void)bytes;
-    return fail(MT_ERR_UNSUPPORTED, "backward not built yet");
+    if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    *bytes = backward_layout(f, b, m, k, n).total;
+    return MT_OK;
 }
 
 mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G, const void* C,
@@ -434,9 +474,129 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
                                      int64_t k, int64_t n, const mt_options* opt, void* dA, void* dB,
                                      void* workspace, size_t ws_bytes, void* stream) {
     g_last_error.clear();
-    (void)A; (void)B; (void)G; (void)C; (void)p_star; (void)dtype; (void)b; (void)m; (void)k; (void)n;
-    (void)opt; (void)dA; (void)dB; (void)workspace; (void)ws_bytes; (void)stream;
-    return fail(MT_ERR_UNSUPPORTED, "backward not built yet");
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if (f.flags & (MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT))
+        return fail(MT_ERR_UNSUPPORTED, "the backward supports the plain estimate only (no norm correction or clamp)");
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    if (!dA && !dB) return MT_OK;
+    if (b == 0 || k == 0) return MT_OK;  // nothing to write (dA, dB are empty)
+    if (m > 0 && n > 0 && (!A || !B || !G || !C || !p_star))
+        return fail(MT_ERR_INVALID_ARG, "A, B, G, C and p_star must be non-NULL");
+    const BwdLayout L = backward_layout(f, b, m, k, n);
+    if ((s = check_ws(workspace, ws_bytes, L.total)) != MT_OK) return s;
+
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)workspace;
+    const int f64 = dtype == MT_F64;
+    const size_t esz = f64 ? 8 : 4;
+    if (m == 0 || n == 0) {
+        // C is empty: both gradients are zero
+        if (dA) MT_TRY(launch_fill_zero_u32(dA, b * m * k * esz / 4, st), "zero dA");
+        if (dB) MT_TRY(launch_fill_zero_u32(dB, b * k * n * esz / 4, st), "zero dB");
+        return MT_OK;
+    }
+    int32_t* flag = (int32_t*)(ws + L.hdr);
+    int32_t* hist = ((WsHeader*)(ws + L.hdr))->hist;
+    double* r = (double*)(ws + L.r);
+    double* c = (double*)(ws + L.c);
+    MT_TRY(launch_fill_zero_u32(ws + L.hdr, sizeof(WsHeader) / 4, st), "clear header");
+    MT_TRY(launch_rowmax(A, f64, b * m, k, r, flag, st), "row max");
+    MT_TRY(launch_colmax(B, f64, b, k, n, c, flag, st), "column max");
+    MT_TRY(launch_pstar_hist(p_star, b * m * n, f.n, hist, st), "p* histogram");
+
+    AdjPrepSpec sp;
+    memset(&sp, 0, sizeof sp);
+    sp.n_p = f.n;
+    for (int q = 0; q < f.n; ++q) sp.p[q] = f.p[q];
+    sp.planes = L.g_planes;
+    sp.xa_rows_pad = L.m_out;
+    sp.xa_cols_pad = L.n_in;
+    sp.yb_rows_pad = L.n_out;
+    sp.yb_cols_pad = L.m_in;
+    MT_TRY(launch_adjoint_prep(G, C, p_star, f64, r, c, b, m, n, sp, hist, f.bf16, ws + L.xa, ws + L.yb, st),
+           "adjoint planes");
+
+    // every power split into hi + lo on the BF16 path (G has mixed signs)
+    PlaneSpec ps;
+    memset(&ps, 0, sizeof ps);
+    ps.n_p = f.n;
+    for (int q = 0; q < f.n; ++q) {
+        ps.p[q] = f.p[q];
+        ps.split[q] = f.bf16 ? 1 : 0;
+        ps.first_plane[q] = f.bf16 ? 2 * q : q;
+    }
+    ps.n_planes = f.bf16 ? 2 * f.n : f.n;
+    FamilyPlan plan;
+    memset(&plan, 0, sizeof plan);
+    plan.n = f.n;
+    plan.tau = f.tau;
+    plan.tau_f = round_up_to_float(f.tau);
+    for (int e = 0; e < f.n; ++e) {
+        PlanEntry& pe = plan.e[e];
+        pe.pidx = e;
+        pe.p = f.p[e];
+        pe.inv_p = 1.0f / (float)f.p[e];
+        pe.corr = 1.0f;
+        if (f.bf16) {
+            const int h = 2 * e;
+            pe.nseg = 3;
+            pe.a_plane[0] = h; pe.b_plane[0] = h;
+            pe.a_plane[1] = h; pe.b_plane[1] = h + 1;
+            pe.a_plane[2] = h + 1; pe.b_plane[2] = h;
+        } else {
+            pe.nseg = 1;
+            pe.a_plane[0] = e;
+            pe.b_plane[0] = e;
+        }
+    }
+    if (dA) {
+        // dA (m x k) = sum_p A'^(p-1) .* (Gt_p B'^p^T): X = Gt planes (rows m, inner n),
+        // Y = B'^p planes (rows k, inner n; B row-major is already K-contiguous)
+        MT_TRY(launch_power_planes(B, f64, 0, b, k, n, L.k_out, L.n_in, nullptr, c, ps, f.bf16, ws + L.pa, st),
+               "power planes (B, adjoint)");
+        AdjArgs aa;
+        memset(&aa, 0, sizeof aa);
+        aa.M = A;
+        aa.m_f64 = f64;
+        aa.scale_rows = r;
+        aa.hist = hist;
+        aa.out = dA;
+        aa.out_f64 = f64;
+        if (f.bf16)
+            MT_TRY(launch_adjoint_gemm_bf16((const uint16_t*)(ws + L.xa), (const uint16_t*)(ws + L.pa), b, m, k,
+                                            L.m_out, L.k_out, L.n_in, L.g_planes, ps.n_planes, plan, aa, st),
+                   "adjoint GEMM (dA)");
+        else
+            MT_TRY(launch_adjoint_gemm_f64((const double*)(ws + L.xa), (const double*)(ws + L.pa), b, m, k,
+                                           L.m_out, L.k_out, L.n_in, L.g_planes, ps.n_planes, plan, aa, st),
+                   "adjoint GEMM (dA)");
+    }
+    if (dB) {
+        // dB (k x n) = sum_p B'^(p-1) .* (A'^p^T Gt'_p): X = A'^p transposed (rows k,
+        // inner m), Y = Gt' planes transposed (rows n, inner m)
+        MT_TRY(launch_power_planes(A, f64, 1, b, k, m, L.k_out, L.m_in, nullptr, r, ps, f.bf16, ws + L.pb, st),
+               "power planes (A, adjoint)");
+        AdjArgs ab;
+        memset(&ab, 0, sizeof ab);
+        ab.M = B;
+        ab.m_f64 = f64;
+        ab.scale_cols = c;
+        ab.hist = hist;
+        ab.out = dB;
+        ab.out_f64 = f64;
+        if (f.bf16)
+            MT_TRY(launch_adjoint_gemm_bf16((const uint16_t*)(ws + L.pb), (const uint16_t*)(ws + L.yb), b, k, n,
+                                            L.k_out, L.n_out, L.m_in, ps.n_planes, L.g_planes, plan, ab, st),
+                   "adjoint GEMM (dB)");
+        else
+            MT_TRY(launch_adjoint_gemm_f64((const double*)(ws + L.pb), (const double*)(ws + L.yb), b, k, n,
+                                           L.k_out, L.n_out, L.m_in, ps.n_planes, L.g_planes, plan, ab, st),
+                   "adjoint GEMM (dB)");
+    }
+    return MT_OK;
 }
 
 mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,

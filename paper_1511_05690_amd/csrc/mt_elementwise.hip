@@ -107,12 +107,15 @@ __device__ inline T ipow(T x, int p) {
 // Power planes.  Tile: 64 plane rows x 64 plane columns per block.
 //   transpose == 0: plane row t = src row t (src is rows x cols)
 //   transpose == 1: plane row t = src column t (src is cols x rows)
+// Plane element (t, u) is src / (scale_rows[t] * scale_cols[u]) (each scale
+// optional; a zero scale gives 0), the scaled input of Sec. 2.1's H'.
 // Every thread produces 8 consecutive plane columns (one 16-byte BF16 chunk)
 // of two plane rows.
 template <typename TS, bool kBf16, bool kTranspose>
 __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
     const TS* __restrict__ src, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
-    const double* __restrict__ scale, PlaneSpec spec, void* __restrict__ planes) {
+    const double* __restrict__ scale_rows, const double* __restrict__ scale_cols, PlaneSpec spec,
+    void* __restrict__ planes) {
     __shared__ TS tile[64][64 + 1];
     const int64_t bi = blockIdx.z;
     const int64_t t0 = (int64_t)blockIdx.y * 64;  // plane row
@@ -139,14 +142,16 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
         if (t >= rows_pad || u >= cols_pad) continue;
         TC x[8];
         double sc = 1.0;
-        if (scale != nullptr && t < rows) sc = scale[bi * rows + t];
+        if (scale_rows != nullptr && t < rows) sc = scale_rows[bi * rows + t];
         const bool zero_row = (t >= rows) || (sc == 0.0);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             double v = 0.0;
             if (!zero_row && u + i < cols) {
                 v = kTranspose ? (double)tile[tt][ch * 8 + i] : (double)s[t * cols + u + i];
-                if (scale != nullptr) v = v / sc;
+                double d = sc;
+                if (scale_cols != nullptr) d *= scale_cols[bi * cols + u + i];
+                v = d > 0.0 ? v / d : 0.0;
             }
             x[i] = (TC)v;
         }
@@ -310,13 +315,14 @@ hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n
 
 hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int64_t b, int64_t rows,
                                int64_t cols, int64_t rows_pad, int64_t cols_pad,
-                               const double* scale, const PlaneSpec& spec, int bf16, void* planes,
-                               hipStream_t st) {
+                               const double* scale_rows, const double* scale_cols,
+                               const PlaneSpec& spec, int bf16, void* planes, hipStream_t st) {
     if (rows_pad <= 0 || cols_pad <= 0) return hipSuccess;
     const dim3 grid((unsigned)((cols_pad + 63) / 64), (unsigned)((rows_pad + 63) / 64), (unsigned)b);
 #define MT_PLANES(TS, BF, TR)                                                                   \
     hipLaunchKernelGGL((mt_power_planes_kernel<TS, BF, TR>), grid, dim3(kThreads), 0, st,      \
-                       (const TS*)src, rows, cols, rows_pad, cols_pad, scale, spec, planes)
+                       (const TS*)src, rows, cols, rows_pad, cols_pad, scale_rows, scale_cols, spec,  \
+                       planes)
     timing_before(bf16 ? "mt_power_planes_bf16" : "mt_power_planes_f64", st);
     if (src_f64) {
         if (bf16) {

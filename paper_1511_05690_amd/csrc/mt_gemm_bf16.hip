@@ -1,20 +1,27 @@
-// Fused p-family GEMM on BF16 MFMA (gfx950) with the selection epilogue.
+// p-family GEMMs on BF16 MFMA (gfx950): one main loop, two epilogues.
 //
-// For one output tile the kernel runs the ring product S_p = A'^p B'^p of
-// every p of the family (Alg. 5, first loop; Sec. 2.1 distributivity), one
-// after the other, largest p first, and after each p keeps, per entry, the
-// first p whose ring result passes the stability test S_p >= tau (Sec. 1,
-// the highest stable p).  Because the entries are visited from the largest p
-// down, the first pass is the largest stable p, and C = r c S^(1/p) is
-// written exactly once per entry.  Entries that never pass take the smallest
-// p (index MT_PSTAR_NONE).
+// Forward (selection epilogue).  For one output tile the kernel runs the ring
+// product S_p = A'^p B'^p of every p of the family (Alg. 5, first loop;
+// Sec. 2.1 distributivity), one after the other, largest p first, and after
+// each p keeps, per entry, the first p whose ring result passes the stability
+// test S_p >= tau (Sec. 1, the highest stable p).  Because the entries are
+// visited from the largest p down, the first pass is the largest stable p,
+// and C = r c S^(1/p) is written exactly once per entry.  Entries that never
+// pass take the smallest p (index MT_PSTAR_NONE).
 //
-// Operands are the BF16 power planes written by the plane kernel: A planes
-// m_pad x k_pad and B^T planes n_pad x k_pad, K contiguous.  A split p is
+// Adjoint (accumulating epilogue).  For the gradient with p* held fixed the
+// kernel runs, for every p that some entry uses, the product X_p Y_p of an
+// adjoint plane and a power plane, multiplies it elementwise by the scaled
+// input to the power p - 1 and sums over p in registers; the tile is written
+// once at the end.
+//
+// Operands are BF16 planes, K contiguous: X planes rows x k_pad and Y planes
+// cols x k_pad (Y holds the transpose of the right factor).  A split p is
 // three segments (hi.hi + hi.lo + lo.hi) accumulated into one FP32 sum.
 //
-// Tiling: 256 threads = 4 waves in 2 x 2; each wave owns WT_M x WT_N MFMA
-// tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16).  K step 64: the A and B tiles
+// Tiling: 512 threads = 8 waves (two per SIMD, so one wave's barrier and LDS
+// waits overlap the other's MFMAs) in 2 x 4; each wave owns WT_M x WT_N MFMA
+// tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16).  K step 64: the X and Y tiles
 // of a step are copied global -> LDS by the direct-to-LDS loads
 // (global_load_lds_dwordx4), double buffered, so the next step's loads fly
 // while the current step's MFMAs run.  The LDS rows are 128 bytes; the
@@ -28,8 +35,6 @@
 namespace mt {
 namespace {
 
-constexpr int kThreads = 256;
-
 __device__ __forceinline__ int swz(int row) { return (row >> 1) & 7; }
 
 // S^(1/p) in FP32 with the hardware log2 / exp2 (about 1 ulp each); S = 0
@@ -41,182 +46,94 @@ __device__ __forceinline__ float root_f32(float S, float inv_p) {
 }
 
 struct GemmGeom {
-    const uint16_t* A;
-    const uint16_t* B;
-    int64_t a_plane_elems;  // m_pad * k_pad
-    int64_t b_plane_elems;  // n_pad * k_pad
-    int64_t m, n, kp;
-    int32_t n_planes;
+    const uint16_t* X;
+    const uint16_t* Y;
+    int64_t x_plane_elems;  // rows_pad * k_pad
+    int64_t y_plane_elems;  // cols_pad * k_pad
+    int64_t x_batch_elems;  // planes per batch item * x_plane_elems
+    int64_t y_batch_elems;
+    int64_t kp;             // padded inner length
+    int64_t rows, cols;     // output rows x cols per batch item
     int32_t tiles_m, tiles_n;
 };
 
-template <int WT_M, int WT_N>
+// WAVES_M x WAVES_N waves, each owning WT_M x WT_N MFMA tiles of 32 x 32.
+template <int WAVES_M, int WAVES_N, int WT_M_, int WT_N_>
 struct Cfg {
-    static constexpr int BM = 2 * WT_M * 32;
-    static constexpr int BN = 2 * WT_N * 32;
+    static constexpr int NW = WAVES_M * WAVES_N;
+    static constexpr int THREADS = 64 * NW;
+    static constexpr int WT_M = WT_M_, WT_N = WT_N_;
+    static constexpr int BM = WAVES_M * WT_M_ * 32;
+    static constexpr int BN = WAVES_N * WT_N_ * 32;
+    static constexpr int WN = WAVES_N;
     static constexpr int A_BYTES = BM * 128;
     static constexpr int B_BYTES = BN * 128;
     static constexpr int BUF_BYTES = A_BYTES + B_BYTES;
-    static constexpr int NDEC = (WT_M * WT_N * 16 + 31) / 32;
-    static constexpr int STG = 32 * 33;  // floats of one wave's staging tile
-    static constexpr int LDS_BYTES = 2 * BUF_BYTES + (BM + BN) * 4 + 4 * STG * 4;
+    static constexpr int PIPE_BYTES = 2 * BUF_BYTES;
+    static constexpr int GA = BM / 8 / NW;  // load instructions per wave per step (X)
+    static constexpr int GB = BN / 8 / NW;  // (Y)
+    static_assert(GA % 2 == 0 && GB % 2 == 0, "row groups per wave must be even");
 };
 
-template <int WT_M, int WT_N, int MODE, typename TO>
-__global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_bf16_kernel(GemmGeom g,
-                                                                          FamilyPlan plan,
-                                                                          EpiArgs epi) {
-    using C = Cfg<WT_M, WT_N>;
-    static_assert((C::BM / 32) % 2 == 0 && (C::BN / 32) % 2 == 0, "row groups per wave must be even");
-    extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
-    float* rs = (float*)(smem + 2 * C::BUF_BYTES);  // BM row scales
-    float* cs = rs + C::BM;                         // BN column scales
-    float* stg_all = cs + C::BN;                    // 4 x (32 x 33) epilogue staging
+struct TileCtx {
+    int lane, wave, wm, wn, bi;
+    int64_t row0, col0;
+};
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave >> 1, wn = wave & 1;
+// ------------------------------------------------------------ selection epilogue
+template <class C, int MODE, typename TO>
+struct SelectEpi {
+    static constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
+    static constexpr int NDEC = (WT_M * WT_N * 16 + 31) / 32;
+    static constexpr int STG = 32 * 33;  // floats of one wave's staging tile
+    static constexpr int LDS_BYTES = (C::BM + C::BN) * 4;
+    static_assert(C::NW * STG * 4 <= C::BUF_BYTES, "staging must fit in one pipeline buffer");
 
-    // Workgroup -> tile.  Consecutive workgroup ids are spread over the 8
-    // XCDs; regroup so each XCD owns a contiguous run of tiles, then walk the
-    // run in bands of 8 tile rows so concurrently resident tiles share A rows
-    // and B columns in that XCD's L2.
-    int id = blockIdx.x;
-    const int nwg = gridDim.x;
-    if ((nwg & 7) == 0) id = (id & 7) * (nwg >> 3) + (id >> 3);
-    const int per_batch = g.tiles_m * g.tiles_n;
-    const int bi = id / per_batch;
-    const int t = id - bi * per_batch;
-    constexpr int GROUP = 8;
-    const int group = t / (GROUP * g.tiles_n);
-    const int first_m = group * GROUP;
-    const int gsz = min(GROUP, g.tiles_m - first_m);
-    const int in_g = t - group * GROUP * g.tiles_n;
-    const int tm = first_m + in_g % gsz;
-    const int tn = in_g / gsz;
-    const int64_t row0 = (int64_t)tm * C::BM;
-    const int64_t col0 = (int64_t)tn * C::BN;
+    using Args = EpiArgs;
+    EpiArgs a;
+    int64_t m, n;
+    uint32_t decided[NDEC];
+    float* rs;
+    float* cs;
+    int lr0, lc0;
+    int64_t out_lane;
+    int32_t rows_left, cols_left, diag_off;
 
-    // Row / column scales of this tile into LDS (1 where absent or padding).
-    for (int i = tid; i < C::BM + C::BN; i += kThreads) {
-        double v = 1.0;
-        if (i < C::BM) {
-            if (epi.r && row0 + i < g.m) v = epi.r[(int64_t)bi * g.m + row0 + i];
-        } else {
-            const int64_t cc = col0 + (i - C::BM);
-            if (epi.c && cc < g.n) v = epi.c[(int64_t)bi * g.n + cc];
+    __device__ bool active(int, const FamilyPlan&) const { return true; }
+
+    __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
+        m = g.rows;
+        n = g.cols;
+        rs = (float*)lds;
+        cs = rs + C::BM;
+        // Row / column scales of this tile (1 where absent or padding).
+        for (int i = tid; i < C::BM + C::BN; i += C::THREADS) {
+            double v = 1.0;
+            if (i < C::BM) {
+                if (a.r && t.row0 + i < m) v = a.r[(int64_t)t.bi * m + t.row0 + i];
+            } else {
+                const int64_t cc = t.col0 + (i - C::BM);
+                if (a.c && cc < n) v = a.c[(int64_t)t.bi * n + cc];
+            }
+            rs[i] = (float)v;
         }
-        rs[i] = (float)v;
+#pragma unroll
+        for (int i = 0; i < NDEC; ++i) decided[i] = 0u;
+        // Tile (i, j) of this wave is staged through LDS as a 32 x 32 block;
+        // lane l then handles rows 2q + l/32 (q = 0..15) of column l%32, so
+        // lanes 0-31 and 32-63 store two consecutive row runs.
+        lr0 = t.wm * WT_M * 32 + (t.lane >> 5);
+        lc0 = t.wn * WT_N * 32 + (t.lane & 31);
+        out_lane = ((int64_t)t.bi * m + t.row0 + lr0) * n + t.col0 + lc0;
+        rows_left = (int32_t)min<int64_t>(m - (t.row0 + lr0), 1 << 30);
+        cols_left = (int32_t)min<int64_t>(n - (t.col0 + lc0), 1 << 30);
+        diag_off = (int32_t)((t.col0 + lc0) - (t.row0 + lr0));
     }
 
-    const uint16_t* Abase = g.A + (int64_t)bi * g.n_planes * g.a_plane_elems + row0 * g.kp;
-    const uint16_t* Bbase = g.B + (int64_t)bi * g.n_planes * g.b_plane_elems + col0 * g.kp;
-    const int nkt = (int)(g.kp / 64);
-
-    // Global source offsets of the direct-to-LDS loads.  Load instruction i
-    // of this wave fills LDS rows R0 .. R0+7, R0 = (wave * G + i) * 8 with G
-    // row groups per wave; lane l fills row R0 + l/8, physical chunk l%8,
-    // which holds logical chunk (l%8) ^ swz(row).  For even G the swizzle is
-    // (i&1)*4 + l/16, so two lane offsets cover every instruction.
-    const int32_t ld_even = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (lane >> 4)) * 8);
-    const int32_t ld_odd = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (4 + (lane >> 4))) * 8);
-    // LDS operand reads: row (lane & 31) of a 32-row block, logical chunk
-    // 2*kk + lane/32, swizzle (lane >> 1) & 7 (block bases are multiples of 32).
-    const int32_t rd_base = (lane & 31) * 128 + (((lane >> 5) ^ ((lane >> 1) & 7)) * 16);
-
-    auto issue = [&](int e, int s, int kt, int buf) {
-        const uint16_t* asrc = Abase + (int64_t)plan.e[e].a_plane[s] * g.a_plane_elems + kt * 64;
-        const uint16_t* bsrc = Bbase + (int64_t)plan.e[e].b_plane[s] * g.b_plane_elems + kt * 64;
-        uint8_t* la = smem + buf * C::BUF_BYTES;
-        uint8_t* lb = la + C::A_BYTES;
-#pragma unroll
-        for (int i = 0; i < C::BM / 32; ++i) {
-            const int R0 = (wave * (C::BM / 32) + i) * 8;
-            __builtin_amdgcn_global_load_lds(
-                (glb_cvoid*)(asrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
-                (lds_void*)(la + R0 * 128), 16, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < C::BN / 32; ++i) {
-            const int R0 = (wave * (C::BN / 32) + i) * 8;
-            __builtin_amdgcn_global_load_lds(
-                (glb_cvoid*)(bsrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
-                (lds_void*)(lb + R0 * 128), 16, 0, 0);
-        }
-    };
-    auto advance = [&](int& e, int& s, int& kt) {
-        if (++kt == nkt) {
-            kt = 0;
-            if (++s == plan.e[e].nseg) {
-                s = 0;
-                ++e;
-            }
-        }
-    };
-
-    uint32_t decided[C::NDEC];
-#pragma unroll
-    for (int i = 0; i < C::NDEC; ++i) decided[i] = 0u;
-
-    // Epilogue addressing.  Tile (i, j) of this wave is staged through LDS as
-    // a 32 x 32 block; lane l then handles rows 2q + l/32 (q = 0..15) of
-    // column l%32, so lanes 0-31 and 32-63 store two consecutive row runs.
-    float* stg = stg_all + wave * C::STG;
-    const int lr0 = wm * WT_M * 32 + (lane >> 5);
-    const int lc0 = wn * WT_N * 32 + (lane & 31);
-    const int64_t out_lane = ((int64_t)bi * g.m + row0 + lr0) * g.n + col0 + lc0;
-    // entry valid iff its row offset < rows_left and column offset < cols_left
-    const int32_t rows_left = (int32_t)min<int64_t>(g.m - (row0 + lr0), 1 << 30);
-    const int32_t cols_left = (int32_t)min<int64_t>(g.n - (col0 + lc0), 1 << 30);
-    const int32_t diag_off = (int32_t)((col0 + lc0) - (row0 + lr0));  // APSP diagonal
-
-    // Software pipeline: the loads of the next K step (possibly of the next
-    // segment or family entry) are issued before the MFMAs of the current one.
-    int le = 0, ls = 0, lkt = 0;
-    if (nkt > 0) {
-        issue(le, ls, lkt, 0);
-        advance(le, ls, lkt);
-    }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-
-    int buf = 0;
-    for (int e = 0; e < plan.n; ++e) {
-        f32x16 acc[WT_M][WT_N];
-#pragma unroll
-        for (int i = 0; i < WT_M; ++i)
-#pragma unroll
-            for (int j = 0; j < WT_N; ++j) acc[i][j] = f32x16{};
-
-        const int ntiles = plan.e[e].nseg * nkt;
-        for (int t = 0; t < ntiles; ++t) {
-            if (le < plan.n) {
-                issue(le, ls, lkt, buf ^ 1);
-                advance(le, ls, lkt);
-            }
-            const uint8_t* la = smem + buf * C::BUF_BYTES + wm * WT_M * 32 * 128;
-            const uint8_t* lb = smem + buf * C::BUF_BYTES + C::A_BYTES + wn * WT_N * 32 * 128;
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int32_t ro = rd_base ^ (kk << 5);
-                bf16x8 a[WT_M], b[WT_N];
-#pragma unroll
-                for (int i = 0; i < WT_M; ++i) a[i] = *(const bf16x8*)(la + i * 32 * 128 + ro);
-#pragma unroll
-                for (int j = 0; j < WT_N; ++j) b[j] = *(const bf16x8*)(lb + j * 32 * 128 + ro);
-#pragma unroll
-                for (int i = 0; i < WT_M; ++i)
-#pragma unroll
-                    for (int j = 0; j < WT_N; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-            }
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-            buf ^= 1;
-        }
-
-        // ---- selection epilogue for family entry ce
+    // stage: a free pipeline buffer (C::NW staging tiles of STG floats).
+    __device__ void entry(int e, const FamilyPlan& plan, f32x16 (&acc)[WT_M][WT_N], const TileCtx& t,
+                          uint8_t* stage) {
+        float* stg = (float*)stage + t.wave * STG;
         const bool last = (e == plan.n - 1);
         const float inv_p = plan.e[e].inv_p;
         const bool p_is_1 = plan.e[e].p == 1;
@@ -224,8 +141,9 @@ __global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_bf16_kernel(GemmG
         // S >= tau in FP64 is S >= tau_f in FP32 (tau_f: tau rounded up to FP32)
         const float tau_f = plan.tau_f;
         const uint8_t pcode = (uint8_t)plan.e[e].pidx;
-        TO* out = (TO*)epi.out + out_lane;
-        uint8_t* ps = epi.pstar ? epi.pstar + out_lane : nullptr;
+        TO* out = (TO*)a.out + out_lane;
+        uint8_t* ps = a.pstar ? a.pstar + out_lane : nullptr;
+        const int lane = t.lane;
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
@@ -248,9 +166,9 @@ __global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_bf16_kernel(GemmG
                     if (col_ok && roff < rows_left && !(dec & mask) && (stable || last)) {
                         dec |= mask;
                         float v = rs[lr0 + roff] * cj * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
-                        if (MODE == EPI_APSP_X || epi.clamp) v = fminf(v, 1.f);
+                        if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
                         if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) v = 1.f;
-                        const int64_t o = (int64_t)roff * g.n + j * 32;
+                        const int64_t o = (int64_t)roff * n + j * 32;
                         out[o] = (TO)v;
                         if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
                     }
@@ -259,14 +177,271 @@ __global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_bf16_kernel(GemmG
                 __builtin_amdgcn_wave_barrier();
             }
     }
+
+    __device__ void finish(const TileCtx&) {}
+};
+
+// ------------------------------------------------------------ adjoint epilogue
+// out[bi, row, col] = sum over active p of M'(row, col)^(p-1) * acc_p, where
+// M' = M / scale_rows[row] / scale_cols[col] is the scaled input (A' for the
+// gradient of A, B' for the gradient of B).
+template <class C, typename TM>
+struct AdjointEpi {
+    static constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
+    static constexpr int LDS_BYTES = (C::BM + C::BN) * 4;
+
+    using Args = AdjArgs;
+    AdjArgs a;
+    int64_t rows, cols;
+    f32x16 tot[WT_M][WT_N];
+    float* rs;
+    float* cs;
+    int lr0, lc0;
+    int64_t lane_off;
+    int32_t rows_left, cols_left;
+
+    __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
+
+    __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
+        rows = g.rows;
+        cols = g.cols;
+        rs = (float*)lds;
+        cs = rs + C::BM;
+        for (int i = tid; i < C::BM + C::BN; i += C::THREADS) {
+            double v = 1.0;
+            if (i < C::BM) {
+                if (a.scale_rows && t.row0 + i < rows) v = a.scale_rows[(int64_t)t.bi * rows + t.row0 + i];
+            } else {
+                const int64_t cc = t.col0 + (i - C::BM);
+                if (a.scale_cols && cc < cols) v = a.scale_cols[(int64_t)t.bi * cols + cc];
+            }
+            rs[i] = v > 0.0 ? (float)(1.0 / v) : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) tot[i][j] = f32x16{};
+        // MFMA output layout: entry (i, j, r) of lane l is tile row
+        // wm*WT_M*32 + i*32 + (r/4)*8 + (l/32)*4 + r%4, column wn*WT_N*32 + j*32 + l%32.
+        lr0 = t.wm * WT_M * 32 + (t.lane >> 5) * 4;
+        lc0 = t.wn * WT_N * 32 + (t.lane & 31);
+        lane_off = ((int64_t)t.bi * rows + t.row0 + lr0) * cols + t.col0 + lc0;
+        rows_left = (int32_t)min<int64_t>(rows - (t.row0 + lr0), 1 << 30);
+        cols_left = (int32_t)min<int64_t>(cols - (t.col0 + lc0), 1 << 30);
+    }
+
+    __device__ void entry(int e, const FamilyPlan& plan, f32x16 (&acc)[WT_M][WT_N], const TileCtx&,
+                          uint8_t*) {
+        const int pm1 = plan.e[e].p - 1;
+        const TM* src = (const TM*)a.M + lane_off;
+#pragma unroll
+        for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) {
+                const bool col_ok = j * 32 < cols_left;
+                const float cinv = cs[lc0 + j * 32];
+                float x[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int roff = i * 32 + (r >> 2) * 8 + (r & 3);
+                    x[r] = (col_ok && roff < rows_left)
+                               ? (float)((double)src[(int64_t)roff * cols + j * 32]) * rs[lr0 + roff] * cinv
+                               : 0.f;
+                }
+                // x^(p-1) by binary powering (p uniform); 0^0 = 1
+                float pw[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) pw[r] = 1.f;
+                for (int ex = pm1; ex; ex >>= 1) {
+                    if (ex & 1) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) pw[r] *= x[r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) x[r] *= x[r];
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) tot[i][j][r] += pw[r] * acc[i][j][r];
+            }
+    }
+
+    __device__ void finish(const TileCtx&) {
+#pragma unroll
+        for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) {
+                if (!(j * 32 < cols_left)) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int roff = i * 32 + (r >> 2) * 8 + (r & 3);
+                    if (roff < rows_left) {
+                        const int64_t o = lane_off + (int64_t)roff * cols + j * 32;
+                        if (a.out_f64)
+                            ((double*)a.out)[o] = (double)tot[i][j][r];
+                        else
+                            ((float*)a.out)[o] = tot[i][j][r];
+                    }
+                }
+            }
+    }
+};
+
+// ------------------------------------------------------------ the main loop
+template <class C, class Epi>
+__global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(GemmGeom g,
+                                                                            FamilyPlan plan,
+                                                                            typename Epi::Args args) {
+    constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
+    extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
+    __shared__ int s_act[MT_MAX_P + 1];
+
+    const int tid = threadIdx.x;
+    TileCtx t;
+    t.lane = tid & 63;
+    t.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    t.wm = t.wave / C::WN;
+    t.wn = t.wave % C::WN;
+    const int lane = t.lane;
+    const int wave = t.wave;
+
+    // Workgroup -> tile.  Consecutive workgroup ids are spread over the 8
+    // XCDs; regroup so each XCD owns a contiguous run of tiles, then walk the
+    // run in bands of 8 tile rows so concurrently resident tiles share X rows
+    // and Y rows in that XCD's L2.
+    int id = blockIdx.x;
+    const int nwg = gridDim.x;
+    if ((nwg & 7) == 0) id = (id & 7) * (nwg >> 3) + (id >> 3);
+    const int per_batch = g.tiles_m * g.tiles_n;
+    t.bi = id / per_batch;
+    const int tt = id - t.bi * per_batch;
+    constexpr int GROUP = 8;
+    const int group = tt / (GROUP * g.tiles_n);
+    const int first_m = group * GROUP;
+    const int gsz = min(GROUP, g.tiles_m - first_m);
+    const int in_g = tt - group * GROUP * g.tiles_n;
+    const int tm = first_m + in_g % gsz;
+    const int tn = in_g / gsz;
+    t.row0 = (int64_t)tm * C::BM;
+    t.col0 = (int64_t)tn * C::BN;
+
+    Epi epi;
+    epi.a = args;
+    epi.setup(t, g, smem + C::PIPE_BYTES, tid);
+    if (tid == 0) {
+        int na = 0;
+        for (int e = 0; e < plan.n; ++e)
+            if (epi.active(e, plan)) s_act[1 + na++] = e;
+        s_act[0] = na;
+    }
+
+    const uint16_t* Xbase = g.X + (int64_t)t.bi * g.x_batch_elems + t.row0 * g.kp;
+    const uint16_t* Ybase = g.Y + (int64_t)t.bi * g.y_batch_elems + t.col0 * g.kp;
+    const int nkt = (int)(g.kp / 64);
+
+    // Global source offsets of the direct-to-LDS loads.  Load instruction i
+    // of this wave fills LDS rows R0 .. R0+7, R0 = (wave * G + i) * 8 with G
+    // (even) row groups per wave; lane l fills row R0 + l/8, physical chunk l%8,
+    // which holds logical chunk (l%8) ^ swz(row).  For even G the swizzle is
+    // (i&1)*4 + l/16, so two lane offsets cover every instruction.
+    const int32_t ld_even = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (lane >> 4)) * 8);
+    const int32_t ld_odd = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (4 + (lane >> 4))) * 8);
+    // LDS operand reads: row (lane & 31) of a 32-row block, logical chunk
+    // 2*kk + lane/32, swizzle (lane >> 1) & 7 (block bases are multiples of 32).
+    const int32_t rd_base = (lane & 31) * 128 + (((lane >> 5) ^ ((lane >> 1) & 7)) * 16);
+
+    __syncthreads();
+    const int nact = __builtin_amdgcn_readfirstlane(s_act[0]);
+
+    auto issue = [&](int ai, int s, int kt, int buf) {
+        const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+        const uint16_t* xsrc = Xbase + (int64_t)plan.e[e].a_plane[s] * g.x_plane_elems + kt * 64;
+        const uint16_t* ysrc = Ybase + (int64_t)plan.e[e].b_plane[s] * g.y_plane_elems + kt * 64;
+        uint8_t* la = smem + buf * C::BUF_BYTES;
+        uint8_t* lb = la + C::A_BYTES;
+#pragma unroll
+        for (int i = 0; i < C::GA; ++i) {
+            const int R0 = (wave * C::GA + i) * 8;
+            __builtin_amdgcn_global_load_lds(
+                (glb_cvoid*)(xsrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
+                (lds_void*)(la + R0 * 128), 16, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < C::GB; ++i) {
+            const int R0 = (wave * C::GB + i) * 8;
+            __builtin_amdgcn_global_load_lds(
+                (glb_cvoid*)(ysrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
+                (lds_void*)(lb + R0 * 128), 16, 0, 0);
+        }
+    };
+    auto advance = [&](int& ai, int& s, int& kt) {
+        if (++kt == nkt) {
+            kt = 0;
+            const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+            if (++s == plan.e[e].nseg) {
+                s = 0;
+                ++ai;
+            }
+        }
+    };
+
+    // Software pipeline: the loads of the next K step (possibly of the next
+    // segment or family entry) are issued before the MFMAs of the current one.
+    int la_ = 0, ls = 0, lkt = 0;
+    if (nkt > 0 && nact > 0) {
+        issue(la_, ls, lkt, 0);
+        advance(la_, ls, lkt);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+
+    int buf = 0;
+    for (int ai = 0; ai < nact; ++ai) {
+        const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+        f32x16 acc[WT_M][WT_N];
+#pragma unroll
+        for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) acc[i][j] = f32x16{};
+
+        const int ntiles = plan.e[e].nseg * nkt;
+        for (int st = 0; st < ntiles; ++st) {
+            if (la_ < nact) {
+                issue(la_, ls, lkt, buf ^ 1);
+                advance(la_, ls, lkt);
+            }
+            const uint8_t* pa = smem + buf * C::BUF_BYTES + t.wm * WT_M * 32 * 128;
+            const uint8_t* pb = smem + buf * C::BUF_BYTES + C::A_BYTES + t.wn * WT_N * 32 * 128;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int32_t ro = rd_base ^ (kk << 5);
+                bf16x8 a[WT_M], b[WT_N];
+#pragma unroll
+                for (int i = 0; i < WT_M; ++i) a[i] = *(const bf16x8*)(pa + i * 32 * 128 + ro);
+#pragma unroll
+                for (int j = 0; j < WT_N; ++j) b[j] = *(const bf16x8*)(pb + j * 32 * 128 + ro);
+#pragma unroll
+                for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+                    for (int j = 0; j < WT_N; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            buf ^= 1;
+        }
+        // the buffer the last step read is free until the next step's loads,
+        // which wait for the barrier below
+        epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
+        __syncthreads();
+    }
+    epi.finish(t);
 }
 
-template <int WT_M, int WT_N, int MODE, typename TO>
-hipError_t launch_cfg(const GemmGeom& g, int64_t b, const FamilyPlan& plan, const EpiArgs& epi,
-                      hipStream_t st) {
-    using C = Cfg<WT_M, WT_N>;
-    const int lds = C::LDS_BYTES;
-    auto kern = mt_pfamily_gemm_bf16_kernel<WT_M, WT_N, MODE, TO>;
+template <class C, class Epi>
+hipError_t launch_gemm(const GemmGeom& g, int64_t b, const FamilyPlan& plan,
+                       const typename Epi::Args& args, const char* name, hipStream_t st) {
+    const int lds = C::PIPE_BYTES + Epi::LDS_BYTES;
+    auto kern = mt_pfamily_gemm_bf16_kernel<C, Epi>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -274,10 +449,36 @@ hipError_t launch_cfg(const GemmGeom& g, int64_t b, const FamilyPlan& plan, cons
         attr_set = true;
     }
     const int64_t nwg = b * (int64_t)g.tiles_m * g.tiles_n;
-    timing_before("mt_pfamily_gemm_bf16", st);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(kThreads), lds, st, g, plan, epi);
+    timing_before(name, st);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(C::THREADS), lds, st, g, plan, args);
     timing_after(st);
     return hipGetLastError();
+}
+
+// Forward: 8 waves (2 per SIMD) in 2 x 4, each 128 x 64 -> 256 x 256 tiles.
+using FwdCfg = Cfg<2, 4, 4, 2>;
+// Adjoint: 8 waves in 2 x 4, each 64 x 32 -> 128 x 128 tiles (accumulator
+// plus running sum fit the two-waves-per-SIMD register budget).
+using AdjCfg = Cfg<2, 4, 2, 1>;
+static_assert(FwdCfg::BM == kBf16BM && FwdCfg::BN == kBf16BN, "forward tile");
+static_assert(AdjCfg::BM == kAdjBM && AdjCfg::BN == kAdjBM, "adjoint tile");
+
+GemmGeom make_geom(const uint16_t* X, const uint16_t* Y, int64_t rows, int64_t cols,
+                   int64_t rows_pad, int64_t cols_pad, int64_t kp, int32_t x_planes,
+                   int32_t y_planes, int bm, int bn) {
+    GemmGeom g;
+    g.rows = rows;
+    g.cols = cols;
+    g.X = X;
+    g.Y = Y;
+    g.x_plane_elems = rows_pad * kp;
+    g.y_plane_elems = cols_pad * kp;
+    g.x_batch_elems = g.x_plane_elems * x_planes;
+    g.y_batch_elems = g.y_plane_elems * y_planes;
+    g.kp = kp;
+    g.tiles_m = (int32_t)(rows_pad / bm);
+    g.tiles_n = (int32_t)(cols_pad / bn);
+    return g;
 }
 
 }  // namespace
@@ -286,23 +487,27 @@ hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int6
                                     int64_t n, int64_t mp, int64_t np, int64_t kp,
                                     int32_t n_planes, const FamilyPlan& plan, const EpiArgs& epi,
                                     hipStream_t st) {
-    GemmGeom g;
-    g.A = Ap;
-    g.B = Bp;
-    g.a_plane_elems = mp * kp;
-    g.b_plane_elems = np * kp;
-    g.m = m;
-    g.n = n;
-    g.kp = kp;
-    g.n_planes = n_planes;
-    g.tiles_m = (int32_t)(mp / kBf16BM);
-    g.tiles_n = (int32_t)(np / kBf16BN);
+    const GemmGeom g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, kBf16BM, kBf16BN);
+    const char* name = "mt_pfamily_gemm_bf16";
+    using CF = FwdCfg;
+#define MT_SEL(MODE, TO) return launch_gemm<CF, SelectEpi<CF, MODE, TO>>(g, b, plan, epi, name, st);
     if (epi.mode == EPI_APSP_X) {
-        if (epi.out_f64) return launch_cfg<4, 4, EPI_APSP_X, double>(g, b, plan, epi, st);
-        return launch_cfg<4, 4, EPI_APSP_X, float>(g, b, plan, epi, st);
+        if (epi.out_f64) MT_SEL(EPI_APSP_X, double) else MT_SEL(EPI_APSP_X, float)
     }
-    if (epi.out_f64) return launch_cfg<4, 4, EPI_PLAIN, double>(g, b, plan, epi, st);
-    return launch_cfg<4, 4, EPI_PLAIN, float>(g, b, plan, epi, st);
+    if (epi.out_f64) MT_SEL(EPI_PLAIN, double) else MT_SEL(EPI_PLAIN, float)
+#undef MT_SEL
+}
+
+hipError_t launch_adjoint_gemm_bf16(const uint16_t* Xp, const uint16_t* Yp, int64_t b, int64_t rows,
+                                    int64_t cols, int64_t rows_pad, int64_t cols_pad, int64_t kp,
+                                    int32_t x_planes, int32_t y_planes, const FamilyPlan& plan,
+                                    const AdjArgs& adj, hipStream_t st) {
+    const GemmGeom g =
+        make_geom(Xp, Yp, rows, cols, rows_pad, cols_pad, kp, x_planes, y_planes, kAdjBM, kAdjBM);
+    const char* name = "mt_adjoint_gemm_bf16";
+    using CA = AdjCfg;
+    if (adj.m_f64) return launch_gemm<CA, AdjointEpi<CA, double>>(g, b, plan, adj, name, st);
+    return launch_gemm<CA, AdjointEpi<CA, float>>(g, b, plan, adj, name, st);
 }
 
 }  // namespace mt

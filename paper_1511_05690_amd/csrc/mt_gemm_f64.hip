@@ -1,15 +1,22 @@
-// Fused p-family GEMM on FP64 MFMA (gfx950) with the selection step: the
-// plain-precision path of the p-norm estimate.  Same scheme as the BF16
-// kernel (ring product of every p of the family per output tile, largest p
-// first; Alg. 5 and Sec. 1), with FP64 power planes, v_mfma_f64_16x16x4f64 and
-// an FP64 stability test.  The epilogue records, once per entry, the ring
-// result S at the largest p with S_p >= tau and that p's index; the FP64 root
-// C = r c S^(1/p) is taken by the select-root pass (mt_elementwise.hip).
+// p-family GEMMs on FP64 MFMA (gfx950): the plain-precision path.  Same
+// scheme as the BF16 kernels (one main loop, two epilogues), with FP64 planes
+// and v_mfma_f64_16x16x4f64.
+//
+// Forward (selection-record epilogue).  Ring products of every p of the
+// family per output tile, largest p first (Alg. 5 and Sec. 1).  Once per
+// entry the epilogue records the ring result S at the largest p with
+// S_p >= tau (FP64 test) and that p's index; the FP64 root C = r c S^(1/p) is
+// taken by the select-root pass (mt_elementwise.hip), which keeps the
+// library's log / exp out of the unrolled epilogue.
+//
+// Adjoint (accumulating epilogue).  As in the BF16 kernel: sum over the p
+// some entry uses of (scaled input)^(p-1) .* (X_p Y_p^T), written once.
 //
 // Tiling: 256 threads = 4 waves in 2 x 2; each wave owns WT x WT MFMA tiles of
 // 16 x 16.  K step 16 doubles = 128-byte LDS rows, loaded by
 // global_load_lds_dwordx4 and double buffered; 16-byte chunk index
-// XOR-swizzled with (row >> 1) & 7.
+// XOR-swizzled with (row >> 1) & 7.  At most 256 registers per lane, so two
+// workgroups share a CU and one hides the other's barrier waits.
 #include <cfloat>
 #include <cmath>
 
@@ -21,55 +28,243 @@ namespace {
 constexpr int kThreads = 256;
 
 struct GemmGeomF64 {
-    const double* A;
-    const double* B;
-    int64_t a_plane_elems;
-    int64_t b_plane_elems;
-    int64_t m, n, kp;
-    int32_t n_planes;
+    const double* X;
+    const double* Y;
+    int64_t x_plane_elems;
+    int64_t y_plane_elems;
+    int64_t x_batch_elems;
+    int64_t y_batch_elems;
+    int64_t kp;
+    int64_t rows, cols;
     int32_t tiles_m, tiles_n;
 };
 
-template <int WT>
+template <int WT_>
 struct CfgF64 {
+    static constexpr int WT = WT_;
     static constexpr int BM = 2 * WT * 16;
     static constexpr int A_BYTES = BM * 128;
     static constexpr int BUF_BYTES = 2 * A_BYTES;
-    static constexpr int NDEC = (WT * WT * 4 + 31) / 32;
-    static constexpr int LDS_BYTES = 2 * BUF_BYTES;
+    static constexpr int PIPE_BYTES = 2 * BUF_BYTES;
+    static_assert((BM / 32) % 2 == 0, "row groups per wave must be even");
 };
 
-template <int WT>
-__global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_f64_kernel(GemmGeomF64 g,
+struct TileCtx {
+    int lane, wave, wm, wn, bi;
+    int64_t row0, col0;
+};
+
+// ------------------------------------------------------------ selection record
+template <class C>
+struct RecordEpi {
+    static constexpr int WT = C::WT;
+    static constexpr int NDEC = (WT * WT * 4 + 31) / 32;
+    static constexpr int LDS_BYTES = 0;
+    using Args = EpiArgs;
+    EpiArgs a;
+    int64_t n;
+    uint32_t decided[NDEC];
+    int64_t out_lane;
+    int32_t rows_left, cols_left;
+
+    __device__ bool active(int, const FamilyPlan&) const { return true; }
+
+    __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t*, int) {
+        n = g.cols;
+#pragma unroll
+        for (int i = 0; i < NDEC; ++i) decided[i] = 0u;
+        // Entry (i, j, r) of this lane: tile row wm*WT*16 + i*16 + l/16 + 4r,
+        // tile column wn*WT*16 + j*16 + l%16.
+        const int lr0 = t.wm * WT * 16 + (t.lane >> 4);
+        const int lc0 = t.wn * WT * 16 + (t.lane & 15);
+        out_lane = ((int64_t)t.bi * g.rows + t.row0 + lr0) * n + t.col0 + lc0;
+        rows_left = (int32_t)min<int64_t>(g.rows - (t.row0 + lr0), 1 << 30);
+        cols_left = (int32_t)min<int64_t>(n - (t.col0 + lc0), 1 << 30);
+    }
+
+    // stage: a free pipeline buffer; each wave stages one 16 x 16 tile
+    // (lane-major) and walks its four entries per lane in a rolled loop.
+    __device__ void entry(int e, const FamilyPlan& plan, f64x4 (&acc)[WT][WT], const TileCtx& t,
+                          uint8_t* stage) {
+        const bool last = (e == plan.n - 1);
+        const double tau = plan.tau;
+        const uint8_t pcode = (uint8_t)plan.e[e].pidx;
+        double* out = (double*)a.out + out_lane;
+        uint8_t* ps = a.pstar + out_lane;
+        double* stg = (double*)stage + t.wave * 256;
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) stg[r * 64 + t.lane] = acc[i][j][r];
+                __builtin_amdgcn_wave_barrier();
+                const bool col_ok = j * 16 < cols_left;
+                const int tix = i * WT + j;
+                uint32_t dec = decided[tix >> 3];
+                const int sh = (tix & 7) * 4;
+#pragma unroll 1
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t mask = 1u << (sh + r);
+                    const int roff = i * 16 + 4 * r;
+                    const double S = stg[r * 64 + t.lane];
+                    const bool stable = S >= tau;
+                    if (col_ok && roff < rows_left && !(dec & mask) && (stable || last)) {
+                        dec |= mask;
+                        const int64_t o = (int64_t)roff * n + j * 16;
+                        out[o] = S;
+                        ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                    }
+                }
+                decided[tix >> 3] = dec;
+                __builtin_amdgcn_wave_barrier();
+            }
+    }
+
+    __device__ void finish(const TileCtx&) {}
+};
+
+// ------------------------------------------------------------ adjoint epilogue
+template <class C, typename TM>
+struct AdjointEpiF64 {
+    static constexpr int WT = C::WT;
+    static constexpr int LDS_BYTES = 2 * C::BM * 8;
+    using Args = AdjArgs;
+    AdjArgs a;
+    int64_t rows, cols;
+    f64x4 tot[WT][WT];
+    double* rs;
+    double* cs;
+    int lr0, lc0;
+    int64_t lane_off;
+    int32_t rows_left, cols_left;
+
+    __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
+
+    __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t* lds, int tid) {
+        rows = g.rows;
+        cols = g.cols;
+        rs = (double*)lds;
+        cs = rs + C::BM;
+        for (int i = tid; i < 2 * C::BM; i += kThreads) {
+            double v = 1.0;
+            if (i < C::BM) {
+                if (a.scale_rows && t.row0 + i < rows) v = a.scale_rows[(int64_t)t.bi * rows + t.row0 + i];
+            } else {
+                const int64_t cc = t.col0 + (i - C::BM);
+                if (a.scale_cols && cc < cols) v = a.scale_cols[(int64_t)t.bi * cols + cc];
+            }
+            rs[i] = v > 0.0 ? 1.0 / v : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j) tot[i][j] = f64x4{};
+        lr0 = t.wm * WT * 16 + (t.lane >> 4);
+        lc0 = t.wn * WT * 16 + (t.lane & 15);
+        lane_off = ((int64_t)t.bi * rows + t.row0 + lr0) * cols + t.col0 + lc0;
+        rows_left = (int32_t)min<int64_t>(rows - (t.row0 + lr0), 1 << 30);
+        cols_left = (int32_t)min<int64_t>(cols - (t.col0 + lc0), 1 << 30);
+    }
+
+    __device__ void entry(int e, const FamilyPlan& plan, f64x4 (&acc)[WT][WT], const TileCtx&, uint8_t*) {
+        const int pm1 = plan.e[e].p - 1;
+        const TM* src = (const TM*)a.M + lane_off;
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j) {
+                const bool col_ok = j * 16 < cols_left;
+                const double cinv = cs[lc0 + j * 16];
+                double x[4], pw[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int roff = i * 16 + 4 * r;
+                    x[r] = (col_ok && roff < rows_left)
+                               ? (double)src[(int64_t)roff * cols + j * 16] * rs[lr0 + roff] * cinv
+                               : 0.0;
+                    pw[r] = 1.0;
+                }
+                for (int ex = pm1; ex; ex >>= 1) {
+                    if (ex & 1) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) pw[r] *= x[r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) x[r] *= x[r];
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tot[i][j][r] += pw[r] * acc[i][j][r];
+            }
+    }
+
+    __device__ void finish(const TileCtx&) {
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j) {
+                if (!(j * 16 < cols_left)) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int roff = i * 16 + 4 * r;
+                    if (roff < rows_left) {
+                        const int64_t o = lane_off + (int64_t)roff * cols + j * 16;
+                        if (a.out_f64)
+                            ((double*)a.out)[o] = tot[i][j][r];
+                        else
+                            ((float*)a.out)[o] = (float)tot[i][j][r];
+                    }
+                }
+            }
+    }
+};
+
+// ------------------------------------------------------------ the main loop
+template <class C, class Epi>
+__global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGeomF64 g,
                                                                          FamilyPlan plan,
-                                                                         EpiArgs epi) {
-    using C = CfgF64<WT>;
-    static_assert((C::BM / 32) % 2 == 0, "row groups per wave must be even");
+                                                                         typename Epi::Args args) {
+    constexpr int WT = C::WT;
     extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
+    __shared__ int s_act[MT_MAX_P + 1];
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave >> 1, wn = wave & 1;
+    TileCtx t;
+    t.lane = tid & 63;
+    t.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    t.wm = t.wave >> 1;
+    t.wn = t.wave & 1;
+    const int lane = t.lane;
+    const int wave = t.wave;
 
     int id = blockIdx.x;
     const int nwg = gridDim.x;
     if ((nwg & 7) == 0) id = (id & 7) * (nwg >> 3) + (id >> 3);
     const int per_batch = g.tiles_m * g.tiles_n;
-    const int bi = id / per_batch;
-    const int t = id - bi * per_batch;
+    t.bi = id / per_batch;
+    const int tt = id - t.bi * per_batch;
     constexpr int GROUP = 8;
-    const int group = t / (GROUP * g.tiles_n);
+    const int group = tt / (GROUP * g.tiles_n);
     const int first_m = group * GROUP;
     const int gsz = min(GROUP, g.tiles_m - first_m);
-    const int in_g = t - group * GROUP * g.tiles_n;
+    const int in_g = tt - group * GROUP * g.tiles_n;
     const int tm = first_m + in_g % gsz;
     const int tn = in_g / gsz;
-    const int64_t row0 = (int64_t)tm * C::BM;
-    const int64_t col0 = (int64_t)tn * C::BM;
+    t.row0 = (int64_t)tm * C::BM;
+    t.col0 = (int64_t)tn * C::BM;
 
-    const double* Abase = g.A + (int64_t)bi * g.n_planes * g.a_plane_elems + row0 * g.kp;
-    const double* Bbase = g.B + (int64_t)bi * g.n_planes * g.b_plane_elems + col0 * g.kp;
+    Epi epi;
+    epi.a = args;
+    epi.setup(t, g, smem + C::PIPE_BYTES, tid);
+    if (tid == 0) {
+        int na = 0;
+        for (int e = 0; e < plan.n; ++e)
+            if (epi.active(e, plan)) s_act[1 + na++] = e;
+        s_act[0] = na;
+    }
+
+    const double* Xbase = g.X + (int64_t)t.bi * g.x_batch_elems + t.row0 * g.kp;
+    const double* Ybase = g.Y + (int64_t)t.bi * g.y_batch_elems + t.col0 * g.kp;
     const int nkt = (int)(g.kp / 16);
 
     // Loads: lane l fills row R0 + l/8, physical 16-byte chunk l%8 holding
@@ -80,53 +275,47 @@ __global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_f64_kernel(GemmGe
     // logical chunk 2*kk + l/32, half (l/16)&1; swizzle (l >> 1) & 7.
     const int32_t rd_base = (lane & 15) * 128 + (((lane >> 5) ^ ((lane >> 1) & 7)) * 16) + ((lane >> 4) & 1) * 8;
 
-    auto issue = [&](int e, int s, int kt, int buf) {
-        const double* asrc = Abase + (int64_t)plan.e[e].a_plane[s] * g.a_plane_elems + kt * 16;
-        const double* bsrc = Bbase + (int64_t)plan.e[e].b_plane[s] * g.b_plane_elems + kt * 16;
+    __syncthreads();
+    const int nact = __builtin_amdgcn_readfirstlane(s_act[0]);
+
+    auto issue = [&](int ai, int s, int kt, int buf) {
+        const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+        const double* xsrc = Xbase + (int64_t)plan.e[e].a_plane[s] * g.x_plane_elems + kt * 16;
+        const double* ysrc = Ybase + (int64_t)plan.e[e].b_plane[s] * g.y_plane_elems + kt * 16;
         uint8_t* la = smem + buf * C::BUF_BYTES;
         uint8_t* lb = la + C::A_BYTES;
 #pragma unroll
         for (int i = 0; i < C::BM / 32; ++i) {
             const int R0 = (wave * (C::BM / 32) + i) * 8;
             const int32_t lo = (i & 1) ? ld_odd : ld_even;
-            __builtin_amdgcn_global_load_lds((glb_cvoid*)(asrc + (int64_t)R0 * g.kp + lo),
+            __builtin_amdgcn_global_load_lds((glb_cvoid*)(xsrc + (int64_t)R0 * g.kp + lo),
                                              (lds_void*)(la + R0 * 128), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((glb_cvoid*)(bsrc + (int64_t)R0 * g.kp + lo),
+            __builtin_amdgcn_global_load_lds((glb_cvoid*)(ysrc + (int64_t)R0 * g.kp + lo),
                                              (lds_void*)(lb + R0 * 128), 16, 0, 0);
         }
     };
-    auto advance = [&](int& e, int& s, int& kt) {
+    auto advance = [&](int& ai, int& s, int& kt) {
         if (++kt == nkt) {
             kt = 0;
+            const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
             if (++s == plan.e[e].nseg) {
                 s = 0;
-                ++e;
+                ++ai;
             }
         }
     };
 
-    uint32_t decided[C::NDEC];
-#pragma unroll
-    for (int i = 0; i < C::NDEC; ++i) decided[i] = 0u;
-
-    // Entry (i, j, r) of this lane: tile row wm*WT*16 + i*16 + l/16 + 4r,
-    // tile column wn*WT*16 + j*16 + l%16.
-    const int lr0 = wm * WT * 16 + (lane >> 4);
-    const int lc0 = wn * WT * 16 + (lane & 15);
-    const int64_t out_lane = ((int64_t)bi * g.m + row0 + lr0) * g.n + col0 + lc0;
-    const int32_t rows_left = (int32_t)min<int64_t>(g.m - (row0 + lr0), 1 << 30);
-    const int32_t cols_left = (int32_t)min<int64_t>(g.n - (col0 + lc0), 1 << 30);
-
-    int le = 0, ls = 0, lkt = 0;
-    if (nkt > 0) {
-        issue(le, ls, lkt, 0);
-        advance(le, ls, lkt);
+    int la_ = 0, ls = 0, lkt = 0;
+    if (nkt > 0 && nact > 0) {
+        issue(la_, ls, lkt, 0);
+        advance(la_, ls, lkt);
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
     int buf = 0;
-    for (int e = 0; e < plan.n; ++e) {
+    for (int ai = 0; ai < nact; ++ai) {
+        const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
         f64x4 acc[WT][WT];
 #pragma unroll
         for (int i = 0; i < WT; ++i)
@@ -134,21 +323,21 @@ __global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_f64_kernel(GemmGe
             for (int j = 0; j < WT; ++j) acc[i][j] = f64x4{};
 
         const int ntiles = plan.e[e].nseg * nkt;
-        for (int t2 = 0; t2 < ntiles; ++t2) {
-            if (le < plan.n) {
-                issue(le, ls, lkt, buf ^ 1);
-                advance(le, ls, lkt);
+        for (int st = 0; st < ntiles; ++st) {
+            if (la_ < nact) {
+                issue(la_, ls, lkt, buf ^ 1);
+                advance(la_, ls, lkt);
             }
-            const uint8_t* la = smem + buf * C::BUF_BYTES + wm * WT * 16 * 128;
-            const uint8_t* lb = smem + buf * C::BUF_BYTES + C::A_BYTES + wn * WT * 16 * 128;
+            const uint8_t* pa = smem + buf * C::BUF_BYTES + t.wm * WT * 16 * 128;
+            const uint8_t* pb = smem + buf * C::BUF_BYTES + C::A_BYTES + t.wn * WT * 16 * 128;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int32_t ro = rd_base ^ (kk << 5);
                 double a[WT], b[WT];
 #pragma unroll
-                for (int i = 0; i < WT; ++i) a[i] = *(const double*)(la + i * 16 * 128 + ro);
+                for (int i = 0; i < WT; ++i) a[i] = *(const double*)(pa + i * 16 * 128 + ro);
 #pragma unroll
-                for (int j = 0; j < WT; ++j) b[j] = *(const double*)(lb + j * 16 * 128 + ro);
+                for (int j = 0; j < WT; ++j) b[j] = *(const double*)(pb + j * 16 * 128 + ro);
 #pragma unroll
                 for (int i = 0; i < WT; ++i)
 #pragma unroll
@@ -159,66 +348,47 @@ __global__ __launch_bounds__(kThreads, 1) void mt_pfamily_gemm_f64_kernel(GemmGe
             __syncthreads();
             buf ^= 1;
         }
-
-        // ---- selection for family entry e: record S at the selected p and
-        // the p index; the root r c S^(1/p) is applied by the select-root pass.
-        const bool last = (e == plan.n - 1);
-        const double tau = plan.tau;
-        const uint8_t pcode = (uint8_t)plan.e[e].pidx;
-        double* out = (double*)epi.out + out_lane;
-        uint8_t* ps = epi.pstar + out_lane;
-        // Stage each 16 x 16 tile (lane-major) in the buffer just consumed
-        // (free until the next issue, which waits for the barrier below) and
-        // walk its four entries per lane in a rolled loop.
-        double* stg = (double*)(smem + (buf ^ 1) * C::BUF_BYTES) + wave * 256;
-#pragma unroll
-        for (int i = 0; i < WT; ++i)
-#pragma unroll
-            for (int j = 0; j < WT; ++j) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) stg[r * 64 + lane] = acc[i][j][r];
-                __builtin_amdgcn_wave_barrier();
-                const bool col_ok = j * 16 < cols_left;
-                const int tix = i * WT + j;
-                uint32_t dec = decided[tix >> 3];
-                const int sh = (tix & 7) * 4;
-#pragma unroll 1
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t mask = 1u << (sh + r);
-                    const int roff = i * 16 + 4 * r;
-                    const double S = stg[r * 64 + lane];
-                    const bool stable = S >= tau;
-                    if (col_ok && roff < rows_left && !(dec & mask) && (stable || last)) {
-                        dec |= mask;
-                        const int64_t o = (int64_t)roff * g.n + j * 16;
-                        out[o] = S;
-                        ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
-                    }
-                }
-                decided[tix >> 3] = dec;
-                __builtin_amdgcn_wave_barrier();
-            }
+        // the buffer the last step read is free until the next step's loads,
+        // which wait for the barrier below
+        epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
         __syncthreads();
     }
+    epi.finish(t);
 }
 
-template <int WT>
-hipError_t launch_cfg(const GemmGeomF64& g, int64_t b, const FamilyPlan& plan, const EpiArgs& epi,
-                      hipStream_t st) {
-    using C = CfgF64<WT>;
-    auto kern = mt_pfamily_gemm_f64_kernel<WT>;
+template <class C, class Epi>
+hipError_t launch_gemm(const GemmGeomF64& g, int64_t b, const FamilyPlan& plan,
+                       const typename Epi::Args& args, const char* name, hipStream_t st) {
+    const int lds = C::PIPE_BYTES + Epi::LDS_BYTES;
+    auto kern = mt_pfamily_gemm_f64_kernel<C, Epi>;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e =
-            hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const int64_t nwg = b * (int64_t)g.tiles_m * g.tiles_n;
-    timing_before("mt_pfamily_gemm_f64", st);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(kThreads), C::LDS_BYTES, st, g, plan, epi);
+    timing_before(name, st);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(kThreads), lds, st, g, plan, args);
     timing_after(st);
     return hipGetLastError();
+}
+
+GemmGeomF64 make_geom(const double* X, const double* Y, int64_t rows, int64_t cols, int64_t rows_pad,
+                      int64_t cols_pad, int64_t kp, int32_t x_planes, int32_t y_planes, int bm) {
+    GemmGeomF64 g;
+    g.X = X;
+    g.Y = Y;
+    g.x_plane_elems = rows_pad * kp;
+    g.y_plane_elems = cols_pad * kp;
+    g.x_batch_elems = g.x_plane_elems * x_planes;
+    g.y_batch_elems = g.y_plane_elems * y_planes;
+    g.kp = kp;
+    g.rows = rows;
+    g.cols = cols;
+    g.tiles_m = (int32_t)(rows_pad / bm);
+    g.tiles_n = (int32_t)(cols_pad / bm);
+    return g;
 }
 
 }  // namespace
@@ -227,20 +397,23 @@ hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b
                                    int64_t n, int64_t mp, int64_t np, int64_t kp, int32_t n_planes,
                                    int bm, const FamilyPlan& plan, const EpiArgs& epi,
                                    hipStream_t st) {
-    GemmGeomF64 g;
-    g.A = Ap;
-    g.B = Bp;
-    g.a_plane_elems = mp * kp;
-    g.b_plane_elems = np * kp;
-    g.m = m;
-    g.n = n;
-    g.kp = kp;
-    g.n_planes = n_planes;
-    g.tiles_m = (int32_t)(mp / bm);
-    g.tiles_n = (int32_t)(np / bm);
-    if (bm == 128) return launch_cfg<4>(g, b, plan, epi, st);
-    if (bm == 64) return launch_cfg<2>(g, b, plan, epi, st);
+    const GemmGeomF64 g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, bm);
+    const char* name = "mt_pfamily_gemm_f64";
+    if (bm == 128) return launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>>>(g, b, plan, epi, name, st);
+    if (bm == 64) return launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>>>(g, b, plan, epi, name, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_gemm_f64(const double* Xp, const double* Yp, int64_t b, int64_t rows,
+                                   int64_t cols, int64_t rows_pad, int64_t cols_pad, int64_t kp,
+                                   int32_t x_planes, int32_t y_planes, const FamilyPlan& plan,
+                                   const AdjArgs& adj, hipStream_t st) {
+    using CA = CfgF64<2>;
+    static_assert(CA::BM == kAdjF64BM, "adjoint tile");
+    const GemmGeomF64 g = make_geom(Xp, Yp, rows, cols, rows_pad, cols_pad, kp, x_planes, y_planes, CA::BM);
+    const char* name = "mt_adjoint_gemm_f64";
+    if (adj.m_f64) return launch_gemm<CA, AdjointEpiF64<CA, double>>(g, b, plan, adj, name, st);
+    return launch_gemm<CA, AdjointEpiF64<CA, float>>(g, b, plan, adj, name, st);
 }
 
 }  // namespace mt

@@ -26,6 +26,9 @@ constexpr int kBf16BN = 256;
 constexpr int kBf16BK = 64;
 // FP64 p-family GEMM: BM x BM output tile (BM = 128 or 64), K step 16.
 constexpr int kF64BK = 16;
+// Adjoint GEMMs: 128 x 128 (BF16) and 64 x 64 (FP64) output tiles.
+constexpr int kAdjBM = 128;
+constexpr int kAdjF64BM = 64;
 
 // Workspace header: domain flag word and p* histogram.
 struct WsHeader {
@@ -71,6 +74,18 @@ struct EpiArgs {
     const double* c;     // b x n (nullable: all ones)
 };
 
+// Adjoint epilogue: out = sum over the p that some entry uses of
+// (M / scale_rows / scale_cols)^(p-1) .* (X_p Y_p^T).
+struct AdjArgs {
+    const void* M;            // multiplier source, b x rows x cols (A or B)
+    int32_t m_f64;            // M is double (else float)
+    const double* scale_rows; // b x rows or nullptr
+    const double* scale_cols; // b x cols or nullptr
+    const int32_t* hist;      // per family index: number of entries using that p
+    void* out;                // b x rows x cols (dA or dB)
+    int32_t out_f64;
+};
+
 // ---------------------------------------------------------------- launchers
 // Every launcher returns hipSuccess or the launch error.
 hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st);
@@ -86,9 +101,10 @@ hipError_t launch_apsp_to_dist(const void* X, int x_f64, int64_t n, double s, vo
 // Power planes.  src is b x rows x cols (row-major, element f64 ? double :
 // float) when !transpose, or b x cols x rows when transpose (then planes hold
 // the transpose).  Output planes: [b][plane][rows_pad][cols_pad] of bf16
-// (bf16 != 0) or double.  scale (nullable) is b x rows: plane row t is
-// (src row t) / scale[t].  powers: ascending list; split[q] says whether
-// power q gets a hi/lo pair (bf16 only).
+// (bf16 != 0) or double.  Plane element (t, u) is src / (scale_rows[t] *
+// scale_cols[u]); scale_rows is b x rows, scale_cols b x cols, each nullable.
+// powers: ascending list; split[q] says whether power q gets a hi/lo pair
+// (bf16 only).
 struct PlaneSpec {
     int32_t n_p;
     int32_t p[MT_MAX_P];
@@ -98,8 +114,8 @@ struct PlaneSpec {
 };
 hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int64_t b,
                                int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
-                               const double* scale, const PlaneSpec& spec, int bf16, void* planes,
-                               hipStream_t st);
+                               const double* scale_rows, const double* scale_cols,
+                               const PlaneSpec& spec, int bf16, void* planes, hipStream_t st);
 
 // Fused p-family GEMM + selection epilogue.
 hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m,
@@ -120,6 +136,31 @@ struct RootSpec {
 hipError_t launch_select_root_f64(const double* S, const uint8_t* code, int64_t b, int64_t m,
                                   int64_t n, const double* r, const double* c, const RootSpec& spec,
                                   void* out, int out_f64, uint8_t* pstar_out, hipStream_t st);
+
+// Backward: p* histogram and adjoint planes.
+struct AdjPrepSpec {
+    int32_t n_p;
+    int32_t p[MT_MAX_P];
+    int32_t planes;                    // adjoint planes per batch item (2 n_p BF16, n_p FP64)
+    int64_t xa_rows_pad, xa_cols_pad;  // Gt planes (rows m, inner n)
+    int64_t yb_rows_pad, yb_cols_pad;  // Gt' planes, transposed (rows n, inner m)
+};
+hipError_t launch_pstar_hist(const uint8_t* ps, int64_t total, int n_p, int32_t* hist, hipStream_t st);
+hipError_t launch_adjoint_prep(const void* G, const void* C, const uint8_t* pstar, int io_f64,
+                               const double* r, const double* c, int64_t b, int64_t m, int64_t n,
+                               const AdjPrepSpec& spec, const int32_t* hist, int bf16, void* XA,
+                               void* YB, hipStream_t st);
+
+// Adjoint GEMMs (rows x cols output, inner k_pad; X planes per batch item,
+// Y planes per batch item).
+hipError_t launch_adjoint_gemm_bf16(const uint16_t* Xp, const uint16_t* Yp, int64_t b, int64_t rows,
+                                    int64_t cols, int64_t rows_pad, int64_t cols_pad, int64_t kp,
+                                    int32_t x_planes, int32_t y_planes, const FamilyPlan& plan,
+                                    const AdjArgs& adj, hipStream_t st);
+hipError_t launch_adjoint_gemm_f64(const double* Xp, const double* Yp, int64_t b, int64_t rows,
+                                   int64_t cols, int64_t rows_pad, int64_t cols_pad, int64_t kp,
+                                   int32_t x_planes, int32_t y_planes, const FamilyPlan& plan,
+                                   const AdjArgs& adj, hipStream_t st);
 
 // Exact (max, x) product on the vector ALUs.
 hipError_t launch_exact_maxtimes(const void* A, const void* B, int f64, int64_t b, int64_t m,
