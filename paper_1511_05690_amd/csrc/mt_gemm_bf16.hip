@@ -99,6 +99,7 @@ struct SelectEpi {
     int64_t out_lane;
     int32_t rows_left, cols_left, diag_off;
 
+    static constexpr bool kAllActive = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
 
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
@@ -117,8 +118,6 @@ struct SelectEpi {
             }
             rs[i] = (float)v;
         }
-#pragma unroll
-        for (int i = 0; i < NDEC; ++i) decided[i] = 0u;
         // Tile (i, j) of this wave is staged through LDS as a 32 x 32 block;
         // lane l then handles rows 2q + l/32 (q = 0..15) of column l%32, so
         // lanes 0-31 and 32-63 store two consecutive row runs.
@@ -128,6 +127,21 @@ struct SelectEpi {
         rows_left = (int32_t)min<int64_t>(m - (t.row0 + lr0), 1 << 30);
         cols_left = (int32_t)min<int64_t>(n - (t.col0 + lc0), 1 << 30);
         diag_off = (int32_t)((t.col0 + lc0) - (t.row0 + lr0));
+        // Entries outside the matrix count as decided from the start, so a
+        // tile whose every entry is decided can be skipped as a whole.
+#pragma unroll
+        for (int i = 0; i < NDEC; ++i) decided[i] = 0u;
+#pragma unroll
+        for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) {
+                const int tix = i * WT_N + j;
+                uint32_t bits = 0u;
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (!(j * 32 < cols_left && i * 32 + 2 * q < rows_left)) bits |= 1u << q;
+                decided[tix >> 1] |= bits << ((tix & 1) * 16);
+            }
     }
 
     // stage: a free pipeline buffer (C::NW staging tiles of STG floats).
@@ -148,22 +162,22 @@ struct SelectEpi {
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
             for (int j = 0; j < WT_N; ++j) {
+                const int tix = i * WT_N + j;
+                uint32_t dec = decided[tix >> 1];
+                const int sh = (tix & 1) * 16;
+                if (__all(((dec >> sh) & 0xFFFFu) == 0xFFFFu)) continue;  // every entry decided
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
                     stg[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * 33 + (lane & 31)] = acc[i][j][r];
                 __builtin_amdgcn_wave_barrier();
                 const float cj = cs[lc0 + j * 32];
-                const bool col_ok = j * 32 < cols_left;
-                const int tix = i * WT_N + j;
-                uint32_t dec = decided[tix >> 1];
-                const int sh = (tix & 1) * 16;
 #pragma unroll 2
                 for (int q = 0; q < 16; ++q) {
                     const int roff = i * 32 + 2 * q;
                     const float S = stg[(2 * q + (lane >> 5)) * 33 + (lane & 31)];
                     const bool stable = S >= tau_f;
                     const uint32_t mask = 1u << (sh + q);
-                    if (col_ok && roff < rows_left && !(dec & mask) && (stable || last)) {
+                    if (!(dec & mask) && (stable || last)) {
                         dec |= mask;
                         float v = rs[lr0 + roff] * cj * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
                         if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
@@ -200,6 +214,7 @@ struct AdjointEpi {
     int64_t lane_off;
     int32_t rows_left, cols_left;
 
+    static constexpr bool kAllActive = false;
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
 
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
@@ -327,7 +342,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     Epi epi;
     epi.a = args;
     epi.setup(t, g, smem + C::PIPE_BYTES, tid);
-    if (tid == 0) {
+    if (!Epi::kAllActive && tid == 0) {
         int na = 0;
         for (int e = 0; e < plan.n; ++e)
             if (epi.active(e, plan)) s_act[1 + na++] = e;
@@ -350,10 +365,14 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     const int32_t rd_base = (lane & 31) * 128 + (((lane >> 5) ^ ((lane >> 1) & 7)) * 16);
 
     __syncthreads();
-    const int nact = __builtin_amdgcn_readfirstlane(s_act[0]);
+    const int nact = Epi::kAllActive ? plan.n : __builtin_amdgcn_readfirstlane(s_act[0]);
 
+    // entry of active index ai (the identity when every entry is active)
+    auto entry_of = [&](int ai) -> int {
+        return Epi::kAllActive ? ai : __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+    };
     auto issue = [&](int ai, int s, int kt, int buf) {
-        const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+        const int e = entry_of(ai);
         const uint16_t* xsrc = Xbase + (int64_t)plan.e[e].a_plane[s] * g.x_plane_elems + kt * 64;
         const uint16_t* ysrc = Ybase + (int64_t)plan.e[e].b_plane[s] * g.y_plane_elems + kt * 64;
         uint8_t* la = smem + buf * C::BUF_BYTES;
@@ -376,7 +395,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     auto advance = [&](int& ai, int& s, int& kt) {
         if (++kt == nkt) {
             kt = 0;
-            const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+            const int e = entry_of(ai);
             if (++s == plan.e[e].nseg) {
                 s = 0;
                 ++ai;
@@ -396,7 +415,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
 
     int buf = 0;
     for (int ai = 0; ai < nact; ++ai) {
-        const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+        const int e = entry_of(ai);
         f32x16 acc[WT_M][WT_N];
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
@@ -411,20 +430,31 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
             }
             const uint8_t* pa = smem + buf * C::BUF_BYTES + t.wm * WT_M * 32 * 128;
             const uint8_t* pb = smem + buf * C::BUF_BYTES + C::A_BYTES + t.wn * WT_N * 32 * 128;
+            // MFMA issue runs at raised wave priority; the fragments of
+            // sub-step kk + 1 are read from LDS while kk's MFMAs run.
+            __builtin_amdgcn_s_setprio(1);
+            bf16x8 fa[2][WT_M], fb[2][WT_N];
+#pragma unroll
+            for (int i = 0; i < WT_M; ++i) fa[0][i] = *(const bf16x8*)(pa + i * 32 * 128 + rd_base);
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) fb[0][j] = *(const bf16x8*)(pb + j * 32 * 128 + rd_base);
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const int32_t ro = rd_base ^ (kk << 5);
-                bf16x8 a[WT_M], b[WT_N];
+                const int cur = kk & 1;
+                if (kk + 1 < 4) {
+                    const int32_t ro = rd_base ^ ((kk + 1) << 5);
 #pragma unroll
-                for (int i = 0; i < WT_M; ++i) a[i] = *(const bf16x8*)(pa + i * 32 * 128 + ro);
+                    for (int i = 0; i < WT_M; ++i) fa[cur ^ 1][i] = *(const bf16x8*)(pa + i * 32 * 128 + ro);
 #pragma unroll
-                for (int j = 0; j < WT_N; ++j) b[j] = *(const bf16x8*)(pb + j * 32 * 128 + ro);
+                    for (int j = 0; j < WT_N; ++j) fb[cur ^ 1][j] = *(const bf16x8*)(pb + j * 32 * 128 + ro);
+                }
 #pragma unroll
                 for (int i = 0; i < WT_M; ++i)
 #pragma unroll
                     for (int j = 0; j < WT_N; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[cur][i], fb[cur][j], acc[i][j], 0, 0, 0);
             }
+            __builtin_amdgcn_s_setprio(0);
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
             buf ^= 1;
