@@ -104,6 +104,59 @@ def cpu_baseline(A, B, P, tau, rows):
     }
 
 
+def time_call(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def run_legs(mt, torch, np):
+    """The other rows of the hot path, each on its own workload: APSP on the
+    FP64 and BF16 paths, the differentiable form, and the small FP64 product.
+    Effective max-times ops: T n^3 for APSP, b m k n per product."""
+    from workloads import config
+
+    legs = {}
+    c1 = config(1)
+    A1, B1 = torch.from_numpy(c1["A"]).cuda(), torch.from_numpy(c1["B"]).cuda()
+    ms = time_call(lambda: mt.estimate(A1, B1, P=c1["P"], path="fp64"), 20, torch)
+    legs["product_256_fp64"] = {"ms": ms, "ops_per_s": 256.0 ** 3 / (ms / 1e3), "P": c1["P"]}
+
+    c2 = config(2)
+    W2 = torch.from_numpy(c2["W"]).cuda()
+    ms = time_call(lambda: mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"],
+                                   out_dtype=torch.float64), 3, torch)
+    n2 = c2["W"].shape[0]
+    legs["apsp_er2048_fp64"] = {"ms": ms, "squarings": c2["T"], "P": c2["P"],
+                                "ops_per_s": c2["T"] * float(n2) ** 3 / (ms / 1e3)}
+
+    c4 = config(4)
+    A4 = torch.from_numpy(c4["A"]).cuda()
+    B4 = torch.from_numpy(c4["B"]).cuda()
+    G4 = torch.from_numpy(c4["G"]).cuda()
+    for name, P in (("grad_64x512_p16_bf16", c4["P_fixed"]), ("grad_64x512_bf16", c4["P"])):
+        def fwd_bwd():
+            C, ps = mt.estimate(A4, B4, P=P, path="bf16", split_max_p=4096, return_pstar=True)
+            mt.estimate_backward(A4, B4, G4, C, ps, P, path="bf16")
+        ms = time_call(fwd_bwd, 5, torch)
+        legs[name] = {"ms_fwd_bwd": ms, "P": P, "ops_per_s": 64 * 512.0 ** 3 / (ms / 1e3)}
+
+    c5 = config(5)
+    W5 = torch.from_numpy(c5["W"]).cuda()
+    del c5["W"]
+    ms = time_call(lambda: mt.apsp(W5, s=c5["s"], P=c5["P"], path="bf16", n_squarings=c5["T"]), 1, torch)
+    legs["apsp_rgg16384_bf16"] = {"ms": ms, "squarings": c5["T"], "P": c5["P"],
+                                  "ops_per_s": c5["T"] * 16384.0 ** 3 / (ms / 1e3)}
+    return legs
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +167,8 @@ def main():
                     help="time one path only (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=128)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the APSP / gradient / small-product legs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -256,6 +311,12 @@ def main():
             "kernel_ms_per_step": f["kernel_ms_per_step"],
         }
         out["bf16_over_fp64"] = value / fval
+
+    if not args.no_legs and args.only is None:
+        log("[bench] legs: APSP (FP64 ER 2048, BF16 RGG 16384), gradient 64x512^3, 256^2 FP64")
+        del Ad, Bd, E, E64, Asub
+        torch.cuda.empty_cache()
+        out["legs"] = run_legs(mt, torch, np)
 
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_rows} rows")

@@ -108,7 +108,8 @@ mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
  *   C      b x m x n, dtype (output).
  *   p_star b x m x n uint8 (output, nullable): index into p_family of the p
  *          used per entry, MT_PSTAR_NONE if none was stable.
- * b, m, n >= 1; k >= 0 (k = 0 gives C = 0 and p_star = MT_PSTAR_NONE).
+ * b, m, k, n >= 0: an empty C is a no-op; k = 0 gives C = 0 and p_star =
+ * MT_PSTAR_NONE.  Sizes above 2^24 return MT_ERR_UNSUPPORTED.
  * FP32 inputs are converted exactly on load for the FP64 path.
  */
 mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype,
