@@ -186,6 +186,17 @@ mt_status maxtimes_timing_enable(int on);
 mt_status maxtimes_timing_reset(void);
 mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* launches);
 
+/*
+ * MFMA flops executed by the timed launches of the p-family GEMMs whose name
+ * starts with `prefix` since the last reset (kernels that count no work add
+ * nothing).  The forward GEMMs stop a tile as soon as every entry of it has
+ * found its p* (smaller p cannot change the result), so this is at most, and
+ * often less than, 2 * rows_pad * cols_pad * k_pad per segment of the family.
+ * Counters live in device memory that the timing facility allocates on first
+ * use; reset waits for the recorded launches and clears them.
+ */
+mt_status maxtimes_timing_work(const char* prefix, double* flops);
+
 /* Library version string. */
 const char* maxtimes_version(void);
 

@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
     "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
-    "timing_reset", "timing_read", "pfamily", "PSTAR_NONE", "PATHS",
+    "timing_reset", "timing_read", "timing_work", "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
 PSTAR_NONE = 255
@@ -83,6 +83,7 @@ def load_library():
         "maxtimes_timing_reset": [],
         "maxtimes_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(i64)],
+        "maxtimes_timing_work": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -316,3 +317,11 @@ def timing_read(prefix):
     cnt = ctypes.c_int64(0)
     _check(load_library().maxtimes_timing_read(prefix.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def timing_work(prefix):
+    """MFMA flops executed by the timed p-family GEMM launches whose kernel
+    name starts with ``prefix`` (tiles stop once every entry has its p*)."""
+    fl = ctypes.c_double(0.0)
+    _check(load_library().maxtimes_timing_work(prefix.encode(), ctypes.byref(fl)))
+    return fl.value

@@ -46,16 +46,22 @@ struct TimedLaunch {
     const char* name;
     hipEvent_t start;
     hipEvent_t stop;
+    int work_slot;  // index into g_work, -1 if the kernel counts no work
 };
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_launches;
+// Executed-flop counters of timed launches (device memory, one per launch,
+// allocated on first use, zeroed at reset).
+constexpr int kWorkSlots = 8192;
+unsigned long long* g_work = nullptr;
+int g_work_used = 0;
 }  // namespace
 
 void timing_before(const char* name, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing) return;
-    TimedLaunch t{name, nullptr, nullptr};
+    TimedLaunch t{name, nullptr, nullptr, -1};
     if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
     (void)hipEventRecord(t.start, st);
     g_launches.push_back(t);
@@ -66,6 +72,23 @@ void timing_after(hipStream_t st) {
     if (!g_timing || g_launches.empty()) return;
     TimedLaunch& t = g_launches.back();
     if (t.stop) (void)hipEventRecord(t.stop, st);
+}
+
+unsigned long long* timing_work_slot() {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing || g_launches.empty() || g_work_used >= kWorkSlots) return nullptr;
+    if (!g_work) {
+        void* p = nullptr;
+        if (hipMalloc(&p, kWorkSlots * sizeof(unsigned long long)) != hipSuccess) return nullptr;
+        if (hipMemset(p, 0, kWorkSlots * sizeof(unsigned long long)) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess) {
+            (void)hipFree(p);
+            return nullptr;
+        }
+        g_work = (unsigned long long*)p;
+    }
+    g_launches.back().work_slot = g_work_used;
+    return g_work + g_work_used++;
 }
 
 namespace {
@@ -620,12 +643,20 @@ mt_status maxtimes_timing_enable(int on) {
 }
 
 mt_status maxtimes_timing_reset(void) {
+    g_last_error.clear();
     std::lock_guard<std::mutex> lk(g_tmu);
     for (auto& t : g_launches) {
+        if (t.stop) (void)hipEventSynchronize(t.stop);
         if (t.start) (void)hipEventDestroy(t.start);
         if (t.stop) (void)hipEventDestroy(t.stop);
     }
     g_launches.clear();
+    if (g_work && g_work_used > 0) {
+        hipError_t e = hipMemset(g_work, 0, (size_t)g_work_used * sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return device_fail(e, "clearing the work counters");
+    }
+    g_work_used = 0;
     return MT_OK;
 }
 
@@ -648,6 +679,28 @@ mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* la
     }
     *total_ms = ms;
     *launches = cnt;
+    return MT_OK;
+}
+
+mt_status maxtimes_timing_work(const char* prefix, double* flops) {
+    g_last_error.clear();
+    if (!prefix || !flops) return fail(MT_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    *flops = 0.0;
+    if (!g_work || g_work_used == 0) return MT_OK;
+    const size_t pl = strlen(prefix);
+    for (auto& t : g_launches) {
+        if (strncmp(t.name, prefix, pl) != 0 || !t.stop) continue;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e != hipSuccess) return device_fail(e, "event sync");
+    }
+    std::vector<unsigned long long> w((size_t)g_work_used);
+    hipError_t e = hipMemcpy(w.data(), g_work, w.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(e, "reading the work counters");
+    double sum = 0.0;
+    for (auto& t : g_launches)
+        if (t.work_slot >= 0 && strncmp(t.name, prefix, pl) == 0) sum += (double)w[(size_t)t.work_slot];
+    *flops = sum;
     return MT_OK;
 }
 

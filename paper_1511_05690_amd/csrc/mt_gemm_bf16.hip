@@ -7,7 +7,9 @@
 // test S_p >= tau (Sec. 1, the highest stable p).  Because the entries are
 // visited from the largest p down, the first pass is the largest stable p,
 // and C = r c S^(1/p) is written exactly once per entry.  Entries that never
-// pass take the smallest p (index MT_PSTAR_NONE).
+// pass take the smallest p (index MT_PSTAR_NONE).  Once every entry of the
+// tile has its p, the smaller p cannot change the result and the tile stops:
+// the products of those p are not computed at all.
 //
 // Adjoint (accumulating epilogue).  For the gradient with p* held fixed the
 // kernel runs, for every p that some entry uses, the product X_p Y_p of an
@@ -55,6 +57,7 @@ struct GemmGeom {
     int64_t kp;             // padded inner length
     int64_t rows, cols;     // output rows x cols per batch item
     int32_t tiles_m, tiles_n;
+    unsigned long long* work;  // if set: MFMA flops executed, summed over workgroups
 };
 
 // WAVES_M x WAVES_N waves, each owning WT_M x WT_N MFMA tiles of 32 x 32.
@@ -100,7 +103,20 @@ struct SelectEpi {
     int32_t rows_left, cols_left, diag_off;
 
     static constexpr bool kAllActive = true;
+    static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
+
+    // Every entry of this wave has its p (wave-uniform).
+    __device__ bool all_decided() const {
+        constexpr int TOT = WT_M * WT_N * 16;
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < NDEC; ++i) {
+            const uint32_t full = (TOT - 32 * i >= 32) ? 0xFFFFFFFFu : ((1u << (TOT - 32 * i)) - 1u);
+            ok = ok && decided[i] == full;
+        }
+        return __all(ok);
+    }
 
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
         m = g.rows;
@@ -215,7 +231,9 @@ struct AdjointEpi {
     int32_t rows_left, cols_left;
 
     static constexpr bool kAllActive = false;
+    static constexpr bool kCanStop = false;
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
+    __device__ bool all_decided() const { return false; }
 
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
         rows = g.rows;
@@ -309,6 +327,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
     extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
     __shared__ int s_act[MT_MAX_P + 1];
+    __shared__ int s_done[2][C::NW];  // per wave: all entries decided (entry parity)
 
     const int tid = threadIdx.x;
     TileCtx t;
@@ -414,6 +433,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     __syncthreads();
 
     int buf = 0;
+    int64_t steps_done = 0;
     for (int ai = 0; ai < nact; ++ai) {
         const int e = entry_of(ai);
         f32x16 acc[WT_M][WT_N];
@@ -459,12 +479,28 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
             __syncthreads();
             buf ^= 1;
         }
+        steps_done += ntiles;
         // the buffer the last step read is free until the next step's loads,
         // which wait for the barrier below
         epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
+        if (Epi::kCanStop) {
+            const bool wd = epi.all_decided();
+            if (lane == 0) s_done[ai & 1][wave] = wd ? 1 : 0;
+        }
         __syncthreads();
+        if (Epi::kCanStop) {
+            // Every entry of the tile has its p: the remaining (smaller) p
+            // cannot change the output.  The loads already issued for the
+            // next entry have landed (vmcnt(0) above) and are simply unused.
+            int all = 1;
+#pragma unroll
+            for (int w = 0; w < C::NW; ++w) all &= s_done[ai & 1][w];
+            if (__builtin_amdgcn_readfirstlane(all)) break;
+        }
     }
     epi.finish(t);
+    if (g.work && tid == 0)
+        atomicAdd(g.work, (unsigned long long)steps_done * (2ull * C::BM * C::BN * 64));
 }
 
 template <class C, class Epi>
@@ -480,7 +516,9 @@ hipError_t launch_gemm(const GemmGeom& g, int64_t b, const FamilyPlan& plan,
     }
     const int64_t nwg = b * (int64_t)g.tiles_m * g.tiles_n;
     timing_before(name, st);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(C::THREADS), lds, st, g, plan, args);
+    GemmGeom gw = g;
+    gw.work = timing_work_slot();
+    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(C::THREADS), lds, st, gw, plan, args);
     timing_after(st);
     return hipGetLastError();
 }
@@ -508,6 +546,7 @@ GemmGeom make_geom(const uint16_t* X, const uint16_t* Y, int64_t rows, int64_t c
     g.kp = kp;
     g.tiles_m = (int32_t)(rows_pad / bm);
     g.tiles_n = (int32_t)(cols_pad / bn);
+    g.work = nullptr;
     return g;
 }
 

@@ -7,7 +7,8 @@
 // entry the epilogue records the ring result S at the largest p with
 // S_p >= tau (FP64 test) and that p's index; the FP64 root C = r c S^(1/p) is
 // taken by the select-root pass (mt_elementwise.hip), which keeps the
-// library's log / exp out of the unrolled epilogue.
+// library's log / exp out of the unrolled epilogue.  A tile whose entries all
+// have their p stops: the smaller p cannot change the result.
 //
 // Adjoint (accumulating epilogue).  As in the BF16 kernel: sum over the p
 // some entry uses of (scaled input)^(p-1) .* (X_p Y_p^T), written once.
@@ -37,6 +38,7 @@ struct GemmGeomF64 {
     int64_t kp;
     int64_t rows, cols;
     int32_t tiles_m, tiles_n;
+    unsigned long long* work;  // if set: MFMA flops executed, summed over workgroups
 };
 
 template <int WT_>
@@ -67,7 +69,20 @@ struct RecordEpi {
     int64_t out_lane;
     int32_t rows_left, cols_left;
 
+    static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
+
+    // Every entry of this wave has its p (wave-uniform).
+    __device__ bool all_decided() const {
+        constexpr int TOT = WT * WT * 4;
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < NDEC; ++i) {
+            const uint32_t full = (TOT - 32 * i >= 32) ? 0xFFFFFFFFu : ((1u << (TOT - 32 * i)) - 1u);
+            ok = ok && decided[i] == full;
+        }
+        return __all(ok);
+    }
 
     __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t*, int) {
         n = g.cols;
@@ -80,6 +95,17 @@ struct RecordEpi {
         out_lane = ((int64_t)t.bi * g.rows + t.row0 + lr0) * n + t.col0 + lc0;
         rows_left = (int32_t)min<int64_t>(g.rows - (t.row0 + lr0), 1 << 30);
         cols_left = (int32_t)min<int64_t>(n - (t.col0 + lc0), 1 << 30);
+        // Entries outside the matrix count as decided from the start.
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int tix = i * WT + j;
+                    if (!(j * 16 < cols_left && i * 16 + 4 * r < rows_left))
+                        decided[tix >> 3] |= 1u << ((tix & 7) * 4 + r);
+                }
     }
 
     // stage: a free pipeline buffer; each wave stages one 16 x 16 tile
@@ -130,6 +156,7 @@ struct AdjointEpiF64 {
     static constexpr int WT = C::WT;
     static constexpr int LDS_BYTES = 2 * C::BM * 8;
     using Args = AdjArgs;
+    static constexpr bool kCanStop = false;
     AdjArgs a;
     int64_t rows, cols;
     f64x4 tot[WT][WT];
@@ -140,6 +167,7 @@ struct AdjointEpiF64 {
     int32_t rows_left, cols_left;
 
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
+    __device__ bool all_decided() const { return false; }
 
     __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t* lds, int tid) {
         rows = g.rows;
@@ -227,6 +255,7 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
     constexpr int WT = C::WT;
     extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
     __shared__ int s_act[MT_MAX_P + 1];
+    __shared__ int s_done[2][4];  // per wave: all entries decided (entry parity)
 
     const int tid = threadIdx.x;
     TileCtx t;
@@ -314,6 +343,7 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
     __syncthreads();
 
     int buf = 0;
+    int64_t steps_done = 0;
     for (int ai = 0; ai < nact; ++ai) {
         const int e = __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
         f64x4 acc[WT][WT];
@@ -348,12 +378,25 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
             __syncthreads();
             buf ^= 1;
         }
+        steps_done += ntiles;
         // the buffer the last step read is free until the next step's loads,
         // which wait for the barrier below
         epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
+        if (Epi::kCanStop) {
+            const bool wd = epi.all_decided();
+            if (lane == 0) s_done[ai & 1][wave] = wd ? 1 : 0;
+        }
         __syncthreads();
+        if (Epi::kCanStop) {
+            // every entry has its p; the next entry's loads have landed
+            // (vmcnt(0) above) and are left unused
+            const int all = s_done[ai & 1][0] & s_done[ai & 1][1] & s_done[ai & 1][2] & s_done[ai & 1][3];
+            if (__builtin_amdgcn_readfirstlane(all)) break;
+        }
     }
     epi.finish(t);
+    if (g.work && tid == 0)
+        atomicAdd(g.work, (unsigned long long)steps_done * (2ull * C::BM * C::BM * 16));
 }
 
 template <class C, class Epi>
@@ -369,7 +412,9 @@ hipError_t launch_gemm(const GemmGeomF64& g, int64_t b, const FamilyPlan& plan,
     }
     const int64_t nwg = b * (int64_t)g.tiles_m * g.tiles_n;
     timing_before(name, st);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(kThreads), lds, st, g, plan, args);
+    GemmGeomF64 gw = g;
+    gw.work = timing_work_slot();
+    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(kThreads), lds, st, gw, plan, args);
     timing_after(st);
     return hipGetLastError();
 }
@@ -388,6 +433,7 @@ GemmGeomF64 make_geom(const double* X, const double* Y, int64_t rows, int64_t co
     g.cols = cols;
     g.tiles_m = (int32_t)(rows_pad / bm);
     g.tiles_n = (int32_t)(cols_pad / bm);
+    g.work = nullptr;
     return g;
 }
 

@@ -169,5 +169,8 @@ hipError_t launch_exact_maxtimes(const void* A, const void* B, int f64, int64_t 
 // Per-kernel event timing (api.cpp).
 void timing_before(const char* name, hipStream_t st);
 void timing_after(hipStream_t st);
+// Device counter for the launch just opened by timing_before, into which a
+// kernel may add the MFMA flops it executed; nullptr when timing is off.
+unsigned long long* timing_work_slot();
 
 }  // namespace mt
