@@ -19,16 +19,22 @@
 //
 // Operands are BF16 planes, K contiguous: X planes rows x k_pad and Y planes
 // cols x k_pad (Y holds the transpose of the right factor).  A split p is
-// three segments (hi.hi + hi.lo + lo.hi) accumulated into one FP32 sum.
+// three products (hi.hi + hi.lo + lo.hi) accumulated into one FP32 sum.
 //
 // Tiling: 512 threads = 8 waves (two per SIMD, so one wave's barrier and LDS
 // waits overlap the other's MFMAs) in 2 x 4; each wave owns WT_M x WT_N MFMA
-// tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16).  K step 64: the X and Y tiles
-// of a step are copied global -> LDS by the direct-to-LDS loads
+// tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16).  The operand tiles of a step
+// are copied global -> LDS by the direct-to-LDS loads
 // (global_load_lds_dwordx4), double buffered, so the next step's loads fly
-// while the current step's MFMAs run.  The LDS rows are 128 bytes; the
-// 16-byte chunk index is XOR-swizzled with (row >> 1) & 7 so that the MFMA
-// operand reads (16 rows x one chunk per 256 bytes) hit distinct banks.
+// while the current step's MFMAs run.  Every step moves the same bytes:
+//   plain p: X and Y tiles, K step 64, 128-byte LDS rows, 16-byte chunk
+//            index XOR-swizzled with (row >> 1) & 7;
+//   split p: X hi, X lo, Y hi, Y lo tiles, K step 32, 64-byte LDS rows,
+//            chunk index XOR-swizzled with (row >> 2) & 3; the three
+//            products share each loaded tile, so a split p loads 4/6 of the
+//            bytes of three separate products.
+// Either swizzle puts the MFMA operand reads (16 rows x one chunk per LDS
+// read phase) on distinct banks.
 #include <cfloat>
 #include <cmath>
 
@@ -38,6 +44,7 @@ namespace mt {
 namespace {
 
 __device__ __forceinline__ int swz(int row) { return (row >> 1) & 7; }
+
 
 // S^(1/p) in FP32 with the hardware log2 / exp2 (about 1 ulp each); S = 0
 // gives 0 (log2 0 = -inf, 2^-inf = 0), denormal S is rescaled first.
@@ -73,9 +80,12 @@ struct Cfg {
     static constexpr int B_BYTES = BN * 128;
     static constexpr int BUF_BYTES = A_BYTES + B_BYTES;
     static constexpr int PIPE_BYTES = 2 * BUF_BYTES;
-    static constexpr int GA = BM / 8 / NW;  // load instructions per wave per step (X)
+    static constexpr int GA = BM / 8 / NW;  // load instructions per wave per plain step (X)
     static constexpr int GB = BN / 8 / NW;  // (Y)
+    static constexpr int SA = BM / 16 / NW;  // per wave per split step, each of X hi / X lo
+    static constexpr int SB = BN / 16 / NW;  // (Y hi / Y lo)
     static_assert(GA % 2 == 0 && GB % 2 == 0, "row groups per wave must be even");
+    static_assert(SA >= 1 && SB >= 1, "split steps need 16 rows per wave");
 };
 
 struct TileCtx {
@@ -370,18 +380,23 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
 
     const uint16_t* Xbase = g.X + (int64_t)t.bi * g.x_batch_elems + t.row0 * g.kp;
     const uint16_t* Ybase = g.Y + (int64_t)t.bi * g.y_batch_elems + t.col0 * g.kp;
-    const int nkt = (int)(g.kp / 64);
 
-    // Global source offsets of the direct-to-LDS loads.  Load instruction i
-    // of this wave fills LDS rows R0 .. R0+7, R0 = (wave * G + i) * 8 with G
-    // (even) row groups per wave; lane l fills row R0 + l/8, physical chunk l%8,
-    // which holds logical chunk (l%8) ^ swz(row).  For even G the swizzle is
-    // (i&1)*4 + l/16, so two lane offsets cover every instruction.
+    // Global source offsets of the direct-to-LDS loads.  Plain step: load
+    // instruction i of this wave fills LDS rows R0 .. R0+7, R0 = (wave * G +
+    // i) * 8 with G (even) row groups per wave; lane l fills row R0 + l/8,
+    // physical chunk l%8, which holds logical chunk (l%8) ^ swz(row).  For
+    // even G the swizzle is (i&1)*4 + l/16, so two lane offsets cover every
+    // instruction.  Split step: instruction i fills 64-byte rows R0 .. R0+15,
+    // R0 a multiple of 16; lane l fills row R0 + l/4, physical chunk l%4,
+    // holding logical chunk (l%4) ^ ((row >> 2) & 3) = (l%4) ^ ((l >> 4) & 3).
     const int32_t ld_even = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (lane >> 4)) * 8);
     const int32_t ld_odd = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (4 + (lane >> 4))) * 8);
+    const int32_t ld_split = (lane >> 2) * (int32_t)g.kp + (((lane & 3) ^ ((lane >> 4) & 3)) * 8);
     // LDS operand reads: row (lane & 31) of a 32-row block, logical chunk
-    // 2*kk + lane/32, swizzle (lane >> 1) & 7 (block bases are multiples of 32).
+    // 2*kk + lane/32; plain swizzle (lane >> 1) & 7, split swizzle
+    // (lane >> 2) & 3 (block bases are multiples of 32 rows).
     const int32_t rd_base = (lane & 31) * 128 + (((lane >> 5) ^ ((lane >> 1) & 7)) * 16);
+    const int32_t rd_split = (lane & 31) * 64 + (((lane >> 5) ^ ((lane >> 2) & 3)) * 16);
 
     __syncthreads();
     const int nact = Epi::kAllActive ? plan.n : __builtin_amdgcn_readfirstlane(s_act[0]);
@@ -390,50 +405,73 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     auto entry_of = [&](int ai) -> int {
         return Epi::kAllActive ? ai : __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
     };
-    auto issue = [&](int ai, int s, int kt, int buf) {
+    const int nkt64 = (int)(g.kp / 64);  // plain steps per entry
+    const int nkt32 = 2 * nkt64;          // split steps per entry
+    auto issue = [&](int ai, int kt, int buf) {
         const int e = entry_of(ai);
-        const uint16_t* xsrc = Xbase + (int64_t)plan.e[e].a_plane[s] * g.x_plane_elems + kt * 64;
-        const uint16_t* ysrc = Ybase + (int64_t)plan.e[e].b_plane[s] * g.y_plane_elems + kt * 64;
         uint8_t* la = smem + buf * C::BUF_BYTES;
-        uint8_t* lb = la + C::A_BYTES;
+        if (plan.e[e].nseg == 3) {
+            const uint16_t* xh = Xbase + (int64_t)plan.e[e].a_plane[0] * g.x_plane_elems + kt * 32;
+            const uint16_t* xl = Xbase + (int64_t)plan.e[e].a_plane[2] * g.x_plane_elems + kt * 32;
+            const uint16_t* yh = Ybase + (int64_t)plan.e[e].b_plane[0] * g.y_plane_elems + kt * 32;
+            const uint16_t* yl = Ybase + (int64_t)plan.e[e].b_plane[1] * g.y_plane_elems + kt * 32;
+            uint8_t* lxl = la + C::BM * 64;
+            uint8_t* lyh = la + C::A_BYTES;
+            uint8_t* lyl = lyh + C::BN * 64;
 #pragma unroll
-        for (int i = 0; i < C::GA; ++i) {
-            const int R0 = (wave * C::GA + i) * 8;
-            __builtin_amdgcn_global_load_lds(
-                (glb_cvoid*)(xsrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
-                (lds_void*)(la + R0 * 128), 16, 0, 0);
-        }
+            for (int i = 0; i < C::SA; ++i) {
+                const int R0 = (wave * C::SA + i) * 16;
+                const int64_t go = (int64_t)R0 * g.kp + ld_split;
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(xh + go), (lds_void*)(la + R0 * 64), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(xl + go), (lds_void*)(lxl + R0 * 64), 16, 0, 0);
+            }
 #pragma unroll
-        for (int i = 0; i < C::GB; ++i) {
-            const int R0 = (wave * C::GB + i) * 8;
-            __builtin_amdgcn_global_load_lds(
-                (glb_cvoid*)(ysrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
-                (lds_void*)(lb + R0 * 128), 16, 0, 0);
+            for (int i = 0; i < C::SB; ++i) {
+                const int R0 = (wave * C::SB + i) * 16;
+                const int64_t go = (int64_t)R0 * g.kp + ld_split;
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(yh + go), (lds_void*)(lyh + R0 * 64), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(yl + go), (lds_void*)(lyl + R0 * 64), 16, 0, 0);
+            }
+        } else {
+            const uint16_t* xsrc = Xbase + (int64_t)plan.e[e].a_plane[0] * g.x_plane_elems + kt * 64;
+            const uint16_t* ysrc = Ybase + (int64_t)plan.e[e].b_plane[0] * g.y_plane_elems + kt * 64;
+            uint8_t* lb = la + C::A_BYTES;
+#pragma unroll
+            for (int i = 0; i < C::GA; ++i) {
+                const int R0 = (wave * C::GA + i) * 8;
+                __builtin_amdgcn_global_load_lds(
+                    (glb_cvoid*)(xsrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
+                    (lds_void*)(la + R0 * 128), 16, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < C::GB; ++i) {
+                const int R0 = (wave * C::GB + i) * 8;
+                __builtin_amdgcn_global_load_lds(
+                    (glb_cvoid*)(ysrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
+                    (lds_void*)(lb + R0 * 128), 16, 0, 0);
+            }
         }
     };
-    auto advance = [&](int& ai, int& s, int& kt) {
-        if (++kt == nkt) {
+    auto advance = [&](int& ai, int& kt) {
+        const int e = entry_of(ai);
+        if (++kt == (plan.e[e].nseg == 3 ? nkt32 : nkt64)) {
             kt = 0;
-            const int e = entry_of(ai);
-            if (++s == plan.e[e].nseg) {
-                s = 0;
-                ++ai;
-            }
+            ++ai;
         }
     };
 
     // Software pipeline: the loads of the next K step (possibly of the next
-    // segment or family entry) are issued before the MFMAs of the current one.
-    int la_ = 0, ls = 0, lkt = 0;
-    if (nkt > 0 && nact > 0) {
-        issue(la_, ls, lkt, 0);
-        advance(la_, ls, lkt);
+    // family entry) are issued before the MFMAs of the current one.
+    int la_ = 0, lkt = 0;
+    if (nkt64 > 0 && nact > 0) {
+        issue(la_, lkt, 0);
+        advance(la_, lkt);
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
     int buf = 0;
-    int64_t steps_done = 0;
+    int64_t kunits = 0;  // executed MFMA work in units of BM x BN x 1 products
     for (int ai = 0; ai < nact; ++ai) {
         const int e = entry_of(ai);
         f32x16 acc[WT_M][WT_N];
@@ -442,44 +480,88 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
 #pragma unroll
             for (int j = 0; j < WT_N; ++j) acc[i][j] = f32x16{};
 
-        const int ntiles = plan.e[e].nseg * nkt;
-        for (int st = 0; st < ntiles; ++st) {
-            if (la_ < nact) {
-                issue(la_, ls, lkt, buf ^ 1);
-                advance(la_, ls, lkt);
-            }
-            const uint8_t* pa = smem + buf * C::BUF_BYTES + t.wm * WT_M * 32 * 128;
-            const uint8_t* pb = smem + buf * C::BUF_BYTES + C::A_BYTES + t.wn * WT_N * 32 * 128;
-            // MFMA issue runs at raised wave priority; the fragments of
-            // sub-step kk + 1 are read from LDS while kk's MFMAs run.
-            __builtin_amdgcn_s_setprio(1);
-            bf16x8 fa[2][WT_M], fb[2][WT_N];
-#pragma unroll
-            for (int i = 0; i < WT_M; ++i) fa[0][i] = *(const bf16x8*)(pa + i * 32 * 128 + rd_base);
-#pragma unroll
-            for (int j = 0; j < WT_N; ++j) fb[0][j] = *(const bf16x8*)(pb + j * 32 * 128 + rd_base);
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int cur = kk & 1;
-                if (kk + 1 < 4) {
-                    const int32_t ro = rd_base ^ ((kk + 1) << 5);
-#pragma unroll
-                    for (int i = 0; i < WT_M; ++i) fa[cur ^ 1][i] = *(const bf16x8*)(pa + i * 32 * 128 + ro);
-#pragma unroll
-                    for (int j = 0; j < WT_N; ++j) fb[cur ^ 1][j] = *(const bf16x8*)(pb + j * 32 * 128 + ro);
+        if (plan.e[e].nseg == 3) {
+            // split p: hi.hi + hi.lo + lo.hi per K step of 32
+            for (int st = 0; st < nkt32; ++st) {
+                if (la_ < nact) {
+                    issue(la_, lkt, buf ^ 1);
+                    advance(la_, lkt);
                 }
+                const uint8_t* pxh = smem + buf * C::BUF_BYTES + t.wm * WT_M * 32 * 64;
+                const uint8_t* pxl = pxh + C::BM * 64;
+                const uint8_t* pyh = smem + buf * C::BUF_BYTES + C::A_BYTES + t.wn * WT_N * 32 * 64;
+                const uint8_t* pyl = pyh + C::BN * 64;
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-                for (int i = 0; i < WT_M; ++i)
+                for (int kk = 0; kk < 2; ++kk) {
+                    const int32_t ro = rd_split ^ (kk << 5);
+                    bf16x8 ah[WT_M], al[WT_M], bh[WT_N], bl[WT_N];
 #pragma unroll
-                    for (int j = 0; j < WT_N; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[cur][i], fb[cur][j], acc[i][j], 0, 0, 0);
+                    for (int i = 0; i < WT_M; ++i) ah[i] = *(const bf16x8*)(pxh + i * 32 * 64 + ro);
+#pragma unroll
+                    for (int j = 0; j < WT_N; ++j) bh[j] = *(const bf16x8*)(pyh + j * 32 * 64 + ro);
+#pragma unroll
+                    for (int j = 0; j < WT_N; ++j) bl[j] = *(const bf16x8*)(pyl + j * 32 * 64 + ro);
+#pragma unroll
+                    for (int i = 0; i < WT_M; ++i) al[i] = *(const bf16x8*)(pxl + i * 32 * 64 + ro);
+#pragma unroll
+                    for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+                        for (int j = 0; j < WT_N; ++j) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        }
+#pragma unroll
+                    for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+                        for (int j = 0; j < WT_N; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+                __builtin_amdgcn_s_setprio(0);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                buf ^= 1;
             }
-            __builtin_amdgcn_s_setprio(0);
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-            buf ^= 1;
+            kunits += (int64_t)nkt32 * 96;
+        } else {
+            for (int st = 0; st < nkt64; ++st) {
+                if (la_ < nact) {
+                    issue(la_, lkt, buf ^ 1);
+                    advance(la_, lkt);
+                }
+                const uint8_t* pa = smem + buf * C::BUF_BYTES + t.wm * WT_M * 32 * 128;
+                const uint8_t* pb = smem + buf * C::BUF_BYTES + C::A_BYTES + t.wn * WT_N * 32 * 128;
+                // MFMA issue runs at raised wave priority; the fragments of
+                // sub-step kk + 1 are read from LDS while kk's MFMAs run.
+                __builtin_amdgcn_s_setprio(1);
+                bf16x8 fa[2][WT_M], fb[2][WT_N];
+#pragma unroll
+                for (int i = 0; i < WT_M; ++i) fa[0][i] = *(const bf16x8*)(pa + i * 32 * 128 + rd_base);
+#pragma unroll
+                for (int j = 0; j < WT_N; ++j) fb[0][j] = *(const bf16x8*)(pb + j * 32 * 128 + rd_base);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int cur = kk & 1;
+                    if (kk + 1 < 4) {
+                        const int32_t ro = rd_base ^ ((kk + 1) << 5);
+#pragma unroll
+                        for (int i = 0; i < WT_M; ++i) fa[cur ^ 1][i] = *(const bf16x8*)(pa + i * 32 * 128 + ro);
+#pragma unroll
+                        for (int j = 0; j < WT_N; ++j) fb[cur ^ 1][j] = *(const bf16x8*)(pb + j * 32 * 128 + ro);
+                    }
+#pragma unroll
+                    for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+                        for (int j = 0; j < WT_N; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[cur][i], fb[cur][j], acc[i][j], 0, 0, 0);
+                }
+                __builtin_amdgcn_s_setprio(0);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                buf ^= 1;
+            }
+            kunits += (int64_t)nkt64 * 64;
         }
-        steps_done += ntiles;
         // the buffer the last step read is free until the next step's loads,
         // which wait for the barrier below
         epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
@@ -499,8 +581,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
         }
     }
     epi.finish(t);
-    if (g.work && tid == 0)
-        atomicAdd(g.work, (unsigned long long)steps_done * (2ull * C::BM * C::BN * 64));
+    if (g.work && tid == 0) atomicAdd(g.work, (unsigned long long)kunits * (2ull * C::BM * C::BN));
 }
 
 template <class C, class Epi>
