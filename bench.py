@@ -104,6 +104,31 @@ def cpu_baseline(A, B, P, tau, rows):
     }
 
 
+def hbm_kernels(kern_ms, n, P, path, in_bytes=4):
+    """Achieved HBM rate of the bandwidth-bound kernels of one step, from
+    their algorithmic bytes (each input read once, each output written once)
+    and the in-process launch times (ms per step)."""
+    n2 = float(n) * n
+    if path == "bf16":
+        planes = sum(2 if p <= 4 else 1 for p in P)
+        plane_bytes = 2 * (n2 * in_bytes + n2 * 2 * planes)  # both operands
+    else:
+        plane_bytes = 2 * (n2 * in_bytes + n2 * 8 * len(P))
+    algo = {
+        "mt_rowmax": n2 * in_bytes,
+        "mt_colmax": n2 * in_bytes,
+        "mt_power_planes": plane_bytes,
+        "mt_select_root": n2 * (8 + 1 + in_bytes),
+    }
+    out = {}
+    for k, b in algo.items():
+        ms = kern_ms.get(k)
+        if ms:
+            gbs = b / (ms / 1e3) / 1e9
+            out[k] = {"ms": ms, "bytes": b, "GB/s": gbs, "frac_of_8TB/s": gbs / 8000.0}
+    return out
+
+
 def time_call(fn, reps, torch):
     fn()
     torch.cuda.synchronize()
@@ -302,6 +327,7 @@ def main():
             "avg_launch_ms": bf["gemm_ms"],
         },
         "kernel_ms_per_step": bf["kernel_ms_per_step"],
+        "hbm_kernels": hbm_kernels(bf["kernel_ms_per_step"], n, P, main_path),
         "max_rel_err_vs_exact": errs,
         "exact_valu": {"rows": len(rows), "ms": exact_ms,
                        "ops_per_s": len(rows) * float(n) * n / (exact_ms / 1e3)},
@@ -317,6 +343,7 @@ def main():
             "gemm_tflops": f["gemm_flop"] / (f["gemm_ms"] / 1e3) / 1e12,
             "gemm_frac_of_fp64_peak": f["gemm_flop"] / (f["gemm_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
             "kernel_ms_per_step": f["kernel_ms_per_step"],
+            "hbm_kernels": hbm_kernels(f["kernel_ms_per_step"], n, P, "fp64"),
         }
         out["bf16_over_fp64"] = value / fval
 
