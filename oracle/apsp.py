@@ -72,14 +72,15 @@ def apsp_exact_squaring(W, s=1.0, T=None):
     return apsp_by_squaring(W, s, T, exact_maxtimes)
 
 
-def apsp_estimate(W, s, P, tau, T=None):
+def apsp_estimate(W, s, P, tau, T=None, projection=None):
     """APSP estimate: the driver with the p-norm product (Alg. 5) at each
-    squaring.  Returns dict D, X, pstar_idx_last (p* index of the last
-    squaring)."""
+    squaring (projection "r1": the r = 1 projection of Sec. 1 in place of
+    the plain root).  Returns dict D, X, pstar_idx_last (p* index of the
+    last squaring)."""
     last = {}
 
     def product(X, Y):
-        out = pnorm_estimate(X, Y, P, tau)
+        out = pnorm_estimate(X, Y, P, tau, projection=projection)
         last["idx"] = out["pstar_idx"]
         return out["C"]
 

@@ -35,6 +35,14 @@ design notes of the repository):
   R5  A zero row of A (zero column of B) has r = 0 (c = 0); its scaled row
       is 0 and its outputs are 0.  An empty inner dimension (k = 0) gives
       all-zero output with index PSTAR_NONE.
+  R6  The r = 1 projection (Sec. 1, projecting the unique values of u onto
+      one value alpha): the paper's form uses the evenly spaced norms p*/2
+      and p*.  Read with the next smaller p of the family, p_lo, as the
+      lower norm: model u as h copies of alpha, S_p = h alpha^p, so
+      alpha = (S_{p*} / S_{p_lo})^(1/(p* - p_lo)); for a powers-of-two
+      family p_lo = p*/2 and this is (S_{p*} / S_{p*/2})^(2/p*).  Where p*
+      is the smallest p, no p is stable, or S_{p_lo} is 0, the plain root
+      is used.
 """
 
 import numpy as np
@@ -139,11 +147,31 @@ def _root(S, P, idx):
     return root, psel, Ssel
 
 
-def pnorm_estimate(A, B, P, tau, norm_correct=False):
+def _project_r1(S, P, idx, root):
+    """Reading R6 of the r = 1 projection (Sec. 1): per entry with stable
+    index q > 0, alpha = (S_{P[q]} / S_{P[q-1]})^(1/(P[q] - P[q-1])); the
+    plain root ``root`` elsewhere."""
+    P = np.asarray(P, dtype=np.int64)
+    q = idx.astype(np.int64)
+    use = (idx != PSTAR_NONE) & (q > 0)
+    qh = np.where(use, q, 0)
+    ql = np.where(use, q - 1, 0)
+    Sh = np.take_along_axis(S, qh[None], axis=0)[0]
+    Sl = np.take_along_axis(S, ql[None], axis=0)[0]
+    use &= Sl > 0
+    expo = 1.0 / (P[qh] - P[ql]).astype(np.float64).clip(min=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        alpha = np.power(np.where(use, Sh / np.where(use, Sl, 1.0), 1.0), expo)
+    return np.where(use, alpha, root)
+
+
+def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None):
     """The p-norm estimate of the (max, x) product (Alg. 5, Sec. 2.1-2.2).
 
     C_ij = r_i c_j S_{p*}^(1/p*), p* = max{p in P : S_p[i, j] >= tau}.
     With norm_correct, C is divided by k^(1/p*) (Sec. 1, centred error).
+    With projection="r1" the max is taken from the r = 1 projection of the
+    norm sequence instead of the plain root (Sec. 1; reading R6).
 
     Returns a dict: C, pstar_idx (uint8, index into P, 255 = none stable),
     r, c, S (the whole norm power sequence), pstar (the p used per entry).
@@ -151,24 +179,31 @@ def pnorm_estimate(A, B, P, tau, norm_correct=False):
     P = [int(p) for p in P]
     if any(p <= 0 for p in P) or any(P[i] >= P[i + 1] for i in range(len(P) - 1)):
         raise ValueError("P must be strictly ascending positive integers")
+    if projection not in (None, "r1"):
+        raise ValueError("projection must be None or 'r1'")
+    if projection and norm_correct:
+        raise ValueError("norm_correct applies to the plain root only")
     A = _f64(A)
     B = _f64(B)
     k = A.shape[-1]
     S, r, c = norm_power_sequence(A, B, P)
     idx = select_pstar(S, tau)
     root, psel, _ = _root(S, P, idx)
+    if projection == "r1":
+        root = _project_r1(S, P, idx, root)
     C = r[..., :, None] * c[..., None, :] * root
     if norm_correct and k > 0:
         C = C / np.power(float(k), 1.0 / psel)
     return {"C": C, "pstar_idx": idx, "pstar": psel, "r": r, "c": c, "S": S}
 
 
-def pnorm_estimate_rows(A, B, P, tau, rows, norm_correct=False):
+def pnorm_estimate_rows(A, B, P, tau, rows, norm_correct=False, projection=None):
     """The estimate restricted to output rows ``rows``: row i of C depends
     only on row i of A (through r_i and A'_i) and on all of B, so this is
     pnorm_estimate(A[rows], B)."""
     A = _f64(A)
-    return pnorm_estimate(A[..., rows, :], B, P, tau, norm_correct=norm_correct)
+    return pnorm_estimate(A[..., rows, :], B, P, tau, norm_correct=norm_correct,
+                          projection=projection)
 
 
 def pnorm_forward_fixed(A, B, P, pstar_idx):
