@@ -77,6 +77,23 @@ typedef enum { MT_PATH_FP64 = 0, MT_PATH_BF16_SPLIT = 1 } mt_path;
 #define MT_FLAG_NORM_CORRECT 2u  /* divide C by k^(1/p*): centred error (Sec. 1) */
 #define MT_FLAG_CLAMP        4u  /* clamp C to <= 1 (always on inside apsp_estimate) */
 #define MT_FLAG_RAW_OUTPUT   8u  /* apsp_estimate: write X (the (x,max) matrix) instead of D */
+/*
+ * MT_FLAG_PROJECT_R1: estimate the max by the r = 1 projection of the norm
+ * sequence (Sec. 1: the terms u_k are modelled as h copies of one value
+ * alpha, so S_p = h alpha^p).  With p* selected as above and p_lo the next
+ * smaller p of the family, C = r c (S_{p*} / S_{p_lo})^(1/(p* - p_lo)); for a
+ * powers-of-two family p_lo = p* / 2 and this is the paper's r = 1 form.  It is
+ * exact when the largest terms tie (so the APSP squarings lose the bias of
+ * the tied k = i and k = j terms) and satisfies
+ * E (2 (sqrt(k) - 1) / (k - 1))^(2 / p*) <= C <= E when p_lo = p* / 2.  The plain
+ * root is kept where p* is the smallest p, no p is stable, or S_{p_lo} = 0.
+ * maxtimes_estimate and apsp_estimate; not with MT_FLAG_NORM_CORRECT
+ * (MT_ERR_INVALID_ARG); maxtimes_estimate_backward rejects it
+ * (MT_ERR_UNSUPPORTED).  A tile runs one more p of the family than the
+ * plain estimate needs, and the FP64 path uses 8 more workspace bytes per
+ * output entry.
+ */
+#define MT_FLAG_PROJECT_R1  16u
 
 #define MT_PSTAR_NONE 255  /* p_star value when no p of the family was stable */
 #define MT_MAX_P 32        /* largest family size */

@@ -28,7 +28,8 @@ PSTAR_NONE = 255
 MAX_P = 32
 PATHS = {"fp64": 0, "bf16": 1}
 F32, F64 = 0, 1
-FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT = 1, 2, 4, 8
+FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT, FLAG_PROJECT_R1 = 1, 2, 4, 8, 16
+PROJECTIONS = {None: 0, "r1": FLAG_PROJECT_R1}
 STATUS = {0: "MT_OK", 1: "MT_ERR_INVALID_ARG", 2: "MT_ERR_DOMAIN", 3: "MT_ERR_WORKSPACE",
           4: "MT_ERR_DEVICE", 5: "MT_ERR_UNSUPPORTED"}
 
@@ -248,17 +249,28 @@ class _EstimateFn(torch.autograd.Function):
         return dA, dB, None, None, None, None, None
 
 
+def _projection_flag(projection):
+    if projection not in PROJECTIONS:
+        raise ValueError(f"projection must be one of {sorted(PROJECTIONS, key=str)}")
+    return PROJECTIONS[projection]
+
+
 def estimate(A, B, P=(1, 2, 4, 8, 16, 32, 64), tau=None, path="bf16", split_max_p=None,
-             norm_correct=False, clamp=False, validate=False, return_pstar=False, workspace=None):
+             norm_correct=False, clamp=False, validate=False, return_pstar=False, workspace=None,
+             projection=None):
     """Estimate C_ij = max_k A_ik B_kj for nonnegative A (.., m, k), B (.., k, n).
 
     path "bf16": BF16 MFMA ring products with hi/lo split for p <= split_max_p;
     path "fp64": FP64 MFMA ring products.  tau None = the path default.
-    Differentiable (p* held fixed) when A or B requires grad.
+    projection None: the plain root S_{p*}^(1/p*); "r1": the r = 1
+    projection (S_{p*} / S_{p_lo})^(1/(p* - p_lo)) (MT_FLAG_PROJECT_R1).
+    Differentiable (p* held fixed) when A or B requires grad (plain root only).
     """
     flags = (FLAG_VALIDATE if validate else 0) | (FLAG_NORM_CORRECT if norm_correct else 0) | \
-        (FLAG_CLAMP if clamp else 0)
+        (FLAG_CLAMP if clamp else 0) | _projection_flag(projection)
     if torch.is_grad_enabled() and (A.requires_grad or B.requires_grad):
+        if projection is not None:
+            raise ValueError("the r = 1 projection has no backward; use projection=None for gradients")
         C, ps = _EstimateFn.apply(A, B, list(P), path, tau, split_max_p, flags)
     else:
         C, ps = _forward(A, B, P, path, tau, split_max_p, flags, return_pstar, workspace)
@@ -266,9 +278,11 @@ def estimate(A, B, P=(1, 2, 4, 8, 16, 32, 64), tau=None, path="bf16", split_max_
 
 
 def apsp(W, s=1.0, P=None, path="fp64", n_squarings=-1, tau=None, split_max_p=None,
-         out_dtype=torch.float32, raw=False, validate=False, return_pstar=False, workspace=None):
+         out_dtype=torch.float32, raw=False, validate=False, return_pstar=False, workspace=None,
+         projection=None):
     """Estimated all-pairs shortest distances of the n x n FP32 weight matrix W
-    (+inf = no edge).  raw=True returns the (x, max) matrix X instead."""
+    (+inf = no edge).  raw=True returns the (x, max) matrix X instead.
+    projection "r1" uses the r = 1 projection in every squaring."""
     lib = load_library()
     if P is None:
         P = pfamily(512 if path == "fp64" else 128)
@@ -276,7 +290,7 @@ def apsp(W, s=1.0, P=None, path="fp64", n_squarings=-1, tau=None, split_max_p=No
         raise ValueError("W must be a square FP32 device tensor")
     W = W.contiguous()
     n = W.shape[0]
-    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_RAW_OUTPUT if raw else 0)
+    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_RAW_OUTPUT if raw else 0) | _projection_flag(projection)
     o = _options(P, path, tau, split_max_p, flags)
     need = ctypes.c_size_t(0)
     _check(lib.apsp_workspace_size(n, ctypes.byref(o), ctypes.byref(need)))

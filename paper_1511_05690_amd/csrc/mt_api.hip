@@ -114,8 +114,11 @@ mt_status parse_options(const mt_options* opt, Family* f) {
         return fail(MT_ERR_INVALID_ARG, "n_p = %d outside 1..%d", opt->n_p, MT_MAX_P);
     if (opt->path != MT_PATH_FP64 && opt->path != MT_PATH_BF16_SPLIT)
         return fail(MT_ERR_INVALID_ARG, "unknown path %d", opt->path);
-    const uint32_t known = MT_FLAG_VALIDATE | MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT;
+    const uint32_t known = MT_FLAG_VALIDATE | MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT |
+                           MT_FLAG_PROJECT_R1;
     if (opt->flags & ~known) return fail(MT_ERR_INVALID_ARG, "unknown flag bits 0x%x", opt->flags & ~known);
+    if ((opt->flags & MT_FLAG_PROJECT_R1) && (opt->flags & MT_FLAG_NORM_CORRECT))
+        return fail(MT_ERR_INVALID_ARG, "MT_FLAG_NORM_CORRECT applies to the plain root, not to MT_FLAG_PROJECT_R1");
     if (!(opt->tau <= 0.0 || (opt->tau > 0.0 && std::isfinite(opt->tau))))
         return fail(MT_ERR_INVALID_ARG, "tau must be finite");
     f->n = opt->n_p;
@@ -161,6 +164,7 @@ FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
     FamilyPlan plan;
     memset(&plan, 0, sizeof plan);
     plan.n = f.n;
+    plan.r1 = (f.flags & MT_FLAG_PROJECT_R1) ? 1 : 0;
     plan.tau = f.tau;
     plan.tau_f = round_up_to_float(f.tau);
     for (int e = 0; e < f.n; ++e) {
@@ -169,6 +173,7 @@ FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
         pe.pidx = q;
         pe.p = f.p[q];
         pe.inv_p = 1.0f / (float)f.p[q];
+        pe.inv_dp = q > 0 ? 1.0f / (float)(f.p[q] - f.p[q - 1]) : 0.0f;
         pe.corr = (f.flags & MT_FLAG_NORM_CORRECT) && k > 0 ? (float)std::pow((double)k, -1.0 / f.p[q]) : 1.0f;
         const int hi = ps.first_plane[q];
         if (ps.split[q]) {
@@ -194,6 +199,7 @@ RootSpec root_spec(const Family& f, int64_t k, int mode, int clamp) {
     }
     r.mode = mode;
     r.clamp = clamp;
+    r.r1 = (f.flags & MT_FLAG_PROJECT_R1) ? 1 : 0;
     return r;
 }
 
@@ -223,7 +229,7 @@ Geom product_geom(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
 }
 
 struct Layout {
-    size_t hdr, r, c, ap, bp, s, code, x, total;
+    size_t hdr, r, c, ap, bp, s, s2, code, x, total;
 };
 
 // The workspace of one product (plus an APSP X buffer when x_bytes > 0).
@@ -236,11 +242,13 @@ Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64
     L.c = off;   off += align_up((size_t)(b * n) * 8);
     L.ap = off;  off += align_up((size_t)b * ps.n_planes * g.mp * g.kp * g.esize);
     L.bp = off;  off += align_up((size_t)b * ps.n_planes * g.np * g.kp * g.esize);
+    L.s = L.s2 = L.code = 0;
     if (!f.bf16) {
         L.s = off;    off += align_up((size_t)(b * m * n) * 8);
+        if (f.flags & MT_FLAG_PROJECT_R1) {
+            L.s2 = off; off += align_up((size_t)(b * m * n) * 8);
+        }
         L.code = off; off += align_up((size_t)(b * m * n));
-    } else {
-        L.s = L.code = 0;
     }
     L.x = off;
     off += align_up(x_bytes);
@@ -338,14 +346,15 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     } else {
         epi.mode = EPI_PLAIN;
         epi.out = ws + L.s;
+        epi.out2 = (f.flags & MT_FLAG_PROJECT_R1) ? ws + L.s2 : nullptr;
         epi.out_f64 = 1;
         epi.pstar = ws + L.code;
         MT_TRY(launch_pfamily_gemm_f64((const double*)ap, (const double*)bp, b, m, n, g.mp, g.np, g.kp,
                                        ps.n_planes, g.bm, plan, epi, st),
                "p-family GEMM (FP64)");
         const RootSpec rsp = root_spec(f, k, mode, clamp);
-        MT_TRY(launch_select_root_f64((const double*)(ws + L.s), ws + L.code, b, m, n, r, c, rsp, out,
-                                      out_f64, pstar, st),
+        MT_TRY(launch_select_root_f64((const double*)(ws + L.s), (const double*)(ws + L.s2), ws + L.code, b, m,
+                                      n, r, c, rsp, out, out_f64, pstar, st),
                "select root (FP64)");
     }
     return MT_OK;
@@ -500,8 +509,9 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
     Family f;
     mt_status s = parse_options(opt, &f);
     if (s != MT_OK) return s;
-    if (f.flags & (MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT))
-        return fail(MT_ERR_UNSUPPORTED, "the backward supports the plain estimate only (no norm correction or clamp)");
+    if (f.flags & (MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT | MT_FLAG_PROJECT_R1))
+        return fail(MT_ERR_UNSUPPORTED,
+                    "the backward supports the plain estimate only (no norm correction, clamp or projection)");
     if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
     if (!dA && !dB) return MT_OK;

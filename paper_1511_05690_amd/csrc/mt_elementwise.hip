@@ -238,11 +238,15 @@ __global__ __launch_bounds__(kThreads) void mt_apsp_to_dist_kernel(const TX* __r
 
 // FP64 path, after the GEMM's selection: C = r_i c_j S^(1/p*) (the 1/p root of
 // Sec. 1 with the restored row / column scale), optional clamp, APSP diagonal.
+// With the r = 1 projection (Sec. 1: the terms modelled as copies of one
+// value) the max is (S_{p*} / S_{p_lo})^(1/(p* - p_lo)), p_lo the family's
+// next smaller p, whose ring result S2 the GEMM recorded; the plain root is
+// kept where p* is the smallest p, none was stable, or S2 is 0.
 template <typename TO>
 __global__ __launch_bounds__(kThreads) void mt_select_root_f64_kernel(
-    const double* __restrict__ S, const uint8_t* __restrict__ code, int64_t rows, int64_t m,
-    int64_t n, const double* __restrict__ r, const double* __restrict__ c, RootSpec spec,
-    TO* __restrict__ out, uint8_t* __restrict__ pstar_out) {
+    const double* __restrict__ S, const double* __restrict__ S2, const uint8_t* __restrict__ code,
+    int64_t rows, int64_t m, int64_t n, const double* __restrict__ r, const double* __restrict__ c,
+    RootSpec spec, TO* __restrict__ out, uint8_t* __restrict__ pstar_out) {
     for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
         const int64_t bi = row / m;
         const int64_t i = row - bi * m;
@@ -254,7 +258,11 @@ __global__ __launch_bounds__(kThreads) void mt_select_root_f64_kernel(
             const int qi = q == MT_PSTAR_NONE ? 0 : q;
             const int p = spec.p[qi];
             const double s = S[e];
-            const double root = p == 1 ? s : (s > 0.0 ? exp(log(s) / (double)p) : 0.0);
+            double root = p == 1 ? s : (s > 0.0 ? exp(log(s) / (double)p) : 0.0);
+            if (spec.r1 && q != MT_PSTAR_NONE && q > 0) {
+                const double s2 = S2[e];
+                if (s2 > 0.0) root = exp(log(s / s2) / (double)(p - spec.p[q - 1]));
+            }
             double v = ri * (c ? c[bi * n + j] : 1.0) * root * spec.corr[qi];
             if (spec.mode == EPI_APSP_X || spec.clamp) v = fmin(v, 1.0);
             if (spec.mode == EPI_APSP_X && i == j) v = 1.0;
@@ -380,18 +388,19 @@ hipError_t launch_apsp_to_dist(const void* X, int x_f64, int64_t n, double s, vo
     return hipGetLastError();
 }
 
-hipError_t launch_select_root_f64(const double* S, const uint8_t* code, int64_t b, int64_t m,
-                                  int64_t n, const double* r, const double* c, const RootSpec& spec,
-                                  void* out, int out_f64, uint8_t* pstar_out, hipStream_t st) {
+hipError_t launch_select_root_f64(const double* S, const double* S2, const uint8_t* code, int64_t b,
+                                  int64_t m, int64_t n, const double* r, const double* c,
+                                  const RootSpec& spec, void* out, int out_f64, uint8_t* pstar_out,
+                                  hipStream_t st) {
     const int64_t rows = b * m;
     if (rows <= 0 || n <= 0) return hipSuccess;
     const dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)(rows < 65535 ? rows : 65535));
     timing_before("mt_select_root_f64", st);
     if (out_f64)
-        hipLaunchKernelGGL(mt_select_root_f64_kernel<double>, grid, dim3(kThreads), 0, st, S, code,
+        hipLaunchKernelGGL(mt_select_root_f64_kernel<double>, grid, dim3(kThreads), 0, st, S, S2, code,
                            rows, m, n, r, c, spec, (double*)out, pstar_out);
     else
-        hipLaunchKernelGGL(mt_select_root_f64_kernel<float>, grid, dim3(kThreads), 0, st, S, code,
+        hipLaunchKernelGGL(mt_select_root_f64_kernel<float>, grid, dim3(kThreads), 0, st, S, S2, code,
                            rows, m, n, r, c, spec, (float*)out, pstar_out);
     timing_after(st);
     return hipGetLastError();

@@ -35,6 +35,7 @@
 //            bytes of three separate products.
 // Either swizzle puts the MFMA operand reads (16 rows x one chunk per LDS
 // read phase) on distinct banks.
+#include <atomic>
 #include <cfloat>
 #include <cmath>
 
@@ -94,7 +95,7 @@ struct TileCtx {
 };
 
 // ------------------------------------------------------------ selection epilogue
-template <class C, int MODE, typename TO>
+template <class C, int MODE, typename TO, bool R1>
 struct SelectEpi {
     static constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
     static constexpr int NDEC = (WT_M * WT_N * 16 + 31) / 32;
@@ -106,6 +107,9 @@ struct SelectEpi {
     EpiArgs a;
     int64_t m, n;
     uint32_t decided[NDEC];
+    // r = 1 projection: entries whose p* was found at the previous p and
+    // whose S_{p*} is parked in `out` until S at this (next smaller) p is known
+    uint32_t pending[NDEC];
     float* rs;
     float* cs;
     int lr0, lc0;
@@ -156,7 +160,7 @@ struct SelectEpi {
         // Entries outside the matrix count as decided from the start, so a
         // tile whose every entry is decided can be skipped as a whole.
 #pragma unroll
-        for (int i = 0; i < NDEC; ++i) decided[i] = 0u;
+        for (int i = 0; i < NDEC; ++i) decided[i] = pending[i] = 0u;
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
@@ -181,6 +185,12 @@ struct SelectEpi {
         // S >= tau in FP64 is S >= tau_f in FP32 (tau_f: tau rounded up to FP32)
         const float tau_f = plan.tau_f;
         const uint8_t pcode = (uint8_t)plan.e[e].pidx;
+        // r = 1 projection: an entry stable here, with a smaller p still to
+        // come, parks S_{p*} in `out` and is finished at that p with
+        // (S_{p*} / S_{p_lo})^(1/(p* - p_lo)) (Sec. 1, one projected value)
+        const bool defer = R1 && plan.e[e].inv_dp > 0.f;
+        const float prev_inv_dp = e > 0 ? plan.e[e - 1].inv_dp : 0.f;
+        const float prev_inv_p = e > 0 ? plan.e[e - 1].inv_p : 1.f;
         TO* out = (TO*)a.out + out_lane;
         uint8_t* ps = a.pstar ? a.pstar + out_lane : nullptr;
         const int lane = t.lane;
@@ -190,6 +200,7 @@ struct SelectEpi {
             for (int j = 0; j < WT_N; ++j) {
                 const int tix = i * WT_N + j;
                 uint32_t dec = decided[tix >> 1];
+                uint32_t pnd = pending[tix >> 1];
                 const int sh = (tix & 1) * 16;
                 if (__all(((dec >> sh) & 0xFFFFu) == 0xFFFFu)) continue;  // every entry decided
 #pragma unroll
@@ -203,17 +214,46 @@ struct SelectEpi {
                     const float S = stg[(2 * q + (lane >> 5)) * 33 + (lane & 31)];
                     const bool stable = S >= tau_f;
                     const uint32_t mask = 1u << (sh + q);
-                    if (!(dec & mask) && (stable || last)) {
+                    const int64_t o = (int64_t)roff * n + j * 32;
+                    if constexpr (!R1) {
+                        if (!(dec & mask) && (stable || last)) {
+                            dec |= mask;
+                            float v = rs[lr0 + roff] * cj * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
+                            if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
+                            if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) v = 1.f;
+                            out[o] = (TO)v;
+                            if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                        }
+                        continue;
+                    }
+                    float v;
+                    bool finish = false;
+                    if (pnd & mask) {
+                        // S here is the ring result at p_lo of an entry parked at p*
+                        const float Sh = (float)out[o];
+                        v = S > 0.f ? root_f32(Sh / S, prev_inv_dp) : root_f32(Sh, prev_inv_p);
+                        pnd &= ~mask;
+                        finish = true;
+                    } else if (!(dec & mask) && (stable || last)) {
+                        if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                        if (stable && defer) {
+                            out[o] = (TO)S;
+                            pnd |= mask;
+                        } else {
+                            v = (p_is_1 ? S : root_f32(S, inv_p)) * corr;
+                            finish = true;
+                        }
+                    }
+                    if (finish) {
                         dec |= mask;
-                        float v = rs[lr0 + roff] * cj * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
+                        v *= rs[lr0 + roff] * cj;
                         if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
                         if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) v = 1.f;
-                        const int64_t o = (int64_t)roff * n + j * 32;
                         out[o] = (TO)v;
-                        if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
                     }
                 }
                 decided[tix >> 1] = dec;
+                pending[tix >> 1] = pnd;
                 __builtin_amdgcn_wave_barrier();
             }
     }
@@ -589,11 +629,16 @@ hipError_t launch_gemm(const GemmGeom& g, int64_t b, const FamilyPlan& plan,
                        const typename Epi::Args& args, const char* name, hipStream_t st) {
     const int lds = C::PIPE_BYTES + Epi::LDS_BYTES;
     auto kern = mt_pfamily_gemm_bf16_kernel<C, Epi>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    // the dynamic-LDS limit is a per-device attribute of the kernel
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_set.load() & bit)) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.fetch_or(bit);
     }
     const int64_t nwg = b * (int64_t)g.tiles_m * g.tiles_n;
     timing_before(name, st);
@@ -640,7 +685,9 @@ hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int6
     const GemmGeom g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, kBf16BM, kBf16BN);
     const char* name = "mt_pfamily_gemm_bf16";
     using CF = FwdCfg;
-#define MT_SEL(MODE, TO) return launch_gemm<CF, SelectEpi<CF, MODE, TO>>(g, b, plan, epi, name, st);
+#define MT_SEL(MODE, TO)                                                                      \
+    return plan.r1 ? launch_gemm<CF, SelectEpi<CF, MODE, TO, true>>(g, b, plan, epi, name, st) \
+                   : launch_gemm<CF, SelectEpi<CF, MODE, TO, false>>(g, b, plan, epi, name, st);
     if (epi.mode == EPI_APSP_X) {
         if (epi.out_f64) MT_SEL(EPI_APSP_X, double) else MT_SEL(EPI_APSP_X, float)
     }

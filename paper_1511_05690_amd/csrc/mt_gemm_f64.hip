@@ -18,6 +18,7 @@
 // global_load_lds_dwordx4 and double buffered; 16-byte chunk index
 // XOR-swizzled with (row >> 1) & 7.  At most 256 registers per lane, so two
 // workgroups share a CU and one hides the other's barrier waits.
+#include <atomic>
 #include <cfloat>
 #include <cmath>
 
@@ -57,7 +58,7 @@ struct TileCtx {
 };
 
 // ------------------------------------------------------------ selection record
-template <class C>
+template <class C, bool R1>
 struct RecordEpi {
     static constexpr int WT = C::WT;
     static constexpr int NDEC = (WT * WT * 4 + 31) / 32;
@@ -66,6 +67,7 @@ struct RecordEpi {
     EpiArgs a;
     int64_t n;
     uint32_t decided[NDEC];
+    uint32_t pending[NDEC];  // r = 1 projection: S_{p*} recorded, S at the next smaller p still due
     int64_t out_lane;
     int32_t rows_left, cols_left;
 
@@ -87,7 +89,7 @@ struct RecordEpi {
     __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t*, int) {
         n = g.cols;
 #pragma unroll
-        for (int i = 0; i < NDEC; ++i) decided[i] = 0u;
+        for (int i = 0; i < NDEC; ++i) decided[i] = pending[i] = 0u;
         // Entry (i, j, r) of this lane: tile row wm*WT*16 + i*16 + l/16 + 4r,
         // tile column wn*WT*16 + j*16 + l%16.
         const int lr0 = t.wm * WT * 16 + (t.lane >> 4);
@@ -115,7 +117,11 @@ struct RecordEpi {
         const bool last = (e == plan.n - 1);
         const double tau = plan.tau;
         const uint8_t pcode = (uint8_t)plan.e[e].pidx;
+        // r = 1 projection: S_{p*} goes to `out`, S at the next smaller p to
+        // `out2`; the select-root pass combines them
+        const bool defer = R1 && plan.e[e].inv_dp > 0.f;
         double* out = (double*)a.out + out_lane;
+        double* out2 = a.out2 ? (double*)a.out2 + out_lane : nullptr;
         uint8_t* ps = a.pstar + out_lane;
         double* stg = (double*)stage + t.wave * 256;
 #pragma unroll
@@ -128,6 +134,7 @@ struct RecordEpi {
                 const bool col_ok = j * 16 < cols_left;
                 const int tix = i * WT + j;
                 uint32_t dec = decided[tix >> 3];
+                uint32_t pnd = pending[tix >> 3];
                 const int sh = (tix & 7) * 4;
 #pragma unroll 1
                 for (int r = 0; r < 4; ++r) {
@@ -135,14 +142,22 @@ struct RecordEpi {
                     const int roff = i * 16 + 4 * r;
                     const double S = stg[r * 64 + t.lane];
                     const bool stable = S >= tau;
-                    if (col_ok && roff < rows_left && !(dec & mask) && (stable || last)) {
+                    const int64_t o = (int64_t)roff * n + j * 16;
+                    if (R1 && (pnd & mask)) {
+                        out2[o] = S;
+                        pnd &= ~mask;
                         dec |= mask;
-                        const int64_t o = (int64_t)roff * n + j * 16;
+                    } else if (col_ok && roff < rows_left && !(dec & mask) && (stable || last)) {
                         out[o] = S;
                         ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                        if (stable && defer)
+                            pnd |= mask;
+                        else
+                            dec |= mask;
                     }
                 }
                 decided[tix >> 3] = dec;
+                pending[tix >> 3] = pnd;
                 __builtin_amdgcn_wave_barrier();
             }
     }
@@ -404,11 +419,16 @@ hipError_t launch_gemm(const GemmGeomF64& g, int64_t b, const FamilyPlan& plan,
                        const typename Epi::Args& args, const char* name, hipStream_t st) {
     const int lds = C::PIPE_BYTES + Epi::LDS_BYTES;
     auto kern = mt_pfamily_gemm_f64_kernel<C, Epi>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    // the dynamic-LDS limit is a per-device attribute of the kernel
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_set.load() & bit)) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.fetch_or(bit);
     }
     const int64_t nwg = b * (int64_t)g.tiles_m * g.tiles_n;
     timing_before(name, st);
@@ -445,8 +465,12 @@ hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b
                                    hipStream_t st) {
     const GemmGeomF64 g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, bm);
     const char* name = "mt_pfamily_gemm_f64";
-    if (bm == 128) return launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>>>(g, b, plan, epi, name, st);
-    if (bm == 64) return launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>>>(g, b, plan, epi, name, st);
+    if (bm == 128)
+        return plan.r1 ? launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, true>>(g, b, plan, epi, name, st)
+                       : launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, false>>(g, b, plan, epi, name, st);
+    if (bm == 64)
+        return plan.r1 ? launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>, true>>(g, b, plan, epi, name, st)
+                       : launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>, false>>(g, b, plan, epi, name, st);
     return hipErrorInvalidValue;
 }
 

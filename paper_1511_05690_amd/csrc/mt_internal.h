@@ -48,10 +48,12 @@ struct PlanEntry {
     int32_t b_plane[3]; // plane index per segment (B side)
     float inv_p;        // 1 / p
     float corr;         // k^(-1/p) with MT_FLAG_NORM_CORRECT, else 1
+    float inv_dp;       // 1 / (p - p_next) for the next (smaller) p of the plan, 0 if none
 };
 
 struct FamilyPlan {
     int32_t n;  // entries
+    int32_t r1; // the r = 1 projection replaces the plain root (MT_FLAG_PROJECT_R1)
     double tau;
     float tau_f;  // smallest FP32 value >= tau (exact FP32 form of S >= tau)
     PlanEntry e[MT_MAX_P];
@@ -67,6 +69,7 @@ struct EpiArgs {
     int32_t mode;
     int32_t clamp;       // EPI_PLAIN only
     void* out;           // C (b x m x n) of out dtype
+    void* out2;          // FP64 record epilogue with the r = 1 projection: S at the next smaller p
     int32_t out_f64;     // 1: out is double, 0: float
     uint8_t* pstar;      // nullable
     int32_t* hist;       // nullable: per-family-index counts (+ [MT_MAX_P] = none)
@@ -132,10 +135,12 @@ struct RootSpec {
     double corr[MT_MAX_P];
     int32_t mode;   // EpiMode
     int32_t clamp;
+    int32_t r1;     // r = 1 projection from S (at p*) and S2 (at the family's next smaller p)
 };
-hipError_t launch_select_root_f64(const double* S, const uint8_t* code, int64_t b, int64_t m,
-                                  int64_t n, const double* r, const double* c, const RootSpec& spec,
-                                  void* out, int out_f64, uint8_t* pstar_out, hipStream_t st);
+hipError_t launch_select_root_f64(const double* S, const double* S2, const uint8_t* code, int64_t b,
+                                  int64_t m, int64_t n, const double* r, const double* c,
+                                  const RootSpec& spec, void* out, int out_f64, uint8_t* pstar_out,
+                                  hipStream_t st);
 
 // Backward: p* histogram and adjoint planes.
 struct AdjPrepSpec {

@@ -21,9 +21,11 @@ BAND = {"fp64": 1e-10, "bf16_split": 1e-3, "bf16": 1.2e-2}
 TAU = {"fp64": 1e-290, "bf16": 1e-30}
 
 
-def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, max_flip_frac=0.01):
+def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, max_flip_frac=0.01,
+                     projection=None):
     """Check GPU (C, p*) against the oracle dict ``ref`` (pnorm_estimate
-    output).  Returns a dict of statistics."""
+    output, computed with the same ``projection``).  Returns a dict of
+    statistics."""
     P = np.asarray(P)
     tol = TOL[path]
     tau = TAU[path] if "tau" not in ref else ref["tau"]
@@ -60,6 +62,11 @@ def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, ma
         qg_used = np.where(qg < 0, 0, qg)[flips]
         S_at = np.take_along_axis(S, np.where(qg < 0, 0, qg)[None], 0)[0][flips]
         C_at = rc[flips] * np.power(S_at, 1.0 / P[qg_used])
+        if projection == "r1":
+            # the oracle's projection evaluated at the GPU's p*
+            idx_g = np.where(qg < 0, oracle.PSTAR_NONE, qg).astype(np.uint8)
+            root_g = oracle.pnorm._root(S, P, idx_g)[0]
+            C_at = rc[flips] * oracle.pnorm._project_r1(S, P, idx_g, root_g)[flips]
         if norm_k is not None:
             C_at = C_at / np.power(float(norm_k), 1.0 / P[qg_used])
         rel_at = np.abs(C_gpu[flips] - C_at) / np.maximum(np.abs(C_at), 1e-300)

@@ -129,3 +129,26 @@ def test_apsp_argument_errors():
 def test_timing_read_without_launches():
     mt.timing_reset()
     assert mt.timing_read("mt_") == (0.0, 0)
+
+
+def test_projection_flag_validation():
+    """MT_FLAG_PROJECT_R1: not with the norm correction; the FP64 path needs
+    one more FP64 buffer of the output's size; the backward rejects it."""
+    R1 = mt.FLAG_PROJECT_R1
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([1, 2], flags=R1 | mt.FLAG_NORM_CORRECT)
+    assert e.value.status == 1
+    m = n = 64
+    plain = _ws([1, 2, 4], path="fp64", m=m, n=n)
+    r1 = _ws([1, 2, 4], path="fp64", m=m, n=n, flags=R1)
+    assert r1 - plain == m * n * 8
+    assert _ws([1, 2, 4], path="bf16", flags=R1) == _ws([1, 2, 4], path="bf16")
+    lib = mt.load_library()
+    fake = ctypes.c_void_p(0x100000)
+    null = ctypes.c_void_p(0)
+    o = _opts([1, 2, 4], flags=R1)
+    st = lib.maxtimes_estimate_backward(fake, fake, fake, fake, fake, 0, 1, 8, 8, 8, ctypes.byref(o),
+                                        fake, fake, fake, 1 << 30, null)
+    assert st == 5 and b"projection" in lib.maxtimes_last_error()
+    with pytest.raises(ValueError):
+        mt._projection_flag("r2")
