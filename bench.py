@@ -156,11 +156,29 @@ def run_legs(mt, torch, np):
 
     c2 = config(2)
     W2 = torch.from_numpy(c2["W"]).cuda()
-    ms = time_call(lambda: mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"],
-                                   out_dtype=torch.float64), 3, torch)
     n2 = c2["W"].shape[0]
-    legs["apsp_er2048_fp64"] = {"ms": ms, "squarings": c2["T"], "P": c2["P"],
-                                "ops_per_s": c2["T"] * float(n2) ** 3 / (ms / 1e3)}
+    # exact APSP on the GPU for the error columns: T squarings of the exact
+    # (max, x) product (the library's VALU kernel) on X = exp(-s W)
+    X = torch.exp(-c2["s"] * W2.double())
+    X.fill_diagonal_(1.0)
+    for _ in range(c2["T"]):
+        X = mt.exact(X, X)
+        X.fill_diagonal_(1.0)
+    D_ex = -torch.log(X) / c2["s"]
+    fin = torch.isfinite(D_ex)
+    for proj in (None, "r1"):
+        ms = time_call(lambda: mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"],
+                                       out_dtype=torch.float64, projection=proj), 3, torch)
+        D = mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"], out_dtype=torch.float64,
+                    projection=proj)
+        err = (D - D_ex)[fin]
+        xrel = (torch.exp(-c2["s"] * D[fin]) / torch.exp(-c2["s"] * D_ex[fin]) - 1.0).abs()
+        name = "apsp_er2048_fp64" + ("_r1" if proj else "")
+        legs[name] = {"ms": ms, "squarings": c2["T"], "P": c2["P"], "projection": proj or "plain",
+                      "ops_per_s": c2["T"] * float(n2) ** 3 / (ms / 1e3),
+                      "vs_exact": {"distance_mse": float((err ** 2).mean()), "max_abs": float(err.abs().max()),
+                                   "mean": float(err.mean()), "max_rel_x": float(xrel.max()),
+                                   "reachability_equal": bool(torch.equal(torch.isfinite(D), fin))}}
 
     c4 = config(4)
     A4 = torch.from_numpy(c4["A"]).cuda()
