@@ -273,8 +273,8 @@ def main():
         gemm_ms, gemm_n = mt.timing_read(kname)
         gemm_work = mt.timing_work(kname)
         kern = {}
-        for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_pfamily_gemm", "mt_select_root",
-                   "mt_fill_zero"):
+        for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_pfamily_gemm", "mt_tail",
+                   "mt_select_root", "mt_fill_zero"):
             t, c = mt.timing_read(kn)
             if c:
                 kern[kn] = round(t / steps, 4)

@@ -214,6 +214,23 @@ mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* la
  */
 mt_status maxtimes_timing_work(const char* prefix, double* flops);
 
+/*
+ * Sparse tail.  The forward GEMMs visit the family from the largest p down
+ * and stop a tile once every entry has its p* (Sec. 1: p* is the largest
+ * stable p, so a smaller p cannot change a decided entry).  When at most
+ * `max_entries` entries of a tile are still undecided, the tile hands them
+ * to a second kernel that runs the remaining p for each of them alone (one
+ * dot product of a plane row of A'^p and of B'^p per p, FP32 accumulation on
+ * the BF16 path, FP64 on the FP64 path) and stops.  Results equal the dense
+ * path's up to the order of the FP32 / FP64 summation.  0 disables it; the
+ * default is 256.  The workspace sizes grow by 16 bytes x max_entries per
+ * output tile, so query them after changing the threshold (a workspace sized
+ * before is reported too small).  Process-wide; not synchronised with calls
+ * in flight on other threads.
+ */
+mt_status maxtimes_set_tail_threshold(int32_t max_entries);
+int32_t maxtimes_tail_threshold(void);
+
 /* Library version string. */
 const char* maxtimes_version(void);
 

@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
     "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
-    "timing_reset", "timing_read", "timing_work", "pfamily", "PSTAR_NONE", "PATHS",
+    "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold", "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
 PSTAR_NONE = 255
@@ -85,6 +85,8 @@ def load_library():
         "maxtimes_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(i64)],
         "maxtimes_timing_work": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)],
+        "maxtimes_set_tail_threshold": [ctypes.c_int32],
+        "maxtimes_tail_threshold": [],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -331,6 +333,16 @@ def timing_read(prefix):
     cnt = ctypes.c_int64(0)
     _check(load_library().maxtimes_timing_read(prefix.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def set_tail_threshold(max_entries):
+    """A forward tile with at most ``max_entries`` undecided entries hands
+    them to the sparse-tail kernel (0: never).  Process-wide."""
+    _check(load_library().maxtimes_set_tail_threshold(int(max_entries)))
+
+
+def tail_threshold():
+    return int(load_library().maxtimes_tail_threshold())
 
 
 def timing_work(prefix):

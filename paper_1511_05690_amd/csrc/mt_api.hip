@@ -5,6 +5,7 @@
 // mt_elementwise.hip, mt_gemm_bf16.hip, mt_gemm_f64.hip and mt_backward.hip.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -229,8 +230,13 @@ Geom product_geom(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
 }
 
 struct Layout {
-    size_t hdr, r, c, ap, bp, s, s2, code, x, total;
+    size_t hdr, r, c, ap, bp, s, s2, code, tail, x, total;
+    int32_t tail_max;  // sparse-tail threshold the layout was sized for (0: no tail)
 };
+
+// A tile with at most this many undecided entries hands them to the sparse
+// tail (0 disables it).  256 of a 256 x 256 BF16 tile is 0.4 %.
+std::atomic<int32_t> g_tail_max{256};
 
 // The workspace of one product (plus an APSP X buffer when x_bytes > 0).
 Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64_t b, int64_t m,
@@ -250,6 +256,12 @@ Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64
         }
         L.code = off; off += align_up((size_t)(b * m * n));
     }
+    // sparse-tail list: at most tail_max entries per tile (none if the family
+    // has a single p: nothing would be left to run)
+    L.tail_max = f.n > 1 ? g_tail_max.load() : 0;
+    const int64_t tiles = b * (g.mp / g.bm) * (g.np / g.bm);
+    L.tail = off;
+    off += align_up((size_t)tiles * (size_t)L.tail_max * sizeof(TailEntry));
     L.x = off;
     off += align_up(x_bytes);
     L.total = off;
@@ -334,6 +346,13 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     memset(&epi, 0, sizeof epi);
     epi.r = r;
     epi.c = c;
+    if (L.tail_max > 0 && k > 0) {
+        WsHeader* hdr = (WsHeader*)(ws + L.hdr);
+        MT_TRY(launch_fill_zero_u32(&hdr->tail_count, 1, st), "clear tail count");
+        epi.tail = (TailEntry*)(ws + L.tail);
+        epi.tail_count = &hdr->tail_count;
+        epi.tail_max = L.tail_max;
+    }
     if (f.bf16) {
         epi.mode = mode;
         epi.clamp = clamp;
@@ -645,6 +664,16 @@ mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b
     MT_TRY(launch_exact_maxtimes(A, B, dtype == MT_F64, b, m, k, n, E, (hipStream_t)stream), "exact product");
     return MT_OK;
 }
+
+mt_status maxtimes_set_tail_threshold(int32_t max_entries) {
+    g_last_error.clear();
+    if (max_entries < 0 || max_entries > 65536)
+        return fail(MT_ERR_INVALID_ARG, "tail threshold %d outside 0..65536", max_entries);
+    g_tail_max.store(max_entries);
+    return MT_OK;
+}
+
+int32_t maxtimes_tail_threshold(void) { return g_tail_max.load(); }
 
 mt_status maxtimes_timing_enable(int on) {
     std::lock_guard<std::mutex> lk(g_tmu);

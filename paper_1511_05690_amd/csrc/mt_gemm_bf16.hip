@@ -120,16 +120,41 @@ struct SelectEpi {
     static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
 
-    // Every entry of this wave has its p (wave-uniform).
-    __device__ bool all_decided() const {
+    // Entries of this lane without their final output yet.
+    __device__ int undecided() const {
         constexpr int TOT = WT_M * WT_N * 16;
-        bool ok = true;
+        int c = 0;
 #pragma unroll
         for (int i = 0; i < NDEC; ++i) {
             const uint32_t full = (TOT - 32 * i >= 32) ? 0xFFFFFFFFu : ((1u << (TOT - 32 * i)) - 1u);
-            ok = ok && decided[i] == full;
+            c += __builtin_popcount(~decided[i] & full);
         }
-        return __all(ok);
+        return c;
+    }
+    __device__ bool can_hand_over(int total) const { return a.tail != nullptr && total <= a.tail_max; }
+    __device__ uint32_t* tail_counter() const { return a.tail_count; }
+    // Write this lane's undecided entries to the sparse-tail list from `pos` on.
+    __device__ void hand_over(uint32_t pos, int e_next, const TileCtx& t) const {
+#pragma unroll
+        for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) {
+                const int tix = i * WT_N + j;
+                const int sh = (tix & 1) * 16;
+                const uint32_t dec = decided[tix >> 1] >> sh;
+                const uint32_t pnd = pending[tix >> 1] >> sh;
+#pragma unroll 1
+                for (int q = 0; q < 16; ++q) {
+                    if ((dec >> q) & 1u) continue;
+                    TailEntry te;
+                    te.bi = t.bi;
+                    te.i = (int32_t)(t.row0 + lr0 + i * 32 + 2 * q);
+                    te.j = (int32_t)(t.col0 + lc0 + j * 32);
+                    te.e_next = (int16_t)e_next;
+                    te.pending = (int16_t)((pnd >> q) & 1u);
+                    a.tail[pos++] = te;
+                }
+            }
     }
 
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
@@ -283,7 +308,10 @@ struct AdjointEpi {
     static constexpr bool kAllActive = false;
     static constexpr bool kCanStop = false;
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
-    __device__ bool all_decided() const { return false; }
+    __device__ int undecided() const { return 0; }
+    __device__ bool can_hand_over(int) const { return false; }
+    __device__ uint32_t* tail_counter() const { return nullptr; }
+    __device__ void hand_over(uint32_t, int, const TileCtx&) const {}
 
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
         rows = g.rows;
@@ -377,7 +405,8 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
     extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
     __shared__ int s_act[MT_MAX_P + 1];
-    __shared__ int s_done[2][C::NW];  // per wave: all entries decided (entry parity)
+    __shared__ int s_done[2][C::NW];  // per wave: undecided entries (entry parity)
+    __shared__ uint32_t s_tail_base;
 
     const int tid = threadIdx.x;
     TileCtx t;
@@ -605,23 +634,143 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
         // the buffer the last step read is free until the next step's loads,
         // which wait for the barrier below
         epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
+        int lane_pre = 0;
         if (Epi::kCanStop) {
-            const bool wd = epi.all_decided();
-            if (lane == 0) s_done[ai & 1][wave] = wd ? 1 : 0;
+            // undecided entries per lane -> exclusive prefix in the wave
+            const int cnt = epi.undecided();
+            int incl = cnt;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(incl, d);
+                if (lane >= d) incl += y;
+            }
+            lane_pre = incl - cnt;
+            const int wtot = __shfl(incl, 63);
+            if (lane == 0) s_done[ai & 1][wave] = wtot;
         }
         __syncthreads();
         if (Epi::kCanStop) {
+            int total = 0, wave_pre = 0;
+#pragma unroll
+            for (int w = 0; w < C::NW; ++w) {
+                const int x = s_done[ai & 1][w];
+                total += x;
+                wave_pre += w < wave ? x : 0;
+            }
+            total = __builtin_amdgcn_readfirstlane(total);
             // Every entry of the tile has its p: the remaining (smaller) p
             // cannot change the output.  The loads already issued for the
             // next entry have landed (vmcnt(0) above) and are simply unused.
-            int all = 1;
-#pragma unroll
-            for (int w = 0; w < C::NW; ++w) all &= s_done[ai & 1][w];
-            if (__builtin_amdgcn_readfirstlane(all)) break;
+            if (total == 0) break;
+            // Only a few are left: hand them to the sparse tail, which runs
+            // the remaining p for them alone, and stop the tile.
+            if (ai + 1 < nact && epi.can_hand_over(total)) {
+                if (tid == 0) s_tail_base = atomicAdd(epi.tail_counter(), (uint32_t)total);
+                __syncthreads();
+                epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), entry_of(ai) + 1, t);
+                break;
+            }
         }
     }
     epi.finish(t);
     if (g.work && tid == 0) atomicAdd(g.work, (unsigned long long)kunits * (2ull * C::BM * C::BN));
+}
+
+// ------------------------------------------------------------ the sparse tail
+// One wave per handed-over entry (TailEntry): for the plan entries from
+// e_next on it forms S_p = sum_k A'_ik^p B'_kj^p as a dot product of the
+// entry's X and Y plane rows (split p: hi.hi + hi.lo + lo.hi, FP32
+// accumulation, the same BF16 operands the GEMM reads) and applies the same
+// selection as the GEMM epilogue.  The list length is read on the device;
+// the grid is a fixed set of waves that stride over it.
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+template <int MODE, typename TO, bool R1>
+__global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPlan plan, EpiArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t count = __builtin_amdgcn_readfirstlane(*a.tail_count);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    TO* out = (TO*)a.out;
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < (int64_t)count;
+         w += waves) {
+        const TailEntry te = a.tail[w];
+        const int64_t o = ((int64_t)te.bi * g.rows + te.i) * g.cols + te.j;
+        const uint16_t* xr = g.X + (int64_t)te.bi * g.x_batch_elems + (int64_t)te.i * g.kp;
+        const uint16_t* yr = g.Y + (int64_t)te.bi * g.y_batch_elems + (int64_t)te.j * g.kp;
+        const float rc = (a.r ? (float)a.r[(int64_t)te.bi * g.rows + te.i] : 1.f) *
+                         (a.c ? (float)a.c[(int64_t)te.bi * g.cols + te.j] : 1.f);
+        bool pend = R1 && te.pending != 0;
+        float Sh = pend ? (float)out[o] : 0.f;
+        for (int e = te.e_next; e < plan.n; ++e) {
+            const PlanEntry& pe = plan.e[e];
+            float acc = 0.f;
+            if (pe.nseg == 3) {
+                const uint16_t* xh = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
+                const uint16_t* xl = xr + (int64_t)pe.a_plane[2] * g.x_plane_elems;
+                const uint16_t* yh = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
+                const uint16_t* yl = yr + (int64_t)pe.b_plane[1] * g.y_plane_elems;
+                for (int64_t k0 = lane * 8; k0 < g.kp; k0 += 512) {
+                    const u32x4 vxh = *(const u32x4*)(xh + k0), vxl = *(const u32x4*)(xl + k0);
+                    const u32x4 vyh = *(const u32x4*)(yh + k0), vyl = *(const u32x4*)(yl + k0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc += bf16_lo(vxh[q]) * bf16_lo(vyh[q]);
+                        acc += bf16_lo(vxh[q]) * bf16_lo(vyl[q]);
+                        acc += bf16_lo(vxl[q]) * bf16_lo(vyh[q]);
+                        acc += bf16_hi(vxh[q]) * bf16_hi(vyh[q]);
+                        acc += bf16_hi(vxh[q]) * bf16_hi(vyl[q]);
+                        acc += bf16_hi(vxl[q]) * bf16_hi(vyh[q]);
+                    }
+                }
+            } else {
+                const uint16_t* xp = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
+                const uint16_t* yp = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
+                for (int64_t k0 = lane * 8; k0 < g.kp; k0 += 512) {
+                    const u32x4 vx = *(const u32x4*)(xp + k0), vy = *(const u32x4*)(yp + k0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc += bf16_lo(vx[q]) * bf16_lo(vy[q]);
+                        acc += bf16_hi(vx[q]) * bf16_hi(vy[q]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+            const float S = acc;
+            float v;
+            if (R1 && pend) {
+                v = S > 0.f ? root_f32(Sh / S, plan.e[e - 1].inv_dp) : root_f32(Sh, plan.e[e - 1].inv_p);
+            } else {
+                const bool stable = S >= plan.tau_f;
+                if (!(stable || e == plan.n - 1)) continue;
+                if (lane == 0 && a.pstar) a.pstar[o] = stable ? (uint8_t)pe.pidx : (uint8_t)MT_PSTAR_NONE;
+                if (R1 && stable && pe.inv_dp > 0.f) {
+                    Sh = S;
+                    pend = true;
+                    continue;
+                }
+                v = (pe.p == 1 ? S : root_f32(S, pe.inv_p)) * pe.corr;
+            }
+            v *= rc;
+            if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
+            if (MODE == EPI_APSP_X && te.i == te.j) v = 1.f;
+            if (lane == 0) out[o] = (TO)v;
+            break;
+        }
+    }
+}
+
+template <int MODE, typename TO, bool R1>
+hipError_t launch_tail(const GemmGeom& g, const FamilyPlan& plan, const EpiArgs& epi, int64_t cap,
+                       hipStream_t st) {
+    int64_t blocks = (cap + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    timing_before("mt_tail_bf16", st);
+    hipLaunchKernelGGL((mt_tail_bf16_kernel<MODE, TO, R1>), dim3((unsigned)blocks), dim3(256), 0, st, g, plan, epi);
+    timing_after(st);
+    return hipGetLastError();
 }
 
 template <class C, class Epi>
@@ -685,13 +834,22 @@ hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int6
     const GemmGeom g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, kBf16BM, kBf16BN);
     const char* name = "mt_pfamily_gemm_bf16";
     using CF = FwdCfg;
-#define MT_SEL(MODE, TO)                                                                      \
-    return plan.r1 ? launch_gemm<CF, SelectEpi<CF, MODE, TO, true>>(g, b, plan, epi, name, st) \
-                   : launch_gemm<CF, SelectEpi<CF, MODE, TO, false>>(g, b, plan, epi, name, st);
-    if (epi.mode == EPI_APSP_X) {
-        if (epi.out_f64) MT_SEL(EPI_APSP_X, double) else MT_SEL(EPI_APSP_X, float)
+    // the GEMM, then (when a tail list is given) the sparse tail for the
+    // entries the tiles handed over
+    const int64_t cap = (int64_t)epi.tail_max * b * g.tiles_m * g.tiles_n;
+#define MT_SEL(MODE, TO, R1)                                                                     \
+    {                                                                                            \
+        hipError_t e = launch_gemm<CF, SelectEpi<CF, MODE, TO, R1>>(g, b, plan, epi, name, st);  \
+        if (e == hipSuccess && epi.tail) e = launch_tail<MODE, TO, R1>(g, plan, epi, cap, st);   \
+        return e;                                                                                \
     }
-    if (epi.out_f64) MT_SEL(EPI_PLAIN, double) else MT_SEL(EPI_PLAIN, float)
+#define MT_SEL2(MODE, TO) \
+    if (plan.r1) MT_SEL(MODE, TO, true) else MT_SEL(MODE, TO, false)
+    if (epi.mode == EPI_APSP_X) {
+        if (epi.out_f64) MT_SEL2(EPI_APSP_X, double) else MT_SEL2(EPI_APSP_X, float)
+    }
+    if (epi.out_f64) MT_SEL2(EPI_PLAIN, double) else MT_SEL2(EPI_PLAIN, float)
+#undef MT_SEL2
 #undef MT_SEL
 }
 

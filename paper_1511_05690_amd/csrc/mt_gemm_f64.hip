@@ -68,22 +68,47 @@ struct RecordEpi {
     int64_t n;
     uint32_t decided[NDEC];
     uint32_t pending[NDEC];  // r = 1 projection: S_{p*} recorded, S at the next smaller p still due
+    int lr0, lc0;
     int64_t out_lane;
     int32_t rows_left, cols_left;
 
     static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
 
-    // Every entry of this wave has its p (wave-uniform).
-    __device__ bool all_decided() const {
+    // Entries of this lane without their final record yet.
+    __device__ int undecided() const {
         constexpr int TOT = WT * WT * 4;
-        bool ok = true;
+        int c = 0;
 #pragma unroll
         for (int i = 0; i < NDEC; ++i) {
             const uint32_t full = (TOT - 32 * i >= 32) ? 0xFFFFFFFFu : ((1u << (TOT - 32 * i)) - 1u);
-            ok = ok && decided[i] == full;
+            c += __builtin_popcount(~decided[i] & full);
         }
-        return __all(ok);
+        return c;
+    }
+    __device__ bool can_hand_over(int total) const { return a.tail != nullptr && total <= a.tail_max; }
+    __device__ uint32_t* tail_counter() const { return a.tail_count; }
+    // Write this lane's undecided entries to the sparse-tail list from `pos` on.
+    __device__ void hand_over(uint32_t pos, int e_next, const TileCtx& t) const {
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j) {
+                const int tix = i * WT + j;
+                const int sh = (tix & 7) * 4;
+#pragma unroll 1
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t mask = 1u << (sh + r);
+                    if (decided[tix >> 3] & mask) continue;
+                    TailEntry te;
+                    te.bi = t.bi;
+                    te.i = (int32_t)(t.row0 + lr0 + i * 16 + 4 * r);
+                    te.j = (int32_t)(t.col0 + lc0 + j * 16);
+                    te.e_next = (int16_t)e_next;
+                    te.pending = (pending[tix >> 3] & mask) ? 1 : 0;
+                    a.tail[pos++] = te;
+                }
+            }
     }
 
     __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t*, int) {
@@ -92,8 +117,8 @@ struct RecordEpi {
         for (int i = 0; i < NDEC; ++i) decided[i] = pending[i] = 0u;
         // Entry (i, j, r) of this lane: tile row wm*WT*16 + i*16 + l/16 + 4r,
         // tile column wn*WT*16 + j*16 + l%16.
-        const int lr0 = t.wm * WT * 16 + (t.lane >> 4);
-        const int lc0 = t.wn * WT * 16 + (t.lane & 15);
+        lr0 = t.wm * WT * 16 + (t.lane >> 4);
+        lc0 = t.wn * WT * 16 + (t.lane & 15);
         out_lane = ((int64_t)t.bi * g.rows + t.row0 + lr0) * n + t.col0 + lc0;
         rows_left = (int32_t)min<int64_t>(g.rows - (t.row0 + lr0), 1 << 30);
         cols_left = (int32_t)min<int64_t>(n - (t.col0 + lc0), 1 << 30);
@@ -182,7 +207,10 @@ struct AdjointEpiF64 {
     int32_t rows_left, cols_left;
 
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
-    __device__ bool all_decided() const { return false; }
+    __device__ int undecided() const { return 0; }
+    __device__ bool can_hand_over(int) const { return false; }
+    __device__ uint32_t* tail_counter() const { return nullptr; }
+    __device__ void hand_over(uint32_t, int, const TileCtx&) const {}
 
     __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t* lds, int tid) {
         rows = g.rows;
@@ -270,7 +298,8 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
     constexpr int WT = C::WT;
     extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
     __shared__ int s_act[MT_MAX_P + 1];
-    __shared__ int s_done[2][4];  // per wave: all entries decided (entry parity)
+    __shared__ int s_done[2][4];  // per wave: undecided entries (entry parity)
+    __shared__ uint32_t s_tail_base;
 
     const int tid = threadIdx.x;
     TileCtx t;
@@ -397,21 +426,94 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
         // the buffer the last step read is free until the next step's loads,
         // which wait for the barrier below
         epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
+        int lane_pre = 0;
         if (Epi::kCanStop) {
-            const bool wd = epi.all_decided();
-            if (lane == 0) s_done[ai & 1][wave] = wd ? 1 : 0;
+            const int cnt = epi.undecided();
+            int incl = cnt;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(incl, d);
+                if (lane >= d) incl += y;
+            }
+            lane_pre = incl - cnt;
+            const int wtot = __shfl(incl, 63);
+            if (lane == 0) s_done[ai & 1][wave] = wtot;
         }
         __syncthreads();
         if (Epi::kCanStop) {
+            int total = 0, wave_pre = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int x = s_done[ai & 1][w];
+                total += x;
+                wave_pre += w < wave ? x : 0;
+            }
+            total = __builtin_amdgcn_readfirstlane(total);
             // every entry has its p; the next entry's loads have landed
             // (vmcnt(0) above) and are left unused
-            const int all = s_done[ai & 1][0] & s_done[ai & 1][1] & s_done[ai & 1][2] & s_done[ai & 1][3];
-            if (__builtin_amdgcn_readfirstlane(all)) break;
+            if (total == 0) break;
+            // a few left: the sparse tail finishes them
+            if (ai + 1 < nact && epi.can_hand_over(total)) {
+                if (tid == 0) s_tail_base = atomicAdd(epi.tail_counter(), (uint32_t)total);
+                __syncthreads();
+                epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), e + 1, t);
+                break;
+            }
         }
     }
     epi.finish(t);
     if (g.work && tid == 0)
         atomicAdd(g.work, (unsigned long long)steps_done * (2ull * C::BM * C::BM * 16));
+}
+
+// ------------------------------------------------------------ the sparse tail
+// One wave per handed-over entry: S_p as an FP64 dot product of the entry's
+// X and Y plane rows for the plan entries from e_next on, recorded exactly
+// as the record epilogue does (S, p* index; with the r = 1 projection S at
+// the next smaller p in out2) for the select-root pass.
+template <bool R1>
+__global__ __launch_bounds__(256) void mt_tail_f64_kernel(GemmGeomF64 g, FamilyPlan plan, EpiArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t count = __builtin_amdgcn_readfirstlane(*a.tail_count);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    double* out = (double*)a.out;
+    double* out2 = (double*)a.out2;
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < (int64_t)count;
+         w += waves) {
+        const TailEntry te = a.tail[w];
+        const int64_t o = ((int64_t)te.bi * g.rows + te.i) * g.cols + te.j;
+        const double* xr = g.X + (int64_t)te.bi * g.x_batch_elems + (int64_t)te.i * g.kp;
+        const double* yr = g.Y + (int64_t)te.bi * g.y_batch_elems + (int64_t)te.j * g.kp;
+        bool pend = R1 && te.pending != 0;
+        for (int e = te.e_next; e < plan.n; ++e) {
+            const PlanEntry& pe = plan.e[e];
+            const double* xp = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
+            const double* yp = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
+            double acc = 0.0;
+            for (int64_t k0 = lane * 2; k0 < g.kp; k0 += 128) {
+                const double2 vx = *(const double2*)(xp + k0), vy = *(const double2*)(yp + k0);
+                acc = fma(vx.x, vy.x, acc);
+                acc = fma(vx.y, vy.y, acc);
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+            if (R1 && pend) {
+                if (lane == 0) out2[o] = acc;
+                break;
+            }
+            const bool stable = acc >= plan.tau;
+            if (!(stable || e == plan.n - 1)) continue;
+            if (lane == 0) {
+                out[o] = acc;
+                a.pstar[o] = stable ? (uint8_t)pe.pidx : (uint8_t)MT_PSTAR_NONE;
+            }
+            if (R1 && stable && pe.inv_dp > 0.f) {
+                pend = true;
+                continue;
+            }
+            break;
+        }
+    }
 }
 
 template <class C, class Epi>
@@ -465,13 +567,26 @@ hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b
                                    hipStream_t st) {
     const GemmGeomF64 g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, bm);
     const char* name = "mt_pfamily_gemm_f64";
+    hipError_t e = hipErrorInvalidValue;
     if (bm == 128)
-        return plan.r1 ? launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, true>>(g, b, plan, epi, name, st)
-                       : launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, false>>(g, b, plan, epi, name, st);
-    if (bm == 64)
-        return plan.r1 ? launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>, true>>(g, b, plan, epi, name, st)
-                       : launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>, false>>(g, b, plan, epi, name, st);
-    return hipErrorInvalidValue;
+        e = plan.r1 ? launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, true>>(g, b, plan, epi, name, st)
+                    : launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, false>>(g, b, plan, epi, name, st);
+    else if (bm == 64)
+        e = plan.r1 ? launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>, true>>(g, b, plan, epi, name, st)
+                    : launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>, false>>(g, b, plan, epi, name, st);
+    if (e != hipSuccess || !epi.tail) return e;
+    // the sparse tail for the entries the tiles handed over
+    const int64_t cap = (int64_t)epi.tail_max * b * g.tiles_m * g.tiles_n;
+    int64_t blocks = (cap + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    timing_before("mt_tail_f64", st);
+    if (plan.r1)
+        hipLaunchKernelGGL(mt_tail_f64_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, g, plan, epi);
+    else
+        hipLaunchKernelGGL(mt_tail_f64_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, g, plan, epi);
+    timing_after(st);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_gemm_f64(const double* Xp, const double* Yp, int64_t b, int64_t rows,

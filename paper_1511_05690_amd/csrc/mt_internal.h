@@ -30,11 +30,21 @@ constexpr int kF64BK = 16;
 constexpr int kAdjBM = 128;
 constexpr int kAdjF64BM = 64;
 
-// Workspace header: domain flag word and p* histogram.
+// Workspace header: domain flag word, sparse-tail length and p* histogram.
 struct WsHeader {
     int32_t domain_flag;
-    int32_t pad[7];
+    uint32_t tail_count;
+    int32_t pad[6];
     int32_t hist[MT_MAX_P + 1];
+};
+
+// Sparse tail: an output entry a GEMM tile handed over because only a few of
+// its entries were still undecided; the tail kernel runs the remaining p of
+// the plan for it alone (one dot product per p).
+struct TailEntry {
+    int32_t bi, i, j;  // batch item, row, column
+    int16_t e_next;    // first plan entry still to run
+    int16_t pending;   // r = 1 projection: S at p* parked in the output, finish at e_next
 };
 
 // Processing plan of the p family for one fused GEMM launch.  Entries are in
@@ -75,6 +85,9 @@ struct EpiArgs {
     int32_t* hist;       // nullable: per-family-index counts (+ [MT_MAX_P] = none)
     const double* r;     // b x m (nullable: all ones)
     const double* c;     // b x n (nullable: all ones)
+    TailEntry* tail;     // nullable: sparse-tail list (capacity tail_max per tile)
+    uint32_t* tail_count;
+    int32_t tail_max;    // a tile with 1..tail_max undecided entries hands them over
 };
 
 // Adjoint epilogue: out = sum over the p that some entry uses of
