@@ -54,6 +54,20 @@ __global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict
     double mx = 0.0;
     bool bad = false;
     int64_t j = lane;
+    constexpr int V = 16 / sizeof(T);
+    if (k % V == 0) {
+        // 16-byte loads: lane l reads elements V*l .. V*l+V-1 of each chunk
+        typedef T vecT __attribute__((ext_vector_type(V)));
+        for (int64_t j0 = (int64_t)lane * V; j0 < k; j0 += 64 * V) {
+            const vecT v = *(const vecT*)(a + j0);
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                bad |= bad_value(v[q]);
+                mx = fmax(mx, (double)v[q]);
+            }
+        }
+        j = k;
+    }
     for (; j + 192 < k; j += 256) {
         T v0 = a[j], v1 = a[j + 64], v2 = a[j + 128], v3 = a[j + 192];
         bad |= bad_value(v0) | bad_value(v1) | bad_value(v2) | bad_value(v3);
@@ -69,28 +83,50 @@ __global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict
     if (bad) atomicOr(flag, 1);
 }
 
-// c[b, j] = max_k B[b, k, j]: lanes across j (coalesced), 64 rows per block,
-// combined with an integer atomic max on the bit pattern (exact for >= 0).
+// c[b, j] = max_k B[b, k, j]: each thread owns kColVec consecutive columns
+// (one 16-byte load per row when n allows it), 64 rows per block, combined
+// with an integer atomic max on the bit pattern (exact for >= 0).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void mt_colmax_kernel(const T* __restrict__ B, int64_t k,
                                                              int64_t n, double* __restrict__ c,
                                                              int32_t* __restrict__ flag) {
-    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    constexpr int V = 16 / sizeof(T);
+    const int64_t j0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * V;
     const int64_t k0 = (int64_t)blockIdx.y * 64;
     const int64_t bi = blockIdx.z;
-    if (j >= n) return;
-    const T* bb = B + bi * k * n + j;
-    double mx = 0.0;
+    if (j0 >= n) return;
+    const T* bb = B + bi * k * n + j0;
+    double mx[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) mx[q] = 0.0;
     bool bad = false;
     const int64_t k1 = k0 + 64 < k ? k0 + 64 : k;
-    for (int64_t kk = k0; kk < k1; ++kk) {
-        T v = bb[kk * n];
-        bad |= bad_value(v);
-        mx = fmax(mx, (double)v);
+    if (j0 + V <= n && (n % V) == 0) {
+        typedef T vecT __attribute__((ext_vector_type(V)));
+#pragma unroll 8
+        for (int64_t kk = k0; kk < k1; ++kk) {
+            const vecT v = *(const vecT*)(bb + kk * n);
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                bad |= bad_value(v[q]);
+                mx[q] = fmax(mx[q], (double)v[q]);
+            }
+        }
+    } else {
+        for (int64_t kk = k0; kk < k1; ++kk)
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                if (j0 + q < n) {
+                    const T v = bb[kk * n + q];
+                    bad |= bad_value(v);
+                    mx[q] = fmax(mx[q], (double)v);
+                }
     }
     if (bad) atomicOr(flag, 1);
-    if (mx > 0.0 || mx != mx)
-        atomicMax((unsigned long long*)(c + bi * n + j), (unsigned long long)__double_as_longlong(mx));
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+        if (j0 + q < n && (mx[q] > 0.0 || mx[q] != mx[q]))
+            atomicMax((unsigned long long*)(c + bi * n + j0 + q), (unsigned long long)__double_as_longlong(mx[q]));
 }
 
 template <typename T>
@@ -144,16 +180,39 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
         double sc = 1.0;
         if (scale_rows != nullptr && t < rows) sc = scale_rows[bi * rows + t];
         const bool zero_row = (t >= rows) || (sc == 0.0);
+        if (scale_cols == nullptr && !zero_row && u + 8 <= cols && (kTranspose || (cols & 3) == 0)) {
+            // whole chunk inside the row and (untransposed) 16-byte aligned:
+            // vector loads and one reciprocal per row instead of 8 divisions
+            // (the scaled value may differ from src / scale by one FP64 ulp)
+            TS v[8];
+            if (kTranspose) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            double v = 0.0;
-            if (!zero_row && u + i < cols) {
-                v = kTranspose ? (double)tile[tt][ch * 8 + i] : (double)s[t * cols + u + i];
-                double d = sc;
-                if (scale_cols != nullptr) d *= scale_cols[bi * cols + u + i];
-                v = d > 0.0 ? v / d : 0.0;
+                for (int i = 0; i < 8; ++i) v[i] = tile[tt][ch * 8 + i];
+            } else {
+                typedef TS vec4 __attribute__((ext_vector_type(4)));
+                const vec4 a0 = *(const vec4*)(s + t * cols + u);
+                const vec4 a1 = *(const vec4*)(s + t * cols + u + 4);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = a0[i];
+                    v[4 + i] = a1[i];
+                }
             }
-            x[i] = (TC)v;
+            const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = (TC)((double)v[i] * inv);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                double v = 0.0;
+                if (!zero_row && u + i < cols) {
+                    v = kTranspose ? (double)tile[tt][ch * 8 + i] : (double)s[t * cols + u + i];
+                    double d = sc;
+                    if (scale_cols != nullptr) d *= scale_cols[bi * cols + u + i];
+                    v = d > 0.0 ? v / d : 0.0;
+                }
+                x[i] = (TC)v;
+            }
         }
         TC pw[8];
         int prev = 0;
@@ -309,7 +368,8 @@ hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n
                          int32_t* flag, hipStream_t st) {
     hipError_t e = launch_fill_zero_u32(c, b * n * 2, st);
     if (e != hipSuccess || k <= 0) return e;
-    const dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)((k + 63) / 64), (unsigned)b);
+    const int64_t per_block = (int64_t)kThreads * (f64 ? 2 : 4);  // columns per block
+    const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)((k + 63) / 64), (unsigned)b);
     timing_before("mt_colmax", st);
     if (f64)
         hipLaunchKernelGGL(mt_colmax_kernel<double>, grid, dim3(kThreads), 0, st, (const double*)B,
