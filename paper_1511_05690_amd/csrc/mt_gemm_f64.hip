@@ -418,6 +418,7 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
                     for (int j = 0; j < WT; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
             }
+
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
             buf ^= 1;
