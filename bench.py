@@ -274,7 +274,7 @@ def main():
         gemm_work = mt.timing_work(kname)
         kern = {}
         for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_pfamily_gemm", "mt_tail",
-                   "mt_select_root", "mt_fill_zero"):
+                   "mt_select_root", "mt_fill"):
             t, c = mt.timing_read(kn)
             if c:
                 kern[kn] = round(t / steps, 4)

@@ -126,7 +126,9 @@ mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
  *   p_star b x m x n uint8 (output, nullable): index into p_family of the p
  *          used per entry, MT_PSTAR_NONE if none was stable.
  * b, m, k, n >= 0: an empty C is a no-op; k = 0 gives C = 0 and p_star =
- * MT_PSTAR_NONE.  Sizes above 2^24 return MT_ERR_UNSUPPORTED.
+ * MT_PSTAR_NONE.  Sizes above 2^24 return MT_ERR_UNSUPPORTED, and so does
+ * k above 2^23 on the BF16 path (m or n above 2^23 for its backward, n for
+ * its APSP).
  * FP32 inputs are converted exactly on load for the FP64 path.
  */
 mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype,
@@ -230,6 +232,23 @@ mt_status maxtimes_timing_work(const char* prefix, double* flops);
  */
 mt_status maxtimes_set_tail_threshold(int32_t max_entries);
 int32_t maxtimes_tail_threshold(void);
+
+/*
+ * Where the forward p search starts (Sec. 1 defines p* as the largest stable
+ * p; the search order only decides how much work finds it).  0, the default,
+ * visits the family from the largest p down.  entry = s > 0 starts at the
+ * s-th largest p (clamped to the smallest): going down from there decides
+ * every entry that is not stable at the start; an entry stable at the start
+ * waits unless its S rules out every larger p (S_p' <= S_p^(p'/p) for terms
+ * in [0, 1]), and after the smallest p the search goes up from the (s-1)-th
+ * largest p until each waiting entry meets an unstable p or such an S.
+ * Results equal those of the top-down search up to entries whose S lies
+ * within rounding of tau.  The r = 1 projection always searches from the
+ * largest p.  Returns MT_ERR_INVALID_ARG outside 0 .. MT_MAX_P - 1.
+ * Process-wide; not synchronised with calls in flight on other threads.
+ */
+mt_status maxtimes_set_search_start(int32_t entry);
+int32_t maxtimes_search_start(void);
 
 /* Library version string. */
 const char* maxtimes_version(void);

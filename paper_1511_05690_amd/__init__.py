@@ -21,7 +21,8 @@ import torch
 __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
     "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
-    "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold", "pfamily", "PSTAR_NONE", "PATHS",
+    "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold",
+    "set_search_start", "search_start", "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
 PSTAR_NONE = 255
@@ -87,6 +88,8 @@ def load_library():
         "maxtimes_timing_work": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)],
         "maxtimes_set_tail_threshold": [ctypes.c_int32],
         "maxtimes_tail_threshold": [],
+        "maxtimes_set_search_start": [ctypes.c_int32],
+        "maxtimes_search_start": [],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -343,6 +346,18 @@ def set_tail_threshold(max_entries):
 
 def tail_threshold():
     return int(load_library().maxtimes_tail_threshold())
+
+
+def set_search_start(entry):
+    """Start the forward p search at the ``entry``-th largest p (0: the
+    largest, the default), go down to the smallest p, then up for the entries
+    still stable at the start.  Same p* as the top-down search up to entries
+    whose S lies within rounding of tau.  Process-wide."""
+    _check(load_library().maxtimes_set_search_start(int(entry)))
+
+
+def search_start():
+    return int(load_library().maxtimes_search_start())
 
 
 def timing_work(prefix):

@@ -176,6 +176,20 @@ FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
         pe.inv_p = 1.0f / (float)f.p[q];
         pe.inv_dp = q > 0 ? 1.0f / (float)(f.p[q] - f.p[q - 1]) : 0.0f;
         pe.corr = (f.flags & MT_FLAG_NORM_CORRECT) && k > 0 ? (float)std::pow((double)k, -1.0 / f.p[q]) : 1.0f;
+        // For terms in [0, 1] and a larger p' > p, S_p' <= S_p^(p'/p).  Below
+        // rise_thr no larger p can be stable: the factor 2 under the power
+        // covers the rounding of S_p', the factor 0.9 that of S_p (relative
+        // errors of a few 2^-8 on the BF16 path, plus terms lost to underflow,
+        // each below 2^-126 and together far below tau).
+        if (e == 0) {
+            pe.rise_thr = INFINITY;
+            pe.rise_thr_f = INFINITY;
+        } else {
+            pe.rise_thr = 0.9 * std::pow(f.tau / 2.0, (double)f.p[q] / (double)f.p[q + 1]);
+            float tf = (float)pe.rise_thr;
+            if ((double)tf > pe.rise_thr) tf = nextafterf(tf, 0.0f);
+            pe.rise_thr_f = tf;
+        }
         const int hi = ps.first_plane[q];
         if (ps.split[q]) {
             pe.nseg = 3;
@@ -237,6 +251,7 @@ struct Layout {
 // A tile with at most this many undecided entries hands them to the sparse
 // tail (0 disables it).  256 of a 256 x 256 BF16 tile is 0.4 %.
 std::atomic<int32_t> g_tail_max{256};
+std::atomic<int32_t> g_start_entry{0};
 
 // The workspace of one product (plus an APSP X buffer when x_bytes > 0).
 Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64_t b, int64_t m,
@@ -275,6 +290,15 @@ mt_status check_dims(int64_t b, int64_t m, int64_t k, int64_t n) {
     const int64_t lim = (int64_t)1 << 24;
     if (m > lim || n > lim || k > lim || b > lim)
         return fail(MT_ERR_UNSUPPORTED, "a size exceeds 2^24");
+    return MT_OK;
+}
+
+// The BF16 GEMM addresses a 256-row block of a plane with 32-bit byte
+// offsets: the inner (contracted) dimension stays at or below 2^23.
+mt_status check_bf16_inner(const Family& f, int64_t inner) {
+    if (f.bf16 && inner > ((int64_t)1 << 23))
+        return fail(MT_ERR_UNSUPPORTED, "the BF16 path contracts at most 2^23 terms per entry (got %lld)",
+                    (long long)inner);
     return MT_OK;
 }
 
@@ -346,6 +370,12 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     memset(&epi, 0, sizeof epi);
     epi.r = r;
     epi.c = c;
+    if (!plan.r1) {
+        WsHeader* hdr = (WsHeader*)(ws + L.hdr);
+        const int32_t s0 = g_start_entry.load();
+        MT_TRY(launch_fill_u32(&hdr->start, (uint32_t)(s0 < f.n ? s0 : f.n - 1), 1, st), "p search start");
+        epi.start = &hdr->start;
+    }
     if (L.tail_max > 0 && k > 0) {
         WsHeader* hdr = (WsHeader*)(ws + L.hdr);
         MT_TRY(launch_fill_zero_u32(&hdr->tail_count, 1, st), "clear tail count");
@@ -410,6 +440,7 @@ mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n, co
     mt_status s = parse_options(opt, &f);
     if (s != MT_OK) return s;
     if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    if ((s = check_bf16_inner(f, k)) != MT_OK) return s;
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, b, m, k, n);
     *bytes = product_layout(f, ps, g, b, m, n, 0).total;
@@ -426,6 +457,7 @@ mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype, int64_
     if (f.flags & MT_FLAG_RAW_OUTPUT) return fail(MT_ERR_INVALID_ARG, "MT_FLAG_RAW_OUTPUT is for apsp_estimate");
     if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    if ((s = check_bf16_inner(f, k)) != MT_OK) return s;
     if (b == 0 || m == 0 || n == 0) return MT_OK;
     if (!C) return fail(MT_ERR_INVALID_ARG, "C is NULL");
     if (k > 0 && (!A || !B)) return fail(MT_ERR_INVALID_ARG, "A or B is NULL");
@@ -455,6 +487,7 @@ mt_status apsp_workspace_size(int64_t n, const mt_options* opt, size_t* bytes) {
     mt_status s = parse_options(opt, &f);
     if (s != MT_OK) return s;
     if ((s = check_dims(1, n, n, n)) != MT_OK) return s;
+    if ((s = check_bf16_inner(f, n)) != MT_OK) return s;
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, 1, n, n, n);
     *bytes = product_layout(f, ps, g, 1, n, n, (size_t)(n * n) * (f.bf16 ? 4 : 8)).total;
@@ -471,6 +504,7 @@ mt_status apsp_estimate(const float* W, int64_t n, double s_scale, int32_t n_squ
     if (f.flags & MT_FLAG_NORM_CORRECT) return fail(MT_ERR_UNSUPPORTED, "MT_FLAG_NORM_CORRECT is not defined for APSP");
     if (d_dtype != MT_F32 && d_dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)d_dtype);
     if ((s = check_dims(1, n, n, n)) != MT_OK) return s;
+    if ((s = check_bf16_inner(f, n)) != MT_OK) return s;
     if (!(s_scale > 0.0) || !std::isfinite(s_scale)) return fail(MT_ERR_INVALID_ARG, "s must be finite and > 0");
     if (n == 0) return MT_OK;
     if (!W || !D) return fail(MT_ERR_INVALID_ARG, "W or D is NULL");
@@ -516,6 +550,7 @@ mt_status maxtimes_backward_workspace_size(int64_t b, int64_t m, int64_t k, int6
     mt_status s = parse_options(opt, &f);
     if (s != MT_OK) return s;
     if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    if ((s = check_bf16_inner(f, m > n ? m : n)) != MT_OK) return s;
     *bytes = backward_layout(f, b, m, k, n).total;
     return MT_OK;
 }
@@ -533,6 +568,7 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
                     "the backward supports the plain estimate only (no norm correction, clamp or projection)");
     if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    if ((s = check_bf16_inner(f, m > n ? m : n)) != MT_OK) return s;
     if (!dA && !dB) return MT_OK;
     if (b == 0 || k == 0) return MT_OK;  // nothing to write (dA, dB are empty)
     if (m > 0 && n > 0 && (!A || !B || !G || !C || !p_star))
@@ -674,6 +710,16 @@ mt_status maxtimes_set_tail_threshold(int32_t max_entries) {
 }
 
 int32_t maxtimes_tail_threshold(void) { return g_tail_max.load(); }
+
+mt_status maxtimes_set_search_start(int32_t entry) {
+    g_last_error.clear();
+    if (entry < 0 || entry >= MT_MAX_P)
+        return fail(MT_ERR_INVALID_ARG, "search start %d outside 0..%d", entry, MT_MAX_P - 1);
+    g_start_entry.store(entry);
+    return MT_OK;
+}
+
+int32_t maxtimes_search_start(void) { return g_start_entry.load(); }
 
 mt_status maxtimes_timing_enable(int on) {
     std::lock_guard<std::mutex> lk(g_tmu);

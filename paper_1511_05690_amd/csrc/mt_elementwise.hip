@@ -36,10 +36,10 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-__global__ void fill_zero_u32_kernel(uint32_t* p, int64_t words) {
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t value, int64_t words) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < words; i += stride) p[i] = 0u;
+    for (; i < words; i += stride) p[i] = value;
 }
 
 // One wave per row: r[row] = max_k A[row, k]; flags invalid entries.
@@ -340,14 +340,16 @@ inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = 65535 *
 
 }  // namespace
 
-hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st) {
+hipError_t launch_fill_u32(void* p, uint32_t value, int64_t words, hipStream_t st) {
     if (words <= 0) return hipSuccess;
-    timing_before("mt_fill_zero", st);
-    hipLaunchKernelGGL(fill_zero_u32_kernel, dim3(grid_for(words, kThreads * 4, 4096)),
-                       dim3(kThreads), 0, st, (uint32_t*)p, words);
+    timing_before("mt_fill", st);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(words, kThreads * 4, 4096)), dim3(kThreads), 0, st,
+                       (uint32_t*)p, value, words);
     timing_after(st);
     return hipGetLastError();
 }
+
+hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st) { return launch_fill_u32(p, 0u, words, st); }
 
 hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r, int32_t* flag,
                          hipStream_t st) {

@@ -121,21 +121,33 @@ struct SelectEpi {
     static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
 
-    // Entries of this lane without their final output yet.
-    __device__ int undecided() const {
+    // Entries of this lane without a final output yet: `open` ones have no
+    // stable p so far; `parked` ones are stable at the p the search started
+    // at (or at a larger one on the way up) and a still larger p may be
+    // stable too (their S waits in `out`).  With the r = 1 projection the
+    // search always starts at the largest p and its parked entries (S_{p*}
+    // waiting for S_{p_lo}) count as open.
+    __device__ void counts(int& open, int& parked) const {
         constexpr int TOT = WT_M * WT_N * 16;
-        int c = 0;
+        open = parked = 0;
 #pragma unroll
         for (int i = 0; i < NDEC; ++i) {
             const uint32_t full = (TOT - 32 * i >= 32) ? 0xFFFFFFFFu : ((1u << (TOT - 32 * i)) - 1u);
-            c += __builtin_popcount(~decided[i] & full);
+            const uint32_t und = ~decided[i] & full;
+            if (R1) {
+                open += __builtin_popcount(und);
+            } else {
+                parked += __builtin_popcount(und & pending[i]);
+                open += __builtin_popcount(und & ~pending[i]);
+            }
         }
-        return c;
     }
+    __device__ int32_t start_index() const { return (!R1 && a.start) ? *a.start : 0; }
     __device__ bool can_hand_over(int total) const { return a.tail != nullptr && total <= a.tail_max; }
     __device__ uint32_t* tail_counter() const { return a.tail_count; }
-    // Write this lane's undecided entries to the sparse-tail list from `pos` on.
-    __device__ void hand_over(uint32_t pos, int e_next, const TileCtx& t) const {
+    // Write this lane's undecided entries to the sparse-tail list from `pos`
+    // on, after plan entry e of a search that started at plan entry s.
+    __device__ void hand_over(uint32_t pos, int e, int s, const TileCtx& t) const {
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
@@ -151,8 +163,13 @@ struct SelectEpi {
                     te.bi = t.bi;
                     te.i = (int32_t)(t.row0 + lr0 + i * 32 + 2 * q);
                     te.j = (int32_t)(t.col0 + lc0 + j * 32);
-                    te.e_next = (int16_t)e_next;
-                    te.pending = (int16_t)((pnd >> q) & 1u);
+                    if ((pnd >> q) & 1u) {
+                        te.state = R1 ? kTailR1 : kTailRise;
+                        te.e_next = (int16_t)(R1 ? e + 1 : (e < s ? e - 1 : s - 1));
+                    } else {
+                        te.state = kTailOpen;
+                        te.e_next = (int16_t)(e + 1);
+                    }
                     a.tail[pos++] = te;
                 }
             }
@@ -200,26 +217,14 @@ struct SelectEpi {
             }
     }
 
-    // stage: a free pipeline buffer (C::NW staging tiles of STG floats).
-    __device__ void entry(int e, const FamilyPlan& plan, f32x16 (&acc)[WT_M][WT_N], const TileCtx& t,
-                          uint8_t* stage) {
-        float* stg = (float*)stage + t.wave * STG;
-        const bool last = (e == plan.n - 1);
-        const float inv_p = plan.e[e].inv_p;
-        const bool p_is_1 = plan.e[e].p == 1;
-        const float corr = plan.e[e].corr;
-        // S >= tau in FP64 is S >= tau_f in FP32 (tau_f: tau rounded up to FP32)
-        const float tau_f = plan.tau_f;
-        const uint8_t pcode = (uint8_t)plan.e[e].pidx;
-        // r = 1 projection: an entry stable here, with a smaller p still to
-        // come, parks S_{p*} in `out` and is finished at that p with
-        // (S_{p*} / S_{p_lo})^(1/(p* - p_lo)) (Sec. 1, one projected value)
-        const bool defer = R1 && plan.e[e].inv_dp > 0.f;
-        const float prev_inv_dp = e > 0 ? plan.e[e - 1].inv_dp : 0.f;
-        const float prev_inv_p = e > 0 ? plan.e[e - 1].inv_p : 1.f;
-        TO* out = (TO*)a.out + out_lane;
-        uint8_t* ps = a.pstar ? a.pstar + out_lane : nullptr;
-        const int lane = t.lane;
+    // Walk the (i, j) sub-tiles of this wave: acc[i][j] is staged through
+    // LDS (stg, one wave's tile) and f(roff, j, q, S, mask, dec, pnd) sees
+    // each entry of this lane (row offset roff in the tile, bit `mask` of the
+    // sub-tile's decided / pending words).  A sub-tile whose entries all have
+    // a bit of `skip` set is passed over.  Unrolled: the hot path (every
+    // entry of a top-down search).
+    template <class F>
+    __device__ void each_unrolled(f32x16 (&acc)[WT_M][WT_N], float* stg, int lane, bool skip_pending, F&& f) {
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
@@ -228,60 +233,172 @@ struct SelectEpi {
                 uint32_t dec = decided[tix >> 1];
                 uint32_t pnd = pending[tix >> 1];
                 const int sh = (tix & 1) * 16;
-                if (__all(((dec >> sh) & 0xFFFFu) == 0xFFFFu)) continue;  // every entry decided
+                const uint32_t skip = skip_pending ? (dec | pnd) : dec;
+                if (__all(((skip >> sh) & 0xFFFFu) == 0xFFFFu)) continue;
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
                     stg[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * 33 + (lane & 31)] = acc[i][j][r];
                 __builtin_amdgcn_wave_barrier();
-                const float cj = cs[lc0 + j * 32];
 #pragma unroll 2
-                for (int q = 0; q < 16; ++q) {
-                    const int roff = i * 32 + 2 * q;
-                    const float S = stg[(2 * q + (lane >> 5)) * 33 + (lane & 31)];
-                    const bool stable = S >= tau_f;
-                    const uint32_t mask = 1u << (sh + q);
-                    const int64_t o = (int64_t)roff * n + j * 32;
-                    if constexpr (!R1) {
-                        if (!(dec & mask) && (stable || last)) {
-                            dec |= mask;
-                            float v = rs[lr0 + roff] * cj * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
-                            if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
-                            if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) v = 1.f;
-                            out[o] = (TO)v;
-                            if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
-                        }
-                        continue;
-                    }
-                    float v;
-                    bool finish = false;
-                    if (pnd & mask) {
-                        // S here is the ring result at p_lo of an entry parked at p*
-                        const float Sh = (float)out[o];
-                        v = S > 0.f ? root_f32(Sh / S, prev_inv_dp) : root_f32(Sh, prev_inv_p);
-                        pnd &= ~mask;
-                        finish = true;
-                    } else if (!(dec & mask) && (stable || last)) {
-                        if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
-                        if (stable && defer) {
-                            out[o] = (TO)S;
-                            pnd |= mask;
-                        } else {
-                            v = (p_is_1 ? S : root_f32(S, inv_p)) * corr;
-                            finish = true;
-                        }
-                    }
-                    if (finish) {
-                        dec |= mask;
-                        v *= rs[lr0 + roff] * cj;
-                        if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
-                        if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) v = 1.f;
-                        out[o] = (TO)v;
-                    }
-                }
+                for (int q = 0; q < 16; ++q)
+                    f(i * 32 + 2 * q, j, stg[(2 * q + (lane >> 5)) * 33 + (lane & 31)], 1u << (sh + q), dec, pnd);
                 decided[tix >> 1] = dec;
                 pending[tix >> 1] = pnd;
                 __builtin_amdgcn_wave_barrier();
             }
+    }
+    // The same with the sub-tile loop rolled (the per-entry code appears once):
+    // for the entries of a search that does not start at the largest p,
+    // which run once or a few times per tile.
+    template <class F>
+    __device__ void each_rolled(f32x16 (&acc)[WT_M][WT_N], float* stg, int lane, F&& f) {
+#pragma unroll 1
+        for (int tix = 0; tix < WT_M * WT_N; ++tix) {
+            const int i = tix / WT_N, j = tix % WT_N;
+            uint32_t dec = 0, pnd = 0;
+#pragma unroll
+            for (int w = 0; w < NDEC; ++w)
+                if (w == (tix >> 1)) {
+                    dec = decided[w];
+                    pnd = pending[w];
+                }
+            const int sh = (tix & 1) * 16;
+            if (__all(((dec >> sh) & 0xFFFFu) == 0xFFFFu)) continue;
+#pragma unroll
+            for (int ii = 0; ii < WT_M; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < WT_N; ++jj)
+                    if (ii * WT_N + jj == tix) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            stg[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * 33 + (lane & 31)] = acc[ii][jj][r];
+                    }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+            for (int q = 0; q < 16; ++q)
+                f(i * 32 + 2 * q, j, stg[(2 * q + (lane >> 5)) * 33 + (lane & 31)], 1u << (sh + q), dec, pnd);
+#pragma unroll
+            for (int w = 0; w < NDEC; ++w)
+                if (w == (tix >> 1)) {
+                    decided[w] = dec;
+                    pending[w] = pnd;
+                }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+
+    // Final output of entry (roff, j) from its ring result S at a p with
+    // root factor inv_p (p_is_1: no root) and norm correction corr.
+    __device__ void put(TO* out, int roff, int j, int64_t o, float S, bool p_is_1, float inv_p, float corr) {
+        float v = rs[lr0 + roff] * cs[lc0 + j * 32] * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
+        if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
+        if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) v = 1.f;
+        out[o] = (TO)v;
+    }
+
+    // stage: a free pipeline buffer (C::NW staging tiles of STG floats).
+    // Plan entry e of a p search that started at plan entry s: entries e >= s
+    // go down from the start (smaller p), entries e < s up (larger p).
+    __device__ void entry(int e, int s, const FamilyPlan& plan, f32x16 (&acc)[WT_M][WT_N],
+                          const TileCtx& t, uint8_t* stage) {
+        float* stg = (float*)stage + t.wave * STG;
+        const bool last = (e == plan.n - 1);
+        const float inv_p = plan.e[e].inv_p;
+        const bool p_is_1 = plan.e[e].p == 1;
+        const float corr = plan.e[e].corr;
+        // S >= tau in FP64 is S >= tau_f in FP32 (tau_f: tau rounded up to FP32)
+        const float tau_f = plan.tau_f;
+        const uint8_t pcode = (uint8_t)plan.e[e].pidx;
+        TO* out = (TO*)a.out + out_lane;
+        uint8_t* ps = a.pstar ? a.pstar + out_lane : nullptr;
+        const int lane = t.lane;
+        if constexpr (R1) {
+            // r = 1 projection: an entry stable here, with a smaller p still
+            // to come, parks S_{p*} in `out` and is finished at that p with
+            // (S_{p*} / S_{p_lo})^(1/(p* - p_lo)) (Sec. 1, one projected value)
+            const bool defer = plan.e[e].inv_dp > 0.f;
+            const float prev_inv_dp = e > 0 ? plan.e[e - 1].inv_dp : 0.f;
+            const float prev_inv_p = e > 0 ? plan.e[e - 1].inv_p : 1.f;
+            each_unrolled(acc, stg, lane, false,
+                          [&](int roff, int j, float S, uint32_t mask, uint32_t& dec, uint32_t& pnd) {
+                              const int64_t o = (int64_t)roff * n + j * 32;
+                              const bool stable = S >= tau_f;
+                              if (pnd & mask) {
+                                  // S here is the ring result at p_lo of an entry parked at p*
+                                  const float Sh = (float)out[o];
+                                  pnd &= ~mask;
+                                  dec |= mask;
+                                  if (S > 0.f)
+                                      put(out, roff, j, o, Sh / S, false, prev_inv_dp, 1.f);
+                                  else
+                                      put(out, roff, j, o, Sh, false, prev_inv_p, 1.f);
+                              } else if (!(dec & mask) && (stable || last)) {
+                                  if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                                  if (stable && defer) {
+                                      out[o] = (TO)S;
+                                      pnd |= mask;
+                                  } else {
+                                      dec |= mask;
+                                      put(out, roff, j, o, S, p_is_1, inv_p, corr);
+                                  }
+                              }
+                          });
+        } else if (e > s || s == 0) {
+            // going down: decide entries stable here (or at the smallest p);
+            // entries parked at the start wait
+            each_unrolled(acc, stg, lane, true,
+                          [&](int roff, int j, float S, uint32_t mask, uint32_t& dec, uint32_t& pnd) {
+                              const bool stable = S >= tau_f;
+                              if (((dec | pnd) & mask) || !(stable || last)) return;
+                              const int64_t o = (int64_t)roff * n + j * 32;
+                              dec |= mask;
+                              put(out, roff, j, o, S, p_is_1, inv_p, corr);
+                              if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                          });
+        } else if (e == s) {
+            // the start: an entry stable here whose S does not rule out the
+            // next larger p (S_q <= S^(q/p)) parks S in `out`
+            const float rise_thr = plan.e[e].rise_thr_f;
+            each_rolled(acc, stg, lane, [&](int roff, int j, float S, uint32_t mask, uint32_t& dec, uint32_t& pnd) {
+                const bool stable = S >= tau_f;
+                if ((dec & mask) || !(stable || last)) return;
+                const int64_t o = (int64_t)roff * n + j * 32;
+                if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                if (stable && S >= rise_thr) {
+                    out[o] = (TO)S;
+                    pnd |= mask;
+                    return;
+                }
+                dec |= mask;
+                put(out, roff, j, o, S, p_is_1, inv_p, corr);
+            });
+        } else {
+            // going up: only parked entries are left, their S from plan
+            // entry e + 1 waits in `out`
+            const float rise_thr = plan.e[e].rise_thr_f;
+            const PlanEntry& pb = plan.e[e + 1];
+            const float below_inv_p = pb.inv_p;
+            const bool below_p_is_1 = pb.p == 1;
+            const float below_corr = pb.corr;
+            each_rolled(acc, stg, lane, [&](int roff, int j, float S, uint32_t mask, uint32_t& dec, uint32_t& pnd) {
+                if (dec & mask) return;
+                const bool stable = S >= tau_f;
+                const int64_t o = (int64_t)roff * n + j * 32;
+                if (stable) {
+                    if (ps) ps[o] = pcode;
+                    if (e > 0 && S >= rise_thr) {
+                        out[o] = (TO)S;  // stable here too, and maybe above
+                        return;
+                    }
+                }
+                pnd &= ~mask;
+                dec |= mask;
+                if (stable)
+                    put(out, roff, j, o, S, p_is_1, inv_p, corr);
+                else  // p* is the p below
+                    put(out, roff, j, o, (float)out[o], below_p_is_1, below_inv_p, below_corr);
+            });
+        }
     }
 
     __device__ void finish(const TileCtx&) {}
@@ -309,10 +426,11 @@ struct AdjointEpi {
     static constexpr bool kAllActive = false;
     static constexpr bool kCanStop = false;
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
-    __device__ int undecided() const { return 0; }
+    __device__ void counts(int& open, int& parked) const { open = parked = 0; }
+    __device__ int32_t start_index() const { return 0; }
     __device__ bool can_hand_over(int) const { return false; }
     __device__ uint32_t* tail_counter() const { return nullptr; }
-    __device__ void hand_over(uint32_t, int, const TileCtx&) const {}
+    __device__ void hand_over(uint32_t, int, int, const TileCtx&) const {}
 
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
         rows = g.rows;
@@ -342,7 +460,7 @@ struct AdjointEpi {
         cols_left = (int32_t)min<int64_t>(cols - (t.col0 + lc0), 1 << 30);
     }
 
-    __device__ void entry(int e, const FamilyPlan& plan, f32x16 (&acc)[WT_M][WT_N], const TileCtx&,
+    __device__ void entry(int e, int, const FamilyPlan& plan, f32x16 (&acc)[WT_M][WT_N], const TileCtx&,
                           uint8_t*) {
         const int pm1 = plan.e[e].p - 1;
         const TM* src = (const TM*)a.M + lane_off;
@@ -407,6 +525,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
     __shared__ int s_act[MT_MAX_P + 1];
     __shared__ int s_done[2][C::NW];  // per wave: undecided entries (entry parity)
+    __shared__ int s_open[2][C::NW];  // per wave: of which open (entry parity)
     __shared__ uint32_t s_tail_base;
 
     const int tid = threadIdx.x;
@@ -459,9 +578,19 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     // instruction.  Split step: instruction i fills 64-byte rows R0 .. R0+15,
     // R0 a multiple of 16; lane l fills row R0 + l/4, physical chunk l%4,
     // holding logical chunk (l%4) ^ ((row >> 2) & 3) = (l%4) ^ ((l >> 4) & 3).
-    const int32_t ld_even = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (lane >> 4)) * 8);
-    const int32_t ld_odd = (lane >> 3) * (int32_t)g.kp + (((lane & 7) ^ (4 + (lane >> 4))) * 8);
-    const int32_t ld_split = (lane >> 2) * (int32_t)g.kp + (((lane & 3) ^ ((lane >> 4) & 3)) * 8);
+    // As byte offsets from the plane row block of the step (X and Y load the
+    // same row pattern: GA == GB, SA == SB), 32-bit so that each load is a
+    // uniform base plus one VGPR (kp < 2^22 keeps them in range).
+    static_assert(C::GA == C::GB && C::SA == C::SB, "X and Y share the load offsets");
+    const uint32_t kpb = (uint32_t)g.kp * 2u;
+    const uint32_t ld_even = (lane >> 3) * kpb + (((lane & 7) ^ (lane >> 4)) * 16);
+    const uint32_t ld_odd = (lane >> 3) * kpb + (((lane & 7) ^ (4 + (lane >> 4))) * 16);
+    const uint32_t ld_split = (lane >> 2) * kpb + (((lane & 3) ^ ((lane >> 4) & 3)) * 16);
+    uint32_t voff_p[C::GA], voff_s[C::SA];
+#pragma unroll
+    for (int i = 0; i < C::GA; ++i) voff_p[i] = (uint32_t)((wave * C::GA + i) * 8) * kpb + ((i & 1) ? ld_odd : ld_even);
+#pragma unroll
+    for (int i = 0; i < C::SA; ++i) voff_s[i] = (uint32_t)((wave * C::SA + i) * 16) * kpb + ld_split;
     // LDS operand reads: row (lane & 31) of a 32-row block, logical chunk
     // 2*kk + lane/32; plain swizzle (lane >> 1) & 7, split swizzle
     // (lane >> 2) & 3 (block bases are multiples of 32 rows).
@@ -470,72 +599,78 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
 
     __syncthreads();
     const int nact = Epi::kAllActive ? plan.n : __builtin_amdgcn_readfirstlane(s_act[0]);
+    // The p search starts at plan entry s (0: the largest p), goes down to
+    // the smallest p and then up from s - 1 to the largest (forward only).
+    int s0 = Epi::kAllActive ? __builtin_amdgcn_readfirstlane(epi.start_index()) : 0;
+    const int s = s0 < 0 ? 0 : (s0 >= nact ? nact - 1 : s0);
 
-    // entry of active index ai (the identity when every entry is active)
+    // plan entry of processing index ai
     auto entry_of = [&](int ai) -> int {
-        return Epi::kAllActive ? ai : __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+        if (!Epi::kAllActive) return __builtin_amdgcn_readfirstlane(s_act[1 + ai]);
+        return ai < nact - s ? s + ai : nact - 1 - ai;
     };
     const int nkt64 = (int)(g.kp / 64);  // plain steps per entry
     const int nkt32 = 2 * nkt64;          // split steps per entry
-    auto issue = [&](int ai, int kt, int buf) {
-        const int e = entry_of(ai);
+    // The next K step to load: processing index la_, step lkt of its entry,
+    // and that entry's plane rows (A hi, A lo, B hi, B lo; the lo rows are
+    // unused for a plain p), set once per entry.
+    int la_ = 0, lkt = 0, lnk = 0;
+    bool lsplit = false;
+    const uint16_t *lxh = Xbase, *lxl = Xbase, *lyh = Ybase, *lyl = Ybase;
+    auto set_cursor = [&]() {
+        if (la_ >= nact) return;
+        const PlanEntry& pe = plan.e[entry_of(la_)];
+        lsplit = pe.nseg == 3;
+        lnk = lsplit ? nkt32 : nkt64;
+        lxh = Xbase + (int64_t)pe.a_plane[0] * g.x_plane_elems;
+        lxl = Xbase + (int64_t)pe.a_plane[2] * g.x_plane_elems;
+        lyh = Ybase + (int64_t)pe.b_plane[0] * g.y_plane_elems;
+        lyl = Ybase + (int64_t)pe.b_plane[1] * g.y_plane_elems;
+    };
+    auto issue = [&](int buf) {
         uint8_t* la = smem + buf * C::BUF_BYTES;
-        if (plan.e[e].nseg == 3) {
-            const uint16_t* xh = Xbase + (int64_t)plan.e[e].a_plane[0] * g.x_plane_elems + kt * 32;
-            const uint16_t* xl = Xbase + (int64_t)plan.e[e].a_plane[2] * g.x_plane_elems + kt * 32;
-            const uint16_t* yh = Ybase + (int64_t)plan.e[e].b_plane[0] * g.y_plane_elems + kt * 32;
-            const uint16_t* yl = Ybase + (int64_t)plan.e[e].b_plane[1] * g.y_plane_elems + kt * 32;
-            uint8_t* lxl = la + C::BM * 64;
-            uint8_t* lyh = la + C::A_BYTES;
-            uint8_t* lyl = lyh + C::BN * 64;
+        if (lsplit) {
+            const char* xh = (const char*)lxh + lkt * 64;
+            const char* xl = (const char*)lxl + lkt * 64;
+            const char* yh = (const char*)lyh + lkt * 64;
+            const char* yl = (const char*)lyl + lkt * 64;
+            uint8_t* lxl_ = la + C::BM * 64;
+            uint8_t* lyh_ = la + C::A_BYTES;
+            uint8_t* lyl_ = lyh_ + C::BN * 64;
 #pragma unroll
             for (int i = 0; i < C::SA; ++i) {
                 const int R0 = (wave * C::SA + i) * 16;
-                const int64_t go = (int64_t)R0 * g.kp + ld_split;
-                __builtin_amdgcn_global_load_lds((glb_cvoid*)(xh + go), (lds_void*)(la + R0 * 64), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((glb_cvoid*)(xl + go), (lds_void*)(lxl + R0 * 64), 16, 0, 0);
-            }
-#pragma unroll
-            for (int i = 0; i < C::SB; ++i) {
-                const int R0 = (wave * C::SB + i) * 16;
-                const int64_t go = (int64_t)R0 * g.kp + ld_split;
-                __builtin_amdgcn_global_load_lds((glb_cvoid*)(yh + go), (lds_void*)(lyh + R0 * 64), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((glb_cvoid*)(yl + go), (lds_void*)(lyl + R0 * 64), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(xh + voff_s[i]), (lds_void*)(la + R0 * 64), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(xl + voff_s[i]), (lds_void*)(lxl_ + R0 * 64), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(yh + voff_s[i]), (lds_void*)(lyh_ + R0 * 64), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(yl + voff_s[i]), (lds_void*)(lyl_ + R0 * 64), 16, 0, 0);
             }
         } else {
-            const uint16_t* xsrc = Xbase + (int64_t)plan.e[e].a_plane[0] * g.x_plane_elems + kt * 64;
-            const uint16_t* ysrc = Ybase + (int64_t)plan.e[e].b_plane[0] * g.y_plane_elems + kt * 64;
+            const char* xsrc = (const char*)lxh + lkt * 128;
+            const char* ysrc = (const char*)lyh + lkt * 128;
             uint8_t* lb = la + C::A_BYTES;
 #pragma unroll
             for (int i = 0; i < C::GA; ++i) {
                 const int R0 = (wave * C::GA + i) * 8;
-                __builtin_amdgcn_global_load_lds(
-                    (glb_cvoid*)(xsrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
-                    (lds_void*)(la + R0 * 128), 16, 0, 0);
-            }
-#pragma unroll
-            for (int i = 0; i < C::GB; ++i) {
-                const int R0 = (wave * C::GB + i) * 8;
-                __builtin_amdgcn_global_load_lds(
-                    (glb_cvoid*)(ysrc + (int64_t)R0 * g.kp + ((i & 1) ? ld_odd : ld_even)),
-                    (lds_void*)(lb + R0 * 128), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(xsrc + voff_p[i]), (lds_void*)(la + R0 * 128), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_cvoid*)(ysrc + voff_p[i]), (lds_void*)(lb + R0 * 128), 16, 0, 0);
             }
         }
     };
-    auto advance = [&](int& ai, int& kt) {
-        const int e = entry_of(ai);
-        if (++kt == (plan.e[e].nseg == 3 ? nkt32 : nkt64)) {
-            kt = 0;
-            ++ai;
+    auto advance = [&]() {
+        if (++lkt == lnk) {
+            lkt = 0;
+            ++la_;
+            set_cursor();
         }
     };
 
     // Software pipeline: the loads of the next K step (possibly of the next
     // family entry) are issued before the MFMAs of the current one.
-    int la_ = 0, lkt = 0;
+    set_cursor();
     if (nkt64 > 0 && nact > 0) {
-        issue(la_, lkt, 0);
-        advance(la_, lkt);
+        issue(0);
+        advance();
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -554,8 +689,8 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
             // split p: hi.hi + hi.lo + lo.hi per K step of 32
             for (int st = 0; st < nkt32; ++st) {
                 if (la_ < nact) {
-                    issue(la_, lkt, buf ^ 1);
-                    advance(la_, lkt);
+                    issue(buf ^ 1);
+                    advance();
                 }
                 const uint8_t* pxh = smem + buf * C::BUF_BYTES + t.wm * WT_M * 32 * 64;
                 const uint8_t* pxl = pxh + C::BM * 64;
@@ -597,8 +732,8 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
         } else {
             for (int st = 0; st < nkt64; ++st) {
                 if (la_ < nact) {
-                    issue(la_, lkt, buf ^ 1);
-                    advance(la_, lkt);
+                    issue(buf ^ 1);
+                    advance();
                 }
                 const uint8_t* pa = smem + buf * C::BUF_BYTES + t.wm * WT_M * 32 * 128;
                 const uint8_t* pb = smem + buf * C::BUF_BYTES + C::A_BYTES + t.wn * WT_N * 32 * 128;
@@ -639,42 +774,69 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
         }
         // the buffer the last step read is free until the next step's loads,
         // which wait for the barrier below
-        epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
+        epi.entry(e, s, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
         int lane_pre = 0;
         if (Epi::kCanStop) {
             // undecided entries per lane -> exclusive prefix in the wave
-            const int cnt = epi.undecided();
-            int incl = cnt;
+            int n_open, n_parked;
+            epi.counts(n_open, n_parked);
+            const int cnt = n_open + n_parked;
+            int incl = cnt, incl_open = n_open;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
                 const int y = __shfl_up(incl, d);
-                if (lane >= d) incl += y;
+                const int yo = __shfl_up(incl_open, d);
+                if (lane >= d) {
+                    incl += y;
+                    incl_open += yo;
+                }
             }
             lane_pre = incl - cnt;
             const int wtot = __shfl(incl, 63);
-            if (lane == 0) s_done[ai & 1][wave] = wtot;
+            const int wopen = __shfl(incl_open, 63);
+            if (lane == 0) {
+                s_done[ai & 1][wave] = wtot;
+                s_open[ai & 1][wave] = wopen;
+            }
         }
         __syncthreads();
         if (Epi::kCanStop) {
-            int total = 0, wave_pre = 0;
+            int total = 0, open = 0, wave_pre = 0;
 #pragma unroll
             for (int w = 0; w < C::NW; ++w) {
                 const int x = s_done[ai & 1][w];
                 total += x;
+                open += s_open[ai & 1][w];
                 wave_pre += w < wave ? x : 0;
             }
             total = __builtin_amdgcn_readfirstlane(total);
-            // Every entry of the tile has its p: the remaining (smaller) p
-            // cannot change the output.  The loads already issued for the
-            // next entry have landed (vmcnt(0) above) and are simply unused.
+            open = __builtin_amdgcn_readfirstlane(open);
+            // Every entry of the tile has its p: the remaining p cannot
+            // change the output.  The loads already issued for the next entry
+            // have landed (vmcnt(0) above) and are simply unused.
             if (total == 0) break;
             // Only a few are left: hand them to the sparse tail, which runs
             // the remaining p for them alone, and stop the tile.
             if (ai + 1 < nact && epi.can_hand_over(total)) {
                 if (tid == 0) s_tail_base = atomicAdd(epi.tail_counter(), (uint32_t)total);
                 __syncthreads();
-                epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), entry_of(ai) + 1, t);
+                epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), e, s, t);
                 break;
+            }
+            // Going down with nothing open left: only the entries parked at
+            // the start wait, for larger p.  Skip to the way up (plan entry
+            // s - 1): reload its first K step in place of the prefetched one.
+            if (open == 0 && e >= s && s > 0 && ai + 1 < nact - s) {
+                ai = nact - s - 1;  // ++ai below -> first entry of the way up
+                la_ = nact - s;
+                lkt = 0;
+                set_cursor();
+                if (nkt64 > 0) {
+                    issue(buf);
+                    advance();
+                }
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
             }
         }
     }
@@ -692,6 +854,75 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
+// S_p of one entry for plan entry pe, reduced over the wave.  Lane l sums
+// the 8-element chunks l, l + 64, ... of the row in order; U chunks are
+// loaded before any is used, so that each wave keeps 16 loads in flight
+// (the kernel is bound by load latency, not bandwidth, with one load at a
+// time).
+__device__ float tail_dot_bf16(const uint16_t* xr, const uint16_t* yr, const PlanEntry& pe, const GemmGeom& g,
+                               int lane) {
+    float acc = 0.f;
+    int64_t k0 = lane * 8;
+    if (pe.nseg == 3) {
+        const uint16_t* xh = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
+        const uint16_t* xl = xr + (int64_t)pe.a_plane[2] * g.x_plane_elems;
+        const uint16_t* yh = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
+        const uint16_t* yl = yr + (int64_t)pe.b_plane[1] * g.y_plane_elems;
+        auto chunk = [&](const u32x4& vxh, const u32x4& vxl, const u32x4& vyh, const u32x4& vyl) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc += bf16_lo(vxh[q]) * bf16_lo(vyh[q]);
+                acc += bf16_lo(vxh[q]) * bf16_lo(vyl[q]);
+                acc += bf16_lo(vxl[q]) * bf16_lo(vyh[q]);
+                acc += bf16_hi(vxh[q]) * bf16_hi(vyh[q]);
+                acc += bf16_hi(vxh[q]) * bf16_hi(vyl[q]);
+                acc += bf16_hi(vxl[q]) * bf16_hi(vyh[q]);
+            }
+        };
+        constexpr int U = 4;
+        for (; k0 + (U - 1) * 512 < g.kp; k0 += U * 512) {
+            u32x4 vxh[U], vxl[U], vyh[U], vyl[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                vxh[u] = *(const u32x4*)(xh + k0 + u * 512);
+                vxl[u] = *(const u32x4*)(xl + k0 + u * 512);
+                vyh[u] = *(const u32x4*)(yh + k0 + u * 512);
+                vyl[u] = *(const u32x4*)(yl + k0 + u * 512);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) chunk(vxh[u], vxl[u], vyh[u], vyl[u]);
+        }
+        for (; k0 < g.kp; k0 += 512)
+            chunk(*(const u32x4*)(xh + k0), *(const u32x4*)(xl + k0), *(const u32x4*)(yh + k0),
+                  *(const u32x4*)(yl + k0));
+    } else {
+        const uint16_t* xp = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
+        const uint16_t* yp = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
+        auto chunk = [&](const u32x4& vx, const u32x4& vy) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc += bf16_lo(vx[q]) * bf16_lo(vy[q]);
+                acc += bf16_hi(vx[q]) * bf16_hi(vy[q]);
+            }
+        };
+        constexpr int U = 8;
+        for (; k0 + (U - 1) * 512 < g.kp; k0 += U * 512) {
+            u32x4 vx[U], vy[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                vx[u] = *(const u32x4*)(xp + k0 + u * 512);
+                vy[u] = *(const u32x4*)(yp + k0 + u * 512);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) chunk(vx[u], vy[u]);
+        }
+        for (; k0 < g.kp; k0 += 512) chunk(*(const u32x4*)(xp + k0), *(const u32x4*)(yp + k0));
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+    return acc;
+}
+
 template <int MODE, typename TO, bool R1>
 __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPlan plan, EpiArgs a) {
     const int lane = threadIdx.x & 63;
@@ -706,48 +937,37 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
         const uint16_t* yr = g.Y + (int64_t)te.bi * g.y_batch_elems + (int64_t)te.j * g.kp;
         const float rc = (a.r ? (float)a.r[(int64_t)te.bi * g.rows + te.i] : 1.f) *
                          (a.c ? (float)a.c[(int64_t)te.bi * g.cols + te.j] : 1.f);
-        bool pend = R1 && te.pending != 0;
-        float Sh = pend ? (float)out[o] : 0.f;
-        for (int e = te.e_next; e < plan.n; ++e) {
-            const PlanEntry& pe = plan.e[e];
-            float acc = 0.f;
-            if (pe.nseg == 3) {
-                const uint16_t* xh = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
-                const uint16_t* xl = xr + (int64_t)pe.a_plane[2] * g.x_plane_elems;
-                const uint16_t* yh = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
-                const uint16_t* yl = yr + (int64_t)pe.b_plane[1] * g.y_plane_elems;
-                for (int64_t k0 = lane * 8; k0 < g.kp; k0 += 512) {
-                    const u32x4 vxh = *(const u32x4*)(xh + k0), vxl = *(const u32x4*)(xl + k0);
-                    const u32x4 vyh = *(const u32x4*)(yh + k0), vyl = *(const u32x4*)(yl + k0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        acc += bf16_lo(vxh[q]) * bf16_lo(vyh[q]);
-                        acc += bf16_lo(vxh[q]) * bf16_lo(vyl[q]);
-                        acc += bf16_lo(vxl[q]) * bf16_lo(vyh[q]);
-                        acc += bf16_hi(vxh[q]) * bf16_hi(vyh[q]);
-                        acc += bf16_hi(vxh[q]) * bf16_hi(vyl[q]);
-                        acc += bf16_hi(vxl[q]) * bf16_hi(vyh[q]);
-                    }
+        float Sh = te.state != kTailOpen ? (float)out[o] : 0.f;
+        float v = 0.f;
+        if (!R1 && te.state == kTailRise) {
+            // stable at e_next + 1 (S parked): go up while a larger p may be
+            // stable too
+            for (int e = te.e_next;; --e) {
+                const PlanEntry& pe = plan.e[e];
+                const float S = tail_dot_bf16(xr, yr, pe, g, lane);
+                const bool stable = S >= plan.tau_f;
+                if (stable && lane == 0 && a.pstar) a.pstar[o] = (uint8_t)pe.pidx;
+                if (stable && e > 0 && S >= pe.rise_thr_f) {
+                    Sh = S;
+                    continue;
                 }
-            } else {
-                const uint16_t* xp = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
-                const uint16_t* yp = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
-                for (int64_t k0 = lane * 8; k0 < g.kp; k0 += 512) {
-                    const u32x4 vx = *(const u32x4*)(xp + k0), vy = *(const u32x4*)(yp + k0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        acc += bf16_lo(vx[q]) * bf16_lo(vy[q]);
-                        acc += bf16_hi(vx[q]) * bf16_hi(vy[q]);
-                    }
+                if (stable) {
+                    v = (pe.p == 1 ? S : root_f32(S, pe.inv_p)) * pe.corr;
+                } else {
+                    const PlanEntry& pb = plan.e[e + 1];
+                    v = (pb.p == 1 ? Sh : root_f32(Sh, pb.inv_p)) * pb.corr;
                 }
+                break;
             }
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
-            const float S = acc;
-            float v;
-            if (R1 && pend) {
-                v = S > 0.f ? root_f32(Sh / S, plan.e[e - 1].inv_dp) : root_f32(Sh, plan.e[e - 1].inv_p);
-            } else {
+        } else {
+            bool pend = R1 && te.state == kTailR1;
+            for (int e = te.e_next; e < plan.n; ++e) {
+                const PlanEntry& pe = plan.e[e];
+                const float S = tail_dot_bf16(xr, yr, pe, g, lane);
+                if (R1 && pend) {
+                    v = S > 0.f ? root_f32(Sh / S, plan.e[e - 1].inv_dp) : root_f32(Sh, plan.e[e - 1].inv_p);
+                    break;
+                }
                 const bool stable = S >= plan.tau_f;
                 if (!(stable || e == plan.n - 1)) continue;
                 if (lane == 0 && a.pstar) a.pstar[o] = stable ? (uint8_t)pe.pidx : (uint8_t)MT_PSTAR_NONE;
@@ -757,13 +977,13 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
                     continue;
                 }
                 v = (pe.p == 1 ? S : root_f32(S, pe.inv_p)) * pe.corr;
+                break;
             }
-            v *= rc;
-            if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
-            if (MODE == EPI_APSP_X && te.i == te.j) v = 1.f;
-            if (lane == 0) out[o] = (TO)v;
-            break;
         }
+        v *= rc;
+        if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
+        if (MODE == EPI_APSP_X && te.i == te.j) v = 1.f;
+        if (lane == 0) out[o] = (TO)v;
     }
 }
 

@@ -67,7 +67,10 @@ struct RecordEpi {
     EpiArgs a;
     int64_t n;
     uint32_t decided[NDEC];
-    uint32_t pending[NDEC];  // r = 1 projection: S_{p*} recorded, S at the next smaller p still due
+    // r = 1 projection: S_{p*} recorded, S at the next smaller p still due;
+    // otherwise: parked, i.e. stable at the p recorded and a larger p may be
+    // stable too
+    uint32_t pending[NDEC];
     int lr0, lc0;
     int64_t out_lane;
     int32_t rows_left, cols_left;
@@ -75,21 +78,30 @@ struct RecordEpi {
     static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
 
-    // Entries of this lane without their final record yet.
-    __device__ int undecided() const {
+    // Entries of this lane without their final record yet: `open` ones have
+    // no stable p so far, `parked` ones wait for the way up (with the r = 1
+    // projection, whose search starts at the largest p, all count as open).
+    __device__ void counts(int& open, int& parked) const {
         constexpr int TOT = WT * WT * 4;
-        int c = 0;
+        open = parked = 0;
 #pragma unroll
         for (int i = 0; i < NDEC; ++i) {
             const uint32_t full = (TOT - 32 * i >= 32) ? 0xFFFFFFFFu : ((1u << (TOT - 32 * i)) - 1u);
-            c += __builtin_popcount(~decided[i] & full);
+            const uint32_t und = ~decided[i] & full;
+            if (R1) {
+                open += __builtin_popcount(und);
+            } else {
+                parked += __builtin_popcount(und & pending[i]);
+                open += __builtin_popcount(und & ~pending[i]);
+            }
         }
-        return c;
     }
+    __device__ int32_t start_index() const { return (!R1 && a.start) ? *a.start : 0; }
     __device__ bool can_hand_over(int total) const { return a.tail != nullptr && total <= a.tail_max; }
     __device__ uint32_t* tail_counter() const { return a.tail_count; }
-    // Write this lane's undecided entries to the sparse-tail list from `pos` on.
-    __device__ void hand_over(uint32_t pos, int e_next, const TileCtx& t) const {
+    // Write this lane's undecided entries to the sparse-tail list from `pos`
+    // on, after plan entry e of a search that started at plan entry s.
+    __device__ void hand_over(uint32_t pos, int e, int s, const TileCtx& t) const {
 #pragma unroll
         for (int i = 0; i < WT; ++i)
 #pragma unroll
@@ -104,8 +116,13 @@ struct RecordEpi {
                     te.bi = t.bi;
                     te.i = (int32_t)(t.row0 + lr0 + i * 16 + 4 * r);
                     te.j = (int32_t)(t.col0 + lc0 + j * 16);
-                    te.e_next = (int16_t)e_next;
-                    te.pending = (pending[tix >> 3] & mask) ? 1 : 0;
+                    if (pending[tix >> 3] & mask) {
+                        te.state = R1 ? kTailR1 : kTailRise;
+                        te.e_next = (int16_t)(R1 ? e + 1 : (e < s ? e - 1 : s - 1));
+                    } else {
+                        te.state = kTailOpen;
+                        te.e_next = (int16_t)(e + 1);
+                    }
                     a.tail[pos++] = te;
                 }
             }
@@ -137,9 +154,14 @@ struct RecordEpi {
 
     // stage: a free pipeline buffer; each wave stages one 16 x 16 tile
     // (lane-major) and walks its four entries per lane in a rolled loop.
-    __device__ void entry(int e, const FamilyPlan& plan, f64x4 (&acc)[WT][WT], const TileCtx& t,
+    // Plan entry e of a p search that started at plan entry s: entries e >= s
+    // go down from the start (smaller p), entries e < s up (larger p).
+    __device__ void entry(int e, int s, const FamilyPlan& plan, f64x4 (&acc)[WT][WT], const TileCtx& t,
                           uint8_t* stage) {
         const bool last = (e == plan.n - 1);
+        const bool up = e < s;  // only parked entries are left
+        const bool park_here = !up && e == s && s > 0;
+        const double rise_thr = plan.e[e].rise_thr;
         const double tau = plan.tau;
         const uint8_t pcode = (uint8_t)plan.e[e].pidx;
         // r = 1 projection: S_{p*} goes to `out`, S at the next smaller p to
@@ -168,7 +190,32 @@ struct RecordEpi {
                     const double S = stg[r * 64 + t.lane];
                     const bool stable = S >= tau;
                     const int64_t o = (int64_t)roff * n + j * 16;
-                    if (R1 && (pnd & mask)) {
+                    if constexpr (!R1) {
+                        // entries outside the matrix are decided from the start
+                        if (dec & mask) continue;
+                        if (!up) {
+                            if (pnd & mask) continue;  // parked at the start: waits for the way up
+                            if (!(stable || last)) continue;
+                            out[o] = S;
+                            ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
+                            // S_q <= S^(q/p): the next larger q may still pass
+                            if (stable && park_here && S >= rise_thr)
+                                pnd |= mask;
+                            else
+                                dec |= mask;
+                        } else {
+                            // not stable here: the record of the p below stands
+                            if (stable) {
+                                out[o] = S;
+                                ps[o] = pcode;
+                                if (e > 0 && S >= rise_thr) continue;
+                            }
+                            pnd &= ~mask;
+                            dec |= mask;
+                        }
+                        continue;
+                    }
+                    if (pnd & mask) {
                         out2[o] = S;
                         pnd &= ~mask;
                         dec |= mask;
@@ -207,10 +254,11 @@ struct AdjointEpiF64 {
     int32_t rows_left, cols_left;
 
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
-    __device__ int undecided() const { return 0; }
+    __device__ void counts(int& open, int& parked) const { open = parked = 0; }
+    __device__ int32_t start_index() const { return 0; }
     __device__ bool can_hand_over(int) const { return false; }
     __device__ uint32_t* tail_counter() const { return nullptr; }
-    __device__ void hand_over(uint32_t, int, const TileCtx&) const {}
+    __device__ void hand_over(uint32_t, int, int, const TileCtx&) const {}
 
     __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t* lds, int tid) {
         rows = g.rows;
@@ -238,7 +286,7 @@ struct AdjointEpiF64 {
         cols_left = (int32_t)min<int64_t>(cols - (t.col0 + lc0), 1 << 30);
     }
 
-    __device__ void entry(int e, const FamilyPlan& plan, f64x4 (&acc)[WT][WT], const TileCtx&, uint8_t*) {
+    __device__ void entry(int e, int, const FamilyPlan& plan, f64x4 (&acc)[WT][WT], const TileCtx&, uint8_t*) {
         const int pm1 = plan.e[e].p - 1;
         const TM* src = (const TM*)a.M + lane_off;
 #pragma unroll
@@ -299,6 +347,7 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
     extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
     __shared__ int s_act[MT_MAX_P + 1];
     __shared__ int s_done[2][4];  // per wave: undecided entries (entry parity)
+    __shared__ int s_open[2][4];  // per wave: of which open (entry parity)
     __shared__ uint32_t s_tail_base;
 
     const int tid = threadIdx.x;
@@ -329,9 +378,16 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
     Epi epi;
     epi.a = args;
     epi.setup(t, g, smem + C::PIPE_BYTES, tid);
+    // The p search starts at plan entry e0 (0: the largest p), goes down to
+    // the smallest p and then up from e0 - 1 to the largest; s_act holds the
+    // active plan entries in that order.
+    const int e0_req = __builtin_amdgcn_readfirstlane(epi.start_index());
+    const int e0 = e0_req < 0 ? 0 : (e0_req >= plan.n ? plan.n - 1 : e0_req);
     if (tid == 0) {
         int na = 0;
-        for (int e = 0; e < plan.n; ++e)
+        for (int e = e0; e < plan.n; ++e)
+            if (epi.active(e, plan)) s_act[1 + na++] = e;
+        for (int e = e0 - 1; e >= 0; --e)
             if (epi.active(e, plan)) s_act[1 + na++] = e;
         s_act[0] = na;
     }
@@ -426,30 +482,42 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
         steps_done += ntiles;
         // the buffer the last step read is free until the next step's loads,
         // which wait for the barrier below
-        epi.entry(e, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
+        epi.entry(e, e0, plan, acc, t, smem + (buf ^ 1) * C::BUF_BYTES);
         int lane_pre = 0;
         if (Epi::kCanStop) {
-            const int cnt = epi.undecided();
-            int incl = cnt;
+            int n_open, n_parked;
+            epi.counts(n_open, n_parked);
+            const int cnt = n_open + n_parked;
+            int incl = cnt, incl_open = n_open;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
                 const int y = __shfl_up(incl, d);
-                if (lane >= d) incl += y;
+                const int yo = __shfl_up(incl_open, d);
+                if (lane >= d) {
+                    incl += y;
+                    incl_open += yo;
+                }
             }
             lane_pre = incl - cnt;
             const int wtot = __shfl(incl, 63);
-            if (lane == 0) s_done[ai & 1][wave] = wtot;
+            const int wopen = __shfl(incl_open, 63);
+            if (lane == 0) {
+                s_done[ai & 1][wave] = wtot;
+                s_open[ai & 1][wave] = wopen;
+            }
         }
         __syncthreads();
         if (Epi::kCanStop) {
-            int total = 0, wave_pre = 0;
+            int total = 0, open = 0, wave_pre = 0;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 const int x = s_done[ai & 1][w];
                 total += x;
+                open += s_open[ai & 1][w];
                 wave_pre += w < wave ? x : 0;
             }
             total = __builtin_amdgcn_readfirstlane(total);
+            open = __builtin_amdgcn_readfirstlane(open);
             // every entry has its p; the next entry's loads have landed
             // (vmcnt(0) above) and are left unused
             if (total == 0) break;
@@ -457,8 +525,24 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
             if (ai + 1 < nact && epi.can_hand_over(total)) {
                 if (tid == 0) s_tail_base = atomicAdd(epi.tail_counter(), (uint32_t)total);
                 __syncthreads();
-                epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), e + 1, t);
+                epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), e, e0, t);
                 break;
+            }
+            // going down with nothing open left: only the entries parked at
+            // the start wait, for larger p; skip to the way up (plan entry
+            // e0 - 1) and reload its first K step in place of the prefetched one
+            const int n_down = plan.n - e0;
+            if (open == 0 && e >= e0 && e0 > 0 && ai + 1 < n_down) {
+                ai = n_down - 1;  // ++ai below -> first entry of the way up
+                la_ = n_down;
+                ls = 0;
+                lkt = 0;
+                if (nkt > 0) {
+                    issue(la_, ls, lkt, buf);
+                    advance(la_, ls, lkt);
+                }
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
             }
         }
     }
@@ -472,6 +556,38 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
 // X and Y plane rows for the plan entries from e_next on, recorded exactly
 // as the record epilogue does (S, p* index; with the r = 1 projection S at
 // the next smaller p in out2) for the select-root pass.
+// S_p of one entry: lane l sums the 2-element chunks l, l + 64, ... in
+// order, U chunks loaded before any is used (16 loads in flight per wave).
+__device__ double tail_dot_f64(const double* xr, const double* yr, const PlanEntry& pe, const GemmGeomF64& g,
+                               int lane) {
+    const double* xp = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
+    const double* yp = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
+    double acc = 0.0;
+    int64_t k0 = lane * 2;
+    constexpr int U = 8;
+    for (; k0 + (U - 1) * 128 < g.kp; k0 += U * 128) {
+        double2 vx[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vx[u] = *(const double2*)(xp + k0 + u * 128);
+            vy[u] = *(const double2*)(yp + k0 + u * 128);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc = fma(vx[u].x, vy[u].x, acc);
+            acc = fma(vx[u].y, vy[u].y, acc);
+        }
+    }
+    for (; k0 < g.kp; k0 += 128) {
+        const double2 vx = *(const double2*)(xp + k0), vy = *(const double2*)(yp + k0);
+        acc = fma(vx.x, vy.x, acc);
+        acc = fma(vx.y, vy.y, acc);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+    return acc;
+}
+
 template <bool R1>
 __global__ __launch_bounds__(256) void mt_tail_f64_kernel(GemmGeomF64 g, FamilyPlan plan, EpiArgs a) {
     const int lane = threadIdx.x & 63;
@@ -485,19 +601,25 @@ __global__ __launch_bounds__(256) void mt_tail_f64_kernel(GemmGeomF64 g, FamilyP
         const int64_t o = ((int64_t)te.bi * g.rows + te.i) * g.cols + te.j;
         const double* xr = g.X + (int64_t)te.bi * g.x_batch_elems + (int64_t)te.i * g.kp;
         const double* yr = g.Y + (int64_t)te.bi * g.y_batch_elems + (int64_t)te.j * g.kp;
-        bool pend = R1 && te.pending != 0;
+        if (!R1 && te.state == kTailRise) {
+            // stable at e_next + 1 (recorded): go up while a larger p may be
+            // stable too; an unstable p leaves the record below standing
+            for (int e = te.e_next; e >= 0; --e) {
+                const PlanEntry& pe = plan.e[e];
+                const double acc = tail_dot_f64(xr, yr, pe, g, lane);
+                if (!(acc >= plan.tau)) break;
+                if (lane == 0) {
+                    out[o] = acc;
+                    a.pstar[o] = (uint8_t)pe.pidx;
+                }
+                if (!(acc >= pe.rise_thr)) break;
+            }
+            continue;
+        }
+        bool pend = R1 && te.state == kTailR1;
         for (int e = te.e_next; e < plan.n; ++e) {
             const PlanEntry& pe = plan.e[e];
-            const double* xp = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
-            const double* yp = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
-            double acc = 0.0;
-            for (int64_t k0 = lane * 2; k0 < g.kp; k0 += 128) {
-                const double2 vx = *(const double2*)(xp + k0), vy = *(const double2*)(yp + k0);
-                acc = fma(vx.x, vy.x, acc);
-                acc = fma(vx.y, vy.y, acc);
-            }
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+            const double acc = tail_dot_f64(xr, yr, pe, g, lane);
             if (R1 && pend) {
                 if (lane == 0) out2[o] = acc;
                 break;

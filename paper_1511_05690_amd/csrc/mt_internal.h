@@ -34,7 +34,8 @@ constexpr int kAdjF64BM = 64;
 struct WsHeader {
     int32_t domain_flag;
     uint32_t tail_count;
-    int32_t pad[6];
+    int32_t start;       // plan index the forward's p search starts at
+    int32_t pad[5];
     int32_t hist[MT_MAX_P + 1];
 };
 
@@ -43,9 +44,14 @@ struct WsHeader {
 // the plan for it alone (one dot product per p).
 struct TailEntry {
     int32_t bi, i, j;  // batch item, row, column
-    int16_t e_next;    // first plan entry still to run
-    int16_t pending;   // r = 1 projection: S at p* parked in the output, finish at e_next
+    int16_t e_next;    // next plan entry to run
+    int16_t state;     // kTailOpen, kTailR1 or kTailRise
 };
+// TailEntry::state
+constexpr int16_t kTailOpen = 0;  // no stable p yet: run e_next, e_next + 1, ... (smaller p)
+constexpr int16_t kTailR1 = 1;    // r = 1 projection: S at p* parked in the output, finish at e_next
+constexpr int16_t kTailRise = 2;  // stable at e_next + 1 (S parked), a larger p may be too:
+                                  // run e_next, e_next - 1, ... (larger p)
 
 // Processing plan of the p family for one fused GEMM launch.  Entries are in
 // processing order (largest p first); `pidx` maps back to the family index.
@@ -59,6 +65,11 @@ struct PlanEntry {
     float inv_p;        // 1 / p
     float corr;         // k^(-1/p) with MT_FLAG_NORM_CORRECT, else 1
     float inv_dp;       // 1 / (p - p_next) for the next (smaller) p of the plan, 0 if none
+    // S_q <= S_p^(q/p) for the next larger p = q (terms in [0, 1]): S below
+    // rise_thr = (tau / margin)^(p/q) rules every larger p out; +inf for the
+    // largest p.  rise_thr_f is its FP32 value rounded down.
+    double rise_thr;
+    float rise_thr_f;
 };
 
 struct FamilyPlan {
@@ -88,6 +99,7 @@ struct EpiArgs {
     TailEntry* tail;     // nullable: sparse-tail list (capacity tail_max per tile)
     uint32_t* tail_count;
     int32_t tail_max;    // a tile with 1..tail_max undecided entries hands them over
+    const int32_t* start;  // nullable: plan index the p search starts at (0: largest p)
 };
 
 // Adjoint epilogue: out = sum over the p that some entry uses of
@@ -105,6 +117,7 @@ struct AdjArgs {
 // ---------------------------------------------------------------- launchers
 // Every launcher returns hipSuccess or the launch error.
 hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st);
+hipError_t launch_fill_u32(void* p, uint32_t value, int64_t words, hipStream_t st);
 hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r,
                          int32_t* flag, hipStream_t st);
 hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n, double* c,

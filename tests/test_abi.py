@@ -152,3 +152,27 @@ def test_projection_flag_validation():
     assert st == 5 and b"projection" in lib.maxtimes_last_error()
     with pytest.raises(ValueError):
         mt._projection_flag("r2")
+
+
+def test_search_start_validation():
+    """The forward search start is a plan index in 0 .. MT_MAX_P - 1."""
+    old = mt.search_start()
+    try:
+        for bad in (-1, mt.MAX_P):
+            with pytest.raises(mt.MaxTimesError) as e:
+                mt.set_search_start(bad)
+            assert e.value.status == 1
+        mt.set_search_start(3)
+        assert mt.search_start() == 3
+    finally:
+        mt.set_search_start(old)
+
+
+def test_bf16_inner_dimension_limit():
+    """The BF16 path contracts at most 2^23 terms per entry; the FP64 path
+    keeps the general 2^24 limit."""
+    assert _ws([1, 2], path="bf16", k=1 << 23) > 0
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([1, 2], path="bf16", k=(1 << 23) + 1)
+    assert e.value.status == 5
+    assert _ws([1, 2], path="fp64", k=(1 << 23) + 1) > 0
