@@ -225,9 +225,9 @@ mt_status maxtimes_timing_work(const char* prefix, double* flops);
  * dot product of a plane row of A'^p and of B'^p per p, FP32 accumulation on
  * the BF16 path, FP64 on the FP64 path) and stops.  Results equal the dense
  * path's up to the order of the FP32 / FP64 summation.  0 disables it; the
- * default is 256.  The workspace sizes grow by 16 bytes x max_entries per
- * output tile, so query them after changing the threshold (a workspace sized
- * before is reported too small).  Process-wide; not synchronised with calls
+ * default is 512.  The workspace sizes grow by 32 bytes x max_entries per
+ * output tile (the list and its copy sorted by row), so query them after
+ * changing the threshold (a workspace sized before is reported too small).  Process-wide; not synchronised with calls
  * in flight on other threads.
  */
 mt_status maxtimes_set_tail_threshold(int32_t max_entries);
@@ -235,16 +235,20 @@ int32_t maxtimes_tail_threshold(void);
 
 /*
  * Where the forward p search starts (Sec. 1 defines p* as the largest stable
- * p; the search order only decides how much work finds it).  0, the default,
+ * p; the search order only decides how much work finds it).  entry = 0
  * visits the family from the largest p down.  entry = s > 0 starts at the
  * s-th largest p (clamped to the smallest): going down from there decides
  * every entry that is not stable at the start; an entry stable at the start
  * waits unless its S rules out every larger p (S_p' <= S_p^(p'/p) for terms
  * in [0, 1]), and after the smallest p the search goes up from the (s-1)-th
  * largest p until each waiting entry meets an unstable p or such an S.
+ * entry = -1, the default, lets a pilot choose per product: it forms S_p for
+ * every p on a 64 x 64 grid of sampled output entries and takes the start
+ * with the lowest estimated dense GEMM and sparse-tail work (products with
+ * fewer than 2^22 outputs, or with the tail off, start at the largest p).
  * Results equal those of the top-down search up to entries whose S lies
  * within rounding of tau.  The r = 1 projection always searches from the
- * largest p.  Returns MT_ERR_INVALID_ARG outside 0 .. MT_MAX_P - 1.
+ * largest p.  Returns MT_ERR_INVALID_ARG outside -1 .. MT_MAX_P - 1.
  * Process-wide; not synchronised with calls in flight on other threads.
  */
 mt_status maxtimes_set_search_start(int32_t entry);

@@ -350,9 +350,10 @@ def tail_threshold():
 
 def set_search_start(entry):
     """Start the forward p search at the ``entry``-th largest p (0: the
-    largest, the default), go down to the smallest p, then up for the entries
-    still stable at the start.  Same p* as the top-down search up to entries
-    whose S lies within rounding of tau.  Process-wide."""
+    largest), go down to the smallest p, then up for the entries still stable
+    at the start; -1 (the default): a pilot on sampled entries chooses per
+    product.  Same p* as the top-down search up to entries whose S lies
+    within rounding of tau.  Process-wide."""
     _check(load_library().maxtimes_set_search_start(int(entry)))
 
 

@@ -244,14 +244,22 @@ Geom product_geom(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
 }
 
 struct Layout {
-    size_t hdr, r, c, ap, bp, s, s2, code, tail, x, total;
+    size_t hdr, r, c, ap, bp, s, s2, code, tail, tail_sorted, tail_bucket, pilot, x, total;
     int32_t tail_max;  // sparse-tail threshold the layout was sized for (0: no tail)
+    int32_t tail_shift, tail_buckets;  // row buckets of the tail sort
 };
 
 // A tile with at most this many undecided entries hands them to the sparse
-// tail (0 disables it).  256 of a 256 x 256 BF16 tile is 0.4 %.
-std::atomic<int32_t> g_tail_max{256};
-std::atomic<int32_t> g_start_entry{0};
+// tail (0 disables it).  512 of a 256 x 256 BF16 tile is 0.8 %.
+std::atomic<int32_t> g_tail_max{512};
+// Forward search start: a plan index, or kStartAuto (the pilot chooses).
+constexpr int32_t kStartAuto = -1;
+std::atomic<int32_t> g_start_entry{kStartAuto};
+
+// The pilot runs for products of at least this many output entries (below,
+// its fixed cost is not worth it and the search starts at the largest p).
+constexpr int64_t kPilotMinOutputs = (int64_t)1 << 22;
+constexpr int32_t kPilotKParts = kMaxPilotKParts;
 
 // The workspace of one product (plus an APSP X buffer when x_bytes > 0).
 Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64_t b, int64_t m,
@@ -275,8 +283,24 @@ Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64
     // has a single p: nothing would be left to run)
     L.tail_max = f.n > 1 ? g_tail_max.load() : 0;
     const int64_t tiles = b * (g.mp / g.bm) * (g.np / g.bm);
+    const size_t list_bytes = align_up((size_t)tiles * (size_t)L.tail_max * sizeof(TailEntry));
     L.tail = off;
-    off += align_up((size_t)tiles * (size_t)L.tail_max * sizeof(TailEntry));
+    off += list_bytes;
+    // the list sorted by row bucket and state (two buckets per row bucket):
+    // rows (over the batch) merged in powers of two until at most
+    // kTailBuckets buckets remain
+    L.tail_shift = 0;
+    while (2 * (((b * m - 1) >> L.tail_shift) + 1) > kTailBuckets) ++L.tail_shift;
+    L.tail_buckets = L.tail_max > 0 && b * m > 0 ? (int32_t)(2 * (((b * m - 1) >> L.tail_shift) + 1)) : 0;
+    L.tail_sorted = off;
+    off += L.tail_max > 0 ? list_bytes : 0;
+    L.tail_bucket = off;
+    off += align_up((size_t)(L.tail_buckets + 3) / 4 * 16);
+    // pilot partial sums (float on the BF16 path, double on FP64)
+    L.pilot = off;
+    off += f.n > 1 ? align_up((size_t)kPilotKParts * f.n * kMaxPilotSide * kMaxPilotSide * (f.bf16 ? 4 : 8)) +
+                         align_up(sizeof(PilotCounts))
+                   : 0;
     L.x = off;
     off += align_up(x_bytes);
     L.total = off;
@@ -373,7 +397,35 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     if (!plan.r1) {
         WsHeader* hdr = (WsHeader*)(ws + L.hdr);
         const int32_t s0 = g_start_entry.load();
-        MT_TRY(launch_fill_u32(&hdr->start, (uint32_t)(s0 < f.n ? s0 : f.n - 1), 1, st), "p search start");
+        if (s0 == kStartAuto && L.tail_max > 0 && f.n > 2 && k >= 256 && b * m * n >= kPilotMinOutputs) {
+            PilotArgs pa;
+            memset(&pa, 0, sizeof pa);
+            pa.X = ap;
+            pa.Y = bp;
+            pa.x_plane_elems = g.mp * g.kp;
+            pa.y_plane_elems = g.np * g.kp;
+            pa.x_batch_elems = pa.x_plane_elems * ps.n_planes;
+            pa.y_batch_elems = pa.y_plane_elems * ps.n_planes;
+            pa.kp = g.kp;
+            pa.rows = m;
+            pa.cols = n;
+            pa.b = b;
+            pa.nr = (int32_t)std::min<int64_t>(kMaxPilotSide, m);
+            pa.nc = (int32_t)std::min<int64_t>(kMaxPilotSide, n);
+            pa.kparts = (int32_t)std::max<int64_t>(1, std::min<int64_t>(kPilotKParts, g.kp / 512));
+            pa.tail_max = L.tail_max;
+            pa.tile_entries = (int64_t)std::min<int64_t>(g.bm, m) * std::min<int64_t>(f.bf16 ? kBf16BN : g.bm, n);
+            // one tail dot product (two plane rows of k_pad elements from
+            // HBM) against one dense tile entry (2 BM BN k_pad flops at the
+            // GEMM's rate), measured on MI355X: about 1/250
+            pa.kappa = 1.0f / 250.0f;
+            pa.part = ws + L.pilot;
+            pa.counts = ws + L.pilot + align_up((size_t)kPilotKParts * f.n * kMaxPilotSide * kMaxPilotSide * (f.bf16 ? 4 : 8));
+            MT_TRY(launch_choose_start(pa, plan, &hdr->start, f.bf16 ? 0 : 1, st), "p search start (pilot)");
+        } else {
+            const int32_t s1 = s0 < 0 ? 0 : (s0 < f.n ? s0 : f.n - 1);
+            MT_TRY(launch_fill_u32(&hdr->start, (uint32_t)s1, 1, st), "p search start");
+        }
         epi.start = &hdr->start;
     }
     if (L.tail_max > 0 && k > 0) {
@@ -382,6 +434,10 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
         epi.tail = (TailEntry*)(ws + L.tail);
         epi.tail_count = &hdr->tail_count;
         epi.tail_max = L.tail_max;
+        epi.tail_sorted = (TailEntry*)(ws + L.tail_sorted);
+        epi.tail_bucket = (int32_t*)(ws + L.tail_bucket);
+        epi.tail_shift = L.tail_shift;
+        epi.tail_buckets = L.tail_buckets;
     }
     if (f.bf16) {
         epi.mode = mode;
@@ -713,8 +769,8 @@ int32_t maxtimes_tail_threshold(void) { return g_tail_max.load(); }
 
 mt_status maxtimes_set_search_start(int32_t entry) {
     g_last_error.clear();
-    if (entry < 0 || entry >= MT_MAX_P)
-        return fail(MT_ERR_INVALID_ARG, "search start %d outside 0..%d", entry, MT_MAX_P - 1);
+    if (entry < -1 || entry >= MT_MAX_P)
+        return fail(MT_ERR_INVALID_ARG, "search start %d outside -1..%d", entry, MT_MAX_P - 1);
     g_start_entry.store(entry);
     return MT_OK;
 }

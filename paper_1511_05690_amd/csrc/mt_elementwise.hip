@@ -42,6 +42,72 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, int64_t words) {
     for (; i < words; i += stride) p[i] = value;
 }
 
+// ---------------------------------------------------------------- tail sort
+// Counting sort of the sparse-tail list by row bucket and state: counts, an exclusive
+// scan of the counts (one block), then each entry to its bucket's next slot.
+// The order inside a bucket is whatever the atomics give; each entry's
+// result does not depend on it.
+// Bucket of an entry: its row bucket, and within it the open entries after
+// the others (entries of one row with one state are then adjacent).
+__device__ __forceinline__ int64_t tail_key(const TailEntry& te, int64_t rows, int shift) {
+    return ((((int64_t)te.bi * rows + te.i) >> shift) << 1) | (te.state == kTailOpen ? 1 : 0);
+}
+
+__global__ void tail_hist_kernel(const TailEntry* __restrict__ in, const uint32_t* __restrict__ count,
+                                 int64_t rows, int shift, int32_t* __restrict__ bucket) {
+    const int64_t nent = *count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nent; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&bucket[tail_key(in[i], rows, shift)], 1);
+}
+
+// Exclusive prefix sum of bucket[0 .. nb) in place, one block of
+// kScanThreads: thread t scans a contiguous run of the buckets (a multiple of
+// 4 long, read and written as int4; the bucket array is 16-byte aligned and
+// padded to a multiple of 4 entries).
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void tail_scan_kernel(int32_t* __restrict__ bucket, int32_t nb) {
+    __shared__ int32_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int nb4 = (nb + 3) / 4;
+    const int per4 = (nb4 + kScanThreads - 1) / kScanThreads;
+    const int lo = min(t * per4, nb4), hi = min(lo + per4, nb4);
+    int4* b4 = (int4*)bucket;
+    int32_t sum = 0;
+    for (int i = lo; i < hi; ++i) {
+        const int4 v = b4[i];
+        sum += v.x + v.y + v.z + v.w;
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const int32_t y = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        const int4 v = b4[i];
+        int4 o;
+        o.x = run;
+        o.y = run + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        run = o.w + v.w;
+        b4[i] = o;
+    }
+}
+
+__global__ void tail_scatter_kernel(const TailEntry* __restrict__ in, const uint32_t* __restrict__ count,
+                                    int64_t rows, int shift, int32_t* __restrict__ bucket,
+                                    TailEntry* __restrict__ out) {
+    const int64_t nent = *count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nent; i += (int64_t)gridDim.x * blockDim.x) {
+        const TailEntry te = in[i];
+        out[atomicAdd(&bucket[tail_key(te, rows, shift)], 1)] = te;
+    }
+}
+
 // One wave per row: r[row] = max_k A[row, k]; flags invalid entries.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict__ A, int64_t rows,
@@ -350,6 +416,21 @@ hipError_t launch_fill_u32(void* p, uint32_t value, int64_t words, hipStream_t s
 }
 
 hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st) { return launch_fill_u32(p, 0u, words, st); }
+
+hipError_t launch_tail_sort(const EpiArgs& epi, int64_t rows, int64_t cap, hipStream_t st) {
+    if (cap <= 0) return hipSuccess;
+    hipError_t e = launch_fill_zero_u32(epi.tail_bucket, (epi.tail_buckets + 3) / 4 * 4, st);
+    if (e != hipSuccess) return e;
+    const dim3 grid(grid_for(cap, kThreads, 1024));
+    timing_before("mt_tail_sort", st);
+    hipLaunchKernelGGL(tail_hist_kernel, grid, dim3(kThreads), 0, st, epi.tail, epi.tail_count, rows,
+                       epi.tail_shift, epi.tail_bucket);
+    hipLaunchKernelGGL(tail_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, epi.tail_bucket, epi.tail_buckets);
+    hipLaunchKernelGGL(tail_scatter_kernel, grid, dim3(kThreads), 0, st, epi.tail, epi.tail_count, rows,
+                       epi.tail_shift, epi.tail_bucket, epi.tail_sorted);
+    timing_after(st);
+    return hipGetLastError();
+}
 
 hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r, int32_t* flag,
                          hipStream_t st) {

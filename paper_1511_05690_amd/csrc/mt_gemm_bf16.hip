@@ -854,142 +854,209 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
-// S_p of one entry for plan entry pe, reduced over the wave.  Lane l sums
-// the 8-element chunks l, l + 64, ... of the row in order; U chunks are
-// loaded before any is used, so that each wave keeps 16 loads in flight
-// (the kernel is bound by load latency, not bandwidth, with one load at a
-// time).
-__device__ float tail_dot_bf16(const uint16_t* xr, const uint16_t* yr, const PlanEntry& pe, const GemmGeom& g,
-                               int lane) {
-    float acc = 0.f;
-    int64_t k0 = lane * 8;
+// S_p of up to G entries of one row at once (act: which take part): each
+// chunk of the row's X plane is loaded once for all of them.  Lane l sums the
+// 8-element chunks l, l + 64, ... in order, as tail_dot_bf16 does.
+template <int G>
+__device__ void tail_dot_group_bf16(const uint16_t* xr, const uint16_t* const (&yr)[G], const bool (&act)[G],
+                                    const PlanEntry& pe, const GemmGeom& g, int lane, float (&S)[G]) {
+    float acc[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) acc[q] = 0.f;
     if (pe.nseg == 3) {
         const uint16_t* xh = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
         const uint16_t* xl = xr + (int64_t)pe.a_plane[2] * g.x_plane_elems;
-        const uint16_t* yh = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
-        const uint16_t* yl = yr + (int64_t)pe.b_plane[1] * g.y_plane_elems;
-        auto chunk = [&](const u32x4& vxh, const u32x4& vxl, const u32x4& vyh, const u32x4& vyl) {
+        const int64_t oyh = (int64_t)pe.b_plane[0] * g.y_plane_elems;
+        const int64_t oyl = (int64_t)pe.b_plane[1] * g.y_plane_elems;
+        for (int64_t k0 = lane * 8; k0 < g.kp; k0 += 512) {
+            const u32x4 vxh = *(const u32x4*)(xh + k0), vxl = *(const u32x4*)(xl + k0);
+            u32x4 vyh[G], vyl[G];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc += bf16_lo(vxh[q]) * bf16_lo(vyh[q]);
-                acc += bf16_lo(vxh[q]) * bf16_lo(vyl[q]);
-                acc += bf16_lo(vxl[q]) * bf16_lo(vyh[q]);
-                acc += bf16_hi(vxh[q]) * bf16_hi(vyh[q]);
-                acc += bf16_hi(vxh[q]) * bf16_hi(vyl[q]);
-                acc += bf16_hi(vxl[q]) * bf16_hi(vyh[q]);
-            }
-        };
-        constexpr int U = 4;
-        for (; k0 + (U - 1) * 512 < g.kp; k0 += U * 512) {
-            u32x4 vxh[U], vxl[U], vyh[U], vyl[U];
+            for (int q = 0; q < G; ++q)
+                if (act[q]) {
+                    vyh[q] = *(const u32x4*)(yr[q] + oyh + k0);
+                    vyl[q] = *(const u32x4*)(yr[q] + oyl + k0);
+                }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                vxh[u] = *(const u32x4*)(xh + k0 + u * 512);
-                vxl[u] = *(const u32x4*)(xl + k0 + u * 512);
-                vyh[u] = *(const u32x4*)(yh + k0 + u * 512);
-                vyl[u] = *(const u32x4*)(yl + k0 + u * 512);
-            }
+            for (int q = 0; q < G; ++q)
+                if (act[q]) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) chunk(vxh[u], vxl[u], vyh[u], vyl[u]);
+                    for (int h = 0; h < 4; ++h) {
+                        acc[q] += bf16_lo(vxh[h]) * bf16_lo(vyh[q][h]);
+                        acc[q] += bf16_lo(vxh[h]) * bf16_lo(vyl[q][h]);
+                        acc[q] += bf16_lo(vxl[h]) * bf16_lo(vyh[q][h]);
+                        acc[q] += bf16_hi(vxh[h]) * bf16_hi(vyh[q][h]);
+                        acc[q] += bf16_hi(vxh[h]) * bf16_hi(vyl[q][h]);
+                        acc[q] += bf16_hi(vxl[h]) * bf16_hi(vyh[q][h]);
+                    }
+                }
         }
-        for (; k0 < g.kp; k0 += 512)
-            chunk(*(const u32x4*)(xh + k0), *(const u32x4*)(xl + k0), *(const u32x4*)(yh + k0),
-                  *(const u32x4*)(yl + k0));
     } else {
         const uint16_t* xp = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
-        const uint16_t* yp = yr + (int64_t)pe.b_plane[0] * g.y_plane_elems;
-        auto chunk = [&](const u32x4& vx, const u32x4& vy) {
+        const int64_t oy = (int64_t)pe.b_plane[0] * g.y_plane_elems;
+        for (int64_t k0 = lane * 8; k0 < g.kp; k0 += 512) {
+            const u32x4 vx = *(const u32x4*)(xp + k0);
+            u32x4 vy[G];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc += bf16_lo(vx[q]) * bf16_lo(vy[q]);
-                acc += bf16_hi(vx[q]) * bf16_hi(vy[q]);
-            }
-        };
-        constexpr int U = 8;
-        for (; k0 + (U - 1) * 512 < g.kp; k0 += U * 512) {
-            u32x4 vx[U], vy[U];
+            for (int q = 0; q < G; ++q)
+                if (act[q]) vy[q] = *(const u32x4*)(yr[q] + oy + k0);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                vx[u] = *(const u32x4*)(xp + k0 + u * 512);
-                vy[u] = *(const u32x4*)(yp + k0 + u * 512);
-            }
+            for (int q = 0; q < G; ++q)
+                if (act[q]) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) chunk(vx[u], vy[u]);
+                    for (int h = 0; h < 4; ++h) {
+                        acc[q] += bf16_lo(vx[h]) * bf16_lo(vy[q][h]);
+                        acc[q] += bf16_hi(vx[h]) * bf16_hi(vy[q][h]);
+                    }
+                }
         }
-        for (; k0 < g.kp; k0 += 512) chunk(*(const u32x4*)(xp + k0), *(const u32x4*)(yp + k0));
     }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
-    return acc;
+    for (int q = 0; q < G; ++q) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) acc[q] += __shfl_xor(acc[q], d);
+        S[q] = acc[q];
+    }
 }
+
+// Entries of one row with the same state are taken in groups of up to
+// kTailGroup, which share the row's X plane loads.
+constexpr int kTailGroup = 4;
 
 template <int MODE, typename TO, bool R1>
 __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPlan plan, EpiArgs a) {
+    constexpr int G = kTailGroup;
     const int lane = threadIdx.x & 63;
     const uint32_t count = __builtin_amdgcn_readfirstlane(*a.tail_count);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    // each wave takes a contiguous run of the list, which is sorted by row
+    // (and state within a row)
+    const int64_t run = ((int64_t)count + waves - 1) / waves;
+    const int64_t w0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * run;
+    const int64_t w1 = min<int64_t>(w0 + run, (int64_t)count);
     TO* out = (TO*)a.out;
-    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < (int64_t)count;
-         w += waves) {
-        const TailEntry te = a.tail[w];
-        const int64_t o = ((int64_t)te.bi * g.rows + te.i) * g.cols + te.j;
-        const uint16_t* xr = g.X + (int64_t)te.bi * g.x_batch_elems + (int64_t)te.i * g.kp;
-        const uint16_t* yr = g.Y + (int64_t)te.bi * g.y_batch_elems + (int64_t)te.j * g.kp;
-        const float rc = (a.r ? (float)a.r[(int64_t)te.bi * g.rows + te.i] : 1.f) *
-                         (a.c ? (float)a.c[(int64_t)te.bi * g.cols + te.j] : 1.f);
-        float Sh = te.state != kTailOpen ? (float)out[o] : 0.f;
-        float v = 0.f;
-        if (!R1 && te.state == kTailRise) {
+    const float tau_f = plan.tau_f;
+    for (int64_t w = w0; w < w1;) {
+        TailEntry te[G];
+        te[0] = a.tail_sorted[w];
+        int gn = 1;
+        while (gn < G && w + gn < w1) {
+            const TailEntry t = a.tail_sorted[w + gn];
+            if (t.bi != te[0].bi || t.i != te[0].i || t.state != te[0].state) break;
+            te[gn++] = t;
+        }
+        w += gn;
+        const int16_t state = te[0].state;
+        const uint16_t* xr = g.X + (int64_t)te[0].bi * g.x_batch_elems + (int64_t)te[0].i * g.kp;
+        const float r_i = a.r ? (float)a.r[(int64_t)te[0].bi * g.rows + te[0].i] : 1.f;
+        const uint16_t* yr[G];
+        int64_t o[G];
+        float Sh[G], S[G];
+        int e_first[G];
+        bool live[G], act[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            live[q] = q < gn;
+            const TailEntry& t = te[q < gn ? q : 0];
+            yr[q] = g.Y + (int64_t)t.bi * g.y_batch_elems + (int64_t)t.j * g.kp;
+            o[q] = ((int64_t)t.bi * g.rows + t.i) * g.cols + t.j;
+            e_first[q] = t.e_next;
+            Sh[q] = (live[q] && state != kTailOpen) ? (float)out[o[q]] : 0.f;
+        }
+        // final value of entry q: the scales, clamp and APSP diagonal
+        auto put = [&](int q, float v) {
+            v *= r_i * (a.c ? (float)a.c[(int64_t)te[q].bi * g.cols + te[q].j] : 1.f);
+            if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
+            if (MODE == EPI_APSP_X && te[q].i == te[q].j) v = 1.f;
+            if (lane == 0) out[o[q]] = (TO)v;
+            live[q] = false;
+        };
+        if (!R1 && state == kTailRise) {
             // stable at e_next + 1 (S parked): go up while a larger p may be
             // stable too
-            for (int e = te.e_next;; --e) {
+            int e = e_first[0];
+#pragma unroll
+            for (int q = 1; q < G; ++q)
+                if (live[q] && e_first[q] > e) e = e_first[q];
+            for (; e >= 0; --e) {
+                bool any_live = false, any_act = false;
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    act[q] = live[q] && e <= e_first[q];
+                    any_live |= live[q];
+                    any_act |= act[q];
+                }
+                if (!any_live) break;
+                if (!any_act) continue;
                 const PlanEntry& pe = plan.e[e];
-                const float S = tail_dot_bf16(xr, yr, pe, g, lane);
-                const bool stable = S >= plan.tau_f;
-                if (stable && lane == 0 && a.pstar) a.pstar[o] = (uint8_t)pe.pidx;
-                if (stable && e > 0 && S >= pe.rise_thr_f) {
-                    Sh = S;
-                    continue;
+                tail_dot_group_bf16<G>(xr, yr, act, pe, g, lane, S);
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (!act[q]) continue;
+                    const bool stable = S[q] >= tau_f;
+                    if (stable && lane == 0 && a.pstar) a.pstar[o[q]] = (uint8_t)pe.pidx;
+                    if (stable && e > 0 && S[q] >= pe.rise_thr_f) {
+                        Sh[q] = S[q];
+                        continue;
+                    }
+                    if (stable) {
+                        put(q, (pe.p == 1 ? S[q] : root_f32(S[q], pe.inv_p)) * pe.corr);
+                    } else {
+                        const PlanEntry& pb = plan.e[e + 1];
+                        put(q, (pb.p == 1 ? Sh[q] : root_f32(Sh[q], pb.inv_p)) * pb.corr);
+                    }
                 }
-                if (stable) {
-                    v = (pe.p == 1 ? S : root_f32(S, pe.inv_p)) * pe.corr;
-                } else {
-                    const PlanEntry& pb = plan.e[e + 1];
-                    v = (pb.p == 1 ? Sh : root_f32(Sh, pb.inv_p)) * pb.corr;
-                }
-                break;
             }
         } else {
-            bool pend = R1 && te.state == kTailR1;
-            for (int e = te.e_next; e < plan.n; ++e) {
+            // going down from e_next (r = 1: an entry parked at p* finishes
+            // at the next smaller p)
+            bool pend[G];
+            int e = e_first[0];
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                pend[q] = R1 && state == kTailR1;
+                if (live[q] && e_first[q] < e) e = e_first[q];
+            }
+            for (; e < plan.n; ++e) {
+                bool any_live = false, any_act = false;
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    act[q] = live[q] && e >= e_first[q];
+                    any_live |= live[q];
+                    any_act |= act[q];
+                }
+                if (!any_live) break;
+                if (!any_act) continue;
                 const PlanEntry& pe = plan.e[e];
-                const float S = tail_dot_bf16(xr, yr, pe, g, lane);
-                if (R1 && pend) {
-                    v = S > 0.f ? root_f32(Sh / S, plan.e[e - 1].inv_dp) : root_f32(Sh, plan.e[e - 1].inv_p);
-                    break;
+                tail_dot_group_bf16<G>(xr, yr, act, pe, g, lane, S);
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (!act[q]) continue;
+                    if (R1 && pend[q]) {
+                        put(q, S[q] > 0.f ? root_f32(Sh[q] / S[q], plan.e[e - 1].inv_dp)
+                                          : root_f32(Sh[q], plan.e[e - 1].inv_p));
+                        continue;
+                    }
+                    const bool stable = S[q] >= tau_f;
+                    if (!(stable || e == plan.n - 1)) continue;
+                    if (lane == 0 && a.pstar) a.pstar[o[q]] = stable ? (uint8_t)pe.pidx : (uint8_t)MT_PSTAR_NONE;
+                    if (R1 && stable && pe.inv_dp > 0.f) {
+                        Sh[q] = S[q];
+                        pend[q] = true;
+                        continue;
+                    }
+                    put(q, (pe.p == 1 ? S[q] : root_f32(S[q], pe.inv_p)) * pe.corr);
                 }
-                const bool stable = S >= plan.tau_f;
-                if (!(stable || e == plan.n - 1)) continue;
-                if (lane == 0 && a.pstar) a.pstar[o] = stable ? (uint8_t)pe.pidx : (uint8_t)MT_PSTAR_NONE;
-                if (R1 && stable && pe.inv_dp > 0.f) {
-                    Sh = S;
-                    pend = true;
-                    continue;
-                }
-                v = (pe.p == 1 ? S : root_f32(S, pe.inv_p)) * pe.corr;
-                break;
             }
         }
-        v *= rc;
-        if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
-        if (MODE == EPI_APSP_X && te.i == te.j) v = 1.f;
-        if (lane == 0) out[o] = (TO)v;
     }
 }
 
 template <int MODE, typename TO, bool R1>
 hipError_t launch_tail(const GemmGeom& g, const FamilyPlan& plan, const EpiArgs& epi, int64_t cap,
                        hipStream_t st) {
+    hipError_t e = launch_tail_sort(epi, g.rows, cap, st);
+    if (e != hipSuccess) return e;
     int64_t blocks = (cap + 3) / 4;
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;

@@ -593,11 +593,14 @@ __global__ __launch_bounds__(256) void mt_tail_f64_kernel(GemmGeomF64 g, FamilyP
     const int lane = threadIdx.x & 63;
     const uint32_t count = __builtin_amdgcn_readfirstlane(*a.tail_count);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    // each wave takes a contiguous run of the row-sorted list
+    const int64_t run = ((int64_t)count + waves - 1) / waves;
+    const int64_t w0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * run;
+    const int64_t w1 = min<int64_t>(w0 + run, (int64_t)count);
     double* out = (double*)a.out;
     double* out2 = (double*)a.out2;
-    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < (int64_t)count;
-         w += waves) {
-        const TailEntry te = a.tail[w];
+    for (int64_t w = w0; w < w1; ++w) {
+        const TailEntry te = a.tail_sorted[w];
         const int64_t o = ((int64_t)te.bi * g.rows + te.i) * g.cols + te.j;
         const double* xr = g.X + (int64_t)te.bi * g.x_batch_elems + (int64_t)te.i * g.kp;
         const double* yr = g.Y + (int64_t)te.bi * g.y_batch_elems + (int64_t)te.j * g.kp;
@@ -700,6 +703,8 @@ hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b
     if (e != hipSuccess || !epi.tail) return e;
     // the sparse tail for the entries the tiles handed over
     const int64_t cap = (int64_t)epi.tail_max * b * g.tiles_m * g.tiles_n;
+    e = launch_tail_sort(epi, g.rows, cap, st);
+    if (e != hipSuccess) return e;
     int64_t blocks = (cap + 3) / 4;
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;

@@ -100,7 +100,16 @@ struct EpiArgs {
     uint32_t* tail_count;
     int32_t tail_max;    // a tile with 1..tail_max undecided entries hands them over
     const int32_t* start;  // nullable: plan index the p search starts at (0: largest p)
+    // The tail kernel runs the list sorted by row bucket (bi * rows + i) >>
+    // tail_shift and state, so that entries of one row can share its plane
+    // rows: tail_sorted has the list's capacity, tail_bucket one int32 per
+    // bucket (tail_buckets of them, two per row bucket, at most kTailBuckets).
+    TailEntry* tail_sorted;
+    int32_t* tail_bucket;
+    int32_t tail_shift;
+    int32_t tail_buckets;
 };
+constexpr int64_t kTailBuckets = 65536;
 
 // Adjoint epilogue: out = sum over the p that some entry uses of
 // (M / scale_rows / scale_cols)^(p-1) .* (X_p Y_p^T).
@@ -118,6 +127,37 @@ struct AdjArgs {
 // Every launcher returns hipSuccess or the launch error.
 hipError_t launch_fill_zero_u32(void* p, int64_t words, hipStream_t st);
 hipError_t launch_fill_u32(void* p, uint32_t value, int64_t words, hipStream_t st);
+
+// Pilot of the search start: S_p of every plan entry on a grid of nr x nc
+// sampled output entries (nr, nc <= kMaxPilotSide) of the planes, then the
+// start with the lowest estimated cost (dense tile entries + kappa per tail
+// dot product) into *start.
+constexpr int kMaxPilotSide = 64;
+constexpr int kMaxPilotKParts = 16;
+struct PilotArgs {
+    const void* X;  // planes as the GEMM reads them (BF16 or FP64)
+    const void* Y;
+    int64_t x_plane_elems, y_plane_elems, x_batch_elems, y_batch_elems, kp;
+    int64_t rows, cols, b;
+    int32_t nr, nc, kparts;
+    int32_t tail_max;      // per-tile tail capacity of the launch
+    int64_t tile_entries;  // output entries of one GEMM tile
+    float kappa;           // one tail dot product in dense tile-entry units
+    void* part;            // kparts x n x kMaxPilotSide^2 partial sums (float or double)
+    void* counts;          // PilotCounts
+};
+// Counts over the sampled entries: es_hist[e] of e* = e (the first stable
+// plan entry, the last if none); stop[s][u]: waiting at start s and decided
+// at plan entry u < s on the way up.
+struct PilotCounts {
+    int32_t es_hist[MT_MAX_P];
+    int32_t stop[MT_MAX_P][MT_MAX_P];
+};
+hipError_t launch_choose_start(const PilotArgs& pa, const FamilyPlan& plan, int32_t* start, int f64,
+                               hipStream_t st);
+// Counting sort of the sparse-tail list (length *count, read on the device)
+// into epi.tail_sorted by row bucket; rows = rows of the output per batch item.
+hipError_t launch_tail_sort(const EpiArgs& epi, int64_t rows, int64_t cap, hipStream_t st);
 hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r,
                          int32_t* flag, hipStream_t st);
 hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n, double* c,

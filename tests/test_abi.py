@@ -155,10 +155,12 @@ def test_projection_flag_validation():
 
 
 def test_search_start_validation():
-    """The forward search start is a plan index in 0 .. MT_MAX_P - 1."""
+    """The forward search start is a plan index in 0 .. MT_MAX_P - 1, or -1
+    (the default: a pilot chooses)."""
+    assert mt.search_start() == -1
     old = mt.search_start()
     try:
-        for bad in (-1, mt.MAX_P):
+        for bad in (-2, mt.MAX_P):
             with pytest.raises(mt.MaxTimesError) as e:
                 mt.set_search_start(bad)
             assert e.value.status == 1

@@ -80,7 +80,7 @@ def test_start_beyond_family_is_clamped(knobs):
     C, ps = knobs.estimate(_dev(A), _dev(B), P=[1, 2, 4], path="bf16", return_pstar=True)
     compare_estimate(C.cpu().numpy(), ps.cpu().numpy(), ref, [1, 2, 4], "bf16")
     with pytest.raises(knobs.MaxTimesError):
-        knobs.set_search_start(-1)
+        knobs.set_search_start(-2)
     with pytest.raises(knobs.MaxTimesError):
         knobs.set_search_start(32)
 
@@ -192,3 +192,33 @@ def test_bf16_apsp_one_squaring(knobs, s):
     Xo = ref["X"]
     assert (X[Xo == 0] == 0).all() and (Xo[X == 0] == 0).all()
     assert (np.abs(X - Xo) / np.maximum(Xo, 1e-300)).max() <= 2e-3
+
+
+@pytest.mark.parametrize("path", ["bf16", "fp64"])
+def test_pilot_start(knobs, path):
+    """The default start (-1): a pilot picks it for a product of >= 2^22
+    outputs.  The chosen start (workspace header, third word) is a plan
+    index, the p* equal those of the top-down search up to entries on tau,
+    and sampled rows match the oracle."""
+    import torch
+
+    m, k, n = 2048, 1024, 2304
+    A, B = lognormal_product(m, k, n, seed=81)
+    if path == "fp64":
+        A, B = A.astype(np.float64), B.astype(np.float64)
+    dA, dB = _dev(A), _dev(B)
+    res = {}
+    for s in (-1, 0):
+        knobs.set_search_start(s)
+        ws = torch.zeros(knobs.workspace_size(1, m, k, n, P128, path=path), dtype=torch.uint8, device="cuda")
+        C, ps = knobs.estimate(dA, dB, P=P128, path=path, return_pstar=True, workspace=ws)
+        torch.cuda.synchronize()
+        res[s] = (C.cpu().numpy(), ps.cpu().numpy(), int(ws[8:12].view(torch.int32).item()))
+    chosen = res[-1][2]
+    print(f"[pilot] {path}: start {chosen}", flush=True)
+    assert 0 <= chosen < len(P128)
+    assert res[0][2] == 0
+    assert (res[-1][1] != res[0][1]).sum() <= 2 + 1e-4 * m * n
+    rows = np.arange(0, m, 97)
+    ref = oracle.pnorm_estimate_rows(A, B, P128, TAU[path], rows)
+    compare_estimate(res[-1][0][rows], res[-1][1][rows], ref, P128, path)
