@@ -273,7 +273,7 @@ def main():
         gemm_ms, gemm_n = mt.timing_read(kname)
         gemm_work = mt.timing_work(kname)
         kern = {}
-        for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_pfamily_gemm", "mt_tail",
+        for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_pilot", "mt_pfamily_gemm", "mt_tail",
                    "mt_select_root", "mt_fill"):
             t, c = mt.timing_read(kn)
             if c:
