@@ -307,8 +307,10 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
                     }
                 }
                 const int64_t off = ((bi * spec.n_planes + pl) * plane_elems) + t * cols_pad + u;
-                *(u32x4*)(base + off) = hi;
-                if (spec.split[q]) *(u32x4*)(base + off + plane_elems) = lo;
+                // streaming stores: the planes are read back only by the GEMM,
+                // long after (measured: the GEMM 1.5 % faster, the planes even)
+                __builtin_nontemporal_store(hi, (u32x4*)(base + off));
+                if (spec.split[q]) __builtin_nontemporal_store(lo, (u32x4*)(base + off + plane_elems));
             } else {
                 double* base = (double*)planes;
                 const int64_t off = ((bi * spec.n_planes + pl) * plane_elems) + t * cols_pad + u;
