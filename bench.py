@@ -179,6 +179,22 @@ def run_legs(mt, torch, np):
                       "vs_exact": {"distance_mse": float((err ** 2).mean()), "max_abs": float(err.abs().max()),
                                    "mean": float(err.mean()), "max_rel_x": float(xrel.max()),
                                    "reachability_equal": bool(torch.equal(torch.isfinite(D), fin))}}
+        # the affine correction (Sec. 4) fitted on the exact rows of 64
+        # sampled sources (Bellman-Ford on the GPU), timed with them
+        src = np.random.default_rng(2002).choice(n2, 64, replace=False).astype(np.int32)
+
+        def correct():
+            rows, _ = mt.apsp_exact_rows(W2, src)
+            return rows, mt.apsp_affine_correct(D, src, rows, apply=False)
+        ms_fit = time_call(correct, 3, torch)
+        rows, ab = correct()
+        Dc = D.clone()
+        ab = mt.apsp_affine_correct(Dc, src, rows)
+        errc = (Dc - D_ex)[fin]
+        a_, b_ = [float(x) for x in ab.cpu()]
+        legs[name]["affine_64_sources"] = {"ms_exact_rows_and_fit": ms_fit, "a": a_, "b": b_,
+                                           "distance_mse": float((errc ** 2).mean()),
+                                           "max_abs": float(errc.abs().max()), "mean": float(errc.mean())}
 
     c4 = config(4)
     A4 = torch.from_numpy(c4["A"]).cuda()

@@ -189,6 +189,50 @@ mt_status apsp_estimate(const float* W, int64_t n, double s, int32_t n_squarings
 mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,
                          int64_t k, int64_t n, void* E, void* stream);
 
+/*
+ * Exact distances from a few sources: the exact pairs on which the affine
+ * correction below is fitted (Sec. 4 suggests Dijkstra's algorithm for a
+ * small number of vertex pairs; on the dense weight matrix the GPU runs
+ * Bellman-Ford instead).
+ *   W        n x n FP32 device, row-major; W[u][v] >= 0 the weight of edge
+ *            u -> v, +inf for no edge (the diagonal is ignored).
+ *   sources  n_src int32 device, each in 0 .. n - 1.
+ *   D        n_src x n FP64 device (output): D[q][v] = the smallest sum of
+ *            weights over paths from sources[q] to v (0 at the source, +inf
+ *            where v is unreachable).
+ *   rounds   host, nullable (output): relaxation rounds run.
+ * Rounds D <- min(D, D (min,+) W) in FP64 from the one-edge distances,
+ * until a round changes nothing (at most n - 1).  Synchronous: the call
+ * waits on the stream every 8 rounds for the convergence flag.  Workspace
+ * from apsp_exact_rows_workspace_size (8 n_src n bytes + 256).  A source
+ * outside 0 .. n - 1 returns MT_ERR_INVALID_ARG.
+ */
+mt_status apsp_exact_rows_workspace_size(int64_t n, int32_t n_src, size_t* bytes);
+mt_status apsp_exact_rows(const float* W, int64_t n, const int32_t* sources, int32_t n_src, double* D,
+                          int64_t* rounds, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Affine correction of an APSP estimate (Sec. 4: an affine model between a
+ * few exact distances and the estimated ones corrects the numerical error,
+ * reducing bias and MSE).  Least squares d_exact = a d_est + b over the pairs
+ * (sources[q], v), v != sources[q], with both distances finite; without such
+ * pairs a = 1, b = 0, and a = 1 when every estimated distance is equal.
+ *   D        n x n estimated distances, dtype (FP32 / FP64), device.
+ *   sources, exact  n_src sources and their n_src x n exact FP64 distances
+ *            (as apsp_exact_rows returns them); sources outside 0 .. n - 1
+ *            contribute no pairs.
+ *   ab       2 doubles device (output): a, b.
+ *   apply    nonzero: D <- max(0, a D + b) in place on every finite
+ *            off-diagonal entry (+inf and the zero diagonal stay).
+ * Asynchronous on the stream; deterministic (fixed-order reductions in
+ * FP64, two passes: means, then centred sums).  Workspace from
+ * apsp_affine_workspace_size.
+ */
+mt_status apsp_affine_workspace_size(size_t* bytes);
+mt_status apsp_affine_correct(void* D, mt_dtype dtype, int64_t n, const int32_t* sources, int32_t n_src,
+                              const double* exact, double* ab, int32_t apply, void* workspace, size_t ws_bytes,
+                              void* stream);
+
 /* Static description of a status code. */
 const char* maxtimes_status_string(mt_status status);
 

@@ -17,7 +17,8 @@ Modules
 pnorm   exact (max, x) product (Alg. 2), the p-norm estimate (Alg. 5 with the
         scaled ring call H' of Sec. 2.1), and its analytic gradient.
 apsp    the (+, min) <-> (x, max) transform (Sec. 2.2), APSP by repeated
-        squaring, Floyd-Warshall and Dijkstra.
+        squaring, Floyd-Warshall and Dijkstra, and the affine correction of
+        an APSP estimate fitted on a few exact distances (Sec. 4).
 exact_c ctypes wrapper of ``exact_maxtimes.c`` (same definition as
         ``pnorm.exact_maxtimes``, for sizes numpy cannot finish quickly).
 
@@ -47,4 +48,6 @@ from .apsp import (  # noqa: F401
     default_squarings,
     floyd_warshall,
     dijkstra,
+    affine_fit,
+    affine_apply,
 )

@@ -127,3 +127,40 @@ def dijkstra(W, sources):
                     dist[v] = nd
                     heapq.heappush(heap, (nd, int(v)))
     return out
+
+
+def affine_fit(D_est, sources, exact_rows):
+    """Sec. 4: an affine model between a few exact distances and the
+    estimated ones.  Least squares d_exact = a d_est + b over the pairs
+    (sources[q], v), v != sources[q], where both distances are finite:
+    a = sum (x - mean x)(y - mean y) / sum (x - mean x)^2, b = mean y -
+    a mean x.  Readings (the paper gives no formula): ordinary least squares
+    on distances; no pairs -> (1, 0); all x equal -> a = 1.  Returns (a, b)."""
+    D_est = np.asarray(D_est, dtype=np.float64)
+    exact_rows = np.asarray(exact_rows, dtype=np.float64)
+    xs, ys = [], []
+    for q, s in enumerate(sources):
+        x = D_est[s].copy()
+        y = exact_rows[q].copy()
+        keep = np.isfinite(x) & np.isfinite(y)
+        keep[s] = False
+        xs.append(x[keep])
+        ys.append(y[keep])
+    x = np.concatenate(xs) if xs else np.zeros(0)
+    y = np.concatenate(ys) if ys else np.zeros(0)
+    if x.size == 0:
+        return 1.0, 0.0
+    mx, my = x.mean(), y.mean()
+    sxx = np.sum((x - mx) ** 2)
+    a = np.sum((x - mx) * (y - my)) / sxx if sxx > 0 else 1.0
+    return float(a), float(my - a * mx)
+
+
+def affine_apply(D, a, b):
+    """D <- max(0, a D + b) on every finite off-diagonal entry (distances are
+    nonnegative; +inf and the zero diagonal stay)."""
+    D = np.array(D, dtype=np.float64, copy=True)
+    n = D.shape[0]
+    m = np.isfinite(D) & ~np.eye(n, dtype=bool)
+    D[m] = np.maximum(0.0, a * D[m] + b)
+    return D

@@ -22,7 +22,7 @@ __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
     "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
     "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold",
-    "set_search_start", "search_start", "pfamily", "PSTAR_NONE", "PATHS",
+    "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
 PSTAR_NONE = 255
@@ -81,6 +81,11 @@ def load_library():
         "apsp_estimate": [vp, i64, ctypes.c_double, ctypes.c_int32, opt, vp, ctypes.c_int, vp, vp,
                           sz, vp],
         "maxtimes_exact": [vp, vp, ctypes.c_int, i64, i64, i64, i64, vp, vp],
+        "apsp_exact_rows_workspace_size": [i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+        "apsp_exact_rows": [vp, i64, vp, ctypes.c_int32, vp, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp],
+        "apsp_affine_workspace_size": [ctypes.POINTER(ctypes.c_size_t)],
+        "apsp_affine_correct": [vp, ctypes.c_int, i64, vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp,
+                                ctypes.c_size_t, vp],
         "maxtimes_timing_enable": [ctypes.c_int],
         "maxtimes_timing_reset": [],
         "maxtimes_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -319,6 +324,50 @@ def exact(A, B):
     E = torch.empty((b, m, n) if batched else (m, n), dtype=A.dtype, device=A.device)
     _check(lib.maxtimes_exact(_ptr(A), _ptr(B), _dtype_code(A), b, m, k, n, _ptr(E), _stream(A.device)))
     return E
+
+
+def apsp_exact_rows(W, sources):
+    """Exact shortest-path distances (FP64, shape len(sources) x n) from each
+    vertex in ``sources`` on the dense FP32 weights W (n x n, +inf = no
+    edge), by Bellman-Ford on the GPU.  Returns (D_rows, rounds).
+    Synchronous."""
+    lib = load_library()
+    if W.dtype != torch.float32 or W.dim() != 2 or W.shape[0] != W.shape[1]:
+        raise TypeError("W must be a square float32 matrix")
+    W = W.contiguous()
+    n = W.shape[0]
+    src = torch.as_tensor(sources, dtype=torch.int32, device=W.device).contiguous()
+    nsrc = src.numel()
+    D = torch.empty((nsrc, n), dtype=torch.float64, device=W.device)
+    nb = ctypes.c_size_t(0)
+    _check(lib.apsp_exact_rows_workspace_size(n, nsrc, ctypes.byref(nb)))
+    ws = _workspace(nb.value, W.device, None)
+    rounds = ctypes.c_int64(0)
+    _check(lib.apsp_exact_rows(_ptr(W), n, _ptr(src), nsrc, _ptr(D), ctypes.byref(rounds), _ptr(ws), nb.value,
+                               _stream(W.device)))
+    return D, rounds.value
+
+
+def apsp_affine_correct(D, sources, exact_rows, apply=True):
+    """Affine correction of an APSP estimate D (n x n, FP32 or FP64, device):
+    least squares exact = a D + b over the pairs (sources[q], v) with both
+    distances finite, then (apply) D <- max(0, a D + b) in place on finite
+    off-diagonal entries.  Returns the device tensor (a, b)."""
+    lib = load_library()
+    if D.dim() != 2 or D.shape[0] != D.shape[1] or not D.is_contiguous():
+        raise TypeError("D must be a contiguous square matrix")
+    n = D.shape[0]
+    src = torch.as_tensor(sources, dtype=torch.int32, device=D.device).contiguous()
+    ex = exact_rows.to(torch.float64).contiguous()
+    if ex.shape != (src.numel(), n):
+        raise ValueError("exact_rows must be len(sources) x n")
+    ab = torch.empty(2, dtype=torch.float64, device=D.device)
+    nb = ctypes.c_size_t(0)
+    _check(lib.apsp_affine_workspace_size(ctypes.byref(nb)))
+    ws = _workspace(nb.value, D.device, None)
+    _check(lib.apsp_affine_correct(_ptr(D), _dtype_code(D), n, _ptr(src), src.numel(), _ptr(ex), _ptr(ab),
+                                   1 if apply else 0, _ptr(ws), nb.value, _stream(D.device)))
+    return ab
 
 
 def timing_enable(on=True):

@@ -757,6 +757,62 @@ mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b
     return MT_OK;
 }
 
+mt_status apsp_exact_rows_workspace_size(int64_t n, int32_t n_src, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");
+    if (n < 0 || n_src < 0) return fail(MT_ERR_INVALID_ARG, "negative size (n=%lld n_src=%d)", (long long)n, n_src);
+    if (n > ((int64_t)1 << 24) || n_src > 65535 * 64)
+        return fail(MT_ERR_UNSUPPORTED, "n above 2^24 or n_src above 65535 x 64");
+    *bytes = exact_rows_workspace(n, n_src);
+    return MT_OK;
+}
+
+mt_status apsp_exact_rows(const float* W, int64_t n, const int32_t* sources, int32_t n_src, double* D,
+                          int64_t* rounds, void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    size_t need = 0;
+    mt_status s = apsp_exact_rows_workspace_size(n, n_src, &need);
+    if (s != MT_OK) return s;
+    if (n == 0 || n_src == 0) {
+        if (rounds) *rounds = 0;
+        return MT_OK;
+    }
+    if (!W || !sources || !D) return fail(MT_ERR_INVALID_ARG, "W, sources or D is NULL");
+    if ((s = check_ws(workspace, ws_bytes, need)) != MT_OK) return s;
+    int64_t r = 0;
+    int32_t bad = 0;
+    MT_TRY(launch_exact_rows(W, n, sources, n_src, D, (uint8_t*)workspace, (hipStream_t)stream, &r, &bad),
+           "exact rows (Bellman-Ford)");
+    if (bad) return fail(MT_ERR_INVALID_ARG, "a source index is outside 0..%lld", (long long)(n - 1));
+    if (rounds) *rounds = r;
+    return MT_OK;
+}
+
+mt_status apsp_affine_workspace_size(size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");
+    *bytes = affine_workspace();
+    return MT_OK;
+}
+
+mt_status apsp_affine_correct(void* D, mt_dtype dtype, int64_t n, const int32_t* sources, int32_t n_src,
+                              const double* exact, double* ab, int32_t apply, void* workspace, size_t ws_bytes,
+                              void* stream) {
+    g_last_error.clear();
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (n < 0 || n_src < 0) return fail(MT_ERR_INVALID_ARG, "negative size (n=%lld n_src=%d)", (long long)n, n_src);
+    if (n > ((int64_t)1 << 24)) return fail(MT_ERR_UNSUPPORTED, "n above 2^24");
+    if (!ab) return fail(MT_ERR_INVALID_ARG, "ab is NULL");
+    if (n > 0 && (!D || (n_src > 0 && (!sources || !exact))))
+        return fail(MT_ERR_INVALID_ARG, "D, sources or exact is NULL");
+    mt_status s = check_ws(workspace, ws_bytes, affine_workspace());
+    if (s != MT_OK) return s;
+    MT_TRY(launch_affine_correct(D, dtype == MT_F64, n, sources, n_src, exact, ab, (uint8_t*)workspace,
+                                 apply != 0 && n > 0, (hipStream_t)stream),
+           "affine correction");
+    return MT_OK;
+}
+
 mt_status maxtimes_set_tail_threshold(int32_t max_entries) {
     g_last_error.clear();
     if (max_entries < 0 || max_entries > 65536)

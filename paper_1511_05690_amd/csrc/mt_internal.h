@@ -155,6 +155,17 @@ struct PilotCounts {
 };
 hipError_t launch_choose_start(const PilotArgs& pa, const FamilyPlan& plan, int32_t* start, int f64,
                                hipStream_t st);
+
+// Exact rows of the APSP distance matrix from a few sources (Bellman-Ford in
+// FP64; the host checks convergence every kExactRowsChunk rounds, so the
+// launch synchronises the stream) and the affine correction fitted on them.
+constexpr int kExactRowsChunk = 8;
+size_t exact_rows_workspace(int64_t n, int32_t nsrc);
+hipError_t launch_exact_rows(const float* W, int64_t n, const int32_t* src, int32_t nsrc, double* D, uint8_t* ws,
+                             hipStream_t st, int64_t* rounds_out, int32_t* bad_out);
+size_t affine_workspace();
+hipError_t launch_affine_correct(void* D, int f64, int64_t n, const int32_t* src, int32_t nsrc, const double* ex,
+                                 double* ab, uint8_t* ws, int apply, hipStream_t st);
 // Counting sort of the sparse-tail list (length *count, read on the device)
 // into epi.tail_sorted by row bucket; rows = rows of the output per batch item.
 hipError_t launch_tail_sort(const EpiArgs& epi, int64_t rows, int64_t cap, hipStream_t st);

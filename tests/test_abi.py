@@ -178,3 +178,23 @@ def test_bf16_inner_dimension_limit():
         _ws([1, 2], path="bf16", k=(1 << 23) + 1)
     assert e.value.status == 5
     assert _ws([1, 2], path="fp64", k=(1 << 23) + 1) > 0
+
+
+def test_affine_and_exact_rows_validation():
+    """Argument checks of the exact-rows and affine entry points (no GPU)."""
+    lib = mt.load_library()
+    nb = ctypes.c_size_t(0)
+    assert lib.apsp_exact_rows_workspace_size(100, 4, ctypes.byref(nb)) == 0
+    assert nb.value >= 100 * 4 * 8
+    assert lib.apsp_exact_rows_workspace_size(-1, 4, ctypes.byref(nb)) == 1
+    assert lib.apsp_affine_workspace_size(ctypes.byref(nb)) == 0 and nb.value > 0
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x100000)
+    st = lib.apsp_exact_rows(null, 10, fake, 2, fake, None, fake, 1 << 20, null)
+    assert st == 1 and b"NULL" in lib.maxtimes_last_error()
+    st = lib.apsp_affine_correct(fake, 7, 10, fake, 2, fake, fake, 1, fake, 1 << 20, null)
+    assert st == 1 and b"dtype" in lib.maxtimes_last_error()
+    st = lib.apsp_affine_correct(fake, 0, 10, fake, 2, fake, null, 1, fake, 1 << 20, null)
+    assert st == 1 and b"ab" in lib.maxtimes_last_error()
+    st = lib.apsp_affine_correct(fake, 0, 10, fake, 2, fake, fake, 1, fake, 1, null)
+    assert st == 3
