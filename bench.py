@@ -166,14 +166,14 @@ def run_legs(mt, torch, np):
         X.fill_diagonal_(1.0)
     D_ex = -torch.log(X) / c2["s"]
     fin = torch.isfinite(D_ex)
-    for proj in (None, "r1"):
+    for proj in (None, "r1", "r2"):
         ms = time_call(lambda: mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"],
                                        out_dtype=torch.float64, projection=proj), 3, torch)
         D = mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"], out_dtype=torch.float64,
                     projection=proj)
         err = (D - D_ex)[fin]
         xrel = (torch.exp(-c2["s"] * D[fin]) / torch.exp(-c2["s"] * D_ex[fin]) - 1.0).abs()
-        name = "apsp_er2048_fp64" + ("_r1" if proj else "")
+        name = "apsp_er2048_fp64" + ("_" + proj if proj else "")
         legs[name] = {"ms": ms, "squarings": c2["T"], "P": c2["P"], "projection": proj or "plain",
                       "ops_per_s": c2["T"] * float(n2) ** 3 / (ms / 1e3),
                       "vs_exact": {"distance_mse": float((err ** 2).mean()), "max_abs": float(err.abs().max()),

@@ -94,6 +94,27 @@ typedef enum { MT_PATH_FP64 = 0, MT_PATH_BF16_SPLIT = 1 } mt_path;
  * output entry.
  */
 #define MT_FLAG_PROJECT_R1  16u
+/*
+ * MT_FLAG_PROJECT_R2: estimate the max by the r = 2 projection (Sec. 1: the
+ * terms modelled as two values, from the 2r = 4 evenly spaced norms q, 2q,
+ * 3q, 4q).  p* is selected from the family as above; with p* = 4q, q and 2q
+ * in the family, the library adds the norm 3q (every such 3p/4 not in the
+ * family, so the family plus these may hold at most MT_MAX_P powers) and
+ * takes C = r c alpha, alpha^q the largest root of g0 + g1 x + g2 x^2, g the
+ * null vector of the Hankel matrix [[S_q, S_2q, S_3q], [S_2q, S_3q, S_4q]].
+ * It is exact when the terms take at most two distinct values.  Where the
+ * four norms are not all available and positive, the matrix has rank 1 (one
+ * distinct value; numerically: |g| <= 1e-8 of the squared norm of the
+ * matrix, after the norms are rescaled to S_kq / c^k with
+ * c = (S_4q / S_q)^(1/3)), or the roots are complex or not positive, the r = 1
+ * projection (MT_FLAG_PROJECT_R1) is used.  FP64 path only
+ * (MT_ERR_UNSUPPORTED on BF16): every power's ring result is kept (no
+ * early exit, 8 bytes per output entry per power of workspace) and a
+ * separate pass selects and projects.  Not with MT_FLAG_NORM_CORRECT or
+ * MT_FLAG_PROJECT_R1 (MT_ERR_INVALID_ARG); maxtimes_estimate_backward
+ * rejects it (MT_ERR_UNSUPPORTED).
+ */
+#define MT_FLAG_PROJECT_R2  32u
 
 #define MT_PSTAR_NONE 255  /* p_star value when no p of the family was stable */
 #define MT_MAX_P 32        /* largest family size */

@@ -43,6 +43,15 @@ design notes of the repository):
       family p_lo = p*/2 and this is (S_{p*} / S_{p*/2})^(2/p*).  Where p*
       is the smallest p, no p is stable, or S_{p_lo} is 0, the plain root
       is used.
+  R7  The r = 2 projection (Sec. 1, onto two values): the paper's 2r
+      evenly spaced norms are read as q, 2q, 3q, 4q with 4q = p* (the
+      largest stable p of the family P; the selection never picks one of
+      the added norms 3q).  The estimate is the largest of the two
+      projected values, i.e. of the positive roots x = alpha^q of the
+      null-space polynomial.  Where p* is not a multiple of 4 with p*/4 and
+      p*/2 in P, a norm is 0, the Hankel matrix has rank 1 (a single
+      distinct value), or no root is real and positive, the r = 1
+      projection (R6) is used instead.
 """
 
 import numpy as np
@@ -165,6 +174,73 @@ def _project_r1(S, P, idx, root):
     return np.where(use, alpha, root)
 
 
+def r2_aux_powers(P):
+    """The extra norms the r = 2 projection needs (Sec. 1: 2r evenly spaced
+    norms q, 2q, 3q, 4q with 4q = p*): 3p/4 for every p of P with p/4 and
+    p/2 in P, where 3p/4 is not in P itself.  Ascending."""
+    Ps = set(int(p) for p in P)
+    return sorted({3 * p // 4 for p in Ps if p % 4 == 0 and p // 4 in Ps and p // 2 in Ps} - Ps)
+
+
+def _project_r2(S, P, idx, fallback, S_aux, aux):
+    """The r = 2 projection of Sec. 1 (reading R7): with p* = P[q] = 4t and
+    the ring results S_t, S_2t, S_3t, S_4t, a null vector g of the Hankel
+    matrix [[S_t, S_2t, S_3t], [S_2t, S_3t, S_4t]] (taken from the SVD) gives
+    the polynomial g0 + g1 x + g2 x^2 whose roots are the projected values
+    alpha^t; the estimate is the largest positive root to the power 1/t.
+    The norms are first divided by c^k (c = (S_4t / S_t)^(1/3)), which only
+    scales the roots by c.  Where the four norms are not all positive and
+    available, the Hankel matrix has rank below 2 (sigma_2 <= 1e-8
+    sigma_1: one distinct value, or so close to one that rounding in the
+    norms, about 1e-16 relative, would decide the roots), or the roots are
+    complex or not positive, ``fallback`` (the r = 1 projection) is used."""
+    P = [int(p) for p in P]
+    pos = {p: ("P", i) for i, p in enumerate(P)}
+    pos.update({p: ("A", i) for i, p in enumerate(aux)})
+    out = np.array(fallback, dtype=np.float64, copy=True)
+    shp = idx.shape
+    flat_idx = idx.reshape(-1)
+    flatS = S.reshape(S.shape[0], -1)
+    flatA = S_aux.reshape(S_aux.shape[0], -1) if len(aux) else None
+    flat_out = out.reshape(-1)
+    for e in range(flat_idx.size):
+        q = int(flat_idx[e])
+        if q == PSTAR_NONE:
+            continue
+        ps = P[q]
+        if ps % 4:
+            continue
+        t = ps // 4
+        need = [t, 2 * t, 3 * t, 4 * t]
+        if any(p not in pos for p in need):
+            continue
+        vals = []
+        for p in need:
+            kind, i = pos[p]
+            vals.append(flatS[i, e] if kind == "P" else flatA[i, e])
+        Sk = np.array(vals, dtype=np.float64)
+        if np.any(Sk <= 0):
+            continue
+        logc = (np.log(Sk[3]) - np.log(Sk[0])) / 3.0
+        tk = np.exp(np.log(Sk) - np.arange(1, 5) * logc)
+        H = np.array([[tk[0], tk[1], tk[2]], [tk[1], tk[2], tk[3]]])
+        _, sv, Vh = np.linalg.svd(H)
+        if sv[1] <= 1e-8 * sv[0]:
+            continue
+        g0, g1, g2 = Vh[-1]
+        if g2 == 0:
+            continue
+        disc = g1 * g1 - 4 * g2 * g0
+        if disc < 0:
+            continue
+        roots = [(-g1 + np.sqrt(disc)) / (2 * g2), (-g1 - np.sqrt(disc)) / (2 * g2)]
+        ymax = max(roots)
+        if not ymax > 0:
+            continue
+        flat_out[e] = np.exp((np.log(ymax) + logc) / t)
+    return out
+
+
 def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None):
     """The p-norm estimate of the (max, x) product (Alg. 5, Sec. 2.1-2.2).
 
@@ -179,8 +255,8 @@ def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None):
     P = [int(p) for p in P]
     if any(p <= 0 for p in P) or any(P[i] >= P[i + 1] for i in range(len(P) - 1)):
         raise ValueError("P must be strictly ascending positive integers")
-    if projection not in (None, "r1"):
-        raise ValueError("projection must be None or 'r1'")
+    if projection not in (None, "r1", "r2"):
+        raise ValueError("projection must be None, 'r1' or 'r2'")
     if projection and norm_correct:
         raise ValueError("norm_correct applies to the plain root only")
     A = _f64(A)
@@ -189,12 +265,20 @@ def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None):
     S, r, c = norm_power_sequence(A, B, P)
     idx = select_pstar(S, tau)
     root, psel, _ = _root(S, P, idx)
-    if projection == "r1":
+    out_aux = {}
+    if projection in ("r1", "r2"):
         root = _project_r1(S, P, idx, root)
+    if projection == "r2":
+        aux = r2_aux_powers(P)
+        S_aux = norm_power_sequence(A, B, aux)[0] if aux else np.zeros((0,) + S.shape[1:])
+        root = _project_r2(S, P, idx, root, S_aux, aux)
+        out_aux = {"S_aux": S_aux, "aux": aux}
     C = r[..., :, None] * c[..., None, :] * root
     if norm_correct and k > 0:
         C = C / np.power(float(k), 1.0 / psel)
-    return {"C": C, "pstar_idx": idx, "pstar": psel, "r": r, "c": c, "S": S}
+    out = {"C": C, "pstar_idx": idx, "pstar": psel, "r": r, "c": c, "S": S}
+    out.update(out_aux)
+    return out
 
 
 def pnorm_estimate_rows(A, B, P, tau, rows, norm_correct=False, projection=None):

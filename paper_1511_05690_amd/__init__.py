@@ -29,8 +29,8 @@ PSTAR_NONE = 255
 MAX_P = 32
 PATHS = {"fp64": 0, "bf16": 1}
 F32, F64 = 0, 1
-FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT, FLAG_PROJECT_R1 = 1, 2, 4, 8, 16
-PROJECTIONS = {None: 0, "r1": FLAG_PROJECT_R1}
+FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT, FLAG_PROJECT_R1, FLAG_PROJECT_R2 = 1, 2, 4, 8, 16, 32
+PROJECTIONS = {None: 0, "r1": FLAG_PROJECT_R1, "r2": FLAG_PROJECT_R2}
 STATUS = {0: "MT_OK", 1: "MT_ERR_INVALID_ARG", 2: "MT_ERR_DOMAIN", 3: "MT_ERR_WORKSPACE",
           4: "MT_ERR_DEVICE", 5: "MT_ERR_UNSUPPORTED"}
 
@@ -273,14 +273,16 @@ def estimate(A, B, P=(1, 2, 4, 8, 16, 32, 64), tau=None, path="bf16", split_max_
     path "bf16": BF16 MFMA ring products with hi/lo split for p <= split_max_p;
     path "fp64": FP64 MFMA ring products.  tau None = the path default.
     projection None: the plain root S_{p*}^(1/p*); "r1": the r = 1
-    projection (S_{p*} / S_{p_lo})^(1/(p* - p_lo)) (MT_FLAG_PROJECT_R1).
+    projection (S_{p*} / S_{p_lo})^(1/(p* - p_lo)) (MT_FLAG_PROJECT_R1);
+    "r2": the r = 2 projection from S at p*/4, p*/2, 3p*/4, p*
+    (MT_FLAG_PROJECT_R2, FP64 path only).
     Differentiable (p* held fixed) when A or B requires grad (plain root only).
     """
     flags = (FLAG_VALIDATE if validate else 0) | (FLAG_NORM_CORRECT if norm_correct else 0) | \
         (FLAG_CLAMP if clamp else 0) | _projection_flag(projection)
     if torch.is_grad_enabled() and (A.requires_grad or B.requires_grad):
         if projection is not None:
-            raise ValueError("the r = 1 projection has no backward; use projection=None for gradients")
+            raise ValueError("the projections have no backward; use projection=None for gradients")
         C, ps = _EstimateFn.apply(A, B, list(P), path, tau, split_max_p, flags)
     else:
         C, ps = _forward(A, B, P, path, tau, split_max_p, flags, return_pstar, workspace)
@@ -292,7 +294,8 @@ def apsp(W, s=1.0, P=None, path="fp64", n_squarings=-1, tau=None, split_max_p=No
          projection=None):
     """Estimated all-pairs shortest distances of the n x n FP32 weight matrix W
     (+inf = no edge).  raw=True returns the (x, max) matrix X instead.
-    projection "r1" uses the r = 1 projection in every squaring."""
+    projection "r1" / "r2" uses that projection in every squaring ("r2":
+    FP64 path only)."""
     lib = load_library()
     if P is None:
         P = pfamily(512 if path == "fp64" else 128)

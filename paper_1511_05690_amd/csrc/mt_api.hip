@@ -106,6 +106,9 @@ struct Family {
     double tau;
     int32_t split_max_p;
     uint32_t flags;
+    // r = 2 projection: the added norms 3p/4 (not in the family), ascending
+    int32_t naux;
+    int32_t paux[MT_MAX_P];
 };
 
 mt_status parse_options(const mt_options* opt, Family* f) {
@@ -116,10 +119,14 @@ mt_status parse_options(const mt_options* opt, Family* f) {
     if (opt->path != MT_PATH_FP64 && opt->path != MT_PATH_BF16_SPLIT)
         return fail(MT_ERR_INVALID_ARG, "unknown path %d", opt->path);
     const uint32_t known = MT_FLAG_VALIDATE | MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT |
-                           MT_FLAG_PROJECT_R1;
+                           MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2;
     if (opt->flags & ~known) return fail(MT_ERR_INVALID_ARG, "unknown flag bits 0x%x", opt->flags & ~known);
-    if ((opt->flags & MT_FLAG_PROJECT_R1) && (opt->flags & MT_FLAG_NORM_CORRECT))
-        return fail(MT_ERR_INVALID_ARG, "MT_FLAG_NORM_CORRECT applies to the plain root, not to MT_FLAG_PROJECT_R1");
+    if ((opt->flags & (MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2)) && (opt->flags & MT_FLAG_NORM_CORRECT))
+        return fail(MT_ERR_INVALID_ARG, "MT_FLAG_NORM_CORRECT applies to the plain root, not to a projection");
+    if ((opt->flags & MT_FLAG_PROJECT_R1) && (opt->flags & MT_FLAG_PROJECT_R2))
+        return fail(MT_ERR_INVALID_ARG, "MT_FLAG_PROJECT_R1 and MT_FLAG_PROJECT_R2 exclude each other");
+    if ((opt->flags & MT_FLAG_PROJECT_R2) && opt->path != MT_PATH_FP64)
+        return fail(MT_ERR_UNSUPPORTED, "MT_FLAG_PROJECT_R2 is implemented on the FP64 path only");
     if (!(opt->tau <= 0.0 || (opt->tau > 0.0 && std::isfinite(opt->tau))))
         return fail(MT_ERR_INVALID_ARG, "tau must be finite");
     f->n = opt->n_p;
@@ -135,18 +142,49 @@ mt_status parse_options(const mt_options* opt, Family* f) {
     f->tau = opt->tau > 0.0 ? opt->tau : (f->bf16 ? MT_TAU_BF16_DEFAULT : MT_TAU_FP64_DEFAULT);
     f->split_max_p = opt->split_max_p < 0 ? 4 : opt->split_max_p;
     f->flags = opt->flags;
+    f->naux = 0;
+    if (f->flags & MT_FLAG_PROJECT_R2) {
+        // 3p/4 for every p with p/4 and p/2 in the family, not in it itself
+        auto in_family = [&](int32_t v) {
+            for (int q = 0; q < f->n; ++q)
+                if (f->p[q] == v) return true;
+            return false;
+        };
+        for (int q = 0; q < f->n; ++q) {
+            const int32_t p = f->p[q];
+            if (p % 4 || !in_family(p / 4) || !in_family(p / 2) || in_family(3 * p / 4)) continue;
+            if (f->n + f->naux >= MT_MAX_P)
+                return fail(MT_ERR_UNSUPPORTED, "the family and the norms 3p/4 of MT_FLAG_PROJECT_R2 exceed %d powers",
+                            MT_MAX_P);
+            f->paux[f->naux++] = 3 * p / 4;  // ascending: p ascends
+        }
+    }
     return MT_OK;
+}
+
+// The powers whose planes and ring results a product needs, ascending: the
+// family, plus the added norms of the r = 2 projection.
+int all_powers(const Family& f, int32_t* out) {
+    int a = 0, b = 0, n = 0;
+    while (a < f.n || b < f.naux) {
+        if (b >= f.naux || (a < f.n && f.p[a] < f.paux[b]))
+            out[n++] = f.p[a++];
+        else
+            out[n++] = f.paux[b++];
+    }
+    return n;
 }
 
 // Planes of one operand: one per p (FP64), or hi (+ lo when split) per p (BF16).
 PlaneSpec plane_spec(const Family& f) {
     PlaneSpec s;
     memset(&s, 0, sizeof s);
-    s.n_p = f.n;
+    int32_t pw[MT_MAX_P];
+    s.n_p = all_powers(f, pw);
     int pl = 0;
-    for (int q = 0; q < f.n; ++q) {
-        s.p[q] = f.p[q];
-        s.split[q] = f.bf16 && f.p[q] <= f.split_max_p;
+    for (int q = 0; q < s.n_p; ++q) {
+        s.p[q] = pw[q];
+        s.split[q] = f.bf16 && pw[q] <= f.split_max_p;
         s.first_plane[q] = pl;
         pl += s.split[q] ? 2 : 1;
     }
@@ -160,22 +198,27 @@ float round_up_to_float(double tau) {
     return f;
 }
 
-// Largest p first; a split p runs (hi,hi), (hi,lo), (lo,hi).
+// Largest p first; a split p runs (hi,hi), (hi,lo), (lo,hi).  The plan
+// covers the powers of the plane spec: the family (pidx = family index), or
+// with the r = 2 projection the family and its added norms (pidx = position
+// among all of them, the plane of the S stack).
 FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
     FamilyPlan plan;
     memset(&plan, 0, sizeof plan);
-    plan.n = f.n;
+    const int np = ps.n_p;
+    const int32_t* P = ps.p;
+    plan.n = np;
     plan.r1 = (f.flags & MT_FLAG_PROJECT_R1) ? 1 : 0;
     plan.tau = f.tau;
     plan.tau_f = round_up_to_float(f.tau);
-    for (int e = 0; e < f.n; ++e) {
-        const int q = f.n - 1 - e;
+    for (int e = 0; e < np; ++e) {
+        const int q = np - 1 - e;
         PlanEntry& pe = plan.e[e];
         pe.pidx = q;
-        pe.p = f.p[q];
-        pe.inv_p = 1.0f / (float)f.p[q];
-        pe.inv_dp = q > 0 ? 1.0f / (float)(f.p[q] - f.p[q - 1]) : 0.0f;
-        pe.corr = (f.flags & MT_FLAG_NORM_CORRECT) && k > 0 ? (float)std::pow((double)k, -1.0 / f.p[q]) : 1.0f;
+        pe.p = P[q];
+        pe.inv_p = 1.0f / (float)P[q];
+        pe.inv_dp = q > 0 ? 1.0f / (float)(P[q] - P[q - 1]) : 0.0f;
+        pe.corr = (f.flags & MT_FLAG_NORM_CORRECT) && k > 0 ? (float)std::pow((double)k, -1.0 / P[q]) : 1.0f;
         // For terms in [0, 1] and a larger p' > p, S_p' <= S_p^(p'/p).  Below
         // rise_thr no larger p can be stable: the factor 2 under the power
         // covers the rounding of S_p', the factor 0.9 that of S_p (relative
@@ -185,7 +228,7 @@ FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
             pe.rise_thr = INFINITY;
             pe.rise_thr_f = INFINITY;
         } else {
-            pe.rise_thr = 0.9 * std::pow(f.tau / 2.0, (double)f.p[q] / (double)f.p[q + 1]);
+            pe.rise_thr = 0.9 * std::pow(f.tau / 2.0, (double)P[q] / (double)P[q + 1]);
             float tf = (float)pe.rise_thr;
             if ((double)tf > pe.rise_thr) tf = nextafterf(tf, 0.0f);
             pe.rise_thr_f = tf;
@@ -203,6 +246,30 @@ FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
         }
     }
     return plan;
+}
+
+// The r = 2 selection over the S stack (planes in the order of ps).
+R2Spec r2_spec(const Family& f, const PlaneSpec& ps, int mode, int clamp) {
+    R2Spec r;
+    memset(&r, 0, sizeof r);
+    auto plane_of = [&](int32_t v) {
+        for (int t = 0; t < ps.n_p; ++t)
+            if (ps.p[t] == v) return t;
+        return -1;
+    };
+    r.n = f.n;
+    for (int q = 0; q < f.n; ++q) {
+        const int32_t p = f.p[q];
+        r.p[q] = p;
+        r.plane[q] = plane_of(p);
+        r.lo[q] = q > 0 ? plane_of(f.p[q - 1]) : -1;
+        const bool ok = p % 4 == 0 && plane_of(p / 4) >= 0 && plane_of(p / 2) >= 0 && plane_of(3 * p / 4) >= 0;
+        for (int k = 0; k < 4; ++k) r.q4[q][k] = ok ? plane_of((k + 1) * (p / 4)) : -1;
+    }
+    r.tau = f.tau;
+    r.mode = mode;
+    r.clamp = clamp;
+    return r;
 }
 
 RootSpec root_spec(const Family& f, int64_t k, int mode, int clamp) {
@@ -272,7 +339,11 @@ Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64
     L.ap = off;  off += align_up((size_t)b * ps.n_planes * g.mp * g.kp * g.esize);
     L.bp = off;  off += align_up((size_t)b * ps.n_planes * g.np * g.kp * g.esize);
     L.s = L.s2 = L.code = 0;
-    if (!f.bf16) {
+    const bool r2 = (f.flags & MT_FLAG_PROJECT_R2) != 0;
+    if (!f.bf16 && r2) {
+        // the S stack: one plane per power of the plane spec
+        L.s = off;    off += align_up((size_t)ps.n_p * (size_t)(b * m * n) * 8);
+    } else if (!f.bf16) {
         L.s = off;    off += align_up((size_t)(b * m * n) * 8);
         if (f.flags & MT_FLAG_PROJECT_R1) {
             L.s2 = off; off += align_up((size_t)(b * m * n) * 8);
@@ -280,8 +351,9 @@ Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64
         L.code = off; off += align_up((size_t)(b * m * n));
     }
     // sparse-tail list: at most tail_max entries per tile (none if the family
-    // has a single p: nothing would be left to run)
-    L.tail_max = f.n > 1 ? g_tail_max.load() : 0;
+    // has a single p: nothing would be left to run; none for the r = 2
+    // projection, which keeps every ring result)
+    L.tail_max = f.n > 1 && !r2 ? g_tail_max.load() : 0;
     const int64_t tiles = b * (g.mp / g.bm) * (g.np / g.bm);
     const size_t list_bytes = align_up((size_t)tiles * (size_t)L.tail_max * sizeof(TailEntry));
     L.tail = off;
@@ -394,6 +466,21 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     memset(&epi, 0, sizeof epi);
     epi.r = r;
     epi.c = c;
+    if (f.flags & MT_FLAG_PROJECT_R2) {
+        // every ring result to the S stack, then selection and projection
+        epi.mode = EPI_STORE_ALL;
+        epi.out = ws + L.s;
+        epi.out_f64 = 1;
+        epi.stack_stride = b * m * n;
+        MT_TRY(launch_pfamily_gemm_f64((const double*)ap, (const double*)bp, b, m, n, g.mp, g.np, g.kp,
+                                       ps.n_planes, g.bm, plan, epi, st),
+               "p-family GEMM (FP64, every ring result)");
+        const R2Spec rs = r2_spec(f, ps, mode, clamp);
+        MT_TRY(launch_select_r2_f64((const double*)(ws + L.s), b * m * n, b, m, n, r, c, rs, out, out_f64, pstar,
+                                    st),
+               "select and r = 2 projection");
+        return MT_OK;
+    }
     if (!plan.r1) {
         WsHeader* hdr = (WsHeader*)(ws + L.hdr);
         const int32_t s0 = g_start_entry.load();
@@ -619,7 +706,7 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
     Family f;
     mt_status s = parse_options(opt, &f);
     if (s != MT_OK) return s;
-    if (f.flags & (MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT | MT_FLAG_PROJECT_R1))
+    if (f.flags & (MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT | MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2))
         return fail(MT_ERR_UNSUPPORTED,
                     "the backward supports the plain estimate only (no norm correction, clamp or projection)");
     if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);

@@ -399,6 +399,80 @@ __global__ __launch_bounds__(kThreads) void mt_select_root_f64_kernel(
     }
 }
 
+// Selection and r = 2 projection from the S stack (Sec. 1): p* is the
+// largest family p with S >= tau; with p* = 4q and S_q, S_2q, S_3q, S_4q all
+// positive, the null vector of [[t1, t2, t3], [t2, t3, t4]] (t_k = S_kq /
+// c^k, c = (S_4q / S_q)^(1/3), which scales the roots by c) is the cross
+// product of its rows, g = (t2 t4 - t3^2, t2 t3 - t1 t4, t1 t3 - t2^2), and
+// the estimate is the largest root x of g0 + g1 x + g2 x^2 (x = alpha^q / c)
+// as alpha = (c x)^(1/q).  Rank 1 (|g| <= 1e-8 (|row1|^2 + |row2|^2): one
+// distinct value, or so close to it that rounding decides), complex or
+// nonpositive roots, or a missing norm: the r = 1
+// projection with the next smaller family p; no such p or S_lo = 0: the
+// plain root.
+template <typename TO>
+__global__ __launch_bounds__(kThreads) void mt_select_r2_kernel(const double* __restrict__ stack, int64_t stride,
+                                                                int64_t rows, int64_t m, int64_t n,
+                                                                const double* __restrict__ r,
+                                                                const double* __restrict__ c, R2Spec spec,
+                                                                TO* __restrict__ out, uint8_t* __restrict__ pstar_out) {
+    for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int64_t bi = row / m;
+        const int64_t i = row - bi * m;
+        const double ri = r ? r[row] : 1.0;
+        for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads) {
+            const int64_t e = row * n + j;
+            int q = -1;
+            for (int fi = spec.n - 1; fi >= 0; --fi)
+                if (stack[(int64_t)spec.plane[fi] * stride + e] >= spec.tau) {
+                    q = fi;
+                    break;
+                }
+            const int qi = q < 0 ? 0 : q;
+            const int p = spec.p[qi];
+            const double s = stack[(int64_t)spec.plane[qi] * stride + e];
+            double alpha = p == 1 ? s : (s > 0.0 ? exp(log(s) / (double)p) : 0.0);
+            if (q > 0 && spec.lo[q] >= 0) {
+                const double sl = stack[(int64_t)spec.lo[q] * stride + e];
+                if (sl > 0.0) alpha = exp(log(s / sl) / (double)(p - spec.p[q - 1]));
+            }
+            if (q >= 0 && spec.q4[q][0] >= 0) {
+                double lS[4];
+                bool ok = true;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double v = stack[(int64_t)spec.q4[q][k] * stride + e];
+                    ok &= v > 0.0;
+                    lS[k] = v > 0.0 ? log(v) : 0.0;
+                }
+                if (ok) {
+                    const double logc = (lS[3] - lS[0]) / 3.0;
+                    double t[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) t[k] = exp(lS[k] - (k + 1) * logc);
+                    const double g0 = t[1] * t[3] - t[2] * t[2];
+                    const double g1 = t[1] * t[2] - t[0] * t[3];
+                    const double g2 = t[0] * t[2] - t[1] * t[1];
+                    const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+                    const double rn = t[0] * t[0] + 2 * t[1] * t[1] + 2 * t[2] * t[2] + t[3] * t[3];
+                    const double disc = g1 * g1 - 4.0 * g2 * g0;
+                    if (gn > 1e-8 * rn && g2 != 0.0 && disc >= 0.0) {
+                        const double sq = sqrt(disc);
+                        const double x1 = (-g1 + sq) / (2.0 * g2), x2 = (-g1 - sq) / (2.0 * g2);
+                        const double xm = x1 > x2 ? x1 : x2;
+                        if (xm > 0.0) alpha = exp((log(xm) + logc) / (double)(p / 4));
+                    }
+                }
+            }
+            double v = ri * (c ? c[bi * n + j] : 1.0) * alpha;
+            if (spec.mode == EPI_APSP_X || spec.clamp) v = fmin(v, 1.0);
+            if (spec.mode == EPI_APSP_X && i == j) v = 1.0;
+            out[e] = (TO)v;
+            if (pstar_out) pstar_out[e] = q < 0 ? (uint8_t)MT_PSTAR_NONE : (uint8_t)q;
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = 65535 * 8) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -547,6 +621,23 @@ hipError_t launch_select_root_f64(const double* S, const double* S2, const uint8
     else
         hipLaunchKernelGGL(mt_select_root_f64_kernel<float>, grid, dim3(kThreads), 0, st, S, S2, code,
                            rows, m, n, r, c, spec, (float*)out, pstar_out);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_r2_f64(const double* stack, int64_t stride, int64_t b, int64_t m, int64_t n,
+                                const double* r, const double* c, const R2Spec& spec, void* out, int out_f64,
+                                uint8_t* pstar_out, hipStream_t st) {
+    const int64_t rows = b * m;
+    if (rows <= 0 || n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)std::min<int64_t>(rows, 65535));
+    timing_before("mt_select_r2", st);
+    if (out_f64)
+        hipLaunchKernelGGL(mt_select_r2_kernel<double>, grid, dim3(kThreads), 0, st, stack, stride, rows, m, n, r, c,
+                           spec, (double*)out, pstar_out);
+    else
+        hipLaunchKernelGGL(mt_select_r2_kernel<float>, grid, dim3(kThreads), 0, st, stack, stride, rows, m, n, r, c,
+                           spec, (float*)out, pstar_out);
     timing_after(st);
     return hipGetLastError();
 }

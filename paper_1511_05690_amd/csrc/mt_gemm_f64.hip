@@ -237,6 +237,53 @@ struct RecordEpi {
     __device__ void finish(const TileCtx&) {}
 };
 
+// ------------------------------------------------------------ store-all epilogue
+// S of plan entry e to plane pidx of the stack out (planes of b x rows x n),
+// every entry of the tile, every entry of the plan: the r = 2 projection
+// needs four ring results per entry, chosen after p* is known.
+template <class C>
+struct StoreAllEpi {
+    static constexpr int WT = C::WT;
+    static constexpr int LDS_BYTES = 0;
+    using Args = EpiArgs;
+    static constexpr bool kCanStop = false;
+    EpiArgs a;
+    int64_t n, out_lane;
+    int32_t rows_left, cols_left;
+
+    __device__ bool active(int, const FamilyPlan&) const { return true; }
+    __device__ void counts(int& open, int& parked) const { open = parked = 0; }
+    __device__ int32_t start_index() const { return 0; }
+    __device__ bool can_hand_over(int) const { return false; }
+    __device__ uint32_t* tail_counter() const { return nullptr; }
+    __device__ void hand_over(uint32_t, int, int, const TileCtx&) const {}
+
+    __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t*, int) {
+        n = g.cols;
+        const int lr0 = t.wm * WT * 16 + (t.lane >> 4);
+        const int lc0 = t.wn * WT * 16 + (t.lane & 15);
+        out_lane = ((int64_t)t.bi * g.rows + t.row0 + lr0) * n + t.col0 + lc0;
+        rows_left = (int32_t)min<int64_t>(g.rows - (t.row0 + lr0), 1 << 30);
+        cols_left = (int32_t)min<int64_t>(n - (t.col0 + lc0), 1 << 30);
+    }
+
+    // accumulator (i, j, r) of this lane: tile row i*16 + l/16 + 4r, column
+    // j*16 + l%16 (the v_mfma_f64_16x16x4f64 layout)
+    __device__ void entry(int e, int, const FamilyPlan& plan, f64x4 (&acc)[WT][WT], const TileCtx&, uint8_t*) {
+        double* out = (double*)a.out + (int64_t)plan.e[e].pidx * a.stack_stride + out_lane;
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (j * 16 < cols_left && i * 16 + 4 * r < rows_left)
+                        out[(int64_t)(i * 16 + 4 * r) * n + j * 16] = acc[i][j][r];
+    }
+
+    __device__ void finish(const TileCtx&) {}
+};
+
 // ------------------------------------------------------------ adjoint epilogue
 template <class C, typename TM>
 struct AdjointEpiF64 {
@@ -694,6 +741,11 @@ hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b
     const GemmGeomF64 g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, bm);
     const char* name = "mt_pfamily_gemm_f64";
     hipError_t e = hipErrorInvalidValue;
+    if (epi.mode == EPI_STORE_ALL) {
+        if (bm == 128) return launch_gemm<CfgF64<4>, StoreAllEpi<CfgF64<4>>>(g, b, plan, epi, name, st);
+        if (bm == 64) return launch_gemm<CfgF64<2>, StoreAllEpi<CfgF64<2>>>(g, b, plan, epi, name, st);
+        return e;
+    }
     if (bm == 128)
         e = plan.r1 ? launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, true>>(g, b, plan, epi, name, st)
                     : launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, false>>(g, b, plan, epi, name, st);

@@ -84,6 +84,7 @@ struct FamilyPlan {
 enum EpiMode : int32_t {
     EPI_PLAIN = 0,      // C = r c S^(1/p)   (optional clamp <= 1)
     EPI_APSP_X = 1,     // X = min(C, 1), X_ii = 1
+    EPI_STORE_ALL = 2,  // FP64: S of every plan entry to its plane of a stack (r = 2 projection)
 };
 
 struct EpiArgs {
@@ -108,6 +109,7 @@ struct EpiArgs {
     int32_t* tail_bucket;
     int32_t tail_shift;
     int32_t tail_buckets;
+    int64_t stack_stride;  // EPI_STORE_ALL: elements per plane of the S stack (b m n)
 };
 constexpr int64_t kTailBuckets = 65536;
 
@@ -214,6 +216,23 @@ struct RootSpec {
     int32_t clamp;
     int32_t r1;     // r = 1 projection from S (at p*) and S2 (at the family's next smaller p)
 };
+// r = 2 projection over an S stack (plane t holds S at the t-th smallest of
+// the family's p and the added 3q): per family index fi, the stack plane of
+// its p (plane), of the next smaller family p (lo, -1 if none) and of q,
+// 2q, 3q, 4q with 4q = its p (q4, -1 where the projection does not apply).
+struct R2Spec {
+    int32_t n;  // family size
+    int32_t p[MT_MAX_P];
+    int32_t plane[MT_MAX_P];
+    int32_t lo[MT_MAX_P];
+    int32_t q4[MT_MAX_P][4];
+    double tau;
+    int32_t mode;
+    int32_t clamp;
+};
+hipError_t launch_select_r2_f64(const double* stack, int64_t stride, int64_t b, int64_t m, int64_t n,
+                                const double* r, const double* c, const R2Spec& spec, void* out, int out_f64,
+                                uint8_t* pstar_out, hipStream_t st);
 hipError_t launch_select_root_f64(const double* S, const double* S2, const uint8_t* code, int64_t b,
                                   int64_t m, int64_t n, const double* r, const double* c,
                                   const RootSpec& spec, void* out, int out_f64, uint8_t* pstar_out,

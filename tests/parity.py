@@ -62,11 +62,14 @@ def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, ma
         qg_used = np.where(qg < 0, 0, qg)[flips]
         S_at = np.take_along_axis(S, np.where(qg < 0, 0, qg)[None], 0)[0][flips]
         C_at = rc[flips] * np.power(S_at, 1.0 / P[qg_used])
-        if projection == "r1":
+        if projection in ("r1", "r2"):
             # the oracle's projection evaluated at the GPU's p*
             idx_g = np.where(qg < 0, oracle.PSTAR_NONE, qg).astype(np.uint8)
             root_g = oracle.pnorm._root(S, P, idx_g)[0]
-            C_at = rc[flips] * oracle.pnorm._project_r1(S, P, idx_g, root_g)[flips]
+            proj = oracle.pnorm._project_r1(S, P, idx_g, root_g)
+            if projection == "r2":
+                proj = oracle.pnorm._project_r2(S, P, idx_g, proj, ref["S_aux"], ref["aux"])
+            C_at = rc[flips] * proj[flips]
         if norm_k is not None:
             C_at = C_at / np.power(float(norm_k), 1.0 / P[qg_used])
         rel_at = np.abs(C_gpu[flips] - C_at) / np.maximum(np.abs(C_at), 1e-300)

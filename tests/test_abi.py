@@ -151,7 +151,7 @@ def test_projection_flag_validation():
                                         fake, fake, fake, 1 << 30, null)
     assert st == 5 and b"projection" in lib.maxtimes_last_error()
     with pytest.raises(ValueError):
-        mt._projection_flag("r2")
+        mt._projection_flag("r3")
 
 
 def test_search_start_validation():
@@ -198,3 +198,24 @@ def test_affine_and_exact_rows_validation():
     assert st == 1 and b"ab" in lib.maxtimes_last_error()
     st = lib.apsp_affine_correct(fake, 0, 10, fake, 2, fake, fake, 1, fake, 1, null)
     assert st == 3
+
+
+def test_r2_flag_validation():
+    """MT_FLAG_PROJECT_R2: FP64 path only, not with R1 or the norm
+    correction, and the added norms 3p/4 enlarge the FP64 workspace by one
+    output-sized stack plane per power (no GPU needed)."""
+    R2 = mt.FLAG_PROJECT_R2
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([1, 2, 4], path="bf16", flags=R2)
+    assert e.value.status == 5
+    for bad in (R2 | mt.FLAG_PROJECT_R1, R2 | mt.FLAG_NORM_CORRECT):
+        with pytest.raises(mt.MaxTimesError) as e:
+            _ws([1, 2, 4], path="fp64", flags=bad)
+        assert e.value.status == 1
+    m = n = 64
+    # {1, 2, 4, 8}: added norms 3 and 6 -> 6 stack planes of 64 x 64 doubles
+    r2 = _ws([1, 2, 4, 8], path="fp64", m=m, n=n, flags=R2)
+    assert r2 >= 6 * m * n * 8
+    # 32 powers at most, family and added norms together
+    with pytest.raises(mt.MaxTimesError) as e:
+        _ws([2 ** i for i in range(13)] + [3 * 2 ** i for i in range(12, 19)], path="fp64", flags=R2)

@@ -136,6 +136,6 @@ def test_apsp_chain_unbiased(w):
 
 def test_rejects_bad_projection():
     with pytest.raises(ValueError):
-        oracle.pnorm_estimate(np.ones((2, 2)), np.ones((2, 2)), P, TAU, projection="r2")
+        oracle.pnorm_estimate(np.ones((2, 2)), np.ones((2, 2)), P, TAU, projection="r3")
     with pytest.raises(ValueError):
         oracle.pnorm_estimate(np.ones((2, 2)), np.ones((2, 2)), P, TAU, norm_correct=True, projection="r1")
