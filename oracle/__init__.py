@@ -19,6 +19,7 @@ pnorm   exact (max, x) product (Alg. 2), the p-norm estimate (Alg. 5 with the
 apsp    the (+, min) <-> (x, max) transform (Sec. 2.2), APSP by repeated
         squaring, Floyd-Warshall and Dijkstra, and the affine correction of
         an APSP estimate fitted on a few exact distances (Sec. 4).
+maxconv the max-convolution (Sec. 1), exact and its p-norm estimate.
 exact_c ctypes wrapper of ``exact_maxtimes.c`` (same definition as
         ``pnorm.exact_maxtimes``, for sizes numpy cannot finish quickly).
 
@@ -51,3 +52,4 @@ from .apsp import (  # noqa: F401
     affine_fit,
     affine_apply,
 )
+from .maxconv import TAU_FFT, exact_maxconv, maxconv_estimate  # noqa: F401,E402

@@ -17,6 +17,12 @@ dense graphs, Sec. 3 Table 1, so every input here is synthetic):
                      scale * Euclidean length, FP32, +inf = no edge
   dense_graph        complete digraph with U[lo, hi) weights (the shape of
                      the paper's Table 1 instances)
+  maxconv_vectors    b pairs of nonnegative vectors (x of length n, y of
+                     length m) for the max-convolution of Sec. 1: "uniform"
+                     (1 - U[0, 1)), "lognormal" (exp(N(0, 2^2))), "sparse"
+                     (uniform with 70 % zeros), "distribution" (Dirichlet(1)
+                     rows: probability vectors, the operands of max-product
+                     inference)
 """
 
 import numpy as np
@@ -92,6 +98,25 @@ def dense_graph(n, lo, hi, seed):
 #      P = {1..64}, BF16-split forward + backward
 #   5  RGG APSP n=16384, radius 0.02, weight 100 x length, s=0.35,
 #      14 squarings, P = {1..128}, BF16-split path
+def maxconv_vectors(b, n, m, seed, kind="uniform", dtype=np.float64):
+    rng = rng_for(seed)
+
+    def draw(length):
+        if kind == "uniform":
+            v = 1.0 - rng.random((b, length))
+        elif kind == "lognormal":
+            v = np.exp(rng.normal(0.0, 2.0, (b, length)))
+        elif kind == "sparse":
+            v = (1.0 - rng.random((b, length))) * (rng.random((b, length)) >= 0.7)
+        elif kind == "distribution":
+            v = rng.dirichlet(np.ones(length), size=b) if length else np.zeros((b, 0))
+        else:
+            raise ValueError(kind)
+        return v.astype(dtype)
+
+    return draw(n), draw(m)
+
+
 def pfamily(pmax):
     p, out = 1, []
     while p <= pmax:
