@@ -125,6 +125,8 @@ typedef enum { MT_PATH_FP64 = 0, MT_PATH_BF16_SPLIT = 1 } mt_path;
  * underflow: 1e-290 in FP64, 1e-30 for the BF16/FP32 exponent range. */
 #define MT_TAU_FP64_DEFAULT 1e-290
 #define MT_TAU_BF16_DEFAULT 1e-30
+/* FFT convolution does cancel: Sec. 2.1 puts its threshold at 1e-12. */
+#define MT_TAU_FFT_DEFAULT 1e-12
 
 typedef struct {
     const int32_t* p_family; /* host; n_p entries, strictly ascending, 1..MT_MAX_POWER */
@@ -253,6 +255,42 @@ mt_status apsp_affine_workspace_size(size_t* bytes);
 mt_status apsp_affine_correct(void* D, mt_dtype dtype, int64_t n, const int32_t* sources, int32_t n_src,
                               const double* exact, double* ab, int32_t apply, void* workspace, size_t ws_bytes,
                               void* stream);
+
+/*
+ * Max-convolution estimate (Sec. 1; ring kernel H = FFT convolution and its
+ * threshold, Sec. 2.1), batched:
+ *     z[t] = max_i x[i] y[t - i],  t = 0 .. n + m - 2  (i over 0 .. n - 1 with
+ *                                                       0 <= t - i < m)
+ *   rx = max x, ry = max y, x' = x / rx, y' = y / ry,
+ *   S_p = x'^p * y'^p                  (ordinary convolution, by FFT in FP64)
+ *   p*[t] = max{ p in P : S_p[t] >= tau },   z[t] = rx ry S_{p*}[t]^(1/p*).
+ * The estimate satisfies E <= z <= K^(1/p*) E up to the FFT's rounding
+ * (E the exact max-convolution, K the number of terms at t).  No stable p:
+ * the smallest p of the family with S clamped to >= 0, p* = MT_PSTAR_NONE.
+ *   x        b x n, y  b x m, dtype (FP32 / FP64), device, nonnegative and
+ *            finite (other values give unspecified results).
+ *   opt      family as for maxtimes_estimate; path must be MT_PATH_FP64
+ *            (else MT_ERR_UNSUPPORTED); tau <= 0 -> MT_TAU_FFT_DEFAULT;
+ *            split_max_p is ignored; flags must be 0 (else
+ *            MT_ERR_UNSUPPORTED).
+ *   z        b x (n + m - 1), dtype, device (output).
+ *   p_star   b x (n + m - 1) uint8 device (output, nullable): index of p*
+ *            in the family.
+ * One workgroup per batch item transforms in LDS: n + m - 1 <= 4096 and
+ * b < 2^31 (else MT_ERR_UNSUPPORTED).  n = 0, m = 0 or b = 0: empty output,
+ * nothing written.  No workspace; asynchronous on the stream.
+ */
+mt_status maxconv_estimate(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
+                           const mt_options* opt, void* z, uint8_t* p_star, void* stream);
+
+/*
+ * The exact max-convolution z[t] = max_i x[i] y[t - i] (the definition of
+ * Sec. 1, z starting at 0), one GPU thread per output, products rounded once
+ * in dtype.  x b x n, y b x m, z b x (n + m - 1), device; b (n + m - 1) <= 2^38,
+ * n, m <= 2^24 (else MT_ERR_UNSUPPORTED).  For measuring the estimate's error.
+ */
+mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
+                        void* z, void* stream);
 
 /* Static description of a status code. */
 const char* maxtimes_status_string(mt_status status);

@@ -11,6 +11,7 @@ product, Sec. 2.2 for all-pairs shortest paths.
 
     C = estimate(A, B, P=(1, 2, 4, ..., 64), path="bf16")   # C ~ max_k A_ik B_kj
     D = apsp(W, s=1.0, P=..., path="fp64")                  # shortest distances
+    z = maxconv(x, y, P=(1, 2, 4, ..., 64))                 # z ~ max_i x_i y_(t-i)
 """
 
 import ctypes
@@ -22,7 +23,8 @@ __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
     "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
     "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold",
-    "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "pfamily", "PSTAR_NONE", "PATHS",
+    "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "maxconv", "maxconv_exact",
+    "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
 PSTAR_NONE = 255
@@ -81,6 +83,8 @@ def load_library():
         "apsp_estimate": [vp, i64, ctypes.c_double, ctypes.c_int32, opt, vp, ctypes.c_int, vp, vp,
                           sz, vp],
         "maxtimes_exact": [vp, vp, ctypes.c_int, i64, i64, i64, i64, vp, vp],
+        "maxconv_estimate": [vp, vp, ctypes.c_int, i64, i64, i64, opt, vp, vp, vp],
+        "maxconv_exact": [vp, vp, ctypes.c_int, i64, i64, i64, vp, vp],
         "apsp_exact_rows_workspace_size": [i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
         "apsp_exact_rows": [vp, i64, vp, ctypes.c_int32, vp, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp],
         "apsp_affine_workspace_size": [ctypes.POINTER(ctypes.c_size_t)],
@@ -327,6 +331,49 @@ def exact(A, B):
     E = torch.empty((b, m, n) if batched else (m, n), dtype=A.dtype, device=A.device)
     _check(lib.maxtimes_exact(_ptr(A), _ptr(B), _dtype_code(A), b, m, k, n, _ptr(E), _stream(A.device)))
     return E
+
+
+def _conv_shapes(x, y):
+    if not (x.is_cuda and y.is_cuda):
+        raise ValueError("x and y must be device tensors")
+    if x.dtype != y.dtype:
+        raise TypeError("x and y must have the same dtype")
+    if x.dim() == 1 and y.dim() == 1:
+        return 1, x.shape[0], y.shape[0], False
+    if x.dim() == 2 and y.dim() == 2 and x.shape[0] == y.shape[0]:
+        return x.shape[0], x.shape[1], y.shape[1], True
+    raise ValueError("x and y must both be 1-D, or 2-D with the same batch size")
+
+
+def maxconv(x, y, P=(1, 2, 4, 8, 16, 32, 64), tau=None, return_pstar=False):
+    """Estimate the max-convolution z[t] = max_i x[i] y[t - i] of nonnegative
+    x (.., n) and y (.., m) by FFT convolutions of x'^p and y'^p (FP64, one
+    workgroup per batch row, n + m - 1 <= 4096); tau None = 1e-12."""
+    lib = load_library()
+    b, n, m, batched = _conv_shapes(x, y)
+    x = x.contiguous()
+    y = y.contiguous()
+    o = _options(P, "fp64", tau, None, 0)
+    L = n + m - 1 if n and m else 0
+    shape = (b, L) if batched else (L,)
+    z = torch.empty(shape, dtype=x.dtype, device=x.device)
+    ps = torch.empty(shape, dtype=torch.uint8, device=x.device) if return_pstar else None
+    _check(lib.maxconv_estimate(_ptr(x), _ptr(y), _dtype_code(x), b, n, m, ctypes.byref(o), _ptr(z), _ptr(ps),
+                                _stream(x.device)))
+    return (z, ps) if return_pstar else z
+
+
+def maxconv_exact(x, y):
+    """The exact max-convolution max_i x[i] y[t - i] on the GPU (products
+    rounded once in the input precision)."""
+    lib = load_library()
+    b, n, m, batched = _conv_shapes(x, y)
+    x = x.contiguous()
+    y = y.contiguous()
+    L = n + m - 1 if n and m else 0
+    z = torch.empty((b, L) if batched else (L,), dtype=x.dtype, device=x.device)
+    _check(lib.maxconv_exact(_ptr(x), _ptr(y), _dtype_code(x), b, n, m, _ptr(z), _stream(x.device)))
+    return z
 
 
 def apsp_exact_rows(W, sources):

@@ -844,6 +844,48 @@ mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b
     return MT_OK;
 }
 
+mt_status maxconv_estimate(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
+                           const mt_options* opt, void* z, uint8_t* p_star, void* stream) {
+    g_last_error.clear();
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if (f.bf16) return fail(MT_ERR_UNSUPPORTED, "the max-convolution runs on the FP64 path only");
+    if (f.flags) return fail(MT_ERR_UNSUPPORTED, "the max-convolution takes no flags");
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (b < 0 || n < 0 || m < 0)
+        return fail(MT_ERR_INVALID_ARG, "negative size (b=%lld n=%lld m=%lld)", (long long)b, (long long)n,
+                    (long long)m);
+    if (b == 0 || n == 0 || m == 0) return MT_OK;
+    if (n + m - 1 > kMaxConvN)
+        return fail(MT_ERR_UNSUPPORTED, "n + m - 1 = %lld exceeds %d", (long long)(n + m - 1), kMaxConvN);
+    if (b >= ((int64_t)1 << 31)) return fail(MT_ERR_UNSUPPORTED, "b must be below 2^31");
+    if (!x || !y || !z) return fail(MT_ERR_INVALID_ARG, "x, y or z is NULL");
+    MaxconvSpec spec{};
+    spec.n = f.n;
+    for (int q = 0; q < f.n; ++q) spec.p[q] = f.p[q];
+    spec.tau = opt->tau > 0.0 ? opt->tau : MT_TAU_FFT_DEFAULT;
+    MT_TRY(launch_maxconv(x, y, dtype == MT_F64, b, n, m, spec, z, p_star, (hipStream_t)stream),
+           "max-convolution");
+    return MT_OK;
+}
+
+mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
+                        void* z, void* stream) {
+    g_last_error.clear();
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (b < 0 || n < 0 || m < 0)
+        return fail(MT_ERR_INVALID_ARG, "negative size (b=%lld n=%lld m=%lld)", (long long)b, (long long)n,
+                    (long long)m);
+    if (b == 0 || n == 0 || m == 0) return MT_OK;
+    const int64_t lim = (int64_t)1 << 24;
+    if (n > lim || m > lim || b > ((int64_t)1 << 38) / (n + m - 1))
+        return fail(MT_ERR_UNSUPPORTED, "n or m above 2^24, or b (n + m - 1) above 2^38");
+    if (!x || !y || !z) return fail(MT_ERR_INVALID_ARG, "x, y or z is NULL");
+    MT_TRY(launch_maxconv_exact(x, y, dtype == MT_F64, b, n, m, z, (hipStream_t)stream), "exact max-convolution");
+    return MT_OK;
+}
+
 mt_status apsp_exact_rows_workspace_size(int64_t n, int32_t n_src, size_t* bytes) {
     g_last_error.clear();
     if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");

@@ -263,6 +263,21 @@ hipError_t launch_adjoint_gemm_f64(const double* Xp, const double* Yp, int64_t b
                                    int32_t x_planes, int32_t y_planes, const FamilyPlan& plan,
                                    const AdjArgs& adj, hipStream_t st);
 
+// Max-convolution (Sec. 1): FFT size N = 2^logN >= n + m - 1, at most
+// kMaxConvN points (the FFT runs in one workgroup's LDS).
+constexpr int kMaxConvLog = 12;
+constexpr int kMaxConvN = 1 << kMaxConvLog;
+struct MaxconvSpec {
+    int32_t n;  // family size
+    int32_t p[MT_MAX_P];
+    double tau;
+};
+int maxconv_log_size(int64_t n, int64_t m);
+hipError_t launch_maxconv(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,
+                          const MaxconvSpec& spec, void* z, uint8_t* pstar, hipStream_t st);
+hipError_t launch_maxconv_exact(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,
+                                void* z, hipStream_t st);
+
 // Exact (max, x) product on the vector ALUs.
 hipError_t launch_exact_maxtimes(const void* A, const void* B, int f64, int64_t b, int64_t m,
                                  int64_t k, int64_t n, void* E, hipStream_t st);

@@ -219,3 +219,30 @@ def test_r2_flag_validation():
     # 32 powers at most, family and added norms together
     with pytest.raises(mt.MaxTimesError) as e:
         _ws([2 ** i for i in range(13)] + [3 * 2 ** i for i in range(12, 19)], path="fp64", flags=R2)
+
+
+def test_maxconv_validation():
+    """Argument checks of the max-convolution entry points (no GPU): FP64
+    path only, no flags, n + m - 1 <= 4096, non-NULL pointers; empty sizes
+    return at once."""
+    lib = mt.load_library()
+    fake = ctypes.c_void_p(0x100000)
+    null = ctypes.c_void_p(0)
+    o = _opts([1, 2, 4], path=0)
+    assert lib.maxconv_estimate(fake, fake, 0, 2, 2048, 2049, ctypes.byref(o), null, null, null) == 1
+    assert b"NULL" in lib.maxtimes_last_error()
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 2048, 2050, ctypes.byref(o), fake, null, null)
+    assert st == 5 and b"4096" in lib.maxtimes_last_error()
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, ctypes.byref(_opts([1, 2], path=1)), fake, null, null)
+    assert st == 5
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, ctypes.byref(_opts([1, 2], path=0, flags=4)), fake, null, null)
+    assert st == 5
+    assert lib.maxconv_estimate(fake, fake, 3, 2, 8, 8, ctypes.byref(o), fake, null, null) == 1
+    assert lib.maxconv_estimate(fake, fake, 0, -1, 8, 8, ctypes.byref(o), fake, null, null) == 1
+    assert lib.maxconv_estimate(fake, fake, 0, 1 << 31, 8, 8, ctypes.byref(o), fake, null, null) == 5
+    assert lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, None, fake, null, null) == 1
+    assert lib.maxconv_estimate(null, null, 0, 0, 8, 8, ctypes.byref(o), null, null, null) == 0
+    assert lib.maxconv_estimate(null, null, 0, 4, 0, 8, ctypes.byref(o), null, null, null) == 0
+    assert lib.maxconv_exact(null, fake, 0, 2, 8, 8, fake, null) == 1
+    assert lib.maxconv_exact(fake, fake, 0, 2, (1 << 24) + 1, 8, fake, null) == 5
+    assert lib.maxconv_exact(null, null, 1, 0, 8, 8, null, null) == 0
