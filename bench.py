@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "effective max-times ops/s (n³/t) BF16 vs FP64 path; max rel. err vs exact"
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 matrix
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pfamily_gemm_bf16_8192_pmc.md")
 GEMM_SRC = os.path.join(ROOT, "paper_1511_05690_amd", "csrc", "mt_gemm_bf16.hip")
@@ -207,6 +208,43 @@ def run_legs(mt, torch, np):
         ms = time_call(fwd_bwd, 5, torch)
         legs[name] = {"ms_fwd_bwd": ms, "P": P, "ops_per_s": 64 * 512.0 ** 3 / (ms / 1e3)}
 
+    # max-convolution (Sec. 1): 8192 pairs of 2048-point probability vectors
+    # (Dirichlet(1) rows), P = {1, ..., 64}, FFT convolution in FP64
+    from workloads import maxconv_vectors, pfamily
+    bm, nm = 8192, 2048
+    xc, yc = maxconv_vectors(bm, nm, nm, seed=4004, kind="distribution")
+    xd, yd = torch.from_numpy(xc).cuda(), torch.from_numpy(yc).cuda()
+    del xc, yc
+    Pm = pfamily(64)
+    mt.timing_reset()
+    mt.timing_enable(True)
+    ms = time_call(lambda: mt.maxconv(xd, yd, Pm), 5, torch)
+    kms, kn = mt.timing_read("mt_maxconv")
+    kflop = mt.timing_work("mt_maxconv")
+    mt.timing_reset()
+    ms_exact = time_call(lambda: mt.maxconv_exact(xd, yd), 1, torch)
+    mt.timing_enable(False)
+    z, ps = mt.maxconv(xd, yd, Pm, return_pstar=True)
+    E = mt.maxconv_exact(xd, yd)
+    pos = E > 0
+    rel = (z[pos] / E[pos] - 1.0).abs()
+    hist = torch.bincount(ps.flatten().long(), minlength=256)[:len(Pm)].tolist()
+    achieved = kflop / kn / (kms / kn / 1e3) / 1e12
+    legs["maxconv_8192x2048_fp64"] = {
+        "ms": ms, "pairs": bm, "n": nm, "m": nm, "P": Pm,
+        "ops_per_s": bm * float(nm) * nm / (ms / 1e3),
+        "roofline": {"bound": "alu", "kernel": "mt_maxconv", "achieved": achieved,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "flop_per_launch": kflop / kn, "avg_launch_ms": kms / kn,
+                     "flop_count": "10 N log2 N per pair and p visited (two complex FFTs), N = 4096"},
+        "exact_ms": ms_exact, "speedup_vs_exact": ms_exact / ms,
+        "vs_exact": {"max_rel": float(rel.max()), "median_rel": float(rel.median())},
+        "pstar_hist": hist,
+    }
+    del xd, yd, z, ps, E, pos, rel
+    torch.cuda.empty_cache()
+
     c5 = config(5)
     W5 = torch.from_numpy(c5["W"]).cuda()
     del c5["W"]
@@ -382,7 +420,8 @@ def main():
         out["bf16_over_fp64"] = value / fval
 
     if not args.no_legs and args.only is None:
-        log("[bench] legs: APSP (FP64 ER 2048, BF16 RGG 16384), gradient 64x512^3, 256^2 FP64")
+        log("[bench] legs: APSP (FP64 ER 2048, BF16 RGG 16384), gradient 64x512^3, 256^2 FP64, "
+            "max-convolution 8192 x 2048")
         del Ad, Bd, E, E64, Asub
         torch.cuda.empty_cache()
         out["legs"] = run_legs(mt, torch, np)

@@ -309,11 +309,13 @@ mt_status maxtimes_timing_reset(void);
 mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* launches);
 
 /*
- * MFMA flops executed by the timed launches of the p-family GEMMs whose name
- * starts with `prefix` since the last reset (kernels that count no work add
- * nothing).  The forward GEMMs stop a tile as soon as every entry of it has
- * found its p* (smaller p cannot change the result), so this is at most, and
- * often less than, 2 * rows_pad * cols_pad * k_pad per segment of the family.
+ * Work executed by the timed launches whose kernel name starts with `prefix`
+ * since the last reset (kernels that count no work add nothing).  The p-family
+ * GEMMs count MFMA flops: the forward GEMMs stop a tile as soon as every entry
+ * of it has found its p* (smaller p cannot change the result), so this is at
+ * most, and often less than, 2 * rows_pad * cols_pad * k_pad per segment of
+ * the family.  The max-convolution counts 10 N log2 N flops (two complex FFTs
+ * of N points, 5 N log2 N each by the usual count) per pair and p visited.
  * Counters live in device memory that the timing facility allocates on first
  * use; reset waits for the recorded launches and clears them.
  */

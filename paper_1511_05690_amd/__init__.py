@@ -461,8 +461,10 @@ def search_start():
 
 
 def timing_work(prefix):
-    """MFMA flops executed by the timed p-family GEMM launches whose kernel
-    name starts with ``prefix`` (tiles stop once every entry has its p*)."""
+    """Work executed by the timed launches whose kernel name starts with
+    ``prefix``: MFMA flops of the p-family GEMMs (tiles stop once every entry
+    has its p*); 10 N log2 N flops per pair and p visited for the
+    max-convolution."""
     fl = ctypes.c_double(0.0)
     _check(load_library().maxtimes_timing_work(prefix.encode(), ctypes.byref(fl)))
     return fl.value
