@@ -34,6 +34,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CUs x 128 flop/clk x 2
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pfamily_gemm_bf16_8192_pmc.md")
 GEMM_SRC = os.path.join(ROOT, "paper_1511_05690_amd", "csrc", "mt_gemm_bf16.hip")
+MAXCONV_PMC = os.path.join(ROOT, "profiles", "maxconv_fft_8192x2048_pmc.md")
+MAXCONV_SRC = os.path.join(ROOT, "paper_1511_05690_amd", "csrc", "mt_maxconv.hip")
 
 
 def log(msg):
@@ -45,15 +47,15 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per launch of the BF16 GEMM from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(PMC_SUMMARY):
+def traffic_from_profile(summary=PMC_SUMMARY, src=GEMM_SRC):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter
+    summary, if the summary was taken on the current kernel source."""
+    if not os.path.exists(summary):
         return None
-    text = open(PMC_SUMMARY).read()
+    text = open(summary).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != source_hash(GEMM_SRC):
+    if not m_hash or not m_bytes or m_hash.group(1) != source_hash(src):
         return None
     return float(m_bytes.group(1))
 
@@ -236,6 +238,7 @@ def run_legs(mt, torch, np):
         "roofline": {"bound": "alu", "kernel": "mt_maxconv", "achieved": achieved,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic_from_profile(MAXCONV_PMC, MAXCONV_SRC),
                      "flop_per_launch": kflop / kn, "avg_launch_ms": kms / kn,
                      "flop_count": "10 N log2 N per pair and p visited (two complex FFTs), N = 4096"},
         "exact_ms": ms_exact, "speedup_vs_exact": ms_exact / ms,
