@@ -1,0 +1,98 @@
+"""Oracle: the top k values of x_i + y_j and their indices, FP64 on CPU.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Paper: Serang, arXiv 1511.05690, Sec. 2.3 (algorithm E for x' times y',
+and the index recovery that follows it).
+  * The additive problem maps to (x, max) by x' = e^x, y' = e^y.  Scaled as
+    in Sec. 2.1: x' = e^(x - max x), y' = e^(y - max y), every term in (0, 1].
+  * For every p in the family, sigma^(p)[m] = sum over i + j = m of
+    (x'_i y'_j)^p, the ordinary convolution of x'^p and y'^p (numpy's direct
+    convolution here, the plain definition of the ring result; the paper
+    computes it by FFT).
+  * psi[m] is the estimate of the largest term of diagonal m from its norm
+    sequence: the root sigma^(p*)^(1/p*) at the largest p with
+    sigma^(p) >= tau (the same rule as the product and the max-convolution).
+    Diagonals where no p is stable have no estimate (psi = 0, never popped
+    while anything else is left).
+  * NormQueue: k times, take the diagonal m* with the largest psi (the first
+    one on ties), report it, subtract psi^p from every sigma^(p)[m*] and
+    estimate psi[m*] again from what is left.
+  * Values are reported in the additive space: max x + max y + log(psi).
+  * Index recovery: a second run on y reversed gives, rank by rank, the
+    anti-diagonal m2 = i + (n - 1 - j) of the same value; with m1 = i + j,
+    i = (m1 + m2 - n + 1) / 2 and j = m1 - i (the pair is reported only when
+    that is an integer pair inside the n x n grid).
+"""
+
+import numpy as np
+
+TAU_FFT = 1e-12
+
+
+def exact_topk_xy(x, y, k):
+    """The k largest x_i + y_j (brute force over all pairs), descending, with
+    their indices (ties in the order of i, then j)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    s = (x[:, None] + y[None, :]).ravel()
+    order = np.argsort(-s, kind="stable")[:k]
+    return s[order], order // y.size, order % y.size
+
+
+def _estimate(col, P, tau):
+    """psi (scaled space) and the family index used, from one diagonal's
+    sigma column; (0, -1) when no p is stable."""
+    for q in range(len(P) - 1, -1, -1):
+        if col[q] >= tau:
+            return col[q] ** (1.0 / P[q]), q
+    return 0.0, -1
+
+
+def norm_queue(x, y, P, k, tau=TAU_FFT):
+    """Algorithm E of Sec. 2.3 on one pair of lists (x and y may differ in
+    length here).  Returns dict values (k, additive space), diag (k, m*),
+    sigma (|P| x (n + m - 1), before any pop)."""
+    P = [int(p) for p in P]
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    mx, my = x.max(), y.max()
+    xs = np.exp(x - mx)
+    ys = np.exp(y - my)
+    sigma = np.stack([np.convolve(xs ** p, ys ** p) for p in P])
+    work = sigma.copy()
+    L = work.shape[1]
+    psi = np.zeros(L)
+    for m in range(L):
+        psi[m], _ = _estimate(work[:, m], P, tau)
+    values = np.zeros(k)
+    diag = np.zeros(k, dtype=np.int64)
+    for r in range(k):
+        m = int(np.argmax(psi))
+        a = psi[m]
+        values[r] = mx + my + (np.log(a) if a > 0 else -np.inf)
+        diag[r] = m
+        for q, p in enumerate(P):
+            work[q, m] -= a ** p
+        psi[m], _ = _estimate(work[:, m], P, tau)
+    return {"values": values, "diag": diag, "sigma": sigma}
+
+
+def xy_topk_estimate(x, y, P, k, tau=TAU_FFT):
+    """Top k of x_i + y_j by the NormQueue with index recovery (x and y of
+    the same length n).  Returns dict values, diag (i + j), anti
+    (i + n - 1 - j, from the run on y reversed), i, j (-1 where the two runs
+    do not give an integer pair in the grid)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = x.size
+    if y.size != n:
+        raise ValueError("x and y must have the same length")
+    a = norm_queue(x, y, P, k, tau)
+    b = norm_queue(x, y[::-1], P, k, tau)
+    s = a["diag"] + b["diag"] - (n - 1)
+    i = np.where(s % 2 == 0, s // 2, -1)
+    j = np.where(i >= 0, a["diag"] - i, -1)
+    ok = (i >= 0) & (i < n) & (j >= 0) & (j < n)
+    return {"values": a["values"], "diag": a["diag"], "anti": b["diag"],
+            "i": np.where(ok, i, -1), "j": np.where(ok, j, -1)}

@@ -1,0 +1,118 @@
+"""Pins of the oracle's top k of x_i + y_j (Sec. 2.3, algorithm E and the
+index recovery).  From the definition and the mathematics, not from the
+oracle's own formulas:
+
+* the brute-force top k equals a double loop and a sort;
+* lists whose diagonals hold one term each (x of length 1) are popped
+  exactly, in value order;
+* a near one-hot x (one element, the rest 60 below it) makes every diagonal
+  one dominant term: values and indices are exact, and so on the mirror
+  case with y near one-hot;
+* k = 1 is the largest value of the max-convolution estimate (Sec. 1) of
+  e^x and e^y, and it bounds the true maximum from above;
+* on well separated random lists the estimate finds the true top k and its
+  indices (the behaviour Sec. 3 reports for uniform lists);
+* shifting x and y by constants shifts the values and keeps the indices;
+  the run on y reversed gives the same values (the order of y does not
+  matter, the premise of the index recovery).
+"""
+
+import itertools
+
+import numpy as np
+
+import oracle
+from oracle.xy_topk import exact_topk_xy, norm_queue, xy_topk_estimate
+
+# 24 powers up to 4096, as in Sec. 3 (|P| = 24, p*_max = 4096)
+P24 = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
+
+
+def test_exact_matches_brute_force():
+    rng = np.random.default_rng(81)
+    x = rng.normal(size=7)
+    y = rng.normal(size=5)
+    v, i, j = exact_topk_xy(x, y, 9)
+    pairs = sorted(((x[a] + y[b], a, b) for a, b in itertools.product(range(7), range(5))),
+                   key=lambda t: -t[0])[:9]
+    np.testing.assert_array_equal(v, [p[0] for p in pairs])
+    np.testing.assert_array_equal(i, [p[1] for p in pairs])
+    np.testing.assert_array_equal(j, [p[2] for p in pairs])
+
+
+def test_single_term_diagonals_are_exact():
+    rng = np.random.default_rng(82)
+    y = rng.uniform(0, 3, 20)
+    r = norm_queue([0.7], y, P24, 12)
+    order = np.argsort(-y)[:12]
+    np.testing.assert_allclose(r["values"], 0.7 + y[order], rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(r["diag"], order)
+
+
+def test_near_one_hot_exact_with_indices():
+    rng = np.random.default_rng(83)
+    n, k = 32, 16
+    x = np.full(n, -60.0)
+    x[5] = 1.5
+    y = rng.uniform(0, 3, n)
+    r = xy_topk_estimate(x, y, P24, k)
+    v, i, j = exact_topk_xy(x, y, k)
+    np.testing.assert_allclose(r["values"], v, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(r["i"], i)
+    np.testing.assert_array_equal(r["j"], j)
+    # the mirror: y near one-hot
+    r = xy_topk_estimate(y, x, P24, k)
+    v, i, j = exact_topk_xy(y, x, k)
+    np.testing.assert_allclose(r["values"], v, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(r["i"], i)
+    np.testing.assert_array_equal(r["j"], j)
+
+
+def test_first_pop_is_the_max_convolution_estimate():
+    rng = np.random.default_rng(84)
+    x = rng.uniform(0, 5, 50)
+    y = rng.uniform(0, 5, 50)
+    r = norm_queue(x, y, P24, 1)
+    mc = oracle.maxconv_estimate(np.exp(x), np.exp(y), P24)
+    assert abs(r["values"][0] - np.log(mc["z"].max())) <= 1e-12
+    true_max = x.max() + y.max()
+    assert true_max - 1e-12 <= r["values"][0] <= true_max + np.log(50) / P24[0]
+
+
+def test_well_separated_lists_find_the_true_top_k():
+    rng = np.random.default_rng(85)
+    x = rng.uniform(0, 40, 64)
+    y = rng.uniform(0, 40, 64)
+    r = xy_topk_estimate(x, y, P24, 16)
+    v, i, j = exact_topk_xy(x, y, 16)
+    np.testing.assert_allclose(r["values"], v, rtol=0, atol=1e-4)
+    np.testing.assert_array_equal(r["i"], i)
+    np.testing.assert_array_equal(r["j"], j)
+
+
+def test_shift_invariance_and_order_of_y():
+    rng = np.random.default_rng(86)
+    x = rng.uniform(0, 10, 40)
+    y = rng.uniform(0, 10, 40)
+    a = xy_topk_estimate(x, y, P24, 10)
+    b = xy_topk_estimate(x + 3.25, y - 1.5, P24, 10)
+    np.testing.assert_allclose(b["values"], a["values"] + 1.75, rtol=0, atol=1e-9)
+    np.testing.assert_array_equal(a["diag"], b["diag"])
+    np.testing.assert_array_equal(a["i"], b["i"])
+    rev = norm_queue(x, y[::-1], P24, 10)
+    np.testing.assert_allclose(rev["values"], a["values"], rtol=0, atol=1e-6)
+
+
+def test_no_stable_power_and_validation():
+    # the stability test is S >= tau (Sec. 1): a ring result equal to tau counts
+    r = norm_queue([0.0], [0.0], [1, 2], 1, tau=1.0)
+    assert r["values"][0] == 0.0 and r["diag"][0] == 0
+    # tau above every ring result: nothing is stable, every value is -inf
+    r = norm_queue([0.0, 0.0], [0.0, 0.0], [1, 2], 2, tau=10.0)
+    assert np.isneginf(r["values"]).all()
+    try:
+        xy_topk_estimate([0.0, 1.0], [0.0], [1], 1)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("unequal lengths must be rejected")
