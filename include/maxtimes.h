@@ -292,6 +292,39 @@ mt_status maxconv_estimate(const void* x, const void* y, mt_dtype dtype, int64_t
 mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
                         void* z, void* stream);
 
+/*
+ * Top k of x_i + y_j with their indices (Sec. 2.3: algorithm E, the
+ * NormQueue, and the index recovery from a second run on y reversed).
+ *   x' = e^(x - max x), y' = e^(y - max y)           (the (x, max) image, scaled)
+ *   sigma^(p)[m] = (x'^p * y'^p)[m], m = 0 .. 2n - 2 (FFT convolution in FP64)
+ *   psi[m] = sigma^(p*)[m]^(1/p*), p* the largest p with sigma^(p)[m] >= tau
+ *            (0 if none: such diagonals come last)
+ *   k times: m* = the diagonal with the largest psi (the lowest m on ties);
+ *            report max x + max y + log(psi[m*]) and m*; subtract psi[m*]^p
+ *            from sigma^(p)[m*] for every p; estimate psi[m*] again.
+ *   The same on y reversed gives, rank by rank, m2 = i + (n - 1 - j); with
+ *   m1 = i + j the indices are i = (m1 + m2 - n + 1) / 2, j = m1 - i (-1 when
+ *   that is not an integer pair in the grid).  The values are estimates and
+ *   the pops can come out of order; errors accumulate with the rank (Sec. 3).
+ *   x, y     n values each, dtype (FP32 / FP64), device, finite.
+ *   opt      family as for maxtimes_estimate (Sec. 3 uses 24 powers up to
+ *            4096); path MT_PATH_FP64 (else MT_ERR_UNSUPPORTED); tau <= 0 ->
+ *            MT_TAU_FFT_DEFAULT; flags must be 0 (else MT_ERR_UNSUPPORTED).
+ *   values   k FP64 device (output), in pop order.
+ *   diag, i_idx, j_idx  k int32 device (outputs, each nullable): m1, i, j.
+ * 1 <= n <= 2048 (2n - 1 <= 4096: the transform runs in one workgroup's
+ * LDS), 0 <= k <= 2^24 (else MT_ERR_UNSUPPORTED / MT_ERR_INVALID_ARG).
+ * The pops run on one wave per run, in sequence.  Workspace from
+ * xy_topk_workspace_size (16 (|P| + 1)(2n - 1) + 16 k bytes and alignment).  With
+ * k = 0 only the ring results are formed: the workspace then starts with
+ * sigma^(p)[m] of both runs, FP64, indexed (run |P| + q)(2n - 1) + m (run 1
+ * on y reversed), for inspection.  Asynchronous on the stream.
+ */
+mt_status xy_topk_workspace_size(int64_t n, int32_t k, const mt_options* opt, size_t* bytes);
+mt_status xy_topk_estimate(const void* x, const void* y, mt_dtype dtype, int64_t n, int32_t k,
+                           const mt_options* opt, double* values, int32_t* diag, int32_t* i_idx,
+                           int32_t* j_idx, void* workspace, size_t ws_bytes, void* stream);
+
 /* Static description of a status code. */
 const char* maxtimes_status_string(mt_status status);
 

@@ -72,8 +72,11 @@ def norm_queue(x, y, P, k, tau=TAU_FFT):
         a = psi[m]
         values[r] = mx + my + (np.log(a) if a > 0 else -np.inf)
         diag[r] = m
-        for q, p in enumerate(P):
-            work[q, m] -= a ** p
+        # psi may exceed 1 (the norm bounds the max from above): psi^p can
+        # overflow to inf for large p, leaving -inf, which is not stable
+        with np.errstate(over="ignore"):
+            for q, p in enumerate(P):
+                work[q, m] -= a ** p
         psi[m], _ = _estimate(work[:, m], P, tau)
     return {"values": values, "diag": diag, "sigma": sigma}
 

@@ -12,6 +12,7 @@ product, Sec. 2.2 for all-pairs shortest paths.
     C = estimate(A, B, P=(1, 2, 4, ..., 64), path="bf16")   # C ~ max_k A_ik B_kj
     D = apsp(W, s=1.0, P=..., path="fp64")                  # shortest distances
     z = maxconv(x, y, P=(1, 2, 4, ..., 64))                 # z ~ max_i x_i y_(t-i)
+    v, i, j = xy_topk(x, y, k)                              # top k of x_i + y_j
 """
 
 import ctypes
@@ -24,11 +25,14 @@ __all__ = [
     "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
     "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold",
     "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "maxconv", "maxconv_exact",
-    "pfamily", "PSTAR_NONE", "PATHS",
+    "xy_topk", "xy_topk_workspace_size", "XY_FAMILY", "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
 PSTAR_NONE = 255
 MAX_P = 32
+# 24 powers up to 4096 (Sec. 3 runs the x + y top k with |P| = 24, p*_max = 4096)
+XY_FAMILY = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048,
+             3072, 4096)
 PATHS = {"fp64": 0, "bf16": 1}
 F32, F64 = 0, 1
 FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT, FLAG_PROJECT_R1, FLAG_PROJECT_R2 = 1, 2, 4, 8, 16, 32
@@ -85,6 +89,8 @@ def load_library():
         "maxtimes_exact": [vp, vp, ctypes.c_int, i64, i64, i64, i64, vp, vp],
         "maxconv_estimate": [vp, vp, ctypes.c_int, i64, i64, i64, opt, vp, vp, vp],
         "maxconv_exact": [vp, vp, ctypes.c_int, i64, i64, i64, vp, vp],
+        "xy_topk_workspace_size": [i64, ctypes.c_int32, opt, ctypes.POINTER(sz)],
+        "xy_topk_estimate": [vp, vp, ctypes.c_int, i64, ctypes.c_int32, opt, vp, vp, vp, vp, vp, sz, vp],
         "apsp_exact_rows_workspace_size": [i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
         "apsp_exact_rows": [vp, i64, vp, ctypes.c_int32, vp, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp],
         "apsp_affine_workspace_size": [ctypes.POINTER(ctypes.c_size_t)],
@@ -374,6 +380,41 @@ def maxconv_exact(x, y):
     z = torch.empty((b, L) if batched else (L,), dtype=x.dtype, device=x.device)
     _check(lib.maxconv_exact(_ptr(x), _ptr(y), _dtype_code(x), b, n, m, _ptr(z), _stream(x.device)))
     return z
+
+
+def xy_topk_workspace_size(n, k, P=XY_FAMILY, tau=None):
+    lib = load_library()
+    o = _options(P, "fp64", tau, None, 0)
+    out = ctypes.c_size_t(0)
+    _check(lib.xy_topk_workspace_size(n, k, ctypes.byref(o), ctypes.byref(out)))
+    return out.value
+
+
+def xy_topk(x, y, k, P=XY_FAMILY, tau=None, return_diag=False):
+    """Estimate the k largest x_i + y_j (x, y: 1-D device tensors of the same
+    length n <= 2048) and their indices by the NormQueue of Sec. 2.3 (FFT ring
+    results in FP64, a second run on y reversed for the indices).  Returns
+    (values FP64, i int32, j int32[, diag]); i = j = -1 where the two runs do
+    not give a pair in the grid."""
+    lib = load_library()
+    if not (x.is_cuda and y.is_cuda) or x.dim() != 1 or y.dim() != 1 or x.shape != y.shape:
+        raise ValueError("x and y must be 1-D device tensors of the same length")
+    if x.dtype != y.dtype:
+        raise TypeError("x and y must have the same dtype")
+    x = x.contiguous()
+    y = y.contiguous()
+    n = x.shape[0]
+    o = _options(P, "fp64", tau, None, 0)
+    need = ctypes.c_size_t(0)
+    _check(lib.xy_topk_workspace_size(n, int(k), ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, x.device, None)
+    values = torch.empty(k, dtype=torch.float64, device=x.device)
+    ii = torch.empty(k, dtype=torch.int32, device=x.device)
+    jj = torch.empty(k, dtype=torch.int32, device=x.device)
+    dg = torch.empty(k, dtype=torch.int32, device=x.device)
+    _check(lib.xy_topk_estimate(_ptr(x), _ptr(y), _dtype_code(x), n, int(k), ctypes.byref(o), _ptr(values),
+                                _ptr(dg), _ptr(ii), _ptr(jj), _ptr(ws), need.value, _stream(x.device)))
+    return (values, ii, jj, dg) if return_diag else (values, ii, jj)
 
 
 def apsp_exact_rows(W, sources):

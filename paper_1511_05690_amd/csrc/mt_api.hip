@@ -886,6 +886,75 @@ mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b,
     return MT_OK;
 }
 
+// Workspace of xy_topk_estimate: the ring results of both runs, then the
+// second run's values and both runs' diagonals.
+struct XyLayout {
+    size_t sigma, psi, values1, diag0, diag1, total;
+};
+XyLayout xy_layout(int64_t n, int32_t k, int n_p) {
+    XyLayout L{};
+    const int64_t len = 2 * n - 1;
+    size_t off = 0;
+    L.sigma = off;
+    off += (size_t)round_up(2 * (int64_t)n_p * len * 8, kAlign);
+    L.psi = off;
+    off += (size_t)round_up(2 * len * 8, kAlign);
+    L.values1 = off;
+    off += (size_t)round_up((int64_t)k * 8, kAlign);
+    L.diag0 = off;
+    off += (size_t)round_up((int64_t)k * 4, kAlign);
+    L.diag1 = off;
+    off += (size_t)round_up((int64_t)k * 4, kAlign);
+    L.total = off;
+    return L;
+}
+
+mt_status xy_check(int64_t n, int32_t k, const mt_options* opt, Family* f) {
+    mt_status s = parse_options(opt, f);
+    if (s != MT_OK) return s;
+    if (f->bf16) return fail(MT_ERR_UNSUPPORTED, "the x + y top k runs on the FP64 path only");
+    if (f->flags) return fail(MT_ERR_UNSUPPORTED, "the x + y top k takes no flags");
+    if (n < 1 || k < 0) return fail(MT_ERR_INVALID_ARG, "need n >= 1 and k >= 0 (n=%lld k=%d)", (long long)n, k);
+    if (2 * n - 1 > kMaxConvN) return fail(MT_ERR_UNSUPPORTED, "2n - 1 = %lld exceeds %d", (long long)(2 * n - 1), kMaxConvN);
+    if (k > (1 << 24)) return fail(MT_ERR_UNSUPPORTED, "k above 2^24");
+    return MT_OK;
+}
+
+mt_status xy_topk_workspace_size(int64_t n, int32_t k, const mt_options* opt, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");
+    Family f;
+    mt_status s = xy_check(n, k, opt, &f);
+    if (s != MT_OK) return s;
+    *bytes = xy_layout(n, k, f.n).total;
+    return MT_OK;
+}
+
+mt_status xy_topk_estimate(const void* x, const void* y, mt_dtype dtype, int64_t n, int32_t k,
+                           const mt_options* opt, double* values, int32_t* diag, int32_t* i_idx,
+                           int32_t* j_idx, void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    Family f;
+    mt_status s = xy_check(n, k, opt, &f);
+    if (s != MT_OK) return s;
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (!x || !y) return fail(MT_ERR_INVALID_ARG, "x or y is NULL");
+    if (k > 0 && !values) return fail(MT_ERR_INVALID_ARG, "values is NULL");
+    const XyLayout L = xy_layout(n, k, f.n);
+    s = check_ws(workspace, ws_bytes, L.total);
+    if (s != MT_OK) return s;
+    MaxconvSpec spec{};
+    spec.n = f.n;
+    for (int q = 0; q < f.n; ++q) spec.p[q] = f.p[q];
+    spec.tau = opt->tau > 0.0 ? opt->tau : MT_TAU_FFT_DEFAULT;
+    uint8_t* ws = (uint8_t*)workspace;
+    XyWorkspace w{(double*)(ws + L.sigma), (double*)(ws + L.psi), (double*)(ws + L.values1),
+                  (int32_t*)(ws + L.diag0), (int32_t*)(ws + L.diag1)};
+    MT_TRY(launch_xy_topk(x, y, dtype == MT_F64, n, k, spec, values, diag, i_idx, j_idx, w, (hipStream_t)stream),
+           "x + y top k");
+    return MT_OK;
+}
+
 mt_status apsp_exact_rows_workspace_size(int64_t n, int32_t n_src, size_t* bytes) {
     g_last_error.clear();
     if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");

@@ -277,6 +277,18 @@ hipError_t launch_maxconv(const void* x, const void* y, int f64, int64_t b, int6
                           const MaxconvSpec& spec, void* z, uint8_t* pstar, hipStream_t st);
 hipError_t launch_maxconv_exact(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,
                                 void* z, hipStream_t st);
+// Top k of x + y (Sec. 2.3): ring results of both runs, the second run's
+// values and both runs' diagonals.
+struct XyWorkspace {
+    double* sigma;    // 2 x n_p x (2n - 1)
+    double* psi;      // 2 x (2n - 1): the estimates before any pop
+    double* values1;  // k
+    int32_t* diag0;   // k
+    int32_t* diag1;   // k
+};
+hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int32_t k, const MaxconvSpec& spec,
+                          double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
+                          hipStream_t st);
 
 // Exact (max, x) product on the vector ALUs.
 hipError_t launch_exact_maxtimes(const void* A, const void* B, int f64, int64_t b, int64_t m,

@@ -43,9 +43,6 @@ namespace {
 constexpr int kConvThreads = 256;  // kMaxConvN / 16
 static_assert(kConvThreads * 16 == kMaxConvN, "16 values per thread at the largest N");
 constexpr int kConvMinLog = 4;
-// per log2 N: transform the powers in pairs (one inverse for two p)
-constexpr bool kPairInverse[kMaxConvLog + 1] = {false, false, false, false, false, false, false,
-                                                false, false, false, false, false, false};
 // padded LDS elements per workgroup: one buffer of N + N / 16 per pair, 4096 / N pairs
 constexpr int kConvLdsElems = kMaxConvN + kMaxConvN / 16;
 // twiddle octant: cos and sin of 2 pi k / N, k = 0 .. N / 8
@@ -315,42 +312,11 @@ __device__ __forceinline__ constexpr int last_reg(int i) {
     return (i % B) + B * oreg<R>(i / B);
 }
 
-template <typename T, int LOGN, bool PAIR>
-__global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __restrict__ x,
-                                                                  const T* __restrict__ y, int64_t b, int64_t n,
-                                                                  int64_t m, MaxconvSpec spec,
-                                                                  T* __restrict__ z,
-                                                                  uint8_t* __restrict__ pstar,
-                                                                  unsigned long long* work) {
-    using F = Fft<LOGN>;
-    constexpr int N = F::N, TP = F::T;
-    extern __shared__ double2 lds[];
-    __shared__ double red[2][kConvThreads / 64];
-    double2* tw = lds;  // kConvTwElems
+// Maxima of mx and my over the threads of one slot (contiguous lanes; several
+// waves when TP > 64); red holds one pair per wave.
+template <int TP>
+__device__ __forceinline__ void slot_max(double& mx, double& my, double (*red)[kConvThreads / 64]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int slot = tid / TP, tl0 = tid % TP;
-    const int tl = tl0;
-    const int64_t item = (int64_t)blockIdx.x * F::G + slot;
-    const bool active = item < b;
-    const int L = (int)(n + m - 1);
-    double2* buf = lds + kConvTwElems + slot * F::NP;
-    const T* xi = x + item * n;
-    const T* yi = y + item * m;
-
-    // the thread owns positions tl + i TP, i = 0 .. 15
-    double mx = 0.0, my = 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int t = tl + i * TP;
-        if (active && t < n) mx = fmax(mx, (double)xi[t]);
-        if (active && t < m) my = fmax(my, (double)yi[t]);
-    }
-    for (int k = tid; k <= N / 8; k += kConvThreads) {
-        double sn, cs;
-        sincospi(2.0 * (double)k / (double)N, &sn, &cs);
-        tw[k] = make_double2(cs, sn);
-    }
-    // maxima over the pair's threads (contiguous lanes; several waves when TP > 64)
 #pragma unroll
     for (int d = (TP < 64 ? TP : 64) / 2; d >= 1; d >>= 1) {
         mx = fmax(mx, __shfl_xor(mx, d));
@@ -370,9 +336,100 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
             my = fmax(my, red[1][w0 + w]);
         }
     }
+}
+
+// The octant table cos / sin (2 pi k / N), k = 0 .. N / 8.
+template <int LOGN>
+__device__ __forceinline__ void build_twiddle_table(double2* tw) {
+    constexpr int N = 1 << LOGN;
+    for (int k = threadIdx.x; k <= N / 8; k += kConvThreads) {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)N, &sn, &cs);
+        tw[k] = make_double2(cs, sn);
+    }
+}
+
+// One pair's convolution of the two real sequences held as v[i] = (a, b) at
+// the thread's positions tl + i T (a = x'^p, b = y'^p, zero beyond the
+// lists): the forward transform of a + i b, the product W = X Y formed from
+// Z_t and Z_(N-t), and the inverse as the forward transform of conj(W).  On
+// return v[last_reg(i)].x * 0.25 / N is (a * b)[tl + i T].  Every thread of
+// the workgroup calls it (it holds barriers).
+template <int LOGN>
+__device__ __forceinline__ void convolve_pair(double2 (&v)[16], int tl, double2* buf,
+                                              const PassTwiddles<LOGN>& pt) {
+    using F = Fft<LOGN>;
+    constexpr int N = F::N, TP = F::T;
+    pass_compute<LOGN, 0>(v, pt);
+    pass_store<LOGN, 0>(v, tl, buf);
+    __syncthreads();
+    middle_passes<LOGN, 1, F::NPASS>(v, tl, buf, pt);
+    // conj(4 W_t), 4 W_t = (Z_t + conj Z_-t)(Z_t - conj Z_-t) / i
+    const int bp = padi(tl), bn = padi(N - tl);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        int ik, in;
+        if constexpr (TP % 16 == 0) {
+            // t = tl + i TP > 0 for i > 0
+            ik = bp + i * (TP / 16 * 17);
+            in = i == 0 ? padi((N - tl) & (N - 1)) : bn - i * (TP / 16 * 17);
+        } else {
+            const int t = tl + i * TP;
+            ik = padi(t);
+            in = padi((N - t) & (N - 1));
+        }
+        const double2 zk = buf[ik], zn = buf[in];
+        const double2 a = make_double2(zk.x + zn.x, zk.y - zn.y);
+        const double2 c = make_double2(zk.y + zn.y, zn.x - zk.x);
+        const double2 w = cmul(a, c);
+        v[i] = make_double2(w.x, -w.y);
+    }
+    // the last pass leaves position tl + i TP in register last_reg(i)
+    pass_compute<LOGN, 0>(v, pt);
+    if constexpr (F::NPASS > 1) {
+        __syncthreads();
+        pass_store<LOGN, 0>(v, tl, buf);
+        __syncthreads();
+        middle_passes<LOGN, 1, F::NPASS - 1>(v, tl, buf, pt);
+        pass_load<LOGN>(v, tl, buf);
+        pass_compute<LOGN, F::NPASS - 1>(v, pt);
+    }
+}
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __restrict__ x,
+                                                                  const T* __restrict__ y, int64_t b, int64_t n,
+                                                                  int64_t m, MaxconvSpec spec,
+                                                                  T* __restrict__ z,
+                                                                  uint8_t* __restrict__ pstar,
+                                                                  unsigned long long* work) {
+    using F = Fft<LOGN>;
+    constexpr int N = F::N, TP = F::T;
+    extern __shared__ double2 lds[];
+    __shared__ double red[2][kConvThreads / 64];
+    double2* tw = lds;  // kConvTwElems
+    const int tid = threadIdx.x;
+    const int slot = tid / TP, tl0 = tid % TP;
+    const int64_t item = (int64_t)blockIdx.x * F::G + slot;
+    const bool active = item < b;
+    const int L = (int)(n + m - 1);
+    double2* buf = lds + kConvTwElems + slot * F::NP;
+    const T* xi = x + item * n;
+    const T* yi = y + item * m;
+
+    // the thread owns positions tl + i TP, i = 0 .. 15
+    double mx = 0.0, my = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int t = tl0 + i * TP;
+        if (active && t < n) mx = fmax(mx, (double)xi[t]);
+        if (active && t < m) my = fmax(my, (double)yi[t]);
+    }
+    build_twiddle_table<LOGN>(tw);
+    slot_max<TP>(mx, my, red);
     __syncthreads();
     PassTwiddles<LOGN> pt;
-    load_twiddles<LOGN, 1>(pt, tl, tw);
+    load_twiddles<LOGN, 1>(pt, tl0, tw);
     const double rxy = mx * my;
     const double ix = mx > 0.0 ? 1.0 / mx : 0.0, iy = my > 0.0 ? 1.0 / my : 0.0;
     // 1 / N and the 1 / 4 of X Y (both halves carry 1 / 2)
@@ -384,95 +441,36 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
     for (int i = 0; i < 16; ++i) s_sel[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) q_sel[i] = 0u;
-    int ffts = 0;
+    int iters = 0;
 
-    // With PAIR, powers go in pairs (p_a, p_b) = (P[q], P[q - 1]): two forward
-    // transforms and one inverse of V = W_a + i W_b, whose real and imaginary
-    // parts are S_a and S_b (both ring results are real).
-    for (int q = spec.n - 1; q >= 0; q -= PAIR ? 2 : 1) {
-        const bool two = PAIR && q > 0;
-        ffts += two ? 3 : 2;
-        // re-derive the addresses per step instead of holding them across the loop
+    for (int q = spec.n - 1; q >= 0; --q) {
+        ++iters;
+        const int p = spec.p[q];
+        // re-derive the addresses per p instead of holding them across the loop
         int tl = tl0;
         asm volatile("" : "+v"(tl));
-        const int bp = padi(tl), bn = padi(N - tl);
-        // forward transform of x'^p + i y'^p into the LDS buffer (natural order)
-        auto forward = [&](int p, double2 (&w)[16]) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int t = tl + i * TP;
-                const double a = (active && t < n) ? (double)xi[t] * ix : 0.0;
-                const double c = (active && t < m) ? (double)yi[t] * iy : 0.0;
-                w[i] = make_double2(ipow_d(a, p), ipow_d(c, p));
-            }
-            pass_compute<LOGN, 0>(w, pt);
-            pass_store<LOGN, 0>(w, tl, buf);
-            __syncthreads();
-            middle_passes<LOGN, 1, F::NPASS>(w, tl, buf, pt);
-        };
-        // 4 W_t = (Z_t + conj Z_-t)(Z_t - conj Z_-t) / i at the thread's position i
-        auto product = [&](int i) {
-            int ik, in;
-            if constexpr (TP % 16 == 0) {
-                // t = tl + i TP > 0 for i > 0
-                ik = bp + i * (TP / 16 * 17);
-                in = i == 0 ? padi((N - tl) & (N - 1)) : bn - i * (TP / 16 * 17);
-            } else {
-                const int t = tl + i * TP;
-                ik = padi(t);
-                in = padi((N - t) & (N - 1));
-            }
-            const double2 zk = buf[ik], zn = buf[in];
-            const double2 a = make_double2(zk.x + zn.x, zk.y - zn.y);
-            const double2 c = make_double2(zk.y + zn.y, zn.x - zk.x);
-            return cmul(a, c);
-        };
         double2 v[16];
-        forward(spec.p[q], v);
-        // the inverse is the forward transform of conj(V) = conj(W_a) - i conj(W_b)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const double2 w = product(i);
-            v[i] = make_double2(w.x, -w.y);
+            const int t = tl + i * TP;
+            const double a = (active && t < n) ? (double)xi[t] * ix : 0.0;
+            const double c = (active && t < m) ? (double)yi[t] * iy : 0.0;
+            v[i] = make_double2(ipow_d(a, p), ipow_d(c, p));
         }
-        if constexpr (PAIR) {
-            if (two) {
-                double2 u[16];
-                __syncthreads();
-                forward(spec.p[q - 1], u);
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const double2 w = product(i);
-                    v[i] = make_double2(v[i].x - w.y, v[i].y - w.x);
-                }
-            }
-        }
-        // the last pass leaves position tl + i TP in register last_reg(i)
-        pass_compute<LOGN, 0>(v, pt);
-        if constexpr (F::NPASS > 1) {
-            __syncthreads();
-            pass_store<LOGN, 0>(v, tl, buf);
-            __syncthreads();
-            middle_passes<LOGN, 1, F::NPASS - 1>(v, tl, buf, pt);
-            pass_load<LOGN>(v, tl, buf);
-            pass_compute<LOGN, F::NPASS - 1>(v, pt);
-        }
+        convolve_pair<LOGN>(v, tl, buf, pt);
         // p* test: the first stable p from the top decides an index; the
-        // smallest p decides what is left (its S, no p stable).  S_a = Re / N,
-        // S_b = -Im / N (with the 1 / 4 of X Y).
-        const bool lastp = two ? q == 1 : q == 0;
+        // smallest p decides what is left (its S, no p stable)
         int open = 0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int t = tl + i * TP;
-            const double2 r = v[last_reg<LOGN>(i)];
-            const double sa = r.x * scale, sb = -r.y * scale;
+            const double S = v[last_reg<LOGN>(i)].x * scale;
             const bool live = active && t < L && !(decided & (1u << i));
-            const bool st_a = sa >= spec.tau, st_b = two && sb >= spec.tau;
-            const bool dec = live && (st_a || st_b || lastp);
+            const bool stable = S >= spec.tau;
+            const bool dec = live && (stable || q == 0);
             open |= live && !dec;
-            s_sel[i] = dec ? (st_a || !two ? sa : sb) : s_sel[i];
-            const uint32_t code = st_a ? (uint32_t)q : st_b ? (uint32_t)(q - 1) : (uint32_t)MT_PSTAR_NONE;
+            s_sel[i] = dec ? S : s_sel[i];
+            const uint32_t code = stable ? (uint32_t)q : (uint32_t)MT_PSTAR_NONE;
             q_sel[i / 4] = dec ? (q_sel[i / 4] & ~(0xffu << (8 * (i % 4)))) | (code << (8 * (i % 4))) : q_sel[i / 4];
             decided |= dec ? 1u << i : 0u;
         }
@@ -505,10 +503,190 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
         }
     }
     if (work && tid == 0) {
-        // 5 N log2 N flops per complex transform (the usual FFT count)
+        // two complex transforms per p, 5 N log2 N flops each (the usual FFT count)
         const int64_t pairs = b - (int64_t)blockIdx.x * F::G < F::G ? b - (int64_t)blockIdx.x * F::G : F::G;
-        atomicAdd(work, (unsigned long long)ffts * (unsigned long long)pairs * (5ull * N * LOGN));
+        atomicAdd(work, (unsigned long long)iters * (unsigned long long)pairs * (10ull * N * LOGN));
     }
+}
+
+// Top k of x + y (Sec. 2.3).  The ring results sigma^(p) = x'^p * y'^p with
+// x' = e^(x - max x), y' = e^(y - max y) (terms in (0, 1]), for every p of the
+// family and both runs (run 0 with y, run 1 with y reversed): one convolution
+// per slot, slot = run |P| + q.  sigma is (2, |P|, 2n - 1), FP64.
+template <typename T, int LOGN>
+__global__ __launch_bounds__(kConvThreads, 2) void mt_xy_sigma_kernel(const T* __restrict__ x,
+                                                                   const T* __restrict__ y, int64_t n,
+                                                                   MaxconvSpec spec, double* __restrict__ sigma) {
+    using F = Fft<LOGN>;
+    constexpr int N = F::N, TP = F::T;
+    extern __shared__ double2 lds[];
+    __shared__ double red[2][kConvThreads / 64];
+    double2* tw = lds;  // kConvTwElems
+    const int tid = threadIdx.x;
+    const int slot = tid / TP, tl = tid % TP;
+    const int item = (int)blockIdx.x * F::G + slot;
+    const bool active = item < 2 * spec.n;
+    const int run = active ? item / spec.n : 0, q = active ? item % spec.n : 0;
+    const int L = (int)(2 * n - 1);
+    double2* buf = lds + kConvTwElems + slot * F::NP;
+
+    double mx = -INFINITY, my = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int t = tl + i * TP;
+        if (active && t < n) {
+            mx = fmax(mx, (double)x[t]);
+            my = fmax(my, (double)y[t]);
+        }
+    }
+    build_twiddle_table<LOGN>(tw);
+    slot_max<TP>(mx, my, red);
+    __syncthreads();
+    PassTwiddles<LOGN> pt;
+    load_twiddles<LOGN, 1>(pt, tl, tw);
+    const int p = spec.p[q];
+    double2 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int t = tl + i * TP;
+        double a = 0.0, c = 0.0;
+        if (active && t < n) {
+            a = ipow_d(exp((double)x[t] - mx), p);
+            c = ipow_d(exp((double)y[run ? n - 1 - t : t] - my), p);
+        }
+        v[i] = make_double2(a, c);
+    }
+    convolve_pair<LOGN>(v, tl, buf, pt);
+    if (active) {
+        double* out = sigma + ((int64_t)run * spec.n + q) * L;
+        const double scale = 0.25 / (double)N;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int t = tl + i * TP;
+            if (t < L) out[t] = v[last_reg<LOGN>(i)].x * scale;
+        }
+    }
+}
+
+// psi for every diagonal of both runs before any pop: the root at the largest
+// p with sigma^(p)[m] >= tau, 0 if none.  One thread per (run, m).
+__global__ __launch_bounds__(256) void mt_xy_psi_kernel(const double* __restrict__ sigma, int64_t L,
+                                                       MaxconvSpec spec, double* __restrict__ psi) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 2 * L) return;
+    const int64_t run = g / L, m = g - run * L;
+    const double* col = sigma + run * spec.n * L + m;
+    double s[MT_MAX_P];
+#pragma unroll
+    for (int q = 0; q < MT_MAX_P; ++q) s[q] = q < spec.n ? col[q * L] : 0.0;
+    int qh = -1;
+#pragma unroll
+    for (int q = 0; q < MT_MAX_P; ++q) qh = (q < spec.n && s[q] >= spec.tau) ? q : qh;
+    double sh = 0.0;
+#pragma unroll
+    for (int q = 0; q < MT_MAX_P; ++q) sh = q == qh ? s[q] : sh;
+    psi[g] = qh >= 0 ? pow(sh, 1.0 / (double)spec.p[qh]) : 0.0;
+}
+
+// The NormQueue of Sec. 2.3 for one run (block = run), one wave: psi[m] is the
+// root at the largest stable p of diagonal m (0 if none); k times the largest
+// psi (lowest m on ties) is reported as max x + max y + log(psi) and its
+// diagonal, psi^p is subtracted from every sigma^(p)[m] (in place) and psi[m]
+// is estimated again.
+template <typename T>
+__global__ __launch_bounds__(64) void mt_xy_queue_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                       int64_t n, MaxconvSpec spec, double* __restrict__ sigma,
+                                                       const double* __restrict__ psi0, int32_t k,
+                                                       double* __restrict__ values0,
+                                                       double* __restrict__ values1, int32_t* __restrict__ diag0,
+                                                       int32_t* __restrict__ diag1) {
+    __shared__ double psi[kMaxConvN];
+    const int lane = threadIdx.x, run = blockIdx.x;
+    const int L = (int)(2 * n - 1), np = spec.n;
+    double* sg = sigma + (int64_t)run * np * L;
+    double* values = run ? values1 : values0;
+    int32_t* diag = run ? diag1 : diag0;
+
+    double mx = -INFINITY, my = -INFINITY;
+    for (int i = lane; i < n; i += 64) {
+        mx = fmax(mx, (double)x[i]);
+        my = fmax(my, (double)y[i]);
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, d));
+        my = fmax(my, __shfl_xor(my, d));
+    }
+    const double shift = mx + my;
+    for (int m = lane; m < L; m += 64) psi[m] = psi0[(int64_t)run * L + m];
+    __syncthreads();
+    // the lane's best over m = lane (mod 64): largest psi, lowest m on ties
+    double bv = -1.0;
+    int bm = L;
+    auto rescan = [&]() {
+        bv = -1.0;
+        bm = L;
+#pragma unroll 16
+        for (int m = lane; m < L; m += 64) {
+            const double e = psi[m];
+            if (e > bv) {
+                bv = e;
+                bm = m;
+            }
+        }
+    };
+    rescan();
+    for (int r = 0; r < k; ++r) {
+        double a = bv;
+        int ms = bm;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const double oa = __shfl_xor(a, d);
+            const int om = __shfl_xor(ms, d);
+            if (oa > a || (oa == a && om < ms)) {
+                a = oa;
+                ms = om;
+            }
+        }
+        if (lane == 0) {
+            values[r] = a > 0.0 ? shift + log(a) : -INFINITY;
+            diag[r] = ms;
+        }
+        double s = 0.0;
+        bool st = false;
+        if (lane < np) {
+            double* cell = sg + (int64_t)lane * L + ms;
+            s = *cell - pow(a, (double)spec.p[lane]);
+            *cell = s;
+            st = s >= spec.tau;
+        }
+        const uint64_t mask = __ballot(st);
+        double e = 0.0;
+        if (mask) {
+            const int qh = 63 - __clzll(mask);
+            e = pow(__shfl(s, qh), 1.0 / (double)spec.p[qh]);
+        }
+        if (lane == 0) psi[ms] = e;
+        __syncthreads();
+        if (lane == (ms & 63)) rescan();
+    }
+}
+
+// Index recovery (Sec. 2.3): rank r has diagonal m1 = i + j in run 0 and
+// anti-diagonal m2 = i + (n - 1 - j) in run 1, so i = (m1 + m2 - n + 1) / 2,
+// j = m1 - i; -1 where that is not an integer pair in the n x n grid.
+__global__ __launch_bounds__(256) void mt_xy_index_kernel(const int32_t* __restrict__ d0,
+                                                         const int32_t* __restrict__ d1, int32_t k, int64_t n,
+                                                         int32_t* __restrict__ diag, int32_t* __restrict__ ii,
+                                                         int32_t* __restrict__ jj) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    const int64_t m1 = d0[r], m2 = d1[r];
+    const int64_t sum = m1 + m2 - (n - 1);
+    int64_t i = (sum & 1) == 0 ? sum / 2 : -1;
+    int64_t j = i >= 0 ? m1 - i : -1;
+    if (!(i >= 0 && i < n && j >= 0 && j < n)) i = j = -1;
+    if (diag) diag[r] = (int32_t)m1;
+    if (ii) ii[r] = (int32_t)i;
+    if (jj) jj[r] = (int32_t)j;
 }
 
 template <typename T>
@@ -545,7 +723,7 @@ namespace {
 template <typename T, int LOGN>
 hipError_t launch_maxconv_n(const T* x, const T* y, int64_t b, int64_t n, int64_t m, const MaxconvSpec& spec,
                             T* z, uint8_t* pstar, hipStream_t st) {
-    auto kern = mt_maxconv_kernel<T, LOGN, kPairInverse[LOGN]>;
+    auto kern = mt_maxconv_kernel<T, LOGN>;
     const int lds = (kConvTwElems + kConvLdsElems) * (int)sizeof(double2);
     // the dynamic-LDS limit is a per-device attribute of each kernel
     static std::atomic<uint64_t> attr_set{0};
@@ -593,6 +771,81 @@ hipError_t launch_maxconv(const void* x, const void* y, int f64, int64_t b, int6
     if (f64)
         return launch_maxconv_t<double>((const double*)x, (const double*)y, b, n, m, spec, (double*)z, pstar, st);
     return launch_maxconv_t<float>((const float*)x, (const float*)y, b, n, m, spec, (float*)z, pstar, st);
+}
+
+namespace {
+
+template <typename T, int LOGN>
+hipError_t launch_xy_sigma_n(const T* x, const T* y, int64_t n, const MaxconvSpec& spec, double* sigma,
+                             hipStream_t st) {
+    auto kern = mt_xy_sigma_kernel<T, LOGN>;
+    const int lds = (kConvTwElems + kConvLdsElems) * (int)sizeof(double2);
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_set.load() & bit)) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        attr_set.fetch_or(bit);
+    }
+    constexpr int G = Fft<LOGN>::G;
+    const int blocks = (2 * spec.n + G - 1) / G;
+    timing_before("mt_xy_sigma", st);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kConvThreads), lds, st, x, y, n, spec, sigma);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const MaxconvSpec& spec, double* values,
+                       int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w, hipStream_t st) {
+    hipError_t e = hipErrorInvalidValue;
+    switch (maxconv_log_size(n, n)) {
+        case 4: e = launch_xy_sigma_n<T, 4>(x, y, n, spec, w.sigma, st); break;
+        case 5: e = launch_xy_sigma_n<T, 5>(x, y, n, spec, w.sigma, st); break;
+        case 6: e = launch_xy_sigma_n<T, 6>(x, y, n, spec, w.sigma, st); break;
+        case 7: e = launch_xy_sigma_n<T, 7>(x, y, n, spec, w.sigma, st); break;
+        case 8: e = launch_xy_sigma_n<T, 8>(x, y, n, spec, w.sigma, st); break;
+        case 9: e = launch_xy_sigma_n<T, 9>(x, y, n, spec, w.sigma, st); break;
+        case 10: e = launch_xy_sigma_n<T, 10>(x, y, n, spec, w.sigma, st); break;
+        case 11: e = launch_xy_sigma_n<T, 11>(x, y, n, spec, w.sigma, st); break;
+        case 12: e = launch_xy_sigma_n<T, 12>(x, y, n, spec, w.sigma, st); break;
+        default: break;
+    }
+    if (e != hipSuccess) return e;
+    if (k <= 0) return hipSuccess;
+    const int64_t L = 2 * n - 1;
+    timing_before("mt_xy_psi", st);
+    hipLaunchKernelGGL(mt_xy_psi_kernel, dim3((unsigned)((2 * L + 255) / 256)), dim3(256), 0, st, w.sigma, L, spec,
+                       w.psi);
+    timing_after(st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    timing_before("mt_xy_queue", st);
+    hipLaunchKernelGGL(mt_xy_queue_kernel<T>, dim3(2), dim3(64), 0, st, x, y, n, spec, w.sigma, w.psi, k, values,
+                       w.values1, w.diag0, w.diag1);
+    timing_after(st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    timing_before("mt_xy_index", st);
+    hipLaunchKernelGGL(mt_xy_index_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, st, w.diag0, w.diag1, k,
+                       n, diag, ii, jj);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int32_t k, const MaxconvSpec& spec,
+                          double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (maxconv_log_size(n, n) > kMaxConvLog) return hipErrorInvalidValue;
+    if (f64)
+        return launch_xy_t<double>((const double*)x, (const double*)y, n, k, spec, values, diag, ii, jj, w, st);
+    return launch_xy_t<float>((const float*)x, (const float*)y, n, k, spec, values, diag, ii, jj, w, st);
 }
 
 hipError_t launch_maxconv_exact(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,

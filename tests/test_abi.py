@@ -246,3 +246,27 @@ def test_maxconv_validation():
     assert lib.maxconv_exact(null, fake, 0, 2, 8, 8, fake, null) == 1
     assert lib.maxconv_exact(fake, fake, 0, 2, (1 << 24) + 1, 8, fake, null) == 5
     assert lib.maxconv_exact(null, null, 1, 0, 8, 8, null, null) == 0
+
+
+def test_xy_topk_validation():
+    """Argument checks of the x + y top-k entry points (no GPU): FP64 path
+    only, no flags, 2n - 1 <= 4096, k >= 0, workspace size, NULL pointers."""
+    lib = mt.load_library()
+    o = _opts(list(mt.XY_FAMILY), path=0)
+    nb = ctypes.c_size_t(0)
+    assert lib.xy_topk_workspace_size(1024, 256, ctypes.byref(o), ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 24 * 2047 * 8 + 256 * 16
+    assert lib.xy_topk_workspace_size(2049, 4, ctypes.byref(o), ctypes.byref(nb)) == 5
+    assert lib.xy_topk_workspace_size(0, 4, ctypes.byref(o), ctypes.byref(nb)) == 1
+    assert lib.xy_topk_workspace_size(8, -1, ctypes.byref(o), ctypes.byref(nb)) == 1
+    assert lib.xy_topk_workspace_size(8, 4, ctypes.byref(_opts([1, 2], path=1)), ctypes.byref(nb)) == 5
+    assert lib.xy_topk_workspace_size(8, 4, ctypes.byref(_opts([1, 2], path=0, flags=1)), ctypes.byref(nb)) == 5
+    fake = ctypes.c_void_p(0x100000)
+    null = ctypes.c_void_p(0)
+    assert lib.xy_topk_estimate(null, fake, 0, 8, 4, ctypes.byref(o), fake, null, null, null, fake, 1 << 30,
+                                null) == 1
+    assert lib.xy_topk_estimate(fake, fake, 0, 8, 4, ctypes.byref(o), null, null, null, null, fake, 1 << 30,
+                                null) == 1
+    assert lib.xy_topk_estimate(fake, fake, 0, 8, 4, ctypes.byref(o), fake, null, null, null, fake, 64, null) == 3
+    assert lib.xy_topk_estimate(fake, fake, 5, 8, 4, ctypes.byref(o), fake, null, null, null, fake, 1 << 30,
+                                null) == 1
