@@ -230,3 +230,15 @@ def test_large_batch_sampled_rows(gpu_lib):
     rows = np.random.default_rng(7801).choice(b, 6, replace=False)
     rows = np.concatenate([[0, b - 1], rows])
     compare(z[rows], ps[rows], x[rows], y[rows], P, oracle.TAU_FFT)
+
+
+@pytest.mark.parametrize("shape", [(3, 200, 150), (2, 1024, 1024)], ids=lambda s: "x".join(map(str, s)))
+def test_non_power_of_two_family(gpu_lib, shape):
+    """p that are not powers of two take the root as exp(log S / p) and the
+    powers by repeated squaring with odd steps."""
+    b, n, m = shape
+    P = [1, 3, 5, 7, 12, 20, 33]
+    x, y = maxconv_vectors(b, n, m, seed=7900 + n, kind="lognormal")
+    z, ps = gpu_lib.maxconv(_dev(x), _dev(y), P, return_pstar=True)
+    st = compare(z.cpu().numpy(), ps.cpu().numpy(), x, y, P, oracle.TAU_FFT)
+    print(shape, st, flush=True)
