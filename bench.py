@@ -248,17 +248,17 @@ def run_legs(mt, torch, np):
     del xd, yd, z, ps, E, pos, rel
     torch.cuda.empty_cache()
 
-    # top k of x + y (Sec. 2.3): n = 2048 uniform lists on [0, 1], k = 256, the
-    # 24-power family up to 4096; exact top k on the GPU by torch over all
-    # n^2 sums, for the accuracy columns
+    # top k of x + y (Sec. 2.3, the n = 8192, k = 256 case of Sec. 3): uniform
+    # lists on [0, 1], the 24-power family up to 4096; exact top k on the GPU
+    # by torch over all n^2 sums, for the accuracy columns
     rng = np.random.default_rng(5005)
-    nx, kx = 2048, 256
+    nx, kx = 8192, 256
     xs = torch.from_numpy(rng.uniform(0, 1, nx)).cuda()
     ys = torch.from_numpy(rng.uniform(0, 1, nx)).cuda()
     mt.timing_reset()
     mt.timing_enable(True)
     ms = time_call(lambda: mt.xy_topk(xs, ys, kx), 3, torch)
-    parts = {name: mt.timing_read(name)[0] / 4 for name in ("mt_xy_sigma", "mt_xy_queue", "mt_xy_index")}
+    parts = {name: mt.timing_read(name)[0] / 4 for name in ("mt_xy_sigma", "mt_xy_psi", "mt_xy_queue", "mt_xy_index")}
     mt.timing_enable(False)
     v, ii, jj = mt.xy_topk(xs, ys, kx)
     sums = (xs[:, None] + ys[None, :]).flatten()
@@ -267,7 +267,7 @@ def run_legs(mt, torch, np):
     ei, ej = (eidx // nx).int(), (eidx % nx).int()
     found = int(((ii == ei) & (jj == ej)).sum())
     in_set = int(torch.isin(ii.long() * nx + jj.long(), eidx).sum())
-    legs["xy_topk_2048_k256_fp64"] = {
+    legs["xy_topk_8192_k256_fp64"] = {
         "ms": ms, "n": nx, "k": kx, "P": list(mt.XY_FAMILY), "kernel_ms": parts,
         "naive_gpu_topk_ms": ms_naive,
         "vs_exact": {"indices_found_at_rank": found, "true_top_k_pairs_found": in_set, "k": kx,
@@ -452,7 +452,7 @@ def main():
 
     if not args.no_legs and args.only is None:
         log("[bench] legs: APSP (FP64 ER 2048, BF16 RGG 16384), gradient 64x512^3, 256^2 FP64, "
-            "max-convolution 8192 x 2048, x + y top 256 at n = 2048")
+            "max-convolution 8192 x 2048, x + y top 256 at n = 8192")
         del Ad, Bd, E, E64, Asub
         torch.cuda.empty_cache()
         out["legs"] = run_legs(mt, torch, np)

@@ -312,10 +312,13 @@ mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b,
  *            MT_TAU_FFT_DEFAULT; flags must be 0 (else MT_ERR_UNSUPPORTED).
  *   values   k FP64 device (output), in pop order.
  *   diag, i_idx, j_idx  k int32 device (outputs, each nullable): m1, i, j.
- * 1 <= n <= 2048 (2n - 1 <= 4096: the transform runs in one workgroup's
- * LDS), 0 <= k <= 2^24 (else MT_ERR_UNSUPPORTED / MT_ERR_INVALID_ARG).
+ * 1 <= n <= 8192 (2n - 1 <= 16384; up to n = 2048 each transform runs in
+ * one workgroup's LDS, longer ones through global buffers in the workspace),
+ * 0 <= k <= 2^24 (else MT_ERR_UNSUPPORTED / MT_ERR_INVALID_ARG).
  * The pops run on one wave per run, in sequence.  Workspace from
- * xy_topk_workspace_size (16 (|P| + 1)(2n - 1) + 16 k bytes and alignment).  With
+ * xy_topk_workspace_size (16 (|P| + 1)(2n - 1) + 16 k bytes and alignment, plus
+ * 64 |P| N + 2 N bytes for the global buffers when n > 2048, N the transform
+ * length).  With
  * k = 0 only the ring results are formed: the workspace then starts with
  * sigma^(p)[m] of both runs, FP64, indexed (run |P| + q)(2n - 1) + m (run 1
  * on y reversed), for inspection.  Asynchronous on the stream.

@@ -392,7 +392,7 @@ def xy_topk_workspace_size(n, k, P=XY_FAMILY, tau=None):
 
 def xy_topk(x, y, k, P=XY_FAMILY, tau=None, return_diag=False):
     """Estimate the k largest x_i + y_j (x, y: 1-D device tensors of the same
-    length n <= 2048) and their indices by the NormQueue of Sec. 2.3 (FFT ring
+    length n <= 8192) and their indices by the NormQueue of Sec. 2.3 (FFT ring
     results in FP64, a second run on y reversed for the indices).  Returns
     (values FP64, i int32, j int32[, diag]); i = j = -1 where the two runs do
     not give a pair in the grid."""

@@ -889,7 +889,7 @@ mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b,
 // Workspace of xy_topk_estimate: the ring results of both runs, then the
 // second run's values and both runs' diagonals.
 struct XyLayout {
-    size_t sigma, psi, values1, diag0, diag1, total;
+    size_t sigma, psi, values1, diag0, diag1, tw, mxy, buf0, buf1, total;
 };
 XyLayout xy_layout(int64_t n, int32_t k, int n_p) {
     XyLayout L{};
@@ -905,6 +905,19 @@ XyLayout xy_layout(int64_t n, int32_t k, int n_p) {
     off += (size_t)round_up((int64_t)k * 4, kAlign);
     L.diag1 = off;
     off += (size_t)round_up((int64_t)k * 4, kAlign);
+    L.tw = L.mxy = L.buf0 = L.buf1 = 0;
+    if (len > kMaxConvN) {
+        const int logN = maxconv_log_size(n, n);
+        const int64_t N = (int64_t)1 << logN;
+        L.tw = off;
+        off += (size_t)round_up((N / 8 + 1) * 16, kAlign);
+        L.mxy = off;
+        off += kAlign;
+        L.buf0 = off;
+        off += (size_t)round_up(2 * (int64_t)n_p * N * 16, kAlign);
+        L.buf1 = off;
+        off += (size_t)round_up(2 * (int64_t)n_p * N * 16, kAlign);
+    }
     L.total = off;
     return L;
 }
@@ -915,7 +928,8 @@ mt_status xy_check(int64_t n, int32_t k, const mt_options* opt, Family* f) {
     if (f->bf16) return fail(MT_ERR_UNSUPPORTED, "the x + y top k runs on the FP64 path only");
     if (f->flags) return fail(MT_ERR_UNSUPPORTED, "the x + y top k takes no flags");
     if (n < 1 || k < 0) return fail(MT_ERR_INVALID_ARG, "need n >= 1 and k >= 0 (n=%lld k=%d)", (long long)n, k);
-    if (2 * n - 1 > kMaxConvN) return fail(MT_ERR_UNSUPPORTED, "2n - 1 = %lld exceeds %d", (long long)(2 * n - 1), kMaxConvN);
+    if (2 * n - 1 > kLongConvN)
+        return fail(MT_ERR_UNSUPPORTED, "2n - 1 = %lld exceeds %d", (long long)(2 * n - 1), kLongConvN);
     if (k > (1 << 24)) return fail(MT_ERR_UNSUPPORTED, "k above 2^24");
     return MT_OK;
 }
@@ -949,7 +963,9 @@ mt_status xy_topk_estimate(const void* x, const void* y, mt_dtype dtype, int64_t
     spec.tau = opt->tau > 0.0 ? opt->tau : MT_TAU_FFT_DEFAULT;
     uint8_t* ws = (uint8_t*)workspace;
     XyWorkspace w{(double*)(ws + L.sigma), (double*)(ws + L.psi), (double*)(ws + L.values1),
-                  (int32_t*)(ws + L.diag0), (int32_t*)(ws + L.diag1)};
+                  (int32_t*)(ws + L.diag0), (int32_t*)(ws + L.diag1),
+                  L.tw ? (double2*)(ws + L.tw) : nullptr, L.mxy ? (double*)(ws + L.mxy) : nullptr,
+                  L.buf0 ? (double2*)(ws + L.buf0) : nullptr, L.buf1 ? (double2*)(ws + L.buf1) : nullptr};
     MT_TRY(launch_xy_topk(x, y, dtype == MT_F64, n, k, spec, values, diag, i_idx, j_idx, w, (hipStream_t)stream),
            "x + y top k");
     return MT_OK;

@@ -267,6 +267,10 @@ hipError_t launch_adjoint_gemm_f64(const double* Xp, const double* Yp, int64_t b
 // kMaxConvN points (the FFT runs in one workgroup's LDS).
 constexpr int kMaxConvLog = 12;
 constexpr int kMaxConvN = 1 << kMaxConvLog;
+// The x + y ring results of longer lists go through global buffers, up to
+// kLongConvN points.
+constexpr int kLongConvLog = 14;
+constexpr int kLongConvN = 1 << kLongConvLog;
 struct MaxconvSpec {
     int32_t n;  // family size
     int32_t p[MT_MAX_P];
@@ -285,6 +289,11 @@ struct XyWorkspace {
     double* values1;  // k
     int32_t* diag0;   // k
     int32_t* diag1;   // k
+    // only for N > kMaxConvN: twiddle octant, maxima of x and y, two buffers of 2 n_p N
+    double2* tw;
+    double* mxy;
+    double2* buf0;
+    double2* buf1;
 };
 hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int32_t k, const MaxconvSpec& spec,
                           double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,

@@ -588,6 +588,8 @@ __global__ __launch_bounds__(256) void mt_xy_psi_kernel(const double* __restrict
     psi[g] = qh >= 0 ? pow(sh, 1.0 / (double)spec.p[qh]) : 0.0;
 }
 
+constexpr int kQueueGroups = 16;
+
 // The NormQueue of Sec. 2.3 for one run (block = run), one wave: psi[m] is the
 // root at the largest stable p of diagonal m (0 if none); k times the largest
 // psi (lowest m on ties) is reported as max x + max y + log(psi) and its
@@ -600,7 +602,9 @@ __global__ __launch_bounds__(64) void mt_xy_queue_kernel(const T* __restrict__ x
                                                        double* __restrict__ values0,
                                                        double* __restrict__ values1, int32_t* __restrict__ diag0,
                                                        int32_t* __restrict__ diag1) {
-    __shared__ double psi[kMaxConvN];
+    extern __shared__ double psi[];  // 2n - 1
+    __shared__ double gv[64 * kQueueGroups];
+    __shared__ int gm[64 * kQueueGroups];
     const int lane = threadIdx.x, run = blockIdx.x;
     const int L = (int)(2 * n - 1), np = spec.n;
     double* sg = sigma + (int64_t)run * np * L;
@@ -619,22 +623,46 @@ __global__ __launch_bounds__(64) void mt_xy_queue_kernel(const T* __restrict__ x
     const double shift = mx + my;
     for (int m = lane; m < L; m += 64) psi[m] = psi0[(int64_t)run * L + m];
     __syncthreads();
-    // the lane's best over m = lane (mod 64): largest psi, lowest m on ties
+    // The lane owns m = lane + 64 c, c < C, in kQueueGroups groups of GS
+    // consecutive c; gv / gm hold each group's largest psi and its m (lowest m
+    // on ties), bv / bm the lane's.  A pop rescans one group.
+    const int C = (L + 63) / 64;
+    const int GS = (C + kQueueGroups - 1) / kQueueGroups;
+    double* gvl = gv + lane * kQueueGroups;
+    int* gml = gm + lane * kQueueGroups;
+    auto group_scan = [&](int g) {
+        double v = -1.0;
+        int mm = L;
+        const int c1 = (g + 1) * GS < C ? (g + 1) * GS : C;
+        for (int c = g * GS; c < c1; ++c) {
+            const int m = lane + 64 * c;
+            if (m < L) {
+                const double e = psi[m];
+                if (e > v) {
+                    v = e;
+                    mm = m;
+                }
+            }
+        }
+        gvl[g] = v;
+        gml[g] = mm;
+    };
     double bv = -1.0;
     int bm = L;
-    auto rescan = [&]() {
+    auto lane_best = [&]() {
         bv = -1.0;
         bm = L;
-#pragma unroll 16
-        for (int m = lane; m < L; m += 64) {
-            const double e = psi[m];
-            if (e > bv) {
-                bv = e;
-                bm = m;
+#pragma unroll
+        for (int g = 0; g < kQueueGroups; ++g) {
+            const double v = gvl[g];
+            if (v > bv) {
+                bv = v;
+                bm = gml[g];
             }
         }
     };
-    rescan();
+    for (int g = 0; g < kQueueGroups; ++g) group_scan(g);
+    lane_best();
     for (int r = 0; r < k; ++r) {
         double a = bv;
         int ms = bm;
@@ -666,7 +694,10 @@ __global__ __launch_bounds__(64) void mt_xy_queue_kernel(const T* __restrict__ x
         }
         if (lane == 0) psi[ms] = e;
         __syncthreads();
-        if (lane == (ms & 63)) rescan();
+        if (lane == (ms & 63)) {
+            group_scan((ms >> 6) / GS);
+            lane_best();
+        }
     }
 }
 
@@ -687,6 +718,134 @@ __global__ __launch_bounds__(256) void mt_xy_index_kernel(const int32_t* __restr
     if (diag) diag[r] = (int32_t)m1;
     if (ii) ii[r] = (int32_t)i;
     if (jj) jj[r] = (int32_t)j;
+}
+
+// Long transforms (N up to kLongConvN) for the x + y ring results: every
+// (run, p) transform in a global buffer [slot][N], one thread per radix-R
+// butterfly of a Stockham pass, the passes ordered by kernel boundaries.
+
+// exp(-2 pi i mm / N), 0 <= mm < N, from the octant table (runtime N, N4 = N / 4).
+__device__ __forceinline__ double2 twiddle_rt(const double2* tw, int mm, int N4) {
+    const int q = mm / N4, r = mm & (N4 - 1);
+    const bool refl = r > N4 / 2;
+    const double2 t = tw[refl ? N4 - r : r];
+    double a = refl ? t.y : t.x, b = refl ? -t.x : -t.y;
+    if (q & 1) {
+        const double c = a;
+        a = b;
+        b = -c;
+    }
+    if (q & 2) {
+        a = -a;
+        b = -b;
+    }
+    return make_double2(a, b);
+}
+
+// cos / sin (2 pi k / N), k = 0 .. N / 8; the maxima of x and y in mxy[0], mxy[1].
+template <typename T>
+__global__ __launch_bounds__(1024) void mt_xy_long_setup_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                               int64_t n, int N, double2* __restrict__ tw,
+                                                               double* __restrict__ mxy) {
+    __shared__ double red[2][16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = tid; k <= N / 8; k += 1024) {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)N, &sn, &cs);
+        tw[k] = make_double2(cs, sn);
+    }
+    double mx = -INFINITY, my = -INFINITY;
+    for (int64_t i = tid; i < n; i += 1024) {
+        mx = fmax(mx, (double)x[i]);
+        my = fmax(my, (double)y[i]);
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, d));
+        my = fmax(my, __shfl_xor(my, d));
+    }
+    if (lane == 0) {
+        red[0][wave] = mx;
+        red[1][wave] = my;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < 16; ++w) {
+            mx = fmax(mx, red[0][w]);
+            my = fmax(my, red[1][w]);
+        }
+        mxy[0] = mx;
+        mxy[1] = my;
+    }
+}
+
+// buf[slot][t] = (x'^p, y'^p) for slot = run |P| + q, zero for t >= n.
+template <typename T>
+__global__ __launch_bounds__(256) void mt_xy_long_load_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                             int64_t n, int logN, MaxconvSpec spec,
+                                                             const double* __restrict__ mxy,
+                                                             double2* __restrict__ buf) {
+    const int N = 1 << logN;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)2 * spec.n * N) return;
+    const int slot = (int)(g >> logN), t = (int)(g & (N - 1));
+    const int run = slot / spec.n, p = spec.p[slot % spec.n];
+    double a = 0.0, c = 0.0;
+    if (t < n) {
+        a = ipow_d(exp((double)x[t] - mxy[0]), p);
+        c = ipow_d(exp((double)y[run ? n - 1 - t : t] - mxy[1]), p);
+    }
+    buf[g] = make_double2(a, c);
+}
+
+// One Stockham pass of span Ns and radix R over every transform of the batch.
+template <int R>
+__global__ __launch_bounds__(256) void mt_fft_pass_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+                                                         int logN, int Ns, int64_t butterflies,
+                                                         const double2* __restrict__ tw) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= butterflies) return;
+    const int N = 1 << logN, NR = N / R;
+    const int64_t tr = g / NR;
+    const int j = (int)(g - tr * NR);
+    const double2* src = in + tr * N;
+    double2* dst = out + tr * N;
+    double2 v[16];
+#pragma unroll
+    for (int e = 0; e < R; ++e) v[e] = src[j + e * NR];
+    const int k0 = j & (Ns - 1);
+    if (Ns > 1) {
+        const int step = k0 * (N / (Ns * R));
+#pragma unroll
+        for (int e = 1; e < R; ++e) v[e] = cmul(v[e], twiddle_rt(tw, step * e, N / 4));
+    }
+    dft<R>(v, 0, 1);
+    const int base = (j - k0) * R + k0;
+#pragma unroll
+    for (int e = 0; e < R; ++e) dst[base + e * Ns] = v[oreg<R>(e)];
+}
+
+// conj(4 W_t) of every transform from Z_t and Z_(N-t) (see convolve_pair).
+__global__ __launch_bounds__(256) void mt_fft_product_kernel(const double2* __restrict__ Z, double2* __restrict__ out,
+                                                            int logN, int64_t total) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int N = 1 << logN;
+    const int64_t base = g & ~(int64_t)(N - 1);
+    const int t = (int)(g & (N - 1));
+    const double2 zk = Z[g], zn = Z[base + ((N - t) & (N - 1))];
+    const double2 a = make_double2(zk.x + zn.x, zk.y - zn.y);
+    const double2 c = make_double2(zk.y + zn.y, zn.x - zk.x);
+    const double2 w = cmul(a, c);
+    out[g] = make_double2(w.x, -w.y);
+}
+
+// sigma[slot][t] = Re(result)[t] * 0.25 / N for t < L.
+__global__ __launch_bounds__(256) void mt_xy_long_store_kernel(const double2* __restrict__ res, int logN, int64_t L,
+                                                              int64_t slots, double* __restrict__ sigma) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= slots * L) return;
+    const int64_t slot = g / L, t = g - slot * L;
+    sigma[g] = res[(slot << logN) + t].x * (0.25 / (double)(1 << logN));
 }
 
 template <typename T>
@@ -798,6 +957,70 @@ hipError_t launch_xy_sigma_n(const T* x, const T* y, int64_t n, const MaxconvSpe
     return hipGetLastError();
 }
 
+// The ring results of long lists (N > kMaxConvN) through global buffers.
+template <typename T>
+hipError_t launch_xy_long(const T* x, const T* y, int64_t n, const MaxconvSpec& spec, const XyWorkspace& w,
+                          hipStream_t st) {
+    const int logN = maxconv_log_size(n, n);
+    const int N = 1 << logN;
+    const int64_t slots = 2 * (int64_t)spec.n, total = slots * N, L = 2 * n - 1;
+    auto blocks = [](int64_t count) { return dim3((unsigned)((count + 255) / 256)); };
+    timing_before("mt_xy_sigma_setup", st);
+    hipLaunchKernelGGL(mt_xy_long_setup_kernel<T>, dim3(1), dim3(1024), 0, st, x, y, n, N, w.tw, w.mxy);
+    timing_after(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    timing_before("mt_xy_sigma_load", st);
+    hipLaunchKernelGGL(mt_xy_long_load_kernel<T>, blocks(total), dim3(256), 0, st, x, y, n, logN, spec, w.mxy,
+                       w.buf0);
+    timing_after(st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    double2* cur = w.buf0;
+    double2* nxt = w.buf1;
+    // one transform: radix-16 passes, then the remaining radix 2, 4 or 8
+    auto transform = [&]() -> hipError_t {
+        int Ns = 1;
+        for (int left = logN; left > 0;) {
+            const int r = left >= 4 ? 4 : left;
+            timing_before("mt_xy_sigma_pass", st);
+            switch (r) {
+                case 4: hipLaunchKernelGGL(mt_fft_pass_kernel<16>, blocks(total / 16), dim3(256), 0, st, cur, nxt,
+                                           logN, Ns, total / 16, w.tw); break;
+                case 3: hipLaunchKernelGGL(mt_fft_pass_kernel<8>, blocks(total / 8), dim3(256), 0, st, cur, nxt,
+                                           logN, Ns, total / 8, w.tw); break;
+                case 2: hipLaunchKernelGGL(mt_fft_pass_kernel<4>, blocks(total / 4), dim3(256), 0, st, cur, nxt,
+                                           logN, Ns, total / 4, w.tw); break;
+                default: hipLaunchKernelGGL(mt_fft_pass_kernel<2>, blocks(total / 2), dim3(256), 0, st, cur, nxt,
+                                            logN, Ns, total / 2, w.tw); break;
+            }
+            timing_after(st);
+            hipError_t pe = hipGetLastError();
+            if (pe != hipSuccess) return pe;
+            double2* t = cur;
+            cur = nxt;
+            nxt = t;
+            Ns <<= r;
+            left -= r;
+        }
+        return hipSuccess;
+    };
+    if ((e = transform()) != hipSuccess) return e;
+    timing_before("mt_xy_sigma_product", st);
+    hipLaunchKernelGGL(mt_fft_product_kernel, blocks(total), dim3(256), 0, st, cur, nxt, logN, total);
+    timing_after(st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        double2* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if ((e = transform()) != hipSuccess) return e;
+    timing_before("mt_xy_sigma_store", st);
+    hipLaunchKernelGGL(mt_xy_long_store_kernel, blocks(slots * L), dim3(256), 0, st, cur, logN, L, slots, w.sigma);
+    timing_after(st);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const MaxconvSpec& spec, double* values,
                        int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w, hipStream_t st) {
@@ -812,6 +1035,8 @@ hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const Maxco
         case 10: e = launch_xy_sigma_n<T, 10>(x, y, n, spec, w.sigma, st); break;
         case 11: e = launch_xy_sigma_n<T, 11>(x, y, n, spec, w.sigma, st); break;
         case 12: e = launch_xy_sigma_n<T, 12>(x, y, n, spec, w.sigma, st); break;
+        case 13:
+        case 14: e = launch_xy_long<T>(x, y, n, spec, w, st); break;
         default: break;
     }
     if (e != hipSuccess) return e;
@@ -823,9 +1048,21 @@ hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const Maxco
     timing_after(st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // psi of one run in LDS: up to 8 (kLongConvN - 1) bytes
+    auto queue = mt_xy_queue_kernel<T>;
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_set.load() & bit)) {
+        e = hipFuncSetAttribute((const void*)queue, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kLongConvN * (int)sizeof(double));
+        if (e != hipSuccess) return e;
+        attr_set.fetch_or(bit);
+    }
     timing_before("mt_xy_queue", st);
-    hipLaunchKernelGGL(mt_xy_queue_kernel<T>, dim3(2), dim3(64), 0, st, x, y, n, spec, w.sigma, w.psi, k, values,
-                       w.values1, w.diag0, w.diag1);
+    hipLaunchKernelGGL(queue, dim3(2), dim3(64), (size_t)L * sizeof(double), st, x, y, n, spec, w.sigma, w.psi, k,
+                       values, w.values1, w.diag0, w.diag1);
     timing_after(st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -842,7 +1079,7 @@ hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int3
                           double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
                           hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    if (maxconv_log_size(n, n) > kMaxConvLog) return hipErrorInvalidValue;
+    if (maxconv_log_size(n, n) > kLongConvLog) return hipErrorInvalidValue;
     if (f64)
         return launch_xy_t<double>((const double*)x, (const double*)y, n, k, spec, values, diag, ii, jj, w, st);
     return launch_xy_t<float>((const float*)x, (const float*)y, n, k, spec, values, diag, ii, jj, w, st);

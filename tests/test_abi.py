@@ -250,13 +250,14 @@ def test_maxconv_validation():
 
 def test_xy_topk_validation():
     """Argument checks of the x + y top-k entry points (no GPU): FP64 path
-    only, no flags, 2n - 1 <= 4096, k >= 0, workspace size, NULL pointers."""
+    only, no flags, 2n - 1 <= 16384, k >= 0, workspace size, NULL pointers."""
     lib = mt.load_library()
     o = _opts(list(mt.XY_FAMILY), path=0)
     nb = ctypes.c_size_t(0)
     assert lib.xy_topk_workspace_size(1024, 256, ctypes.byref(o), ctypes.byref(nb)) == 0
     assert nb.value >= 2 * 24 * 2047 * 8 + 256 * 16
-    assert lib.xy_topk_workspace_size(2049, 4, ctypes.byref(o), ctypes.byref(nb)) == 5
+    assert lib.xy_topk_workspace_size(8193, 4, ctypes.byref(o), ctypes.byref(nb)) == 5
+    assert lib.xy_topk_workspace_size(8192, 4, ctypes.byref(o), ctypes.byref(nb)) == 0
     assert lib.xy_topk_workspace_size(0, 4, ctypes.byref(o), ctypes.byref(nb)) == 1
     assert lib.xy_topk_workspace_size(8, -1, ctypes.byref(o), ctypes.byref(nb)) == 1
     assert lib.xy_topk_workspace_size(8, 4, ctypes.byref(_opts([1, 2], path=1)), ctypes.byref(nb)) == 5

@@ -59,8 +59,10 @@ def _sigma_gpu(mt, x, y, P):
     return ws[: 2 * len(P) * L * 8].view(torch.float64).reshape(2, len(P), L).cpu().numpy()
 
 
-@pytest.mark.parametrize("n", [1, 5, 64, 700, 1024, 2048])
+@pytest.mark.parametrize("n", [1, 5, 64, 700, 1024, 2048, 2049, 3000, 8192])
 def test_ring_results_within_fft_bound(gpu_lib, n):
+    """Lists up to n = 2048 transform in LDS; longer ones (to 8192) through
+    global buffers."""
     rng = np.random.default_rng(9100 + n)
     x = rng.normal(0, 2, n)
     y = rng.uniform(-3, 3, n)
@@ -101,7 +103,8 @@ def test_near_one_hot_first_pop_is_exact(gpu_lib):
     np.testing.assert_array_equal(j, ej)
 
 
-@pytest.mark.parametrize("n,seed,k", [(1024, 9600, 128), (1024, 9601, 128), (2048, 9700, 128)])
+@pytest.mark.parametrize("n,seed,k", [(1024, 9600, 128), (1024, 9601, 128), (2048, 9700, 128), (3000, 9801, 128),
+                                      (8192, 9800, 128)])
 def test_uniform_unit_lists_full_sequence(gpu_lib, n, seed, k):
     rng = np.random.default_rng(seed)
     x = rng.uniform(0, 1, n)
@@ -111,10 +114,10 @@ def test_uniform_unit_lists_full_sequence(gpu_lib, n, seed, k):
     print(n, k, "indices found", int(((i == ei) & (j == ej)).sum()), "of", k, flush=True)
 
 
+@pytest.mark.parametrize("n", [1024, 8192])
 @pytest.mark.parametrize("dist", ["normal", "uniform40", "exponential"])
-def test_first_pop_any_input(gpu_lib, dist):
+def test_first_pop_any_input(gpu_lib, dist, n):
     rng = np.random.default_rng(9400)
-    n = 1024
     if dist == "normal":
         x, y = rng.normal(0, 1, n), rng.normal(0, 1, n)
     elif dist == "uniform40":
@@ -150,8 +153,8 @@ def test_fp32_inputs_and_edges(gpu_lib):
     # k = 0: nothing to pop
     v, i, j = mt.xy_topk(_dev(x), _dev(y), 0, P24)
     assert v.numel() == 0
-    # lengths beyond the LDS transform are rejected before launch
+    # lengths beyond the longest transform are rejected before launch
     with pytest.raises(mt.MaxTimesError) as e:
-        mt.xy_topk(torch.zeros(2049, dtype=torch.float64, device="cuda"),
-                   torch.zeros(2049, dtype=torch.float64, device="cuda"), 4, P24)
+        mt.xy_topk(torch.zeros(8193, dtype=torch.float64, device="cuda"),
+                   torch.zeros(8193, dtype=torch.float64, device="cuda"), 4, P24)
     assert e.value.status == 5
