@@ -276,12 +276,19 @@ mt_status apsp_affine_correct(void* D, mt_dtype dtype, int64_t n, const int32_t*
  *   z        b x (n + m - 1), dtype, device (output).
  *   p_star   b x (n + m - 1) uint8 device (output, nullable): index of p*
  *            in the family.
- * One workgroup per batch item transforms in LDS: n + m - 1 <= 4096 and
- * b < 2^31 (else MT_ERR_UNSUPPORTED).  n = 0, m = 0 or b = 0: empty output,
- * nothing written.  No workspace; asynchronous on the stream.
+ * n + m - 1 <= 4096: one workgroup per pair transforms in LDS, largest p
+ * first, and stops once every index of its pair is decided; no workspace
+ * (workspace may be NULL).  4096 < n + m - 1 <= 16384: the pairs go through
+ * global buffers in the workspace, one p at a time for the whole batch (no
+ * early exit).  Larger lengths and b >= 2^31 return MT_ERR_UNSUPPORTED.
+ * n = 0, m = 0 or b = 0: empty output, nothing written.  Asynchronous on the
+ * stream.  Workspace from maxconv_workspace_size (0 bytes up to 4096; about
+ * 32 N + 9 (n + m - 1) bytes per pair above, N the transform length).
  */
+mt_status maxconv_workspace_size(int64_t b, int64_t n, int64_t m, const mt_options* opt, size_t* bytes);
 mt_status maxconv_estimate(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
-                           const mt_options* opt, void* z, uint8_t* p_star, void* stream);
+                           const mt_options* opt, void* z, uint8_t* p_star, void* workspace, size_t ws_bytes,
+                           void* stream);
 
 /*
  * The exact max-convolution z[t] = max_i x[i] y[t - i] (the definition of

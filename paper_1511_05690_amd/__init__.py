@@ -25,7 +25,7 @@ __all__ = [
     "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
     "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold",
     "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "maxconv", "maxconv_exact",
-    "xy_topk", "xy_topk_workspace_size", "XY_FAMILY", "pfamily", "PSTAR_NONE", "PATHS",
+    "maxconv_workspace_size", "xy_topk", "xy_topk_workspace_size", "XY_FAMILY", "pfamily", "PSTAR_NONE", "PATHS",
 ]
 
 PSTAR_NONE = 255
@@ -87,7 +87,8 @@ def load_library():
         "apsp_estimate": [vp, i64, ctypes.c_double, ctypes.c_int32, opt, vp, ctypes.c_int, vp, vp,
                           sz, vp],
         "maxtimes_exact": [vp, vp, ctypes.c_int, i64, i64, i64, i64, vp, vp],
-        "maxconv_estimate": [vp, vp, ctypes.c_int, i64, i64, i64, opt, vp, vp, vp],
+        "maxconv_workspace_size": [i64, i64, i64, opt, ctypes.POINTER(sz)],
+        "maxconv_estimate": [vp, vp, ctypes.c_int, i64, i64, i64, opt, vp, vp, vp, sz, vp],
         "maxconv_exact": [vp, vp, ctypes.c_int, i64, i64, i64, vp, vp],
         "xy_topk_workspace_size": [i64, ctypes.c_int32, opt, ctypes.POINTER(sz)],
         "xy_topk_estimate": [vp, vp, ctypes.c_int, i64, ctypes.c_int32, opt, vp, vp, vp, vp, vp, sz, vp],
@@ -351,21 +352,25 @@ def _conv_shapes(x, y):
     raise ValueError("x and y must both be 1-D, or 2-D with the same batch size")
 
 
-def maxconv(x, y, P=(1, 2, 4, 8, 16, 32, 64), tau=None, return_pstar=False):
+def maxconv(x, y, P=(1, 2, 4, 8, 16, 32, 64), tau=None, return_pstar=False, workspace=None):
     """Estimate the max-convolution z[t] = max_i x[i] y[t - i] of nonnegative
-    x (.., n) and y (.., m) by FFT convolutions of x'^p and y'^p (FP64, one
-    workgroup per batch row, n + m - 1 <= 4096); tau None = 1e-12."""
+    x (.., n) and y (.., m) by FFT convolutions of x'^p and y'^p (FP64; one
+    workgroup per batch row in LDS up to n + m - 1 = 4096, global buffers up
+    to 16384); tau None = 1e-12."""
     lib = load_library()
     b, n, m, batched = _conv_shapes(x, y)
     x = x.contiguous()
     y = y.contiguous()
     o = _options(P, "fp64", tau, None, 0)
+    need = ctypes.c_size_t(0)
+    _check(lib.maxconv_workspace_size(b, n, m, ctypes.byref(o), ctypes.byref(need)))
+    ws = _workspace(need.value, x.device, workspace) if need.value else None
     L = n + m - 1 if n and m else 0
     shape = (b, L) if batched else (L,)
     z = torch.empty(shape, dtype=x.dtype, device=x.device)
     ps = torch.empty(shape, dtype=torch.uint8, device=x.device) if return_pstar else None
     _check(lib.maxconv_estimate(_ptr(x), _ptr(y), _dtype_code(x), b, n, m, ctypes.byref(o), _ptr(z), _ptr(ps),
-                                _stream(x.device)))
+                                _ptr(ws), need.value, _stream(x.device)))
     return (z, ps) if return_pstar else z
 
 
@@ -380,6 +385,14 @@ def maxconv_exact(x, y):
     z = torch.empty((b, L) if batched else (L,), dtype=x.dtype, device=x.device)
     _check(lib.maxconv_exact(_ptr(x), _ptr(y), _dtype_code(x), b, n, m, _ptr(z), _stream(x.device)))
     return z
+
+
+def maxconv_workspace_size(b, n, m, P=(1, 2, 4, 8, 16, 32, 64), tau=None):
+    lib = load_library()
+    o = _options(P, "fp64", tau, None, 0)
+    out = ctypes.c_size_t(0)
+    _check(lib.maxconv_workspace_size(b, n, m, ctypes.byref(o), ctypes.byref(out)))
+    return out.value
 
 
 def xy_topk_workspace_size(n, k, P=XY_FAMILY, tau=None):

@@ -844,28 +844,85 @@ mt_status maxtimes_exact(const void* A, const void* B, mt_dtype dtype, int64_t b
     return MT_OK;
 }
 
-mt_status maxconv_estimate(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
-                           const mt_options* opt, void* z, uint8_t* p_star, void* stream) {
-    g_last_error.clear();
-    Family f;
-    mt_status s = parse_options(opt, &f);
+// Workspace of maxconv_estimate: empty up to n + m - 1 = kMaxConvN, the
+// long-vector buffers above.
+struct MaxconvLayout {
+    size_t tw, rxy, inv, s_sel, code, buf0, buf1, total;
+};
+MaxconvLayout maxconv_layout(int64_t b, int64_t n, int64_t m) {
+    MaxconvLayout L{};
+    const int64_t len = n + m - 1;
+    if (len <= kMaxConvN) return L;
+    const int64_t N = (int64_t)1 << maxconv_log_size(n, m);
+    size_t off = 0;
+    L.tw = off;
+    off += (size_t)round_up((N / 8 + 1) * 16, kAlign);
+    L.rxy = off;
+    off += (size_t)round_up(b * 8, kAlign);
+    L.inv = off;
+    off += (size_t)round_up(2 * b * 8, kAlign);
+    L.s_sel = off;
+    off += (size_t)round_up(b * len * 8, kAlign);
+    L.code = off;
+    off += (size_t)round_up(b * len, kAlign);
+    L.buf0 = off;
+    off += (size_t)round_up(b * N * 16, kAlign);
+    L.buf1 = off;
+    off += (size_t)round_up(b * N * 16, kAlign);
+    L.total = off;
+    return L;
+}
+
+mt_status maxconv_check(int64_t b, int64_t n, int64_t m, const mt_options* opt, Family* f) {
+    mt_status s = parse_options(opt, f);
     if (s != MT_OK) return s;
-    if (f.bf16) return fail(MT_ERR_UNSUPPORTED, "the max-convolution runs on the FP64 path only");
-    if (f.flags) return fail(MT_ERR_UNSUPPORTED, "the max-convolution takes no flags");
-    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (f->bf16) return fail(MT_ERR_UNSUPPORTED, "the max-convolution runs on the FP64 path only");
+    if (f->flags) return fail(MT_ERR_UNSUPPORTED, "the max-convolution takes no flags");
     if (b < 0 || n < 0 || m < 0)
         return fail(MT_ERR_INVALID_ARG, "negative size (b=%lld n=%lld m=%lld)", (long long)b, (long long)n,
                     (long long)m);
     if (b == 0 || n == 0 || m == 0) return MT_OK;
-    if (n + m - 1 > kMaxConvN)
-        return fail(MT_ERR_UNSUPPORTED, "n + m - 1 = %lld exceeds %d", (long long)(n + m - 1), kMaxConvN);
+    if (n + m - 1 > kLongConvN)
+        return fail(MT_ERR_UNSUPPORTED, "n + m - 1 = %lld exceeds %d", (long long)(n + m - 1), kLongConvN);
     if (b >= ((int64_t)1 << 31)) return fail(MT_ERR_UNSUPPORTED, "b must be below 2^31");
+    return MT_OK;
+}
+
+mt_status maxconv_workspace_size(int64_t b, int64_t n, int64_t m, const mt_options* opt, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(MT_ERR_INVALID_ARG, "bytes pointer is NULL");
+    Family f;
+    mt_status s = maxconv_check(b, n, m, opt, &f);
+    if (s != MT_OK) return s;
+    *bytes = (b == 0 || n == 0 || m == 0) ? 0 : maxconv_layout(b, n, m).total;
+    return MT_OK;
+}
+
+mt_status maxconv_estimate(const void* x, const void* y, mt_dtype dtype, int64_t b, int64_t n, int64_t m,
+                           const mt_options* opt, void* z, uint8_t* p_star, void* workspace, size_t ws_bytes,
+                           void* stream) {
+    g_last_error.clear();
+    Family f;
+    mt_status s = maxconv_check(b, n, m, opt, &f);
+    if (s != MT_OK) return s;
+    if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (b == 0 || n == 0 || m == 0) return MT_OK;
     if (!x || !y || !z) return fail(MT_ERR_INVALID_ARG, "x, y or z is NULL");
+    const MaxconvLayout L = maxconv_layout(b, n, m);
+    s = check_ws(workspace, ws_bytes, L.total);
+    if (s != MT_OK) return s;
     MaxconvSpec spec{};
     spec.n = f.n;
     for (int q = 0; q < f.n; ++q) spec.p[q] = f.p[q];
     spec.tau = opt->tau > 0.0 ? opt->tau : MT_TAU_FFT_DEFAULT;
-    MT_TRY(launch_maxconv(x, y, dtype == MT_F64, b, n, m, spec, z, p_star, (hipStream_t)stream),
+    uint8_t* ws = (uint8_t*)workspace;
+    MaxconvWorkspace w{};
+    if (L.total) {
+        w = MaxconvWorkspace{(double2*)(ws + L.tw), (double*)(ws + L.rxy), (double*)(ws + L.inv),
+                             (double*)(ws + L.s_sel), ws + L.code, (double2*)(ws + L.buf0),
+                             (double2*)(ws + L.buf1)};
+    }
+    MT_TRY(launch_maxconv(x, y, dtype == MT_F64, b, n, m, spec, z, p_star, w, (hipStream_t)stream),
            "max-convolution");
     return MT_OK;
 }

@@ -277,8 +277,19 @@ struct MaxconvSpec {
     double tau;
 };
 int maxconv_log_size(int64_t n, int64_t m);
+// Buffers of the long-vector path (N > kMaxConvN); unused (null) below.
+struct MaxconvWorkspace {
+    double2* tw;     // twiddle octant, N / 8 + 1
+    double* rxy;     // b: max x max y
+    double* inv;     // 2b: 1 / max x, 1 / max y
+    double* s_sel;   // b (n + m - 1): S at the selected p
+    uint8_t* code;   // b (n + m - 1): its family index, MT_PSTAR_NONE, or open
+    double2* buf0;   // b N
+    double2* buf1;   // b N
+};
 hipError_t launch_maxconv(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,
-                          const MaxconvSpec& spec, void* z, uint8_t* pstar, hipStream_t st);
+                          const MaxconvSpec& spec, void* z, uint8_t* pstar, const MaxconvWorkspace& w,
+                          hipStream_t st);
 hipError_t launch_maxconv_exact(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,
                                 void* z, hipStream_t st);
 // Top k of x + y (Sec. 2.3): ring results of both runs, the second run's

@@ -778,6 +778,15 @@ __global__ __launch_bounds__(1024) void mt_xy_long_setup_kernel(const T* __restr
     }
 }
 
+// cos / sin (2 pi k / N), k = 0 .. N / 8.
+__global__ __launch_bounds__(256) void mt_twiddle_octant_kernel(double2* __restrict__ tw, int N) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > N / 8) return;
+    double sn, cs;
+    sincospi(2.0 * (double)k / (double)N, &sn, &cs);
+    tw[k] = make_double2(cs, sn);
+}
+
 // buf[slot][t] = (x'^p, y'^p) for slot = run |P| + q, zero for t >= n.
 template <typename T>
 __global__ __launch_bounds__(256) void mt_xy_long_load_kernel(const T* __restrict__ x, const T* __restrict__ y,
@@ -846,6 +855,106 @@ __global__ __launch_bounds__(256) void mt_xy_long_store_kernel(const double2* __
     if (g >= slots * L) return;
     const int64_t slot = g / L, t = g - slot * L;
     sigma[g] = res[(slot << logN) + t].x * (0.25 / (double)(1 << logN));
+}
+
+// Max-convolution of long vectors (kMaxConvN < N <= kLongConvN): the batch of
+// pairs through the global-buffer passes, one p at a time (largest first);
+// every index keeps the S of its first stable p (code = its family index) and
+// the roots are taken at the end.  No early exit.
+constexpr uint8_t kCodeOpen = 254;
+
+// Per pair: rxy[pair] = max x max y, inv[2 pair] = 1 / max x, inv[2 pair + 1] = 1 / max y.
+template <typename T>
+__global__ __launch_bounds__(256) void mt_maxconv_long_scale_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                                   int64_t n, int64_t m, double* __restrict__ rxy,
+                                                                   double* __restrict__ inv) {
+    __shared__ double red[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t pair = blockIdx.x;
+    double mx = 0.0, my = 0.0;
+    for (int64_t i = tid; i < n; i += 256) mx = fmax(mx, (double)x[pair * n + i]);
+    for (int64_t i = tid; i < m; i += 256) my = fmax(my, (double)y[pair * m + i]);
+    for (int d = 32; d >= 1; d >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, d));
+        my = fmax(my, __shfl_xor(my, d));
+    }
+    if (lane == 0) {
+        red[0][wave] = mx;
+        red[1][wave] = my;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < 4; ++w) {
+            mx = fmax(mx, red[0][w]);
+            my = fmax(my, red[1][w]);
+        }
+        rxy[pair] = mx * my;
+        inv[2 * pair] = mx > 0.0 ? 1.0 / mx : 0.0;
+        inv[2 * pair + 1] = my > 0.0 ? 1.0 / my : 0.0;
+    }
+}
+
+// buf[pair][t] = (x'^p, y'^p), zero beyond the vectors.
+template <typename T>
+__global__ __launch_bounds__(256) void mt_maxconv_long_load_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                                  int64_t b, int64_t n, int64_t m, int logN, int p,
+                                                                  const double* __restrict__ inv,
+                                                                  double2* __restrict__ buf) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (b << logN)) return;
+    const int64_t pair = g >> logN;
+    const int64_t t = g & ((1 << logN) - 1);
+    const double a = t < n ? ipow_d((double)x[pair * n + t] * inv[2 * pair], p) : 0.0;
+    const double c = t < m ? ipow_d((double)y[pair * m + t] * inv[2 * pair + 1], p) : 0.0;
+    buf[g] = make_double2(a, c);
+}
+
+// The p* test of family index q for every index still open.
+__global__ __launch_bounds__(256) void mt_maxconv_long_select_kernel(const double2* __restrict__ res, int logN,
+                                                                    int64_t b, int64_t L, int q, double tau,
+                                                                    double* __restrict__ s_sel,
+                                                                    uint8_t* __restrict__ code) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b * L) return;
+    if (code[g] != kCodeOpen) return;
+    const int64_t pair = g / L, t = g - pair * L;
+    const double S = res[(pair << logN) + t].x * (0.25 / (double)(1 << logN));
+    const bool stable = S >= tau;
+    if (stable || q == 0) {
+        s_sel[g] = S;
+        code[g] = stable ? (uint8_t)q : (uint8_t)MT_PSTAR_NONE;
+    }
+}
+
+__global__ __launch_bounds__(256) void mt_fill_u8_kernel(uint8_t* __restrict__ p, int64_t count, uint8_t v) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < count) p[g] = v;
+}
+
+// z = max x max y S^(1/p) at the selected p (the smallest p with S clamped
+// at 0 where none was stable), p* = its code.
+template <typename T>
+__global__ __launch_bounds__(256) void mt_maxconv_long_root_kernel(const double* __restrict__ s_sel,
+                                                                  const uint8_t* __restrict__ code,
+                                                                  const double* __restrict__ rxy, int64_t b,
+                                                                  int64_t L, MaxconvSpec spec, T* __restrict__ z,
+                                                                  uint8_t* __restrict__ pstar) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b * L) return;
+    const uint8_t c = code[g];
+    const int p = spec.p[c == MT_PSTAR_NONE ? 0 : c];
+    const double S = s_sel[g];
+    double root = 0.0;
+    if (S > 0.0) {
+        if ((p & (p - 1)) == 0) {
+            root = S;
+            for (int e = p; e > 1; e >>= 1) root = sqrt(root);
+        } else {
+            root = exp(log(S) / (double)p);
+        }
+    }
+    z[g] = (T)(rxy[g / L] * root);
+    if (pstar) pstar[g] = c;
 }
 
 template <typename T>
@@ -923,14 +1032,6 @@ hipError_t launch_maxconv_t(const T* x, const T* y, int64_t b, int64_t n, int64_
 
 }  // namespace
 
-hipError_t launch_maxconv(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,
-                          const MaxconvSpec& spec, void* z, uint8_t* pstar, hipStream_t st) {
-    if (b <= 0 || n <= 0 || m <= 0) return hipSuccess;
-    if (maxconv_log_size(n, m) > kMaxConvLog) return hipErrorInvalidValue;
-    if (f64)
-        return launch_maxconv_t<double>((const double*)x, (const double*)y, b, n, m, spec, (double*)z, pstar, st);
-    return launch_maxconv_t<float>((const float*)x, (const float*)y, b, n, m, spec, (float*)z, pstar, st);
-}
 
 namespace {
 
@@ -957,6 +1058,93 @@ hipError_t launch_xy_sigma_n(const T* x, const T* y, int64_t n, const MaxconvSpe
     return hipGetLastError();
 }
 
+// The convolution step of every transform of a batch held in cur (count
+// transforms of N = 2^logN points, (a, b) packed as a + i b): the forward
+// passes, the product conj(4 X Y) and the inverse passes.  On return cur holds
+// the result (real part 4 N (a * b)); nxt is scratch.
+hipError_t long_convolve(double2*& cur, double2*& nxt, int logN, int64_t count, const double2* tw,
+                         const char* pass_name, const char* product_name, hipStream_t st) {
+    const int64_t total = count << logN;
+    auto blocks = [](int64_t c) { return dim3((unsigned)((c + 255) / 256)); };
+    auto swap = [&]() {
+        double2* t = cur;
+        cur = nxt;
+        nxt = t;
+    };
+    auto transform = [&]() -> hipError_t {
+        int Ns = 1;
+        for (int left = logN; left > 0;) {
+            const int r = left >= 4 ? 4 : left;
+            timing_before(pass_name, st);
+            switch (r) {
+                case 4: hipLaunchKernelGGL(mt_fft_pass_kernel<16>, blocks(total / 16), dim3(256), 0, st, cur, nxt,
+                                           logN, Ns, total / 16, tw); break;
+                case 3: hipLaunchKernelGGL(mt_fft_pass_kernel<8>, blocks(total / 8), dim3(256), 0, st, cur, nxt,
+                                           logN, Ns, total / 8, tw); break;
+                case 2: hipLaunchKernelGGL(mt_fft_pass_kernel<4>, blocks(total / 4), dim3(256), 0, st, cur, nxt,
+                                           logN, Ns, total / 4, tw); break;
+                default: hipLaunchKernelGGL(mt_fft_pass_kernel<2>, blocks(total / 2), dim3(256), 0, st, cur, nxt,
+                                            logN, Ns, total / 2, tw); break;
+            }
+            timing_after(st);
+            hipError_t pe = hipGetLastError();
+            if (pe != hipSuccess) return pe;
+            swap();
+            Ns <<= r;
+            left -= r;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = transform();
+    if (e != hipSuccess) return e;
+    timing_before(product_name, st);
+    hipLaunchKernelGGL(mt_fft_product_kernel, blocks(total), dim3(256), 0, st, cur, nxt, logN, total);
+    timing_after(st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    swap();
+    return transform();
+}
+
+// Max-convolution of long vectors through the global buffers of ws.
+template <typename T>
+hipError_t launch_maxconv_long(const T* x, const T* y, int64_t b, int64_t n, int64_t m, const MaxconvSpec& spec,
+                               T* z, uint8_t* pstar, const MaxconvWorkspace& w, hipStream_t st) {
+    const int logN = maxconv_log_size(n, m);
+    const int N = 1 << logN;
+    const int64_t L = n + m - 1;
+    auto blocks = [](int64_t c) { return dim3((unsigned)((c + 255) / 256)); };
+    timing_before("mt_maxconv_long_setup", st);
+    hipLaunchKernelGGL(mt_twiddle_octant_kernel, blocks(N / 8 + 1), dim3(256), 0, st, w.tw, N);
+    hipLaunchKernelGGL(mt_maxconv_long_scale_kernel<T>, dim3((unsigned)b), dim3(256), 0, st, x, y, n, m, w.rxy,
+                       w.inv);
+    hipLaunchKernelGGL(mt_fill_u8_kernel, blocks(b * L), dim3(256), 0, st, w.code, b * L, kCodeOpen);
+    timing_after(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int q = spec.n - 1; q >= 0; --q) {
+        double2* cur = w.buf0;
+        double2* nxt = w.buf1;
+        timing_before("mt_maxconv_long_load", st);
+        hipLaunchKernelGGL(mt_maxconv_long_load_kernel<T>, blocks(b << logN), dim3(256), 0, st, x, y, b, n, m, logN,
+                           spec.p[q], w.inv, cur);
+        timing_after(st);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = long_convolve(cur, nxt, logN, b, w.tw, "mt_maxconv_long_pass", "mt_maxconv_long_product", st)) !=
+            hipSuccess)
+            return e;
+        timing_before("mt_maxconv_long_select", st);
+        hipLaunchKernelGGL(mt_maxconv_long_select_kernel, blocks(b * L), dim3(256), 0, st, cur, logN, b, L, q,
+                           spec.tau, w.s_sel, w.code);
+        timing_after(st);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    timing_before("mt_maxconv_long_root", st);
+    hipLaunchKernelGGL(mt_maxconv_long_root_kernel<T>, blocks(b * L), dim3(256), 0, st, w.s_sel, w.code, w.rxy, b,
+                       L, spec, z, pstar);
+    timing_after(st);
+    return hipGetLastError();
+}
+
 // The ring results of long lists (N > kMaxConvN) through global buffers.
 template <typename T>
 hipError_t launch_xy_long(const T* x, const T* y, int64_t n, const MaxconvSpec& spec, const XyWorkspace& w,
@@ -977,44 +1165,8 @@ hipError_t launch_xy_long(const T* x, const T* y, int64_t n, const MaxconvSpec& 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     double2* cur = w.buf0;
     double2* nxt = w.buf1;
-    // one transform: radix-16 passes, then the remaining radix 2, 4 or 8
-    auto transform = [&]() -> hipError_t {
-        int Ns = 1;
-        for (int left = logN; left > 0;) {
-            const int r = left >= 4 ? 4 : left;
-            timing_before("mt_xy_sigma_pass", st);
-            switch (r) {
-                case 4: hipLaunchKernelGGL(mt_fft_pass_kernel<16>, blocks(total / 16), dim3(256), 0, st, cur, nxt,
-                                           logN, Ns, total / 16, w.tw); break;
-                case 3: hipLaunchKernelGGL(mt_fft_pass_kernel<8>, blocks(total / 8), dim3(256), 0, st, cur, nxt,
-                                           logN, Ns, total / 8, w.tw); break;
-                case 2: hipLaunchKernelGGL(mt_fft_pass_kernel<4>, blocks(total / 4), dim3(256), 0, st, cur, nxt,
-                                           logN, Ns, total / 4, w.tw); break;
-                default: hipLaunchKernelGGL(mt_fft_pass_kernel<2>, blocks(total / 2), dim3(256), 0, st, cur, nxt,
-                                            logN, Ns, total / 2, w.tw); break;
-            }
-            timing_after(st);
-            hipError_t pe = hipGetLastError();
-            if (pe != hipSuccess) return pe;
-            double2* t = cur;
-            cur = nxt;
-            nxt = t;
-            Ns <<= r;
-            left -= r;
-        }
-        return hipSuccess;
-    };
-    if ((e = transform()) != hipSuccess) return e;
-    timing_before("mt_xy_sigma_product", st);
-    hipLaunchKernelGGL(mt_fft_product_kernel, blocks(total), dim3(256), 0, st, cur, nxt, logN, total);
-    timing_after(st);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    {
-        double2* t = cur;
-        cur = nxt;
-        nxt = t;
-    }
-    if ((e = transform()) != hipSuccess) return e;
+    if ((e = long_convolve(cur, nxt, logN, slots, w.tw, "mt_xy_sigma_pass", "mt_xy_sigma_product", st)) != hipSuccess)
+        return e;
     timing_before("mt_xy_sigma_store", st);
     hipLaunchKernelGGL(mt_xy_long_store_kernel, blocks(slots * L), dim3(256), 0, st, cur, logN, L, slots, w.sigma);
     timing_after(st);
@@ -1074,6 +1226,23 @@ hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const Maxco
 }
 
 }  // namespace
+
+hipError_t launch_maxconv(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,
+                          const MaxconvSpec& spec, void* z, uint8_t* pstar, const MaxconvWorkspace& w,
+                          hipStream_t st) {
+    if (b <= 0 || n <= 0 || m <= 0) return hipSuccess;
+    const int logN = maxconv_log_size(n, m);
+    if (logN > kLongConvLog) return hipErrorInvalidValue;
+    if (logN > kMaxConvLog) {
+        if (f64)
+            return launch_maxconv_long<double>((const double*)x, (const double*)y, b, n, m, spec, (double*)z, pstar,
+                                               w, st);
+        return launch_maxconv_long<float>((const float*)x, (const float*)y, b, n, m, spec, (float*)z, pstar, w, st);
+    }
+    if (f64)
+        return launch_maxconv_t<double>((const double*)x, (const double*)y, b, n, m, spec, (double*)z, pstar, st);
+    return launch_maxconv_t<float>((const float*)x, (const float*)y, b, n, m, spec, (float*)z, pstar, st);
+}
 
 hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int32_t k, const MaxconvSpec& spec,
                           double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,

@@ -223,26 +223,37 @@ def test_r2_flag_validation():
 
 def test_maxconv_validation():
     """Argument checks of the max-convolution entry points (no GPU): FP64
-    path only, no flags, n + m - 1 <= 4096, non-NULL pointers; empty sizes
-    return at once."""
+    path only, no flags, n + m - 1 <= 16384 (a workspace above 4096),
+    non-NULL pointers; empty sizes return at once."""
     lib = mt.load_library()
     fake = ctypes.c_void_p(0x100000)
     null = ctypes.c_void_p(0)
+    big = ctypes.c_size_t(1 << 40)
     o = _opts([1, 2, 4], path=0)
-    assert lib.maxconv_estimate(fake, fake, 0, 2, 2048, 2049, ctypes.byref(o), null, null, null) == 1
-    assert b"NULL" in lib.maxtimes_last_error()
-    st = lib.maxconv_estimate(fake, fake, 0, 2, 2048, 2050, ctypes.byref(o), fake, null, null)
-    assert st == 5 and b"4096" in lib.maxtimes_last_error()
-    st = lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, ctypes.byref(_opts([1, 2], path=1)), fake, null, null)
+    nb = ctypes.c_size_t(7)
+    assert lib.maxconv_workspace_size(2, 2048, 2049, ctypes.byref(o), ctypes.byref(nb)) == 0 and nb.value == 0
+    assert lib.maxconv_workspace_size(2, 2048, 2050, ctypes.byref(o), ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 2 * 8192 * 16
+    assert lib.maxconv_workspace_size(2, 8192, 8193, ctypes.byref(o), ctypes.byref(nb)) == 0
+    assert lib.maxconv_workspace_size(2, 8192, 8194, ctypes.byref(o), ctypes.byref(nb)) == 5
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 2048, 2049, ctypes.byref(o), null, null, null, 0, null)
+    assert st == 1 and b"NULL" in lib.maxtimes_last_error()
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 8192, 8194, ctypes.byref(o), fake, null, fake, big, null)
+    assert st == 5 and b"16384" in lib.maxtimes_last_error()
+    # a long pair needs its workspace
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 2048, 2050, ctypes.byref(o), fake, null, fake, 16, null)
+    assert st == 3
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, ctypes.byref(_opts([1, 2], path=1)), fake, null, null, 0, null)
     assert st == 5
-    st = lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, ctypes.byref(_opts([1, 2], path=0, flags=4)), fake, null, null)
+    st = lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, ctypes.byref(_opts([1, 2], path=0, flags=4)), fake, null, null,
+                              0, null)
     assert st == 5
-    assert lib.maxconv_estimate(fake, fake, 3, 2, 8, 8, ctypes.byref(o), fake, null, null) == 1
-    assert lib.maxconv_estimate(fake, fake, 0, -1, 8, 8, ctypes.byref(o), fake, null, null) == 1
-    assert lib.maxconv_estimate(fake, fake, 0, 1 << 31, 8, 8, ctypes.byref(o), fake, null, null) == 5
-    assert lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, None, fake, null, null) == 1
-    assert lib.maxconv_estimate(null, null, 0, 0, 8, 8, ctypes.byref(o), null, null, null) == 0
-    assert lib.maxconv_estimate(null, null, 0, 4, 0, 8, ctypes.byref(o), null, null, null) == 0
+    assert lib.maxconv_estimate(fake, fake, 3, 2, 8, 8, ctypes.byref(o), fake, null, null, 0, null) == 1
+    assert lib.maxconv_estimate(fake, fake, 0, -1, 8, 8, ctypes.byref(o), fake, null, null, 0, null) == 1
+    assert lib.maxconv_estimate(fake, fake, 0, 1 << 31, 8, 8, ctypes.byref(o), fake, null, null, 0, null) == 5
+    assert lib.maxconv_estimate(fake, fake, 0, 2, 8, 8, None, fake, null, null, 0, null) == 1
+    assert lib.maxconv_estimate(null, null, 0, 0, 8, 8, ctypes.byref(o), null, null, null, 0, null) == 0
+    assert lib.maxconv_estimate(null, null, 0, 4, 0, 8, ctypes.byref(o), null, null, null, 0, null) == 0
     assert lib.maxconv_exact(null, fake, 0, 2, 8, 8, fake, null) == 1
     assert lib.maxconv_exact(fake, fake, 0, 2, (1 << 24) + 1, 8, fake, null) == 5
     assert lib.maxconv_exact(null, null, 1, 0, 8, 8, null, null) == 0

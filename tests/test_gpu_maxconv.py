@@ -105,8 +105,9 @@ def compare(z_gpu, ps_gpu, x, y, P, tau, fp32_out=False, max_flip_frac=0.01):
             "none": int((q_ref == oracle.PSTAR_NONE).sum())}
 
 
+# up to n + m - 1 = 4096 in LDS; longer pairs (to 16384) through global buffers
 SHAPES = [(3, 1, 1), (2, 5, 3), (4, 100, 37), (3, 257, 256), (2, 2048, 2049), (1, 4096, 1), (1, 1, 4096),
-          (2, 1000, 1500)]
+          (2, 1000, 1500), (2, 2049, 2049), (3, 3000, 2000), (1, 8192, 8193), (1, 16384, 1)]
 KINDS = ["uniform", "lognormal", "sparse", "distribution"]
 
 
@@ -120,7 +121,8 @@ def test_maxconv_parity(gpu_lib, shape, kind):
     print(kind, shape, st, flush=True)
 
 
-@pytest.mark.parametrize("shape", [(4, 100, 37), (2, 2048, 2049)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", [(4, 100, 37), (2, 2048, 2049), (2, 5000, 3000)],
+                         ids=lambda s: "x".join(map(str, s)))
 def test_maxconv_fp32(gpu_lib, shape):
     """FP32 input and output: the transform still runs in FP64; z is rounded
     once to FP32."""
@@ -132,7 +134,8 @@ def test_maxconv_fp32(gpu_lib, shape):
             oracle.TAU_FFT, fp32_out=True)
 
 
-@pytest.mark.parametrize("shape", [(2, 7, 9), (3, 300, 300), (1, 2048, 2049)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", [(2, 7, 9), (3, 300, 300), (1, 2048, 2049), (2, 6000, 6000)],
+                         ids=lambda s: "x".join(map(str, s)))
 def test_fft_convolution_accuracy(gpu_lib, shape):
     """One power p = 1 and tau = 1e-300: z / (rx ry) is the FFT convolution
     itself (clamped at 0), within delta_1 of the direct convolution."""
@@ -232,7 +235,8 @@ def test_large_batch_sampled_rows(gpu_lib):
     compare(z[rows], ps[rows], x[rows], y[rows], P, oracle.TAU_FFT)
 
 
-@pytest.mark.parametrize("shape", [(3, 200, 150), (2, 1024, 1024)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", [(3, 200, 150), (2, 1024, 1024), (2, 4000, 4000)],
+                         ids=lambda s: "x".join(map(str, s)))
 def test_non_power_of_two_family(gpu_lib, shape):
     """p that are not powers of two take the root as exp(log S / p) and the
     powers by repeated squaring with odd steps."""
