@@ -66,6 +66,22 @@ __device__ __forceinline__ double ipow_d(double v, int p) {
     return r;
 }
 
+// v[i] <- v[i]^p componentwise for the 16 values of a thread.  A power of two
+// is one loop of squarings over all values (uniform, in place); other p go
+// value by value (a second array of 16 would not fit beside the rest).  The
+// same products in the same order as ipow_d either way.
+__device__ __forceinline__ void pow_all(double2 (&v)[16], int p) {
+    if ((p & (p - 1)) == 0) {
+        for (int e = p; e > 1; e >>= 1) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = make_double2(v[i].x * v[i].x, v[i].y * v[i].y);
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = make_double2(ipow_d(v[i].x, p), ipow_d(v[i].y, p));
+}
+
 __device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
 
 // An empty asm that claims to change v: values derived from it are then
@@ -455,8 +471,9 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
             const int t = tl + i * TP;
             const double a = (active && t < n) ? (double)xi[t] * ix : 0.0;
             const double c = (active && t < m) ? (double)yi[t] * iy : 0.0;
-            v[i] = make_double2(ipow_d(a, p), ipow_d(c, p));
+            v[i] = make_double2(a, c);
         }
+        pow_all(v, p);
         convolve_pair<LOGN>(v, tl, buf, pt);
         // p* test: the first stable p from the top decides an index; the
         // smallest p decides what is left (its S, no p stable)
@@ -551,11 +568,12 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_xy_sigma_kernel(const T* _
         const int t = tl + i * TP;
         double a = 0.0, c = 0.0;
         if (active && t < n) {
-            a = ipow_d(exp((double)x[t] - mx), p);
-            c = ipow_d(exp((double)y[run ? n - 1 - t : t] - my), p);
+            a = exp((double)x[t] - mx);
+            c = exp((double)y[run ? n - 1 - t : t] - my);
         }
         v[i] = make_double2(a, c);
     }
+    pow_all(v, p);
     convolve_pair<LOGN>(v, tl, buf, pt);
     if (active) {
         double* out = sigma + ((int64_t)run * spec.n + q) * L;
