@@ -1,4 +1,5 @@
-// Max-convolution (Sec. 1).
+// Max-convolution (Sec. 1) and the top k of x + y (Sec. 2.3) on FFT ring
+// results.
 //
 // Estimate: z[t] = max_i x[i] y[t - i] from the norm sequence
 // S_p[t] = (x'^p * y'^p)[t] with x' = x / max x, y' = y / max y (terms in
@@ -7,16 +8,16 @@
 // index the largest p of the family with S_p >= tau, and
 // z = max x max y S_{p*}^(1/p*).
 //
-// Layout: a transform of N = max(16, 2^ceil(log2(n + m - 1))) points is
-// done by N / 16 threads that hold 16 complex values each in registers
-// (N <= 4096: 256 threads, one pair per workgroup; smaller N packs 4096 / N
-// pairs into a workgroup).  Passes are Stockham radix-16 (the last one radix
-// 2, 4 or 8 when log2 N is not a multiple of 4), natural order in and out,
-// through one LDS buffer per pair padded by one element every 16 (the
-// stride-16 writes of the first pass then hit distinct banks).  Twiddles
-// exp(-2 pi i m / N) come from one LDS table of cos and sin of 2 pi k / N for
-// k <= N / 8 (the other octants by symmetry); a butterfly looks up w and w^4
-// and forms the other powers by products.
+// LDS path (n + m - 1 <= 4096): a transform of N = max(16, 2^ceil(log2(n + m
+// - 1))) points is done by N / 16 threads that hold 16 complex values each in
+// registers (N = 4096: 256 threads, one pair per workgroup; smaller N packs
+// 4096 / N pairs into a workgroup).  Passes are Stockham radix-16 (the last
+// one radix 2, 4 or 8 when log2 N is not a multiple of 4), natural order in
+// and out, through one LDS buffer per pair padded by one element every 16
+// (the stride-16 writes of the first pass then hit distinct banks).
+// Twiddles exp(-2 pi i m / N) come from one LDS table of cos and sin of
+// 2 pi k / N for k <= N / 8 (the other octants by symmetry); a thread looks up
+// w and w^4 of its butterflies once and forms the other powers by products.
 // Per p, largest first:
 //   forward: x'^p + i y'^p (x, y re-read per p, times 1 / max), so both real
 //            transforms come out of one complex FFT;
@@ -25,10 +26,17 @@
 //            Z_{N-t}) / 2i (the first pass of the inverse reads these pairs);
 //   inverse: the forward FFT of conj(W), whose real part / N is S_p; the
 //            last pass leaves S in registers at the positions the thread
-//            owns, where the p* test and the root run without another LDS
-//            trip.
-// Indices decided at a larger p keep their value; a workgroup stops once
-// every index of its pairs is decided.
+//            owns, where the p* test runs.
+// Indices decided at a larger p keep their S; a workgroup stops once every
+// index of its pairs is decided, and the roots are taken once per index.
+//
+// Global path (n + m - 1 <= 16384): the same passes through two buffers in
+// the workspace, one thread per butterfly, kernel boundaries between passes,
+// the whole batch one p at a time.
+//
+// Top k of x + y: the ring results of both runs (y and y reversed) for every
+// p by either path, the initial estimates, a one-wave NormQueue per run and
+// the index pairing.
 //
 // Exact: z[t] = max_i x[i] y[t - i] by the definition, one thread per output
 // index, products in the input precision.
