@@ -16,14 +16,15 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ inline uint16_t bf16_rne(float x) {
-    // Round to nearest even on the bit pattern; x is finite and >= 0 here.
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// Two values to BF16 by the hardware conversion, round to nearest even (the
+// same bits as rounding the FP32 bit pattern to nearest even: checked for
+// every finite nonnegative FP32 value), a in the low half.
+typedef float mt_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 mt_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t bf16x2_rne(float a, float b) {
+    const mt_f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, mt_bf16x2));
 }
-
-__device__ inline float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 template <typename T>
 __device__ inline bool bad_value(T x) {
@@ -298,13 +299,11 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
                 u32x4 hi, lo;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const uint16_t h0 = bf16_rne((float)pw[2 * i]), h1 = bf16_rne((float)pw[2 * i + 1]);
-                    hi[i] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-                    if (spec.split[q]) {
-                        const uint16_t l0 = bf16_rne((float)pw[2 * i] - bf16_to_float(h0));
-                        const uint16_t l1 = bf16_rne((float)pw[2 * i + 1] - bf16_to_float(h1));
-                        lo[i] = (uint32_t)l0 | ((uint32_t)l1 << 16);
-                    }
+                    const float f0 = (float)pw[2 * i], f1 = (float)pw[2 * i + 1];
+                    const uint32_t h = bf16x2_rne(f0, f1);
+                    hi[i] = h;
+                    if (spec.split[q])
+                        lo[i] = bf16x2_rne(f0 - __uint_as_float(h << 16), f1 - __uint_as_float(h & 0xFFFF0000u));
                 }
                 const int64_t off = ((bi * spec.n_planes + pl) * plane_elems) + t * cols_pad + u;
                 // streaming stores: the planes are read back only by the GEMM,
