@@ -142,6 +142,32 @@ mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
                                   const mt_options* opt, size_t* bytes);
 
 /*
+ * Where maxtimes_estimate keeps its first results in the workspace (for
+ * inspection after a call with the same sizes and options; byte offsets from
+ * the workspace start):
+ *   r_offset         b x m FP64: r_i = max_k A_ik (Sec. 2.1 scaling)
+ *   c_offset         b x n FP64: c_j = max_k B_kj
+ *   a_planes_offset  [b][n_planes][m_pad][k_pad]: (A / r)^p, row-major
+ *   b_planes_offset  [b][n_planes][n_pad][k_pad]: (B / c)^p, transposed
+ * Plane elements are BF16 bit patterns (elem_bytes = 2, BF16 path: hi, and
+ * for a split p the next plane holds lo = RNE(x - hi)) or FP64 (8).  Power q
+ * of the plane spec (the family, plus the added norms of
+ * MT_FLAG_PROJECT_R2, ascending) is power[q], in plane first_plane[q].
+ * Padding (rows >= m or n, columns >= k) holds zeros.  Host memory; same
+ * argument checks as maxtimes_workspace_size.
+ */
+typedef struct {
+    size_t r_offset, c_offset, a_planes_offset, b_planes_offset;
+    int64_t m_pad, n_pad, k_pad;
+    int32_t n_planes, elem_bytes, n_powers;
+    int32_t power[MT_MAX_P];
+    int32_t first_plane[MT_MAX_P];
+    int32_t split[MT_MAX_P];
+} mt_workspace_map;
+mt_status maxtimes_workspace_map(int64_t b, int64_t m, int64_t k, int64_t n, const mt_options* opt,
+                                 mt_workspace_map* map);
+
+/*
  * The estimate C of the (max, x) product of A and B (Alg. 5, Sec. 2.1-2.2).
  *   A      b x m x k, dtype, entries >= 0 and finite.
  *   B      b x k x n, dtype, entries >= 0 and finite.

@@ -22,7 +22,7 @@ import torch
 
 __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
-    "workspace_size", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
+    "workspace_size", "workspace_map", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
     "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold",
     "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "maxconv", "maxconv_exact",
     "maxconv_workspace_size", "xy_topk", "xy_topk_workspace_size", "XY_FAMILY", "pfamily", "PSTAR_NONE", "PATHS",
@@ -49,6 +49,16 @@ class MaxTimesError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+class _WorkspaceMap(ctypes.Structure):
+    _fields_ = [
+        ("r_offset", ctypes.c_size_t), ("c_offset", ctypes.c_size_t),
+        ("a_planes_offset", ctypes.c_size_t), ("b_planes_offset", ctypes.c_size_t),
+        ("m_pad", ctypes.c_int64), ("n_pad", ctypes.c_int64), ("k_pad", ctypes.c_int64),
+        ("n_planes", ctypes.c_int32), ("elem_bytes", ctypes.c_int32), ("n_powers", ctypes.c_int32),
+        ("power", ctypes.c_int32 * 32), ("first_plane", ctypes.c_int32 * 32), ("split", ctypes.c_int32 * 32),
+    ]
 
 
 class _Options(ctypes.Structure):
@@ -79,6 +89,7 @@ def load_library():
     opt = ctypes.POINTER(_Options)
     sig = {
         "maxtimes_workspace_size": [i64, i64, i64, i64, opt, ctypes.POINTER(sz)],
+        "maxtimes_workspace_map": [i64, i64, i64, i64, opt, ctypes.POINTER(_WorkspaceMap)],
         "maxtimes_estimate": [vp, vp, ctypes.c_int, i64, i64, i64, i64, opt, vp, vp, vp, sz, vp],
         "maxtimes_backward_workspace_size": [i64, i64, i64, i64, opt, ctypes.POINTER(sz)],
         "maxtimes_estimate_backward": [vp, vp, vp, vp, vp, ctypes.c_int, i64, i64, i64, i64, opt,
@@ -180,6 +191,20 @@ def workspace_size(b, m, k, n, P, path="bf16", tau=None, split_max_p=None, flags
     out = ctypes.c_size_t(0)
     _check(lib.maxtimes_workspace_size(b, m, k, n, ctypes.byref(o), ctypes.byref(out)))
     return out.value
+
+
+def workspace_map(b, m, k, n, P, path="bf16", tau=None, split_max_p=None, flags=0):
+    """Where estimate() keeps r, c and the power planes in its workspace (a
+    dict of byte offsets, padded sizes and the plane of each power)."""
+    lib = load_library()
+    o = _options(P, path, tau, split_max_p, flags)
+    mp = _WorkspaceMap()
+    _check(lib.maxtimes_workspace_map(b, m, k, n, ctypes.byref(o), ctypes.byref(mp)))
+    q = mp.n_powers
+    return {"r": mp.r_offset, "c": mp.c_offset, "a_planes": mp.a_planes_offset, "b_planes": mp.b_planes_offset,
+            "m_pad": mp.m_pad, "n_pad": mp.n_pad, "k_pad": mp.k_pad, "n_planes": mp.n_planes,
+            "elem_bytes": mp.elem_bytes, "power": list(mp.power[:q]), "first_plane": list(mp.first_plane[:q]),
+            "split": [bool(v) for v in mp.split[:q]]}
 
 
 def backward_workspace_size(b, m, k, n, P, path="bf16", tau=None, split_max_p=None, flags=0):

@@ -590,6 +590,37 @@ mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n, co
     return MT_OK;
 }
 
+mt_status maxtimes_workspace_map(int64_t b, int64_t m, int64_t k, int64_t n, const mt_options* opt,
+                                 mt_workspace_map* map) {
+    g_last_error.clear();
+    if (!map) return fail(MT_ERR_INVALID_ARG, "map pointer is NULL");
+    Family f;
+    mt_status s = parse_options(opt, &f);
+    if (s != MT_OK) return s;
+    if ((s = check_dims(b, m, k, n)) != MT_OK) return s;
+    if ((s = check_bf16_inner(f, k)) != MT_OK) return s;
+    const PlaneSpec ps = plane_spec(f);
+    const Geom g = product_geom(f, b, m, k, n);
+    const Layout L = product_layout(f, ps, g, b, m, n, 0);
+    memset(map, 0, sizeof *map);
+    map->r_offset = L.r;
+    map->c_offset = L.c;
+    map->a_planes_offset = L.ap;
+    map->b_planes_offset = L.bp;
+    map->m_pad = g.mp;
+    map->n_pad = g.np;
+    map->k_pad = g.kp;
+    map->n_planes = ps.n_planes;
+    map->elem_bytes = (int32_t)g.esize;
+    map->n_powers = ps.n_p;
+    for (int q = 0; q < ps.n_p; ++q) {
+        map->power[q] = ps.p[q];
+        map->first_plane[q] = ps.first_plane[q];
+        map->split[q] = ps.split[q];
+    }
+    return MT_OK;
+}
+
 mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,
                             int64_t k, int64_t n, const mt_options* opt, void* C, uint8_t* p_star,
                             void* workspace, size_t ws_bytes, void* stream) {

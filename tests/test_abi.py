@@ -282,3 +282,23 @@ def test_xy_topk_validation():
     assert lib.xy_topk_estimate(fake, fake, 0, 8, 4, ctypes.byref(o), fake, null, null, null, fake, 64, null) == 3
     assert lib.xy_topk_estimate(fake, fake, 5, 8, 4, ctypes.byref(o), fake, null, null, null, fake, 1 << 30,
                                 null) == 1
+
+
+def test_workspace_map():
+    """The inspection map of the product's workspace (no GPU): ordered,
+    inside the workspace, planes of the plane spec."""
+    for path, P in (("bf16", [1, 2, 4, 8, 16]), ("fp64", [1, 2, 4, 8])):
+        m = mt.workspace_map(2, 100, 70, 50, P, path=path)
+        size = _ws(P, path=path, b=2, m=100, k=70, n=50)
+        assert m["r"] < m["c"] < m["a_planes"] < m["b_planes"] < size
+        esz = m["elem_bytes"]
+        assert m["b_planes"] + 2 * m["n_planes"] * m["n_pad"] * m["k_pad"] * esz <= size
+        assert m["power"] == P
+        assert m["m_pad"] >= 100 and m["n_pad"] >= 50 and m["k_pad"] >= 70
+        if path == "bf16":
+            assert esz == 2 and m["split"] == [True, True, True, False, False]
+            assert m["first_plane"] == [0, 2, 4, 6, 7] and m["n_planes"] == 8
+        else:
+            assert esz == 8 and m["n_planes"] == 4 and not any(m["split"])
+    with pytest.raises(mt.MaxTimesError):
+        mt.workspace_map(1, 8, 8, 8, [2, 1])
