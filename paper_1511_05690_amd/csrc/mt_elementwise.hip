@@ -221,8 +221,13 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
     void* __restrict__ planes) {
     __shared__ TS tile[64][64 + 1];
     const int64_t bi = blockIdx.z;
-    const int64_t t0 = (int64_t)blockIdx.y * 64;  // plane row
-    const int64_t u0 = (int64_t)blockIdx.x * 64;  // plane column
+    // A workgroup covers kPlaneRows x kPlaneCols of a plane: 64 x 64 through
+    // an LDS transpose, or 16 rows x 256 columns straight from the rows (512
+    // contiguous bytes per row and BF16 plane written).
+    constexpr int kPlaneRows = kTranspose ? 64 : 16;
+    constexpr int kChunkShift = kTranspose ? 3 : 5;  // log2 of the 8-column chunks per row
+    const int64_t t0 = (int64_t)blockIdx.y * kPlaneRows;      // plane row
+    const int64_t u0 = (int64_t)blockIdx.x * (8 << kChunkShift);  // plane column
     const TS* s = src + bi * rows * cols;
 
     if (kTranspose) {
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
     const int64_t plane_elems = rows_pad * cols_pad;
     for (int rep = 0; rep < 2; ++rep) {
         const int task = threadIdx.x + rep * kThreads;  // 0..511
-        const int tt = task >> 3, ch = task & 7;
+        const int tt = task >> kChunkShift, ch = task & ((1 << kChunkShift) - 1);
         const int64_t t = t0 + tt;
         const int64_t u = u0 + ch * 8;
         if (t >= rows_pad || u >= cols_pad) continue;
@@ -544,7 +549,10 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
                                const double* scale_rows, const double* scale_cols,
                                const PlaneSpec& spec, int bf16, void* planes, hipStream_t st) {
     if (rows_pad <= 0 || cols_pad <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((cols_pad + 63) / 64), (unsigned)((rows_pad + 63) / 64), (unsigned)b);
+    // 64 x 64 tiles through LDS for the transposed operand, 16 x 256 otherwise
+    const dim3 grid = transpose
+        ? dim3((unsigned)((cols_pad + 63) / 64), (unsigned)((rows_pad + 63) / 64), (unsigned)b)
+        : dim3((unsigned)((cols_pad + 255) / 256), (unsigned)((rows_pad + 15) / 16), (unsigned)b);
 #define MT_PLANES(TS, BF, TR)                                                                   \
     hipLaunchKernelGGL((mt_power_planes_kernel<TS, BF, TR>), grid, dim3(kThreads), 0, st,      \
                        (const TS*)src, rows, cols, rows_pad, cols_pad, scale_rows, scale_cols, spec,  \
