@@ -53,4 +53,4 @@ from .apsp import (  # noqa: F401
     affine_apply,
 )
 from .maxconv import TAU_FFT, exact_maxconv, maxconv_estimate  # noqa: F401,E402
-from .xy_topk import exact_topk_xy, norm_queue, xy_topk_estimate  # noqa: F401,E402
+from .xy_topk import exact_topk_xy, norm_queue, xy_topk_estimate, xy_topk_paired  # noqa: F401,E402

@@ -23,6 +23,18 @@ and the index recovery that follows it).
     anti-diagonal m2 = i + (n - 1 - j) of the same value; with m1 = i + j,
     i = (m1 + m2 - n + 1) / 2 and j = m1 - i (the pair is reported only when
     that is an integer pair inside the n x n grid).
+
+The paired queue (xy_topk_paired) is the refinement that the Discussion
+proposes: the two runs pop in lockstep, so the pair (i, j) of a rank is
+known before the norms are updated; when that pair is accurate its exact
+value x_i + y_j is reported and its scaled value v = x'_i y'_j, not the
+estimate, is subtracted from both runs' norms.  Reading of "accurate" (the
+paper leaves it open): (i, j) is an integer pair inside the grid and v is
+at least the smallest maximum that the norm admits on each of the two
+diagonals, psi len^(-1/p*) (a vector of len entries with p-norm psi has a
+largest entry of at least psi len^(-1/p); len = number of grid pairs on the
+diagonal).  Otherwise the rank is reported as by the plain queue (run 0's
+estimate, i = j = -1) and each run subtracts its own estimate.
 """
 
 import numpy as np
@@ -99,3 +111,70 @@ def xy_topk_estimate(x, y, P, k, tau=TAU_FFT):
     ok = (i >= 0) & (i < n) & (j >= 0) & (j < n)
     return {"values": a["values"], "diag": a["diag"], "anti": b["diag"],
             "i": np.where(ok, i, -1), "j": np.where(ok, j, -1)}
+
+
+def _diag_len(m, n):
+    """Number of pairs (i, j) of the n x n grid with i + j = m (the same
+    count for an anti-diagonal of the run on y reversed)."""
+    return min(m, 2 * n - 2 - m) + 1
+
+
+def _min_admitted(a, q, m, n, P):
+    """Smallest largest entry that a diagonal m with estimate a (root at
+    p = P[q]) admits: a len^(-1/p); 0 when no p is stable (q < 0)."""
+    return a * _diag_len(m, n) ** (-1.0 / P[q]) if q >= 0 else 0.0
+
+
+def xy_topk_paired(x, y, P, k, tau=TAU_FFT):
+    """Top k of x_i + y_j by the paired NormQueue (Discussion): the runs on
+    y and on y reversed pop together; an accurate pair (see the module
+    docstring) is reported exactly and subtracted exactly from both.
+    Returns dict values, diag (run 0), anti (run 1), i, j (-1 on ranks whose
+    pair was not accurate), accepted (bool per rank)."""
+    P = [int(p) for p in P]
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = x.size
+    if y.size != n:
+        raise ValueError("x and y must have the same length")
+    mx, my = x.max(), y.max()
+    xs = np.exp(x - mx)
+    ys = np.exp(y - my)
+    work = [np.stack([np.convolve(xs ** p, ys ** p) for p in P]),
+            np.stack([np.convolve(xs ** p, ys[::-1] ** p) for p in P])]
+    L = 2 * n - 1
+    psi = [np.zeros(L), np.zeros(L)]
+    pq = [np.full(L, -1), np.full(L, -1)]
+    for t in range(2):
+        for m in range(L):
+            psi[t][m], pq[t][m] = _estimate(work[t][:, m], P, tau)
+    out = {"values": np.zeros(k), "diag": np.zeros(k, dtype=np.int64), "anti": np.zeros(k, dtype=np.int64),
+           "i": np.full(k, -1, dtype=np.int64), "j": np.full(k, -1, dtype=np.int64),
+           "accepted": np.zeros(k, dtype=bool)}
+    for r in range(k):
+        m1 = int(np.argmax(psi[0]))
+        m2 = int(np.argmax(psi[1]))
+        a = (psi[0][m1], psi[1][m2])
+        out["diag"][r], out["anti"][r] = m1, m2
+        ok = False
+        s = m1 + m2 - (n - 1)
+        if s % 2 == 0 and 0 <= s // 2 < n and 0 <= m1 - s // 2 < n:
+            i, j = s // 2, m1 - s // 2
+            v = np.exp((x[i] - mx) + (y[j] - my))
+            ok = True
+            for t, m in ((0, m1), (1, m2)):
+                ok = ok and v >= _min_admitted(a[t], pq[t][m], m, n, P)
+        if ok:
+            out["values"][r] = x[i] + y[j]
+            out["i"][r], out["j"][r] = i, j
+            out["accepted"][r] = True
+            sub = (v, v)
+        else:
+            out["values"][r] = mx + my + (np.log(a[0]) if a[0] > 0 else -np.inf)
+            sub = a
+        with np.errstate(over="ignore"):
+            for t, m in ((0, m1), (1, m2)):
+                for q, p in enumerate(P):
+                    work[t][q, m] -= sub[t] ** p
+                psi[t][m], pq[t][m] = _estimate(work[t][:, m], P, tau)
+    return out

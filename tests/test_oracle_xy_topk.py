@@ -15,6 +15,18 @@ oracle's own formulas:
 * shifting x and y by constants shifts the values and keeps the indices;
   the run on y reversed gives the same values (the order of y does not
   matter, the premise of the index recovery).
+
+The paired queue (Discussion: both runs in lockstep, exact values where the
+pair is accurate):
+
+* on an input where every rank's pair is accurate it returns the
+  brute-force top k to the bit, indices included;
+* accepted ranks are grid pairs on both popped diagonals with the exact
+  value x_i + y_j, no pair twice, and rank 0 pops what each plain run pops
+  first;
+* the acceptance threshold psi len^(-1/p*) never exceeds a diagonal's true
+  largest term on exact ring results (the norm inequality), and a diagonal
+  of equal terms attains it.
 """
 
 import itertools
@@ -116,3 +128,72 @@ def test_no_stable_power_and_validation():
         pass
     else:
         raise AssertionError("unequal lengths must be rejected")
+
+
+# ---- the paired queue (Discussion) ----------------------------------------
+
+from oracle.xy_topk import _diag_len, _estimate, _min_admitted, xy_topk_paired  # noqa: E402
+
+
+def test_paired_every_rank_accepted_is_the_exact_top_k():
+    # spread 40, n = 256, k = 64: every rank's pair is accurate, so the
+    # sequence is the brute-force top k to the bit, indices included
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 40, 256)
+    y = rng.uniform(0, 40, 256)
+    r = xy_topk_paired(x, y, P24, 64)
+    v, i, j = exact_topk_xy(x, y, 64)
+    assert r["accepted"].all()
+    np.testing.assert_array_equal(r["values"], v)
+    np.testing.assert_array_equal(r["i"], i)
+    np.testing.assert_array_equal(r["j"], j)
+
+
+def test_paired_accepted_ranks_are_grid_pairs_of_both_diagonals():
+    rng = np.random.default_rng(4)
+    n, k = 256, 64
+    x = rng.uniform(0, 10, n)
+    y = rng.uniform(0, 10, n)
+    r = xy_topk_paired(x, y, P24, k)
+    acc = r["accepted"]
+    assert 0 < acc.sum() < k  # this input has both kinds of rank
+    i, j = r["i"][acc], r["j"][acc]
+    np.testing.assert_array_equal(i + j, r["diag"][acc])
+    np.testing.assert_array_equal(i + n - 1 - j, r["anti"][acc])
+    np.testing.assert_array_equal(r["values"][acc], x[i] + y[j])
+    assert len(set(zip(i.tolist(), j.tolist()))) == acc.sum()  # no pair twice
+    assert (r["i"][~acc] == -1).all() and (r["j"][~acc] == -1).all()
+    # rank 0 pops what each plain run pops first
+    a = norm_queue(x, y, P24, 1)
+    b = norm_queue(x, y[::-1], P24, 1)
+    assert r["diag"][0] == a["diag"][0] and r["anti"][0] == b["diag"][0]
+
+
+def test_min_admitted_bounds_every_diagonal_maximum():
+    # ||u||_inf >= ||u||_p len^(-1/p): on exact ring results the threshold
+    # never exceeds a diagonal's true largest term
+    rng = np.random.default_rng(5)
+    n = 40
+    x = rng.normal(0, 2, n)
+    y = rng.normal(0, 2, n)
+    xs, ys = np.exp(x - x.max()), np.exp(y - y.max())
+    sig = np.stack([np.convolve(xs ** p, ys ** p) for p in P24])
+    for m in range(2 * n - 1):
+        a, q = _estimate(sig[:, m], P24, 1e-12)
+        i = np.arange(max(0, m - n + 1), min(m, n - 1) + 1)
+        assert i.size == _diag_len(m, n)
+        true_max = (xs[i] * ys[m - i]).max()
+        assert _min_admitted(a, q, m, n, P24) <= true_max * (1 + 1e-12)
+        assert a >= true_max * (1 - 1e-12)
+
+
+def test_min_admitted_is_attained_by_a_constant_diagonal():
+    # the bound is tight: a diagonal of len equal terms v has p-norm
+    # v len^(1/p), and the threshold gives v back
+    n = 9
+    for m in (0, 3, 8, 12):
+        ln = _diag_len(m, n)
+        for q, p in enumerate(P24):
+            a = 0.75 * ln ** (1.0 / p)
+            np.testing.assert_allclose(_min_admitted(a, q, m, n, P24), 0.75, rtol=1e-13)
+    assert _min_admitted(0.0, -1, 4, n, P24) == 0.0
