@@ -29,12 +29,15 @@ proposes: the two runs pop in lockstep, so the pair (i, j) of a rank is
 known before the norms are updated; when that pair is accurate its exact
 value x_i + y_j is reported and its scaled value v = x'_i y'_j, not the
 estimate, is subtracted from both runs' norms.  Reading of "accurate" (the
-paper leaves it open): (i, j) is an integer pair inside the grid and v is
+paper leaves it open): (i, j) is an integer pair inside the grid that no
+earlier rank reported (a reported pair is gone from both norms; the two runs
+can meet in it again once their diagonals are popped again), and v is
 at least the smallest maximum that the norm admits on each of the two
 diagonals, psi len^(-1/p*) (a vector of len entries with p-norm psi has a
 largest entry of at least psi len^(-1/p); len = number of grid pairs on the
-diagonal).  Otherwise the rank is reported as by the plain queue (run 0's
-estimate, i = j = -1) and each run subtracts its own estimate.
+diagonal; none when the diagonal has no stable p).  Otherwise the rank is
+reported as by the plain queue (run 0's estimate, i = j = -1) and each run
+subtracts its own estimate.
 """
 
 import numpy as np
@@ -121,8 +124,9 @@ def _diag_len(m, n):
 
 def _min_admitted(a, q, m, n, P):
     """Smallest largest entry that a diagonal m with estimate a (root at
-    p = P[q]) admits: a len^(-1/p); 0 when no p is stable (q < 0)."""
-    return a * _diag_len(m, n) ** (-1.0 / P[q]) if q >= 0 else 0.0
+    p = P[q]) admits: a len^(-1/p).  A diagonal with no stable p (q < 0) has
+    no estimate to judge a pair by: +inf, so no pair on it is accurate."""
+    return a * _diag_len(m, n) ** (-1.0 / P[q]) if q >= 0 else np.inf
 
 
 def xy_topk_paired(x, y, P, k, tau=TAU_FFT):
@@ -151,6 +155,7 @@ def xy_topk_paired(x, y, P, k, tau=TAU_FFT):
     out = {"values": np.zeros(k), "diag": np.zeros(k, dtype=np.int64), "anti": np.zeros(k, dtype=np.int64),
            "i": np.full(k, -1, dtype=np.int64), "j": np.full(k, -1, dtype=np.int64),
            "accepted": np.zeros(k, dtype=bool)}
+    reported = set()
     for r in range(k):
         m1 = int(np.argmax(psi[0]))
         m2 = int(np.argmax(psi[1]))
@@ -161,13 +166,14 @@ def xy_topk_paired(x, y, P, k, tau=TAU_FFT):
         if s % 2 == 0 and 0 <= s // 2 < n and 0 <= m1 - s // 2 < n:
             i, j = s // 2, m1 - s // 2
             v = np.exp((x[i] - mx) + (y[j] - my))
-            ok = True
+            ok = (i, j) not in reported
             for t, m in ((0, m1), (1, m2)):
                 ok = ok and v >= _min_admitted(a[t], pq[t][m], m, n, P)
         if ok:
             out["values"][r] = x[i] + y[j]
             out["i"][r], out["j"][r] = i, j
             out["accepted"][r] = True
+            reported.add((i, j))
             sub = (v, v)
         else:
             out["values"][r] = mx + my + (np.log(a[0]) if a[0] > 0 else -np.inf)

@@ -22,8 +22,8 @@ pair is accurate):
 * on an input where every rank's pair is accurate it returns the
   brute-force top k to the bit, indices included;
 * accepted ranks are grid pairs on both popped diagonals with the exact
-  value x_i + y_j, no pair twice, and rank 0 pops what each plain run pops
-  first;
+  value x_i + y_j, no pair twice (also deep into an exhausted queue), and
+  rank 0 pops what each plain run pops first;
 * the acceptance threshold psi len^(-1/p*) never exceeds a diagonal's true
   largest term on exact ring results (the norm inequality), and a diagonal
   of equal terms attains it.
@@ -196,4 +196,26 @@ def test_min_admitted_is_attained_by_a_constant_diagonal():
         for q, p in enumerate(P24):
             a = 0.75 * ln ** (1.0 / p)
             np.testing.assert_allclose(_min_admitted(a, q, m, n, P24), 0.75, rtol=1e-13)
-    assert _min_admitted(0.0, -1, 4, n, P24) == 0.0
+    assert _min_admitted(0.0, -1, 4, n, P24) == np.inf
+
+
+def test_paired_deep_queue_reports_no_pair_twice():
+    # past the accurate ranks the two runs pop the same two diagonals again
+    # and meet in the pair they already reported: it must not come back
+    rng = np.random.default_rng(1000)
+    x = rng.uniform(0, 8, 17)
+    y = rng.uniform(0, 8, 17)
+    r = xy_topk_paired(x, y, P24, 289)
+    acc = r["accepted"]
+    pairs = set(zip(r["i"][acc].tolist(), r["j"][acc].tolist()))
+    assert len(pairs) == acc.sum() > 17
+    np.testing.assert_array_equal(r["values"][acc], x[r["i"][acc]] + y[r["j"][acc]])
+
+
+def test_paired_exhausted_queue_reports_nothing_more():
+    # n = 1: one pair; rank 0 is that pair exactly, then no p is stable on
+    # either run and the remaining ranks are -inf with no indices
+    r = xy_topk_paired([0.25], [-1.5], P24, 3)
+    assert r["values"][0] == 0.25 + -1.5 and r["i"][0] == 0 and r["j"][0] == 0
+    assert r["accepted"].tolist() == [True, False, False]
+    assert np.isneginf(r["values"][1:]).all() and (r["i"][1:] == -1).all()
