@@ -115,6 +115,22 @@ typedef enum { MT_PATH_FP64 = 0, MT_PATH_BF16_SPLIT = 1 } mt_path;
  * rejects it (MT_ERR_UNSUPPORTED).
  */
 #define MT_FLAG_PROJECT_R2  32u
+/*
+ * MT_FLAG_XY_PAIRED (xy_topk_estimate only; any other entry point answers
+ * MT_ERR_INVALID_ARG): the paired NormQueue that the Discussion proposes.
+ * The run on y and the run on y reversed pop in lockstep; their diagonals
+ * m1 = i + j and m2 = i + n - 1 - j give the pair (i, j) of the rank before
+ * the norms are updated.  The pair is accurate when it lies in the grid and
+ * its scaled value v = e^(x_i - max x + y_j - max y) is at least
+ * psi len^(-1/p*) on both diagonals (psi the diagonal's estimate, p* its
+ * root, len its number of grid pairs: the smallest largest term that its
+ * norm admits; no pair is accurate on a diagonal without a stable p).  An
+ * accurate rank reports the exact x_i + y_j and (i, j) and
+ * subtracts v^p from both runs' norms; any other rank reports run 0's
+ * estimate with i = j = -1, and each run subtracts its own estimate (the
+ * plain queue's update).  Needs k <= 4096 (MT_ERR_UNSUPPORTED above).
+ */
+#define MT_FLAG_XY_PAIRED   64u
 
 #define MT_PSTAR_NONE 255  /* p_star value when no p of the family was stable */
 #define MT_MAX_P 32        /* largest family size */
@@ -342,16 +358,20 @@ mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b,
  *   x, y     n values each, dtype (FP32 / FP64), device, finite.
  *   opt      family as for maxtimes_estimate (Sec. 3 uses 24 powers up to
  *            4096); path MT_PATH_FP64 (else MT_ERR_UNSUPPORTED); tau <= 0 ->
- *            MT_TAU_FFT_DEFAULT; flags must be 0 (else MT_ERR_UNSUPPORTED).
+ *            MT_TAU_FFT_DEFAULT; flags 0 or MT_FLAG_XY_PAIRED (the paired
+ *            queue of the Discussion, k <= 4096; other flags:
+ *            MT_ERR_UNSUPPORTED).
  *   values   k FP64 device (output), in pop order.
  *   diag, i_idx, j_idx  k int32 device (outputs, each nullable): m1, i, j.
  * 1 <= n <= 8192 (2n - 1 <= 16384; up to n = 2048 each transform runs in
  * one workgroup's LDS, longer ones through global buffers in the workspace),
  * 0 <= k <= 2^24 (else MT_ERR_UNSUPPORTED / MT_ERR_INVALID_ARG).
- * The pops run on one wave per run, in sequence.  Workspace from
+ * The pops run on one wave per run, in sequence (paired: one wave for both
+ * runs, over the min(k, 2n - 1) diagonals with the largest initial
+ * estimates, the only ones k pops can reach).  Workspace from
  * xy_topk_workspace_size (16 (|P| + 1)(2n - 1) + 16 k bytes and alignment, plus
  * 64 |P| N + 2 N bytes for the global buffers when n > 2048, N the transform
- * length).  With
+ * length, plus 24 min(k, 2n - 1) bytes for the paired candidates).  With
  * k = 0 only the ring results are formed: the workspace then starts with
  * sigma^(p)[m] of both runs, FP64, indexed (run |P| + q)(2n - 1) + m (run 1
  * on y reversed), for inspection.  Asynchronous on the stream.

@@ -36,6 +36,7 @@ XY_FAMILY = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 5
 PATHS = {"fp64": 0, "bf16": 1}
 F32, F64 = 0, 1
 FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT, FLAG_PROJECT_R1, FLAG_PROJECT_R2 = 1, 2, 4, 8, 16, 32
+FLAG_XY_PAIRED = 64
 PROJECTIONS = {None: 0, "r1": FLAG_PROJECT_R1, "r2": FLAG_PROJECT_R2}
 STATUS = {0: "MT_OK", 1: "MT_ERR_INVALID_ARG", 2: "MT_ERR_DOMAIN", 3: "MT_ERR_WORKSPACE",
           4: "MT_ERR_DEVICE", 5: "MT_ERR_UNSUPPORTED"}
@@ -420,20 +421,22 @@ def maxconv_workspace_size(b, n, m, P=(1, 2, 4, 8, 16, 32, 64), tau=None):
     return out.value
 
 
-def xy_topk_workspace_size(n, k, P=XY_FAMILY, tau=None):
+def xy_topk_workspace_size(n, k, P=XY_FAMILY, tau=None, paired=False):
     lib = load_library()
-    o = _options(P, "fp64", tau, None, 0)
+    o = _options(P, "fp64", tau, None, FLAG_XY_PAIRED if paired else 0)
     out = ctypes.c_size_t(0)
     _check(lib.xy_topk_workspace_size(n, k, ctypes.byref(o), ctypes.byref(out)))
     return out.value
 
 
-def xy_topk(x, y, k, P=XY_FAMILY, tau=None, return_diag=False):
+def xy_topk(x, y, k, P=XY_FAMILY, tau=None, return_diag=False, paired=False):
     """Estimate the k largest x_i + y_j (x, y: 1-D device tensors of the same
     length n <= 8192) and their indices by the NormQueue of Sec. 2.3 (FFT ring
     results in FP64, a second run on y reversed for the indices).  Returns
     (values FP64, i int32, j int32[, diag]); i = j = -1 where the two runs do
-    not give a pair in the grid."""
+    not give a pair in the grid.  paired=True runs the two queues in lockstep
+    (Discussion): a rank whose pair is accurate reports x_i + y_j exactly and
+    is subtracted exactly; k <= 4096."""
     lib = load_library()
     if not (x.is_cuda and y.is_cuda) or x.dim() != 1 or y.dim() != 1 or x.shape != y.shape:
         raise ValueError("x and y must be 1-D device tensors of the same length")
@@ -442,7 +445,7 @@ def xy_topk(x, y, k, P=XY_FAMILY, tau=None, return_diag=False):
     x = x.contiguous()
     y = y.contiguous()
     n = x.shape[0]
-    o = _options(P, "fp64", tau, None, 0)
+    o = _options(P, "fp64", tau, None, FLAG_XY_PAIRED if paired else 0)
     need = ctypes.c_size_t(0)
     _check(lib.xy_topk_workspace_size(n, int(k), ctypes.byref(o), ctypes.byref(need)))
     ws = _workspace(need.value, x.device, None)

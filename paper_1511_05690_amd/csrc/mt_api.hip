@@ -111,7 +111,7 @@ struct Family {
     int32_t paux[MT_MAX_P];
 };
 
-mt_status parse_options(const mt_options* opt, Family* f) {
+mt_status parse_options(const mt_options* opt, Family* f, bool xy = false) {
     if (!opt) return fail(MT_ERR_INVALID_ARG, "options pointer is NULL");
     if (!opt->p_family) return fail(MT_ERR_INVALID_ARG, "p_family is NULL");
     if (opt->n_p < 1 || opt->n_p > MT_MAX_P)
@@ -119,8 +119,10 @@ mt_status parse_options(const mt_options* opt, Family* f) {
     if (opt->path != MT_PATH_FP64 && opt->path != MT_PATH_BF16_SPLIT)
         return fail(MT_ERR_INVALID_ARG, "unknown path %d", opt->path);
     const uint32_t known = MT_FLAG_VALIDATE | MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT |
-                           MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2;
+                           MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2 | MT_FLAG_XY_PAIRED;
     if (opt->flags & ~known) return fail(MT_ERR_INVALID_ARG, "unknown flag bits 0x%x", opt->flags & ~known);
+    if ((opt->flags & MT_FLAG_XY_PAIRED) && !xy)
+        return fail(MT_ERR_INVALID_ARG, "MT_FLAG_XY_PAIRED is for xy_topk_estimate only");
     if ((opt->flags & (MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2)) && (opt->flags & MT_FLAG_NORM_CORRECT))
         return fail(MT_ERR_INVALID_ARG, "MT_FLAG_NORM_CORRECT applies to the plain root, not to a projection");
     if ((opt->flags & MT_FLAG_PROJECT_R1) && (opt->flags & MT_FLAG_PROJECT_R2))
@@ -977,9 +979,9 @@ mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b,
 // Workspace of xy_topk_estimate: the ring results of both runs, then the
 // second run's values and both runs' diagonals.
 struct XyLayout {
-    size_t sigma, psi, values1, diag0, diag1, tw, mxy, buf0, buf1, total;
+    size_t sigma, psi, values1, diag0, diag1, tw, mxy, buf0, buf1, cand_m, cand_psi, total;
 };
-XyLayout xy_layout(int64_t n, int32_t k, int n_p) {
+XyLayout xy_layout(int64_t n, int32_t k, int n_p, bool paired) {
     XyLayout L{};
     const int64_t len = 2 * n - 1;
     size_t off = 0;
@@ -1006,16 +1008,27 @@ XyLayout xy_layout(int64_t n, int32_t k, int n_p) {
         L.buf1 = off;
         off += (size_t)round_up(2 * (int64_t)n_p * N * 16, kAlign);
     }
+    L.cand_m = L.cand_psi = 0;
+    if (paired && k > 0) {
+        const int64_t K = k < len ? k : len;
+        L.cand_m = off;
+        off += (size_t)round_up(2 * K * 4, kAlign);
+        L.cand_psi = off;
+        off += (size_t)round_up(2 * K * 8, kAlign);
+    }
     L.total = off;
     return L;
 }
 
 mt_status xy_check(int64_t n, int32_t k, const mt_options* opt, Family* f) {
-    mt_status s = parse_options(opt, f);
+    mt_status s = parse_options(opt, f, true);
     if (s != MT_OK) return s;
     if (f->bf16) return fail(MT_ERR_UNSUPPORTED, "the x + y top k runs on the FP64 path only");
-    if (f->flags) return fail(MT_ERR_UNSUPPORTED, "the x + y top k takes no flags");
+    if (f->flags & ~MT_FLAG_XY_PAIRED)
+        return fail(MT_ERR_UNSUPPORTED, "the x + y top k takes no flag but MT_FLAG_XY_PAIRED");
     if (n < 1 || k < 0) return fail(MT_ERR_INVALID_ARG, "need n >= 1 and k >= 0 (n=%lld k=%d)", (long long)n, k);
+    if ((f->flags & MT_FLAG_XY_PAIRED) && k > kPairedMaxK)
+        return fail(MT_ERR_UNSUPPORTED, "the paired queue takes k <= %d (k=%d)", kPairedMaxK, k);
     if (2 * n - 1 > kLongConvN)
         return fail(MT_ERR_UNSUPPORTED, "2n - 1 = %lld exceeds %d", (long long)(2 * n - 1), kLongConvN);
     if (k > (1 << 24)) return fail(MT_ERR_UNSUPPORTED, "k above 2^24");
@@ -1028,7 +1041,7 @@ mt_status xy_topk_workspace_size(int64_t n, int32_t k, const mt_options* opt, si
     Family f;
     mt_status s = xy_check(n, k, opt, &f);
     if (s != MT_OK) return s;
-    *bytes = xy_layout(n, k, f.n).total;
+    *bytes = xy_layout(n, k, f.n, (f.flags & MT_FLAG_XY_PAIRED) != 0).total;
     return MT_OK;
 }
 
@@ -1042,7 +1055,8 @@ mt_status xy_topk_estimate(const void* x, const void* y, mt_dtype dtype, int64_t
     if (dtype != MT_F32 && dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     if (!x || !y) return fail(MT_ERR_INVALID_ARG, "x or y is NULL");
     if (k > 0 && !values) return fail(MT_ERR_INVALID_ARG, "values is NULL");
-    const XyLayout L = xy_layout(n, k, f.n);
+    const bool paired = (f.flags & MT_FLAG_XY_PAIRED) != 0;
+    const XyLayout L = xy_layout(n, k, f.n, paired);
     s = check_ws(workspace, ws_bytes, L.total);
     if (s != MT_OK) return s;
     MaxconvSpec spec{};
@@ -1053,8 +1067,10 @@ mt_status xy_topk_estimate(const void* x, const void* y, mt_dtype dtype, int64_t
     XyWorkspace w{(double*)(ws + L.sigma), (double*)(ws + L.psi), (double*)(ws + L.values1),
                   (int32_t*)(ws + L.diag0), (int32_t*)(ws + L.diag1),
                   L.tw ? (double2*)(ws + L.tw) : nullptr, L.mxy ? (double*)(ws + L.mxy) : nullptr,
-                  L.buf0 ? (double2*)(ws + L.buf0) : nullptr, L.buf1 ? (double2*)(ws + L.buf1) : nullptr};
-    MT_TRY(launch_xy_topk(x, y, dtype == MT_F64, n, k, spec, values, diag, i_idx, j_idx, w, (hipStream_t)stream),
+                  L.buf0 ? (double2*)(ws + L.buf0) : nullptr, L.buf1 ? (double2*)(ws + L.buf1) : nullptr,
+                  L.cand_m ? (int32_t*)(ws + L.cand_m) : nullptr, L.cand_psi ? (double*)(ws + L.cand_psi) : nullptr};
+    MT_TRY(launch_xy_topk(x, y, dtype == MT_F64, n, k, spec, paired, values, diag, i_idx, j_idx, w,
+                          (hipStream_t)stream),
            "x + y top k");
     return MT_OK;
 }

@@ -305,10 +305,15 @@ struct XyWorkspace {
     double* mxy;
     double2* buf0;
     double2* buf1;
+    // only for the paired queue: K = min(k, 2n - 1) candidates per run
+    int32_t* cand_m;   // 2 x K
+    double* cand_psi;  // 2 x K
 };
+// largest k of the paired queue (its candidates live in LDS)
+constexpr int kPairedMaxK = 4096;
 hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int32_t k, const MaxconvSpec& spec,
-                          double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
-                          hipStream_t st);
+                          bool paired, double* values, int32_t* diag, int32_t* ii, int32_t* jj,
+                          const XyWorkspace& w, hipStream_t st);
 
 // Exact (max, x) product on the vector ALUs.
 hipError_t launch_exact_maxtimes(const void* A, const void* B, int f64, int64_t b, int64_t m,

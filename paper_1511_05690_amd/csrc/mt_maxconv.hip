@@ -750,6 +750,261 @@ __global__ __launch_bounds__(256) void mt_xy_index_kernel(const int32_t* __restr
     if (jj) jj[r] = (int32_t)j;
 }
 
+// ---- the paired queue (Discussion) -------------------------------------
+//
+// Within k pops a run only ever pops diagonals among the K = min(k, 2n - 1)
+// largest initial estimates (lowest m on ties): an estimate changes only
+// when its diagonal is popped, so a diagonal's first pop takes the largest
+// never-popped estimate, and at most k diagonals are popped.  The paired
+// queue therefore works on those K candidates per run, held in LDS.
+
+constexpr int kSelThreads = 1024;
+constexpr int kSelPer = kLongConvN / kSelThreads;  // covers 2n - 1 < kLongConvN
+
+// Block-wide exclusive count of a flag over threads in thread order; *total
+// receives the block's count.  Every thread of the block calls it.
+__device__ __forceinline__ int block_count_before(bool flag, int* wtot, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t b = __ballot(flag);
+    const int within = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) wtot[wv] = __popcll(b);
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kSelThreads / 64; ++w2) {
+        const int t = wtot[w2];
+        all += t;
+        before += w2 < wv ? t : 0;
+    }
+    __syncthreads();
+    *total = all;
+    return before + within;
+}
+
+// The K candidates of each run (block = run): the K largest psi, lowest m
+// on ties, written in ascending m.  psi >= 0, so its bit pattern orders as
+// its value; the K-th largest key is found by an 8-bit radix select, then
+// the keys above it and the first keys equal to it (in m order) are kept.
+__global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double* __restrict__ psi, int L, int K,
+                                                                   int32_t* __restrict__ cand_m,
+                                                                   double* __restrict__ cand_psi) {
+    __shared__ uint32_t hist[256];
+    __shared__ int s_bin, s_above;
+    __shared__ int wtot[kSelThreads / 64];
+    const int tid = threadIdx.x, run = blockIdx.x, lane = tid & 63;
+    const double* ps = psi + (int64_t)run * L;
+    if (tid == 0) s_bin = s_above = 0;
+    uint64_t key[kSelPer];
+#pragma unroll
+    for (int c = 0; c < kSelPer; ++c) {
+        const int m = c * kSelThreads + tid;
+        key[c] = m < L ? (uint64_t)__double_as_longlong(ps[m]) : 0ull;
+    }
+    uint64_t prefix = 0, mask = 0;
+    int need = K;  // keys still to take among those matching prefix
+    for (int d = 7; d >= 0; --d) {
+        const int shift = 8 * d;
+        if (tid < 256) hist[tid] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kSelPer; ++c)
+            if (c * kSelThreads + tid < L && (key[c] & mask) == prefix)
+                atomicAdd(&hist[(key[c] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (tid < 64) {
+            // lane l holds bins 255 - 4l .. 252 - 4l (descending)
+            int h[4], tot = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                h[u] = (int)hist[255 - 4 * lane - u];
+                tot += h[u];
+            }
+            int inc = tot;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(inc, o);
+                if (lane >= o) inc += t;
+            }
+            const int exc = inc - tot;
+            if (exc < need && inc >= need) {
+                int cum = exc, b = -1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (b < 0) {
+                        if (cum + h[u] >= need)
+                            b = 255 - 4 * lane - u;
+                        else
+                            cum += h[u];
+                    }
+                }
+                s_bin = b;
+                s_above = cum;
+            }
+        }
+        __syncthreads();
+        prefix |= (uint64_t)s_bin << shift;
+        mask |= 255ull << shift;
+        need -= s_above;
+        __syncthreads();
+    }
+    int taken = 0, eq_seen = 0;
+#pragma unroll
+    for (int c = 0; c < kSelPer; ++c) {
+        const int m = c * kSelThreads + tid;
+        const bool ok = m < L;
+        const bool gt = ok && key[c] > prefix, eq = ok && key[c] == prefix;
+        int eq_total, take_total;
+        const int eq_before = block_count_before(eq, wtot, &eq_total);
+        const bool take = gt || (eq && eq_seen + eq_before < need);
+        const int pos = taken + block_count_before(take, wtot, &take_total);
+        if (take && pos < K) {
+            cand_m[(int64_t)run * K + pos] = m;
+            cand_psi[(int64_t)run * K + pos] = __longlong_as_double((long long)key[c]);
+        }
+        taken += take_total;
+        eq_seen += eq_total;
+    }
+}
+
+__device__ __forceinline__ int diag_len(int m, int n) { return (m < 2 * n - 2 - m ? m : 2 * n - 2 - m) + 1; }
+
+// The paired NormQueue (Discussion), one wave: each rank pops run 0
+// (diagonals i + j) and run 1 (anti-diagonals i + n - 1 - j) together; the
+// pair (i, j) they meet in is accurate when it lies in the grid, no earlier
+// rank reported it (a list in LDS, scanned by every lane), and its
+// scaled value v = e^(x_i - max x + y_j - max y) is at least psi len^(-1/p*)
+// on both diagonals (the smallest largest term their norms admit; none on a
+// diagonal without a stable p).  An
+// accurate rank reports x_i + y_j and (i, j) and subtracts v^p from both
+// runs' sigma; otherwise it reports run 0's estimate and i = j = -1, and each
+// run subtracts its own estimate.  Lanes 0..31 hold run 0's powers, lanes
+// 32..63 run 1's; candidate slot s of a run belongs to lane s % 64.
+template <typename T>
+__global__ __launch_bounds__(64) void mt_xy_paired_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                        int64_t n, MaxconvSpec spec, double* __restrict__ sigma,
+                                                        const int32_t* __restrict__ cand_m,
+                                                        const double* __restrict__ cand_psi, int K, int32_t k,
+                                                        double* __restrict__ values, int32_t* __restrict__ diag,
+                                                        int32_t* __restrict__ anti, int32_t* __restrict__ ii,
+                                                        int32_t* __restrict__ jj) {
+    extern __shared__ double cv[];  // 2K estimates, 2K diagonals, k reported pairs i n + j
+    int* cm = (int*)(cv + 2 * K);
+    int* done = cm + 2 * K;
+    int n_done = 0;
+    const int lane = threadIdx.x;
+    const int L = (int)(2 * n - 1), np = spec.n, nn = (int)n;
+    double mx = -INFINITY, my = -INFINITY;
+    for (int i = lane; i < nn; i += 64) {
+        mx = fmax(mx, (double)x[i]);
+        my = fmax(my, (double)y[i]);
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, d));
+        my = fmax(my, __shfl_xor(my, d));
+    }
+    const double shift = mx + my;
+    for (int s = lane; s < 2 * K; s += 64) {
+        cv[s] = cand_psi[s];
+        cm[s] = cand_m[s];
+    }
+    __syncthreads();
+    const int S = (K + 63) / 64;
+    auto lane_best = [&](int t, double& bv, int& bs) {
+        bv = -1.0;
+        bs = K;
+        for (int u = 0; u < S; ++u) {
+            const int s = u * 64 + lane;
+            if (s < K) {
+                const double e = cv[t * K + s];
+                if (e > bv) {
+                    bv = e;
+                    bs = s;
+                }
+            }
+        }
+    };
+    double bv0, bv1;
+    int bs0, bs1;
+    lane_best(0, bv0, bs0);
+    lane_best(1, bv1, bs1);
+    const int half = lane >> 5, q = lane & 31;
+    const bool mine = q < np;
+    for (int r = 0; r < k; ++r) {
+        double a0 = bv0, a1 = bv1;
+        int s0 = bs0, s1 = bs1;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const double o0 = __shfl_xor(a0, d), o1 = __shfl_xor(a1, d);
+            const int p0 = __shfl_xor(s0, d), p1 = __shfl_xor(s1, d);
+            if (o0 > a0 || (o0 == a0 && p0 < s0)) {
+                a0 = o0;
+                s0 = p0;
+            }
+            if (o1 > a1 || (o1 == a1 && p1 < s1)) {
+                a1 = o1;
+                s1 = p1;
+            }
+        }
+        const int m1 = cm[s0], m2 = cm[K + s1];
+        const int sd = m1 + m2 - (nn - 1);
+        const int i = sd >> 1, j = m1 - i;
+        bool valid = (sd & 1) == 0 && sd >= 0 && i < nn && j >= 0 && j < nn;
+        double* cp = sigma + (int64_t)half * np * L + (int64_t)q * L + (half ? m2 : m1);
+        double cell = 0.0, xi = 0.0, yj = 0.0;
+        if (mine) cell = *cp;
+        if (valid) {
+            xi = (double)x[i];
+            yj = (double)y[j];
+        }
+        const int id = i * nn + j;
+        bool seen = false;
+        if (valid)
+            for (int u = lane; u < n_done; u += 64) seen |= done[u] == id;
+        valid = valid && __ballot(seen) == 0;
+        const uint64_t st = __ballot(mine && cell >= spec.tau);
+        const uint32_t lo_b = (uint32_t)st, hi_b = (uint32_t)(st >> 32);
+        const int q0 = lo_b ? 31 - __clz(lo_b) : -1, q1 = hi_b ? 31 - __clz(hi_b) : -1;
+        const double v = exp((xi - mx) + (yj - my));
+        bool acc = valid;
+        if (acc) {
+            // a diagonal with no stable p has no estimate to judge a pair by
+            const double lo0 = q0 >= 0 ? a0 * pow((double)diag_len(m1, nn), -1.0 / (double)spec.p[q0]) : INFINITY;
+            const double lo1 = q1 >= 0 ? a1 * pow((double)diag_len(m2, nn), -1.0 / (double)spec.p[q1]) : INFINITY;
+            acc = v >= lo0 && v >= lo1;
+        }
+        const double sub = acc ? v : (half ? a1 : a0);
+        const double la = sub > 0.0 ? log(sub) : -INFINITY;
+        double s = 0.0;
+        bool ns = false;
+        if (mine) {
+            s = cell - exp(la * (double)spec.p[q]);
+            *cp = s;
+            ns = s >= spec.tau;
+        }
+        const uint64_t nm = __ballot(ns);
+        const uint32_t nlo = (uint32_t)nm, nhi = (uint32_t)(nm >> 32);
+        const int h0 = nlo ? 31 - __clz(nlo) : -1, h1 = nhi ? 31 - __clz(nhi) : -1;
+        const double sh0 = __shfl(s, h0 >= 0 ? h0 : 0), sh1 = __shfl(s, h1 >= 0 ? 32 + h1 : 32);
+        const double e0 = h0 >= 0 ? exp(log(sh0) / (double)spec.p[h0]) : 0.0;
+        const double e1 = h1 >= 0 ? exp(log(sh1) / (double)spec.p[h1]) : 0.0;
+        if (lane == 0) {
+            values[r] = acc ? xi + yj : shift + (a0 > 0.0 ? log(a0) : -INFINITY);
+            if (diag) diag[r] = m1;
+            anti[r] = m2;
+            if (ii) ii[r] = acc ? i : -1;
+            if (jj) jj[r] = acc ? j : -1;
+            if (acc) done[n_done] = id;
+        }
+        n_done += acc ? 1 : 0;
+        if (lane == (s0 & 63)) {
+            cv[s0] = e0;
+            lane_best(0, bv0, bs0);
+        }
+        if (lane == (s1 & 63)) {
+            cv[K + s1] = e1;
+            lane_best(1, bv1, bs1);
+        }
+    }
+}
+
 // Long transforms (N up to kLongConvN) for the x + y ring results: every
 // (run, p) transform in a global buffer [slot][N], one thread per radix-R
 // butterfly of a Stockham pass, the passes ordered by kernel boundaries.
@@ -1204,8 +1459,38 @@ hipError_t launch_xy_long(const T* x, const T* y, int64_t n, const MaxconvSpec& 
 }
 
 template <typename T>
-hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const MaxconvSpec& spec, double* values,
-                       int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w, hipStream_t st) {
+hipError_t launch_xy_paired(const T* x, const T* y, int64_t n, int32_t k, const MaxconvSpec& spec, double* values,
+                            int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w, hipStream_t st) {
+    const int L = (int)(2 * n - 1), K = k < L ? k : L;
+    if (K > kPairedMaxK || L >= kLongConvN) return hipErrorInvalidValue;
+    timing_before("mt_xy_select", st);
+    hipLaunchKernelGGL(mt_xy_select_kernel, dim3(2), dim3(kSelThreads), 0, st, w.psi, L, K, w.cand_m, w.cand_psi);
+    timing_after(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    auto queue = mt_xy_paired_kernel<T>;
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_set.load() & bit)) {
+        e = hipFuncSetAttribute((const void*)queue, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                2 * kPairedMaxK * (int)(sizeof(double) + sizeof(int)) + kPairedMaxK * (int)sizeof(int));
+        if (e != hipSuccess) return e;
+        attr_set.fetch_or(bit);
+    }
+    timing_before("mt_xy_paired", st);
+    const size_t lds = (size_t)2 * K * (sizeof(double) + sizeof(int)) + (size_t)k * sizeof(int);
+    hipLaunchKernelGGL(queue, dim3(1), dim3(64), lds, st, x, y, n, spec, w.sigma, w.cand_m, w.cand_psi, K, k, values,
+                       diag, w.diag1, ii, jj);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const MaxconvSpec& spec, bool paired,
+                       double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
+                       hipStream_t st) {
     hipError_t e = hipErrorInvalidValue;
     switch (maxconv_log_size(n, n)) {
         case 4: e = launch_xy_sigma_n<T, 4>(x, y, n, spec, w.sigma, st); break;
@@ -1230,6 +1515,7 @@ hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const Maxco
     timing_after(st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (paired) return launch_xy_paired<T>(x, y, n, k, spec, values, diag, ii, jj, w, st);
     // psi of one run in LDS: up to 8 (kLongConvN - 1) bytes
     auto queue = mt_xy_queue_kernel<T>;
     static std::atomic<uint64_t> attr_set{0};
@@ -1275,13 +1561,14 @@ hipError_t launch_maxconv(const void* x, const void* y, int f64, int64_t b, int6
 }
 
 hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int32_t k, const MaxconvSpec& spec,
-                          double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
-                          hipStream_t st) {
+                          bool paired, double* values, int32_t* diag, int32_t* ii, int32_t* jj,
+                          const XyWorkspace& w, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (maxconv_log_size(n, n) > kLongConvLog) return hipErrorInvalidValue;
     if (f64)
-        return launch_xy_t<double>((const double*)x, (const double*)y, n, k, spec, values, diag, ii, jj, w, st);
-    return launch_xy_t<float>((const float*)x, (const float*)y, n, k, spec, values, diag, ii, jj, w, st);
+        return launch_xy_t<double>((const double*)x, (const double*)y, n, k, spec, paired, values, diag, ii, jj, w,
+                                   st);
+    return launch_xy_t<float>((const float*)x, (const float*)y, n, k, spec, paired, values, diag, ii, jj, w, st);
 }
 
 hipError_t launch_maxconv_exact(const void* x, const void* y, int f64, int64_t b, int64_t n, int64_t m,

@@ -261,7 +261,8 @@ def test_maxconv_validation():
 
 def test_xy_topk_validation():
     """Argument checks of the x + y top-k entry points (no GPU): FP64 path
-    only, no flags, 2n - 1 <= 16384, k >= 0, workspace size, NULL pointers."""
+    only, no flag but the paired one (k <= 4096 with it), 2n - 1 <= 16384,
+    k >= 0, workspace size, NULL pointers."""
     lib = mt.load_library()
     o = _opts(list(mt.XY_FAMILY), path=0)
     nb = ctypes.c_size_t(0)
@@ -273,6 +274,17 @@ def test_xy_topk_validation():
     assert lib.xy_topk_workspace_size(8, -1, ctypes.byref(o), ctypes.byref(nb)) == 1
     assert lib.xy_topk_workspace_size(8, 4, ctypes.byref(_opts([1, 2], path=1)), ctypes.byref(nb)) == 5
     assert lib.xy_topk_workspace_size(8, 4, ctypes.byref(_opts([1, 2], path=0, flags=1)), ctypes.byref(nb)) == 5
+    # the paired queue: k <= 4096, room for 2 min(k, 2n - 1) candidates, and
+    # its flag is for this entry point only
+    paired = _opts(list(mt.XY_FAMILY), path=0, flags=mt.FLAG_XY_PAIRED)
+    plain_nb = ctypes.c_size_t(0)
+    assert lib.xy_topk_workspace_size(1024, 256, ctypes.byref(paired), ctypes.byref(nb)) == 0
+    assert lib.xy_topk_workspace_size(1024, 256, ctypes.byref(o), ctypes.byref(plain_nb)) == 0
+    assert nb.value >= plain_nb.value + 2 * 256 * 12
+    assert lib.xy_topk_workspace_size(8192, 4096, ctypes.byref(paired), ctypes.byref(nb)) == 0
+    assert lib.xy_topk_workspace_size(8192, 4097, ctypes.byref(paired), ctypes.byref(nb)) == 5
+    assert "k <= 4096" in lib.maxtimes_last_error().decode()
+    assert lib.maxconv_workspace_size(1, 8, 8, ctypes.byref(paired), ctypes.byref(nb)) == 1
     fake = ctypes.c_void_p(0x100000)
     null = ctypes.c_void_p(0)
     assert lib.xy_topk_estimate(null, fake, 0, 8, 4, ctypes.byref(o), fake, null, null, null, fake, 1 << 30,
