@@ -249,32 +249,42 @@ def run_legs(mt, torch, np):
     torch.cuda.empty_cache()
 
     # top k of x + y (Sec. 2.3, the n = 8192, k = 256 case of Sec. 3): uniform
-    # lists on [0, 1], the 24-power family up to 4096; exact top k on the GPU
-    # by torch over all n^2 sums, for the accuracy columns
-    rng = np.random.default_rng(5005)
+    # lists on [0, 1] and on [0, 40], the 24-power family up to 4096, the
+    # plain queue and the paired one (Discussion); exact top k on the GPU by
+    # torch over all n^2 sums, for the accuracy columns
     nx, kx = 8192, 256
-    xs = torch.from_numpy(rng.uniform(0, 1, nx)).cuda()
-    ys = torch.from_numpy(rng.uniform(0, 1, nx)).cuda()
-    mt.timing_reset()
-    mt.timing_enable(True)
-    ms = time_call(lambda: mt.xy_topk(xs, ys, kx), 3, torch)
-    parts = {name: mt.timing_read(name)[0] / 4 for name in ("mt_xy_sigma", "mt_xy_psi", "mt_xy_queue", "mt_xy_index")}
-    mt.timing_enable(False)
-    v, ii, jj = mt.xy_topk(xs, ys, kx)
-    sums = (xs[:, None] + ys[None, :]).flatten()
-    ms_naive = time_call(lambda: torch.topk((xs[:, None] + ys[None, :]).flatten(), kx), 3, torch)
-    ev, eidx = torch.topk(sums, kx)
-    ei, ej = (eidx // nx).int(), (eidx % nx).int()
-    found = int(((ii == ei) & (jj == ej)).sum())
-    in_set = int(torch.isin(ii.long() * nx + jj.long(), eidx).sum())
-    legs["xy_topk_8192_k256_fp64"] = {
-        "ms": ms, "n": nx, "k": kx, "P": list(mt.XY_FAMILY), "kernel_ms": parts,
-        "naive_gpu_topk_ms": ms_naive,
-        "vs_exact": {"indices_found_at_rank": found, "true_top_k_pairs_found": in_set, "k": kx,
-                     "max_abs_value_err_first_16": float((v[:16] - ev[:16]).abs().max()),
-                     "max_abs_value_err": float((v - ev).abs().max())},
-    }
-    del xs, ys, sums
+
+    def lists(spread):
+        rng = np.random.default_rng(5005)
+        return (torch.from_numpy(rng.uniform(0, spread, nx)).cuda(),
+                torch.from_numpy(rng.uniform(0, spread, nx)).cuda())
+
+    def accuracy(xs, ys, paired):
+        v, ii, jj = mt.xy_topk(xs, ys, kx, paired=paired)
+        ev, eidx = torch.topk((xs[:, None] + ys[None, :]).flatten(), kx)
+        ei, ej = (eidx // nx).int(), (eidx % nx).int()
+        return {"indices_found_at_rank": int(((ii == ei) & (jj == ej)).sum()),
+                "true_top_k_pairs_found": int(torch.isin(ii.long() * nx + jj.long(), eidx).sum()), "k": kx,
+                "max_abs_value_err_first_16": float((v[:16] - ev[:16]).abs().max()),
+                "max_abs_value_err": float((v - ev).abs().max())}
+
+    xs, ys = lists(1)
+    leg = {"n": nx, "k": kx, "P": list(mt.XY_FAMILY)}
+    for paired, tag in ((False, ""), (True, "paired_")):
+        mt.timing_reset()
+        mt.timing_enable(True)
+        leg[tag + "ms"] = time_call(lambda: mt.xy_topk(xs, ys, kx, paired=paired), 3, torch)
+        names = ("mt_xy_sigma", "mt_xy_psi", "mt_xy_select", "mt_xy_paired" if paired else "mt_xy_queue")
+        leg[tag + "kernel_ms"] = {name: mt.timing_read(name)[0] / 4 for name in names}
+        mt.timing_enable(False)
+    leg["naive_gpu_topk_ms"] = time_call(lambda: torch.topk((xs[:, None] + ys[None, :]).flatten(), kx), 3, torch)
+    for spread in (1, 40):
+        xs, ys = lists(spread)
+        for paired, tag in ((False, ""), (True, "paired_")):
+            leg[f"{tag}vs_exact_uniform_0_{spread}"] = accuracy(xs, ys, paired)
+    legs["xy_topk_8192_k256_fp64"] = leg
+    del xs, ys
+    torch.cuda.empty_cache()
 
     c5 = config(5)
     W5 = torch.from_numpy(c5["W"]).cuda()

@@ -366,12 +366,15 @@ mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b,
  * 1 <= n <= 8192 (2n - 1 <= 16384; up to n = 2048 each transform runs in
  * one workgroup's LDS, longer ones through global buffers in the workspace),
  * 0 <= k <= 2^24 (else MT_ERR_UNSUPPORTED / MT_ERR_INVALID_ARG).
- * The pops run on one wave per run, in sequence (paired: one wave for both
- * runs, over the min(k, 2n - 1) diagonals with the largest initial
- * estimates, the only ones k pops can reach).  Workspace from
- * xy_topk_workspace_size (16 (|P| + 1)(2n - 1) + 16 k bytes and alignment, plus
- * 64 |P| N + 2 N bytes for the global buffers when n > 2048, N the transform
- * length, plus 24 min(k, 2n - 1) bytes for the paired candidates).  With
+ * The pops run in sequence on one wave.  For k <= 4096 it pops both runs
+ * together over the K = min(k, 2n - 1) diagonals of each run with the
+ * largest initial estimates (lowest m on ties: the only ones k pops can
+ * reach), their sigma columns in LDS when 40 K + 16 |P| K + 4 k bytes fit in
+ * 160 KiB; for larger k one wave per run scans every diagonal.  Workspace
+ * from xy_topk_workspace_size (16 (|P| + 1)(2n - 1) + 16 k bytes and
+ * alignment, plus 64 |P| N + 2 N bytes for the global buffers when n > 2048,
+ * N the transform length, plus (24 + 16 |P|) K bytes for the candidates when
+ * k <= 4096).  With
  * k = 0 only the ring results are formed: the workspace then starts with
  * sigma^(p)[m] of both runs, FP64, indexed (run |P| + q)(2n - 1) + m (run 1
  * on y reversed), for inspection.  Asynchronous on the stream.

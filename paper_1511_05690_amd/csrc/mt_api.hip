@@ -979,9 +979,9 @@ mt_status maxconv_exact(const void* x, const void* y, mt_dtype dtype, int64_t b,
 // Workspace of xy_topk_estimate: the ring results of both runs, then the
 // second run's values and both runs' diagonals.
 struct XyLayout {
-    size_t sigma, psi, values1, diag0, diag1, tw, mxy, buf0, buf1, cand_m, cand_psi, total;
+    size_t sigma, psi, values1, diag0, diag1, tw, mxy, buf0, buf1, cand_m, cand_psi, cand_cols, total;
 };
-XyLayout xy_layout(int64_t n, int32_t k, int n_p, bool paired) {
+XyLayout xy_layout(int64_t n, int32_t k, int n_p) {
     XyLayout L{};
     const int64_t len = 2 * n - 1;
     size_t off = 0;
@@ -1008,13 +1008,15 @@ XyLayout xy_layout(int64_t n, int32_t k, int n_p, bool paired) {
         L.buf1 = off;
         off += (size_t)round_up(2 * (int64_t)n_p * N * 16, kAlign);
     }
-    L.cand_m = L.cand_psi = 0;
-    if (paired && k > 0) {
+    L.cand_m = L.cand_psi = L.cand_cols = 0;
+    if (k > 0 && k <= kPairedMaxK) {
         const int64_t K = k < len ? k : len;
         L.cand_m = off;
         off += (size_t)round_up(2 * K * 4, kAlign);
         L.cand_psi = off;
         off += (size_t)round_up(2 * K * 8, kAlign);
+        L.cand_cols = off;
+        off += (size_t)round_up(2 * (int64_t)n_p * K * 8, kAlign);
     }
     L.total = off;
     return L;
@@ -1041,7 +1043,7 @@ mt_status xy_topk_workspace_size(int64_t n, int32_t k, const mt_options* opt, si
     Family f;
     mt_status s = xy_check(n, k, opt, &f);
     if (s != MT_OK) return s;
-    *bytes = xy_layout(n, k, f.n, (f.flags & MT_FLAG_XY_PAIRED) != 0).total;
+    *bytes = xy_layout(n, k, f.n).total;
     return MT_OK;
 }
 
@@ -1056,7 +1058,7 @@ mt_status xy_topk_estimate(const void* x, const void* y, mt_dtype dtype, int64_t
     if (!x || !y) return fail(MT_ERR_INVALID_ARG, "x or y is NULL");
     if (k > 0 && !values) return fail(MT_ERR_INVALID_ARG, "values is NULL");
     const bool paired = (f.flags & MT_FLAG_XY_PAIRED) != 0;
-    const XyLayout L = xy_layout(n, k, f.n, paired);
+    const XyLayout L = xy_layout(n, k, f.n);
     s = check_ws(workspace, ws_bytes, L.total);
     if (s != MT_OK) return s;
     MaxconvSpec spec{};
@@ -1068,7 +1070,8 @@ mt_status xy_topk_estimate(const void* x, const void* y, mt_dtype dtype, int64_t
                   (int32_t*)(ws + L.diag0), (int32_t*)(ws + L.diag1),
                   L.tw ? (double2*)(ws + L.tw) : nullptr, L.mxy ? (double*)(ws + L.mxy) : nullptr,
                   L.buf0 ? (double2*)(ws + L.buf0) : nullptr, L.buf1 ? (double2*)(ws + L.buf1) : nullptr,
-                  L.cand_m ? (int32_t*)(ws + L.cand_m) : nullptr, L.cand_psi ? (double*)(ws + L.cand_psi) : nullptr};
+                  L.cand_m ? (int32_t*)(ws + L.cand_m) : nullptr, L.cand_psi ? (double*)(ws + L.cand_psi) : nullptr,
+                  L.cand_cols ? (double*)(ws + L.cand_cols) : nullptr};
     MT_TRY(launch_xy_topk(x, y, dtype == MT_F64, n, k, spec, paired, values, diag, i_idx, j_idx, w,
                           (hipStream_t)stream),
            "x + y top k");

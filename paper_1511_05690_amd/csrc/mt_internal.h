@@ -305,11 +305,13 @@ struct XyWorkspace {
     double* mxy;
     double2* buf0;
     double2* buf1;
-    // only for the paired queue: K = min(k, 2n - 1) candidates per run
-    int32_t* cand_m;   // 2 x K
-    double* cand_psi;  // 2 x K
+    // k <= kPairedMaxK: K = min(k, 2n - 1) candidates per run
+    int32_t* cand_m;    // 2 x K
+    double* cand_psi;   // 2 x K
+    double* cand_cols;  // 2 x n_p x K: the candidates' sigma columns
 };
-// largest k of the paired queue (its candidates live in LDS)
+// largest k of the queue over candidates (their estimates live in LDS); the
+// paired queue needs it, the plain one falls back to every diagonal above
 constexpr int kPairedMaxK = 4096;
 hipError_t launch_xy_topk(const void* x, const void* y, int f64, int64_t n, int32_t k, const MaxconvSpec& spec,
                           bool paired, double* values, int32_t* diag, int32_t* ii, int32_t* jj,

@@ -42,6 +42,7 @@
 // index, products in the input precision.
 
 #include <atomic>
+#include <climits>
 
 #include "mt_internal.h"
 
@@ -614,6 +615,67 @@ __global__ __launch_bounds__(256) void mt_xy_psi_kernel(const double* __restrict
     psi[g] = qh >= 0 ? pow(sh, 1.0 / (double)spec.p[qh]) : 0.0;
 }
 
+// ---- wave-wide argmax for the queues ----------------------------------
+//
+// DPP row shifts and row broadcasts (register moves between lanes, no LDS
+// round trip) carry the maximum to lane 63 in six steps; lanes a move has no
+// source for keep their own value, the identity of max.
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_i32(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, kCtrl, kRowMask, 0xf, false);
+}
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_i32<kCtrl, kRowMask>((int)b);
+    const int hi = dpp_i32<kCtrl, kRowMask>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// row_shr:1, 2, 4, 8 leave each row's maximum in its lane 15; row_bcast:15
+// into rows 1 and 3 and row_bcast:31 into rows 2 and 3 bring all four to
+// lane 63.
+__device__ __forceinline__ double wave_max_f64(double m) {
+    m = fmax(m, dpp_f64<0x111, 0xf>(m));
+    m = fmax(m, dpp_f64<0x112, 0xf>(m));
+    m = fmax(m, dpp_f64<0x114, 0xf>(m));
+    m = fmax(m, dpp_f64<0x118, 0xf>(m));
+    m = fmax(m, dpp_f64<0x142, 0xa>(m));
+    m = fmax(m, dpp_f64<0x143, 0xc>(m));
+    return readlane_f64(m, 63);
+}
+
+__device__ __forceinline__ int wave_min_i32(int m) {
+    m = min(m, dpp_i32<0x111, 0xf>(m));
+    m = min(m, dpp_i32<0x112, 0xf>(m));
+    m = min(m, dpp_i32<0x114, 0xf>(m));
+    m = min(m, dpp_i32<0x118, 0xf>(m));
+    m = min(m, dpp_i32<0x142, 0xa>(m));
+    m = min(m, dpp_i32<0x143, 0xc>(m));
+    return __builtin_amdgcn_readlane(m, 63);
+}
+
+// The largest v over the wave and, among the lanes holding it, the smallest
+// s; every lane receives both.  v must not be NaN.
+__device__ __forceinline__ void wave_argmax(double& v, int& s) {
+    const double vm = wave_max_f64(v);
+    const uint64_t tied = __ballot(v == vm);
+    if (__popcll(tied) == 1)
+        s = __builtin_amdgcn_readlane(s, (int)__ffsll((unsigned long long)tied) - 1);
+    else
+        s = wave_min_i32(v == vm ? s : INT_MAX);
+    v = vm;
+}
+
 constexpr int kQueueGroups = 16;
 
 // The NormQueue of Sec. 2.3 for one run (block = run), one wave: psi[m] is the
@@ -694,14 +756,7 @@ __global__ __launch_bounds__(64) void mt_xy_queue_kernel(const T* __restrict__ x
     for (int r = 0; r < k; ++r) {
         double a = bv;
         int ms = bm;
-        for (int d = 32; d >= 1; d >>= 1) {
-            const double oa = __shfl_xor(a, d);
-            const int om = __shfl_xor(ms, d);
-            if (oa > a || (oa == a && om < ms)) {
-                a = oa;
-                ms = om;
-            }
-        }
+        wave_argmax(a, ms);
         // log psi once for the value and every power (psi = 0: -inf, power 0)
         const double la = a > 0.0 ? log(a) : -INFINITY;
         if (lane == 0) {
@@ -720,7 +775,7 @@ __global__ __launch_bounds__(64) void mt_xy_queue_kernel(const T* __restrict__ x
         double e = 0.0;
         if (mask) {
             const int qh = 63 - __clzll(mask);
-            e = exp(log(__shfl(s, qh)) / (double)spec.p[qh]);
+            e = exp(log(__shfl(s, qh)) * (1.0 / (double)spec.p[qh]));
         }
         if (lane == 0) psi[ms] = e;
         __syncthreads();
@@ -782,15 +837,19 @@ __device__ __forceinline__ int block_count_before(bool flag, int* wtot, int* tot
 }
 
 // The K candidates of each run (block = run): the K largest psi, lowest m
-// on ties, written in ascending m.  psi >= 0, so its bit pattern orders as
+// on ties, written in ascending m with their sigma columns
+// (cand_cols[(run np + q) K + slot]).  psi >= 0, so its bit pattern orders as
 // its value; the K-th largest key is found by an 8-bit radix select, then
 // the keys above it and the first keys equal to it (in m order) are kept.
 __global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double* __restrict__ psi, int L, int K,
+                                                                   const double* __restrict__ sigma, int np,
                                                                    int32_t* __restrict__ cand_m,
-                                                                   double* __restrict__ cand_psi) {
+                                                                   double* __restrict__ cand_psi,
+                                                                   double* __restrict__ cand_cols) {
     __shared__ uint32_t hist[256];
     __shared__ int s_bin, s_above;
     __shared__ int wtot[kSelThreads / 64];
+    __shared__ int taken_m[kPairedMaxK];
     const int tid = threadIdx.x, run = blockIdx.x, lane = tid & 63;
     const double* ps = psi + (int64_t)run * L;
     if (tid == 0) s_bin = s_above = 0;
@@ -859,39 +918,60 @@ __global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double*
         if (take && pos < K) {
             cand_m[(int64_t)run * K + pos] = m;
             cand_psi[(int64_t)run * K + pos] = __longlong_as_double((long long)key[c]);
+            taken_m[pos] = m;
         }
         taken += take_total;
         eq_seen += eq_total;
+    }
+    __syncthreads();
+    // the candidates' columns, every thread gathering (q, slot) cells
+    const double* sg = sigma + (int64_t)run * np * L;
+    double* cc = cand_cols + (int64_t)run * np * K;
+    for (int u = tid; u < np * K; u += kSelThreads) {
+        const int q = u / K, slot = u - q * K;
+        cc[u] = sg[(int64_t)q * L + taken_m[slot]];
     }
 }
 
 __device__ __forceinline__ int diag_len(int m, int n) { return (m < 2 * n - 2 - m ? m : 2 * n - 2 - m) + 1; }
 
-// The paired NormQueue (Discussion), one wave: each rank pops run 0
-// (diagonals i + j) and run 1 (anti-diagonals i + n - 1 - j) together; the
-// pair (i, j) they meet in is accurate when it lies in the grid, no earlier
-// rank reported it (a list in LDS, scanned by every lane), and its
-// scaled value v = e^(x_i - max x + y_j - max y) is at least psi len^(-1/p*)
-// on both diagonals (the smallest largest term their norms admit; none on a
-// diagonal without a stable p).  An
-// accurate rank reports x_i + y_j and (i, j) and subtracts v^p from both
-// runs' sigma; otherwise it reports run 0's estimate and i = j = -1, and each
-// run subtracts its own estimate.  Lanes 0..31 hold run 0's powers, lanes
-// 32..63 run 1's; candidate slot s of a run belongs to lane s % 64.
-template <typename T>
-__global__ __launch_bounds__(64) void mt_xy_paired_kernel(const T* __restrict__ x, const T* __restrict__ y,
-                                                        int64_t n, MaxconvSpec spec, double* __restrict__ sigma,
-                                                        const int32_t* __restrict__ cand_m,
-                                                        const double* __restrict__ cand_psi, int K, int32_t k,
-                                                        double* __restrict__ values, int32_t* __restrict__ diag,
-                                                        int32_t* __restrict__ anti, int32_t* __restrict__ ii,
-                                                        int32_t* __restrict__ jj) {
-    extern __shared__ double cv[];  // 2K estimates, 2K diagonals, k reported pairs i n + j
-    int* cm = (int*)(cv + 2 * K);
+// Both runs' NormQueues in lockstep, one wave, over the candidates: each
+// rank pops run 0 (diagonals i + j) and run 1 (anti-diagonals
+// i + n - 1 - j) together.  Plain (Sec. 2.3): each run subtracts its own
+// estimate and the indices are recovered from the two diagonals.  Paired
+// (Discussion): the pair (i, j) the two diagonals meet in is accurate when it
+// lies in the grid, no earlier rank reported it (a list in LDS, scanned by
+// every lane), and its scaled value v = e^(x_i - max x + y_j - max y) is at
+// least psi len^(-1/p*) on both diagonals (the smallest largest term their
+// norms admit; none on a diagonal without a stable p); an accurate rank
+// reports x_i + y_j and (i, j) and subtracts v^p from both runs, any other
+// reports run 0's estimate and i = j = -1, and each run subtracts its own
+// estimate.  Lanes 0..31 hold run 0's powers, lanes 32..63 run 1's;
+// candidate slot s of a run belongs to lane s % 64.  The candidates' sigma
+// columns are updated in LDS when they fit (kColsLds), else in the
+// workspace copy.
+template <typename T, bool kPaired, bool kColsLds>
+__global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                          int64_t n, MaxconvSpec spec,
+                                                          const int32_t* __restrict__ cand_m,
+                                                          const double* __restrict__ cand_psi,
+                                                          double* __restrict__ cand_cols, int K, int32_t k,
+                                                          double* __restrict__ values, int32_t* __restrict__ diag,
+                                                          int32_t* __restrict__ anti, int32_t* __restrict__ ii,
+                                                          int32_t* __restrict__ jj) {
+    // LDS: 2K log estimates, 2K log diagonal lengths, [2 np K column cells],
+    // 2K diagonals, k reported pairs.  The queue keeps log psi: the argmax
+    // order is psi's, the reported value needs the log, the subtraction
+    // exp(p log psi) and the new root exp(log S / p) then need no log or exp
+    // of their own.
+    extern __shared__ double cv[];
+    const int lane = threadIdx.x;
+    const int np = spec.n, nn = (int)n;
+    double* cl = cv + 2 * K;
+    double* cols = kColsLds ? cv + 4 * K : cand_cols;
+    int* cm = (int*)(cv + 4 * K + (kColsLds ? 2 * np * K : 0));
     int* done = cm + 2 * K;
     int n_done = 0;
-    const int lane = threadIdx.x;
-    const int L = (int)(2 * n - 1), np = spec.n, nn = (int)n;
     double mx = -INFINITY, my = -INFINITY;
     for (int i = lane; i < nn; i += 64) {
         mx = fmax(mx, (double)x[i]);
@@ -903,19 +983,26 @@ __global__ __launch_bounds__(64) void mt_xy_paired_kernel(const T* __restrict__ 
     }
     const double shift = mx + my;
     for (int s = lane; s < 2 * K; s += 64) {
-        cv[s] = cand_psi[s];
-        cm[s] = cand_m[s];
+        const double e = cand_psi[s];
+        const int m = cand_m[s];
+        cv[s] = e > 0.0 ? log(e) : -INFINITY;
+        cl[s] = log((double)diag_len(m, nn));
+        cm[s] = m;
     }
+    if (kColsLds)
+        for (int s = lane; s < 2 * np * K; s += 64) cols[s] = cand_cols[s];
     __syncthreads();
     const int S = (K + 63) / 64;
+    // the lane's largest log psi and its slot (the first valid slot always
+    // counts, so a run whose estimates are all -inf still names its lowest)
     auto lane_best = [&](int t, double& bv, int& bs) {
-        bv = -1.0;
+        bv = -INFINITY;
         bs = K;
         for (int u = 0; u < S; ++u) {
             const int s = u * 64 + lane;
             if (s < K) {
                 const double e = cv[t * K + s];
-                if (e > bv) {
+                if (bs == K || e > bv) {
                     bv = e;
                     bs = s;
                 }
@@ -923,84 +1010,81 @@ __global__ __launch_bounds__(64) void mt_xy_paired_kernel(const T* __restrict__ 
         }
     };
     double bv0, bv1;
-    int bs0, bs1;
+    int bs0, bs1, bm0, bm1;
     lane_best(0, bv0, bs0);
     lane_best(1, bv1, bs1);
+    bm0 = bs0 < K ? cm[bs0] : 0;
+    bm1 = bs1 < K ? cm[K + bs1] : 0;
     const int half = lane >> 5, q = lane & 31;
     const bool mine = q < np;
+    // this lane's power and its reciprocal; a rank picks other lanes' by readlane
+    const double pw = mine ? (double)spec.p[q] : 1.0, ipw = 1.0 / pw;
     for (int r = 0; r < k; ++r) {
         double a0 = bv0, a1 = bv1;
         int s0 = bs0, s1 = bs1;
-        for (int d = 32; d >= 1; d >>= 1) {
-            const double o0 = __shfl_xor(a0, d), o1 = __shfl_xor(a1, d);
-            const int p0 = __shfl_xor(s0, d), p1 = __shfl_xor(s1, d);
-            if (o0 > a0 || (o0 == a0 && p0 < s0)) {
-                a0 = o0;
-                s0 = p0;
-            }
-            if (o1 > a1 || (o1 == a1 && p1 < s1)) {
-                a1 = o1;
-                s1 = p1;
-            }
-        }
-        const int m1 = cm[s0], m2 = cm[K + s1];
+        wave_argmax(a0, s0);
+        wave_argmax(a1, s1);
+        const int m1 = __builtin_amdgcn_readlane(bm0, s0 & 63), m2 = __builtin_amdgcn_readlane(bm1, s1 & 63);
         const int sd = m1 + m2 - (nn - 1);
         const int i = sd >> 1, j = m1 - i;
         bool valid = (sd & 1) == 0 && sd >= 0 && i < nn && j >= 0 && j < nn;
-        double* cp = sigma + (int64_t)half * np * L + (int64_t)q * L + (half ? m2 : m1);
-        double cell = 0.0, xi = 0.0, yj = 0.0;
+        double* cp = cols + (half * np + q) * K + (half ? s1 : s0);
+        double cell = 0.0;
         if (mine) cell = *cp;
-        if (valid) {
-            xi = (double)x[i];
-            yj = (double)y[j];
-        }
+        const double la0 = a0, la1 = a1;
+        bool acc = false;
+        double xi = 0.0, yj = 0.0, lv = 0.0;
         const int id = i * nn + j;
-        bool seen = false;
-        if (valid)
-            for (int u = lane; u < n_done; u += 64) seen |= done[u] == id;
-        valid = valid && __ballot(seen) == 0;
-        const uint64_t st = __ballot(mine && cell >= spec.tau);
-        const uint32_t lo_b = (uint32_t)st, hi_b = (uint32_t)(st >> 32);
-        const int q0 = lo_b ? 31 - __clz(lo_b) : -1, q1 = hi_b ? 31 - __clz(hi_b) : -1;
-        const double v = exp((xi - mx) + (yj - my));
-        bool acc = valid;
-        if (acc) {
-            // a diagonal with no stable p has no estimate to judge a pair by
-            const double lo0 = q0 >= 0 ? a0 * pow((double)diag_len(m1, nn), -1.0 / (double)spec.p[q0]) : INFINITY;
-            const double lo1 = q1 >= 0 ? a1 * pow((double)diag_len(m2, nn), -1.0 / (double)spec.p[q1]) : INFINITY;
-            acc = v >= lo0 && v >= lo1;
+        if (kPaired) {
+            if (valid) {
+                xi = (double)x[i];
+                yj = (double)y[j];
+            }
+            bool seen = false;
+            if (valid)
+                for (int u = lane; u < n_done; u += 64) seen |= done[u] == id;
+            valid = valid && __ballot(seen) == 0;
+            const uint64_t st = __ballot(mine && cell >= spec.tau);
+            const uint32_t lo_b = (uint32_t)st, hi_b = (uint32_t)(st >> 32);
+            const int q0 = lo_b ? 31 - __clz(lo_b) : -1, q1 = hi_b ? 31 - __clz(hi_b) : -1;
+            // in logs: log v >= log psi - log(len) / p* on both diagonals
+            lv = (xi - mx) + (yj - my);
+            acc = valid && q0 >= 0 && q1 >= 0 && lv >= la0 - cl[s0] * readlane_f64(ipw, q0 >= 0 ? q0 : 0) &&
+                  lv >= la1 - cl[K + s1] * readlane_f64(ipw, q1 >= 0 ? 32 + q1 : 32);
         }
-        const double sub = acc ? v : (half ? a1 : a0);
-        const double la = sub > 0.0 ? log(sub) : -INFINITY;
+        const double la = acc ? lv : (half ? la1 : la0);
         double s = 0.0;
         bool ns = false;
         if (mine) {
-            s = cell - exp(la * (double)spec.p[q]);
+            s = cell - exp(la * pw);
             *cp = s;
             ns = s >= spec.tau;
         }
         const uint64_t nm = __ballot(ns);
         const uint32_t nlo = (uint32_t)nm, nhi = (uint32_t)(nm >> 32);
         const int h0 = nlo ? 31 - __clz(nlo) : -1, h1 = nhi ? 31 - __clz(nhi) : -1;
-        const double sh0 = __shfl(s, h0 >= 0 ? h0 : 0), sh1 = __shfl(s, h1 >= 0 ? 32 + h1 : 32);
-        const double e0 = h0 >= 0 ? exp(log(sh0) / (double)spec.p[h0]) : 0.0;
-        const double e1 = h1 >= 0 ? exp(log(sh1) / (double)spec.p[h1]) : 0.0;
+        const int l0 = h0 >= 0 ? h0 : 0, l1 = h1 >= 0 ? 32 + h1 : 32;
+        const double e0 = h0 >= 0 ? log(readlane_f64(s, l0)) * readlane_f64(ipw, l0) : -INFINITY;
+        const double e1 = h1 >= 0 ? log(readlane_f64(s, l1)) * readlane_f64(ipw, l1) : -INFINITY;
         if (lane == 0) {
-            values[r] = acc ? xi + yj : shift + (a0 > 0.0 ? log(a0) : -INFINITY);
+            values[r] = acc ? xi + yj : shift + la0;
             if (diag) diag[r] = m1;
             anti[r] = m2;
-            if (ii) ii[r] = acc ? i : -1;
-            if (jj) jj[r] = acc ? j : -1;
-            if (acc) done[n_done] = id;
+            const bool give = kPaired ? acc : valid;
+            if (ii) ii[r] = give ? i : -1;
+            if (jj) jj[r] = give ? j : -1;
+            if (kPaired && acc) done[n_done] = id;
         }
         n_done += acc ? 1 : 0;
         if (lane == (s0 & 63)) {
             cv[s0] = e0;
             lane_best(0, bv0, bs0);
+            bm0 = cm[bs0];
         }
         if (lane == (s1 & 63)) {
             cv[K + s1] = e1;
             lane_best(1, bv1, bs1);
+            bm1 = cm[K + bs1];
         }
     }
 }
@@ -1458,33 +1542,57 @@ hipError_t launch_xy_long(const T* x, const T* y, int64_t n, const MaxconvSpec& 
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_xy_paired(const T* x, const T* y, int64_t n, int32_t k, const MaxconvSpec& spec, double* values,
-                            int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w, hipStream_t st) {
-    const int L = (int)(2 * n - 1), K = k < L ? k : L;
-    if (K > kPairedMaxK || L >= kLongConvN) return hipErrorInvalidValue;
-    timing_before("mt_xy_select", st);
-    hipLaunchKernelGGL(mt_xy_select_kernel, dim3(2), dim3(kSelThreads), 0, st, w.psi, L, K, w.cand_m, w.cand_psi);
-    timing_after(st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    auto queue = mt_xy_paired_kernel<T>;
+// LDS bytes of the lockstep queue: log estimates, log lengths and diagonals
+// of 2K candidates, the reported pairs, and the 2 |P| K column cells when
+// they are kept there.
+size_t lockstep_lds(int K, int k, int np, bool cols) {
+    return (size_t)2 * K * (2 * sizeof(double) + sizeof(int)) + (size_t)k * sizeof(int) +
+           (cols ? (size_t)2 * np * K * sizeof(double) : 0);
+}
+constexpr size_t kLdsBytes = 160 * 1024;
+
+template <typename T, bool kPaired, bool kColsLds>
+hipError_t launch_lockstep(const T* x, const T* y, int64_t n, int32_t k, int K, const MaxconvSpec& spec,
+                           double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
+                           hipStream_t st) {
+    auto queue = mt_xy_lockstep_kernel<T, kPaired, kColsLds>;
     static std::atomic<uint64_t> attr_set{0};
     int dev = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
     const uint64_t bit = 1ull << (dev & 63);
     if (!(attr_set.load() & bit)) {
-        e = hipFuncSetAttribute((const void*)queue, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                2 * kPairedMaxK * (int)(sizeof(double) + sizeof(int)) + kPairedMaxK * (int)sizeof(int));
+        e = hipFuncSetAttribute((const void*)queue, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
         if (e != hipSuccess) return e;
         attr_set.fetch_or(bit);
     }
-    timing_before("mt_xy_paired", st);
-    const size_t lds = (size_t)2 * K * (sizeof(double) + sizeof(int)) + (size_t)k * sizeof(int);
-    hipLaunchKernelGGL(queue, dim3(1), dim3(64), lds, st, x, y, n, spec, w.sigma, w.cand_m, w.cand_psi, K, k, values,
-                       diag, w.diag1, ii, jj);
+    timing_before(kPaired ? "mt_xy_paired" : "mt_xy_queue", st);
+    hipLaunchKernelGGL(queue, dim3(1), dim3(64), lockstep_lds(K, k, spec.n, kColsLds), st, x, y, n, spec, w.cand_m,
+                       w.cand_psi, w.cand_cols, K, k, values, diag, w.diag1, ii, jj);
     timing_after(st);
     return hipGetLastError();
+}
+
+// k <= kPairedMaxK: both runs in lockstep over their K = min(k, 2n - 1)
+// candidates (plain or paired).
+template <typename T>
+hipError_t launch_xy_candidates(const T* x, const T* y, int64_t n, int32_t k, const MaxconvSpec& spec, bool paired,
+                                double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
+                                hipStream_t st) {
+    const int L = (int)(2 * n - 1), K = k < L ? k : L;
+    if (k > kPairedMaxK || L >= kLongConvN || spec.n > 32) return hipErrorInvalidValue;
+    timing_before("mt_xy_select", st);
+    hipLaunchKernelGGL(mt_xy_select_kernel, dim3(2), dim3(kSelThreads), 0, st, w.psi, L, K, w.sigma, spec.n,
+                       w.cand_m, w.cand_psi, w.cand_cols);
+    timing_after(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bool cols = lockstep_lds(K, k, spec.n, true) <= kLdsBytes;
+    if (paired)
+        return cols ? launch_lockstep<T, true, true>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
+                    : launch_lockstep<T, true, false>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+    return cols ? launch_lockstep<T, false, true>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
+                : launch_lockstep<T, false, false>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
 }
 
 template <typename T>
@@ -1515,7 +1623,8 @@ hipError_t launch_xy_t(const T* x, const T* y, int64_t n, int32_t k, const Maxco
     timing_after(st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (paired) return launch_xy_paired<T>(x, y, n, k, spec, values, diag, ii, jj, w, st);
+    if (k <= kPairedMaxK) return launch_xy_candidates<T>(x, y, n, k, spec, paired, values, diag, ii, jj, w, st);
+    if (paired) return hipErrorInvalidValue;
     // psi of one run in LDS: up to 8 (kLongConvN - 1) bytes
     auto queue = mt_xy_queue_kernel<T>;
     static std::atomic<uint64_t> attr_set{0};

@@ -274,13 +274,15 @@ def test_xy_topk_validation():
     assert lib.xy_topk_workspace_size(8, -1, ctypes.byref(o), ctypes.byref(nb)) == 1
     assert lib.xy_topk_workspace_size(8, 4, ctypes.byref(_opts([1, 2], path=1)), ctypes.byref(nb)) == 5
     assert lib.xy_topk_workspace_size(8, 4, ctypes.byref(_opts([1, 2], path=0, flags=1)), ctypes.byref(nb)) == 5
-    # the paired queue: k <= 4096, room for 2 min(k, 2n - 1) candidates, and
-    # its flag is for this entry point only
+    # k <= 4096: room for 2 min(k, 2n - 1) candidates with their columns
+    # (plain and paired alike); the paired flag takes k <= 4096 and is for
+    # this entry point only
     paired = _opts(list(mt.XY_FAMILY), path=0, flags=mt.FLAG_XY_PAIRED)
     plain_nb = ctypes.c_size_t(0)
     assert lib.xy_topk_workspace_size(1024, 256, ctypes.byref(paired), ctypes.byref(nb)) == 0
     assert lib.xy_topk_workspace_size(1024, 256, ctypes.byref(o), ctypes.byref(plain_nb)) == 0
-    assert nb.value >= plain_nb.value + 2 * 256 * 12
+    assert nb.value == plain_nb.value >= 2 * 24 * 2047 * 8 + 2 * 256 * (12 + 24 * 8)
+    assert lib.xy_topk_workspace_size(1024, 5000, ctypes.byref(o), ctypes.byref(plain_nb)) == 0
     assert lib.xy_topk_workspace_size(8192, 4096, ctypes.byref(paired), ctypes.byref(nb)) == 0
     assert lib.xy_topk_workspace_size(8192, 4097, ctypes.byref(paired), ctypes.byref(nb)) == 5
     assert "k <= 4096" in lib.maxtimes_last_error().decode()

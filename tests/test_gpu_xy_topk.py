@@ -158,3 +158,27 @@ def test_fp32_inputs_and_edges(gpu_lib):
         mt.xy_topk(torch.zeros(8193, dtype=torch.float64, device="cuda"),
                    torch.zeros(8193, dtype=torch.float64, device="cuda"), 4, P24)
     assert e.value.status == 5
+
+
+def test_queue_over_every_diagonal_matches_the_candidate_queue(gpu_lib):
+    # k <= 4096 pops both runs together over the min(k, 2n - 1) candidate
+    # diagonals, keeping log psi; a larger k runs one wave per run over every
+    # diagonal, keeping psi.  The same pops (diagonals and indices exactly);
+    # values agree to the rounding of a log, which the subtraction psi^p
+    # (p up to 4096, cancelling deep in the queue) grows to about 1e-11; the
+    # first pop also against the oracle
+    rng = np.random.default_rng(4242)
+    xn = rng.uniform(0, 8, 300)
+    yn = rng.uniform(0, 8, 300)
+    x, y = _dev(xn), _dev(yn)
+    a = gpu_lib.xy_topk(x, y, 4097, return_diag=True)
+    b = gpu_lib.xy_topk(x, y, 4096, return_diag=True)
+    for u, w in zip(a[1:], b[1:]):
+        np.testing.assert_array_equal(u.cpu().numpy()[:4096], w.cpu().numpy())
+    va, vb = a[0].cpu().numpy()[:4096], b[0].cpu().numpy()
+    fin = np.isfinite(vb)
+    np.testing.assert_array_equal(np.isfinite(va), fin)
+    np.testing.assert_allclose(va[fin], vb[fin], rtol=1e-10, atol=0)
+    o = xy_topk_estimate(xn, yn, P24, 1)
+    np.testing.assert_allclose(b[0].cpu().numpy()[0], o["values"][0], rtol=0, atol=1e-9)
+    assert b[3].cpu().numpy()[0] == o["diag"][0]
