@@ -935,6 +935,32 @@ __global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double*
 
 __device__ __forceinline__ int diag_len(int m, int n) { return (m < 2 * n - 2 - m ? m : 2 * n - 2 - m) + 1; }
 
+// A lane's candidate slots held in registers (slot u * 64 + lane in entry u):
+// the largest log psi, the first valid slot on ties and all -inf.
+template <int kS>
+__device__ __forceinline__ void slots_best(const double (&rv)[kS], const int (&rm)[kS], int lane, int K, double& bv,
+                                           int& bs, int& bm) {
+    bv = -INFINITY;
+    bs = K;
+    bm = 0;
+#pragma unroll
+    for (int u = 0; u < kS; ++u) {
+        const int s = u * 64 + lane;
+        if (s < K && (bs == K || rv[u] > bv)) {
+            bv = rv[u];
+            bs = s;
+            bm = rm[u];
+        }
+    }
+}
+
+template <int kS>
+__device__ __forceinline__ void slots_set(double (&rv)[kS], int u, double e) {
+#pragma unroll
+    for (int w = 0; w < kS; ++w)
+        if (w == u) rv[w] = e;
+}
+
 // Both runs' NormQueues in lockstep, one wave, over the candidates: each
 // rank pops run 0 (diagonals i + j) and run 1 (anti-diagonals
 // i + n - 1 - j) together.  Plain (Sec. 2.3): each run subtracts its own
@@ -949,8 +975,9 @@ __device__ __forceinline__ int diag_len(int m, int n) { return (m < 2 * n - 2 - 
 // estimate.  Lanes 0..31 hold run 0's powers, lanes 32..63 run 1's;
 // candidate slot s of a run belongs to lane s % 64.  The candidates' sigma
 // columns are updated in LDS when they fit (kColsLds), else in the
-// workspace copy.
-template <typename T, bool kPaired, bool kColsLds>
+// workspace copy; with kRegS > 0 (K <= 64 kRegS) a lane's slots, estimates
+// and diagonals, stay in registers.
+template <typename T, bool kPaired, bool kColsLds, int kRegS>
 __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict__ x, const T* __restrict__ y,
                                                           int64_t n, MaxconvSpec spec,
                                                           const int32_t* __restrict__ cand_m,
@@ -1009,12 +1036,28 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
             }
         }
     };
+    constexpr int kSR = kRegS > 0 ? kRegS : 1;
+    double rv0[kSR], rv1[kSR];
+    int rm0[kSR], rm1[kSR];
     double bv0, bv1;
     int bs0, bs1, bm0, bm1;
-    lane_best(0, bv0, bs0);
-    lane_best(1, bv1, bs1);
-    bm0 = bs0 < K ? cm[bs0] : 0;
-    bm1 = bs1 < K ? cm[K + bs1] : 0;
+    if (kRegS > 0) {
+#pragma unroll
+        for (int u = 0; u < kSR; ++u) {
+            const int s = u * 64 + lane;
+            rv0[u] = s < K ? cv[s] : -INFINITY;
+            rv1[u] = s < K ? cv[K + s] : -INFINITY;
+            rm0[u] = s < K ? cm[s] : 0;
+            rm1[u] = s < K ? cm[K + s] : 0;
+        }
+        slots_best(rv0, rm0, lane, K, bv0, bs0, bm0);
+        slots_best(rv1, rm1, lane, K, bv1, bs1, bm1);
+    } else {
+        lane_best(0, bv0, bs0);
+        lane_best(1, bv1, bs1);
+        bm0 = bs0 < K ? cm[bs0] : 0;
+        bm1 = bs1 < K ? cm[K + bs1] : 0;
+    }
     const int half = lane >> 5, q = lane & 31;
     const bool mine = q < np;
     // this lane's power and its reciprocal; a rank picks other lanes' by readlane
@@ -1076,15 +1119,26 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
             if (kPaired && acc) done[n_done] = id;
         }
         n_done += acc ? 1 : 0;
-        if (lane == (s0 & 63)) {
-            cv[s0] = e0;
-            lane_best(0, bv0, bs0);
-            bm0 = cm[bs0];
-        }
-        if (lane == (s1 & 63)) {
-            cv[K + s1] = e1;
-            lane_best(1, bv1, bs1);
-            bm1 = cm[K + bs1];
+        if (kRegS > 0) {
+            if (lane == (s0 & 63)) {
+                slots_set(rv0, s0 >> 6, e0);
+                slots_best(rv0, rm0, lane, K, bv0, bs0, bm0);
+            }
+            if (lane == (s1 & 63)) {
+                slots_set(rv1, s1 >> 6, e1);
+                slots_best(rv1, rm1, lane, K, bv1, bs1, bm1);
+            }
+        } else {
+            if (lane == (s0 & 63)) {
+                cv[s0] = e0;
+                lane_best(0, bv0, bs0);
+                bm0 = cm[bs0];
+            }
+            if (lane == (s1 & 63)) {
+                cv[K + s1] = e1;
+                lane_best(1, bv1, bs1);
+                bm1 = cm[K + bs1];
+            }
         }
     }
 }
@@ -1551,11 +1605,11 @@ size_t lockstep_lds(int K, int k, int np, bool cols) {
 }
 constexpr size_t kLdsBytes = 160 * 1024;
 
-template <typename T, bool kPaired, bool kColsLds>
+template <typename T, bool kPaired, bool kColsLds, int kRegS>
 hipError_t launch_lockstep(const T* x, const T* y, int64_t n, int32_t k, int K, const MaxconvSpec& spec,
                            double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
                            hipStream_t st) {
-    auto queue = mt_xy_lockstep_kernel<T, kPaired, kColsLds>;
+    auto queue = mt_xy_lockstep_kernel<T, kPaired, kColsLds, kRegS>;
     static std::atomic<uint64_t> attr_set{0};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1587,12 +1641,18 @@ hipError_t launch_xy_candidates(const T* x, const T* y, int64_t n, int32_t k, co
     timing_after(st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // K <= 256: the columns always fit (at most 2 x 32 x 256 x 8 B plus
+    // 40 K + 4 k bytes), and a lane's 4 slots per run stay in registers
     const bool cols = lockstep_lds(K, k, spec.n, true) <= kLdsBytes;
-    if (paired)
-        return cols ? launch_lockstep<T, true, true>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
-                    : launch_lockstep<T, true, false>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
-    return cols ? launch_lockstep<T, false, true>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
-                : launch_lockstep<T, false, false>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+    const bool regs = K <= 256 && cols;
+    if (paired) {
+        if (regs) return launch_lockstep<T, true, true, 4>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+        return cols ? launch_lockstep<T, true, true, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
+                    : launch_lockstep<T, true, false, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+    }
+    if (regs) return launch_lockstep<T, false, true, 4>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+    return cols ? launch_lockstep<T, false, true, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
+                : launch_lockstep<T, false, false, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
 }
 
 template <typename T>

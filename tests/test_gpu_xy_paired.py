@@ -6,11 +6,13 @@ Accurate ranks subtract an exact value, so the FFT rounding of the ring
 results no longer grows into later pops the way it does in the plain queue;
 the cases below were checked on the CPU to give the same sequence on direct
 ring results (the oracle's) and on numpy FFT ones of two transform lengths
-(uniform lists on [0, s], s = 1 .. 40, FP64 and FP32, both transform paths).
+(uniform lists on [0, s], s = 1 .. 40, FP64 and FP32, both transform paths,
+K = min(k, 2n - 1) up to 256 (a lane's slots in registers), 320 (in LDS) and
+599 (columns in the workspace)).
 Compared: the accept mask, both diagonals and the indices exactly; accepted
 values bit for bit (x_i + y_j in FP64 on both sides); the other values,
 estimates, within 1e-6 (the tolerance of the plain queue's tests, which the
-FFT-run check stays inside: 6.2e-7 at most).
+FFT-run check stays inside: 7.2e-7 at most).
 """
 
 import numpy as np
@@ -29,6 +31,7 @@ CASES = [  # n, k, spread, seed, dtype
     (700, 100, 30, 13, np.float32),
     (2049, 160, 10, 14, np.float64),   # first length on the global-memory transforms
     (3000, 200, 40, 12, np.float64),
+    (1500, 320, 30, 16, np.float64),   # K = 320: columns in LDS, slots in LDS
     (8192, 256, 40, 5005, np.float64),
     (8192, 256, 1, 5005, np.float64),
 ]

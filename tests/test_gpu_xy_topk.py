@@ -172,13 +172,17 @@ def test_queue_over_every_diagonal_matches_the_candidate_queue(gpu_lib):
     yn = rng.uniform(0, 8, 300)
     x, y = _dev(xn), _dev(yn)
     a = gpu_lib.xy_topk(x, y, 4097, return_diag=True)
+    # k = 4096 keeps the columns in the workspace (K = 599), k = 320 in LDS
+    # (K = 320), k = 200 with a lane's slots in registers (K = 200)
+    for kk in (4096, 320, 200):
+        b = gpu_lib.xy_topk(x, y, kk, return_diag=True)
+        for u, w in zip(a[1:], b[1:]):
+            np.testing.assert_array_equal(u.cpu().numpy()[:kk], w.cpu().numpy())
+        va, vb = a[0].cpu().numpy()[:kk], b[0].cpu().numpy()
+        fin = np.isfinite(vb)
+        np.testing.assert_array_equal(np.isfinite(va), fin)
+        np.testing.assert_allclose(va[fin], vb[fin], rtol=1e-10, atol=0)
     b = gpu_lib.xy_topk(x, y, 4096, return_diag=True)
-    for u, w in zip(a[1:], b[1:]):
-        np.testing.assert_array_equal(u.cpu().numpy()[:4096], w.cpu().numpy())
-    va, vb = a[0].cpu().numpy()[:4096], b[0].cpu().numpy()
-    fin = np.isfinite(vb)
-    np.testing.assert_array_equal(np.isfinite(va), fin)
-    np.testing.assert_allclose(va[fin], vb[fin], rtol=1e-10, atol=0)
     o = xy_topk_estimate(xn, yn, P24, 1)
     np.testing.assert_allclose(b[0].cpu().numpy()[0], o["values"][0], rtol=0, atol=1e-9)
     assert b[3].cpu().numpy()[0] == o["diag"][0]
