@@ -816,24 +816,21 @@ __global__ __launch_bounds__(256) void mt_xy_index_kernel(const int32_t* __restr
 constexpr int kSelThreads = 1024;
 constexpr int kSelPer = kLongConvN / kSelThreads;  // covers 2n - 1 < kLongConvN
 
-// Block-wide exclusive count of a flag over threads in thread order; *total
-// receives the block's count.  Every thread of the block calls it.
-__device__ __forceinline__ int block_count_before(bool flag, int* wtot, int* total) {
+// Block-wide exclusive sum of v over threads in thread order; every thread
+// of the block calls it.
+__device__ __forceinline__ uint32_t block_sum_before(uint32_t v, uint32_t* wtot) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint64_t b = __ballot(flag);
-    const int within = __popcll(b & ((1ull << lane) - 1ull));
-    if (lane == 0) wtot[wv] = __popcll(b);
-    __syncthreads();
-    int before = 0, all = 0;
-#pragma unroll
-    for (int w2 = 0; w2 < kSelThreads / 64; ++w2) {
-        const int t = wtot[w2];
-        all += t;
-        before += w2 < wv ? t : 0;
+    uint32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
     }
+    if (lane == 63) wtot[wv] = inc;
     __syncthreads();
-    *total = all;
-    return before + within;
+    uint32_t before = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kSelThreads / 64; ++w2) before += w2 < wv ? wtot[w2] : 0u;
+    return before + inc - v;
 }
 
 // The K candidates of each run (block = run): the K largest psi, lowest m
@@ -848,15 +845,16 @@ __global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double*
                                                                    double* __restrict__ cand_cols) {
     __shared__ uint32_t hist[256];
     __shared__ int s_bin, s_above;
-    __shared__ int wtot[kSelThreads / 64];
+    __shared__ uint32_t wtot[kSelThreads / 64];
     __shared__ int taken_m[kPairedMaxK];
     const int tid = threadIdx.x, run = blockIdx.x, lane = tid & 63;
     const double* ps = psi + (int64_t)run * L;
     if (tid == 0) s_bin = s_above = 0;
     uint64_t key[kSelPer];
+    // thread tid owns m = kSelPer tid + c: thread order is m order
 #pragma unroll
     for (int c = 0; c < kSelPer; ++c) {
-        const int m = c * kSelThreads + tid;
+        const int m = kSelPer * tid + c;
         key[c] = m < L ? (uint64_t)__double_as_longlong(ps[m]) : 0ull;
     }
     uint64_t prefix = 0, mask = 0;
@@ -865,10 +863,21 @@ __global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double*
         const int shift = 8 * d;
         if (tid < 256) hist[tid] = 0u;
         __syncthreads();
+        // the high digits of psi's bits are shared by almost every key: when
+        // a wave's counted keys all fall in one bin, one lane adds them
 #pragma unroll
-        for (int c = 0; c < kSelPer; ++c)
-            if (c * kSelThreads + tid < L && (key[c] & mask) == prefix)
-                atomicAdd(&hist[(key[c] >> shift) & 255u], 1u);
+        for (int c = 0; c < kSelPer; ++c) {
+            const bool counted = kSelPer * tid + c < L && (key[c] & mask) == prefix;
+            const uint32_t bin = (uint32_t)(key[c] >> shift) & 255u;
+            const uint64_t act = __ballot(counted);
+            if (act == 0) continue;
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)bin, (int)__ffsll((unsigned long long)act) - 1);
+            if (__ballot(counted && bin == b0) == act) {
+                if (lane == 0) atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+            } else if (counted) {
+                atomicAdd(&hist[bin], 1u);
+            }
+        }
         __syncthreads();
         if (tid < 64) {
             // lane l holds bins 255 - 4l .. 252 - 4l (descending)
@@ -905,23 +914,31 @@ __global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double*
         need -= s_above;
         __syncthreads();
     }
-    int taken = 0, eq_seen = 0;
+    // keys above the threshold, and the first `need` keys equal to it in m
+    // order: one block scan of the per-thread counts (above | equal << 16)
+    uint32_t n_gt = 0, n_eq = 0;
 #pragma unroll
     for (int c = 0; c < kSelPer; ++c) {
-        const int m = c * kSelThreads + tid;
+        const bool ok = kSelPer * tid + c < L;
+        n_gt += ok && key[c] > prefix ? 1u : 0u;
+        n_eq += ok && key[c] == prefix ? 1u : 0u;
+    }
+    const uint32_t before = block_sum_before(n_gt | (n_eq << 16), wtot);
+    const int gt_before = (int)(before & 0xffffu), eq_before = (int)(before >> 16);
+    int pos = gt_before + (eq_before < need ? eq_before : need), eq_rank = eq_before;
+#pragma unroll
+    for (int c = 0; c < kSelPer; ++c) {
+        const int m = kSelPer * tid + c;
         const bool ok = m < L;
         const bool gt = ok && key[c] > prefix, eq = ok && key[c] == prefix;
-        int eq_total, take_total;
-        const int eq_before = block_count_before(eq, wtot, &eq_total);
-        const bool take = gt || (eq && eq_seen + eq_before < need);
-        const int pos = taken + block_count_before(take, wtot, &take_total);
+        const bool take = gt || (eq && eq_rank < need);
+        eq_rank += eq ? 1 : 0;
         if (take && pos < K) {
             cand_m[(int64_t)run * K + pos] = m;
             cand_psi[(int64_t)run * K + pos] = __longlong_as_double((long long)key[c]);
             taken_m[pos] = m;
         }
-        taken += take_total;
-        eq_seen += eq_total;
+        pos += take ? 1 : 0;
     }
     __syncthreads();
     // the candidates' columns, every thread gathering (q, slot) cells
