@@ -1160,9 +1160,9 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
     }
 }
 
-// Long transforms (N up to kLongConvN) for the x + y ring results: every
-// (run, p) transform in a global buffer [slot][N], one thread per radix-R
-// butterfly of a Stockham pass, the passes ordered by kernel boundaries.
+// Long transforms (N = 8192 or 16384, up to kLongConvN): every transform of
+// the batch in a global buffer [slot][N], the four-step transform below
+// going through two such buffers.
 
 // exp(-2 pi i mm / N), 0 <= mm < N, from the octant table (runtime N, N4 = N / 4).
 __device__ __forceinline__ double2 twiddle_rt(const double2* tw, int mm, int N4) {
@@ -1246,31 +1246,76 @@ __global__ __launch_bounds__(256) void mt_xy_long_load_kernel(const T* __restric
     buf[g] = make_double2(a, c);
 }
 
-// One Stockham pass of span Ns and radix R over every transform of the batch.
-template <int R>
-__global__ __launch_bounds__(256) void mt_fft_pass_kernel(const double2* __restrict__ in, double2* __restrict__ out,
-                                                         int logN, int Ns, int64_t butterflies,
-                                                         const double2* __restrict__ tw) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= butterflies) return;
-    const int N = 1 << logN, NR = N / R;
-    const int64_t tr = g / NR;
-    const int j = (int)(g - tr * NR);
+// Four-step transform of the long lengths (N = N1 N2, N1 = 128, N2 = 64 or
+// 128): with n = N2 n1 + n2 and k = k1 + N1 k2,
+//   X[k] = sum_n2 W_N2^(n2 k2) W_N^(n2 k1) sum_n1 x[N2 n1 + n2] W_N1^(n1 k1),
+// so one kernel transforms the N2 columns (length N1, stride N2) and applies
+// W_N^(n2 k1), storing Y[k1 N2 + n2]; a second transforms the N1 rows of Y
+// (length N2, contiguous) and stores X[k1 + N1 k2].  Each workgroup holds
+// kF4Cols transforms of M points in LDS and runs Stockham stages there, so a
+// direction reads and writes the buffer twice instead of once per radix pass.
+constexpr int kF4Cols = 16;
+
+template <int M, int R>
+__device__ __forceinline__ void f4_stage(double2* buf, int Ns, int N, const double2* tw) {
+    constexpr int MR = M / R;
+    const int t = threadIdx.x;
+    const bool act = t < kF4Cols * MR;
+    double2 v[16];
+    int c = 0, j = 0, k0 = 0;
+    if (act) {
+        c = t / MR;
+        j = t - c * MR;
+        k0 = j & (Ns - 1);
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[e] = buf[c * (M + 1) + j + e * MR];
+        if (Ns > 1) {
+            const int step = k0 * (N / (Ns * R));
+#pragma unroll
+            for (int e = 1; e < R; ++e) v[e] = cmul(v[e], twiddle_rt(tw, step * e, N / 4));
+        }
+        dft<R>(v, 0, 1);
+    }
+    __syncthreads();
+    if (act) {
+        const int base = (j - k0) * R + k0;
+#pragma unroll
+        for (int e = 0; e < R; ++e) buf[c * (M + 1) + base + e * Ns] = v[oreg<R>(e)];
+    }
+    __syncthreads();
+}
+
+// One step of the four-step transform for every transform of the batch:
+// workgroup g takes transform g / groups_per_tr and its kF4Cols consecutive
+// columns (or rows) from (g % groups_per_tr) kF4Cols.  Element i of line c
+// is in[i s_in + c c_in]; result k of line c goes to out[k s_out + c]
+// (multiplied by W_N^(c k) when twiddle).  Lines are contiguous in memory
+// when c_in = 1 (columns) and elements are when s_in = 1 (rows).
+template <int M>
+__global__ __launch_bounds__(256) void mt_fft4_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+                                                    int logN, int groups_per_tr, int s_in, int c_in, int s_out,
+                                                    int twiddle, const double2* __restrict__ tw) {
+    __shared__ double2 buf[kF4Cols * (M + 1)];
+    const int t = threadIdx.x;
+    const int N = 1 << logN;
+    const int64_t tr = blockIdx.x / groups_per_tr;
+    const int c0 = (int)(blockIdx.x - tr * groups_per_tr) * kF4Cols;
     const double2* src = in + tr * N;
     double2* dst = out + tr * N;
-    double2 v[16];
-#pragma unroll
-    for (int e = 0; e < R; ++e) v[e] = src[j + e * NR];
-    const int k0 = j & (Ns - 1);
-    if (Ns > 1) {
-        const int step = k0 * (N / (Ns * R));
-#pragma unroll
-        for (int e = 1; e < R; ++e) v[e] = cmul(v[e], twiddle_rt(tw, step * e, N / 4));
+    for (int idx = t; idx < kF4Cols * M; idx += 256) {
+        const int i = c_in == 1 ? idx / kF4Cols : idx % M;
+        const int c = c_in == 1 ? idx % kF4Cols : idx / M;
+        buf[c * (M + 1) + i] = src[i * s_in + (c0 + c) * c_in];
     }
-    dft<R>(v, 0, 1);
-    const int base = (j - k0) * R + k0;
-#pragma unroll
-    for (int e = 0; e < R; ++e) dst[base + e * Ns] = v[oreg<R>(e)];
+    __syncthreads();
+    f4_stage<M, 16>(buf, 1, N, tw);
+    f4_stage<M, M / 16>(buf, 16, N, tw);
+    for (int idx = t; idx < kF4Cols * M; idx += 256) {
+        const int k = idx / kF4Cols, c = idx % kF4Cols;
+        double2 v = buf[c * (M + 1) + k];
+        if (twiddle) v = cmul(v, twiddle_rt(tw, ((c0 + c) * k) & (N - 1), N / 4));
+        dst[k * s_out + c0 + c] = v;
+    }
 }
 
 // conj(4 W_t) of every transform from Z_t and Z_(N-t) (see convolve_pair).
@@ -1298,9 +1343,9 @@ __global__ __launch_bounds__(256) void mt_xy_long_store_kernel(const double2* __
 }
 
 // Max-convolution of long vectors (kMaxConvN < N <= kLongConvN): the batch of
-// pairs through the global-buffer passes, one p at a time (largest first);
-// every index keeps the S of its first stable p (code = its family index) and
-// the roots are taken at the end.  No early exit.
+// pairs through the four-step transforms in global buffers, one p at a time
+// (largest first); every index keeps the S of its first stable p (code = its
+// family index) and the roots are taken at the end.  No early exit.
 constexpr uint8_t kCodeOpen = 254;
 
 // Per pair: rxy[pair] = max x max y, inv[2 pair] = 1 / max x, inv[2 pair + 1] = 1 / max y.
@@ -1511,38 +1556,38 @@ hipError_t long_convolve(double2*& cur, double2*& nxt, int logN, int64_t count, 
         cur = nxt;
         nxt = t;
     };
-    auto transform = [&]() -> hipError_t {
-        int Ns = 1;
-        for (int left = logN; left > 0;) {
-            const int r = left >= 4 ? 4 : left;
-            timing_before(pass_name, st);
-            switch (r) {
-                case 4: hipLaunchKernelGGL(mt_fft_pass_kernel<16>, blocks(total / 16), dim3(256), 0, st, cur, nxt,
-                                           logN, Ns, total / 16, tw); break;
-                case 3: hipLaunchKernelGGL(mt_fft_pass_kernel<8>, blocks(total / 8), dim3(256), 0, st, cur, nxt,
-                                           logN, Ns, total / 8, tw); break;
-                case 2: hipLaunchKernelGGL(mt_fft_pass_kernel<4>, blocks(total / 4), dim3(256), 0, st, cur, nxt,
-                                           logN, Ns, total / 4, tw); break;
-                default: hipLaunchKernelGGL(mt_fft_pass_kernel<2>, blocks(total / 2), dim3(256), 0, st, cur, nxt,
-                                            logN, Ns, total / 2, tw); break;
-            }
-            timing_after(st);
-            hipError_t pe = hipGetLastError();
-            if (pe != hipSuccess) return pe;
-            swap();
-            Ns <<= r;
-            left -= r;
-        }
+    // N = 8192 or 16384: the four-step transform (columns of 128, rows of N2)
+    auto transform4 = [&]() -> hipError_t {
+        const int N2 = 1 << (logN - 7);
+        timing_before(pass_name, st);
+        hipLaunchKernelGGL(mt_fft4_kernel<128>, dim3((unsigned)(count * (N2 / kF4Cols))), dim3(256), 0, st, cur,
+                           nxt, logN, N2 / kF4Cols, N2, 1, N2, 1, tw);
+        timing_after(st);
+        hipError_t pe = hipGetLastError();
+        if (pe != hipSuccess) return pe;
+        swap();
+        timing_before(pass_name, st);
+        if (N2 == 128)
+            hipLaunchKernelGGL(mt_fft4_kernel<128>, dim3((unsigned)(count * (128 / kF4Cols))), dim3(256), 0, st,
+                               cur, nxt, logN, 128 / kF4Cols, 1, N2, 128, 0, tw);
+        else
+            hipLaunchKernelGGL(mt_fft4_kernel<64>, dim3((unsigned)(count * (128 / kF4Cols))), dim3(256), 0, st, cur,
+                               nxt, logN, 128 / kF4Cols, 1, N2, 128, 0, tw);
+        timing_after(st);
+        pe = hipGetLastError();
+        if (pe != hipSuccess) return pe;
+        swap();
         return hipSuccess;
     };
-    hipError_t e = transform();
+    if (logN != 13 && logN != 14) return hipErrorInvalidValue;
+    hipError_t e = transform4();
     if (e != hipSuccess) return e;
     timing_before(product_name, st);
     hipLaunchKernelGGL(mt_fft_product_kernel, blocks(total), dim3(256), 0, st, cur, nxt, logN, total);
     timing_after(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     swap();
-    return transform();
+    return transform4();
 }
 
 // Max-convolution of long vectors through the global buffers of ws.
