@@ -1254,7 +1254,8 @@ __global__ __launch_bounds__(256) void mt_xy_long_load_kernel(const T* __restric
 // (length N2, contiguous) and stores X[k1 + N1 k2].  Each workgroup holds
 // kF4Cols transforms of M points in LDS and runs Stockham stages there, so a
 // direction reads and writes the buffer twice instead of once per radix pass.
-constexpr int kF4Cols = 16;
+constexpr int kF4Cols = 8;
+constexpr int kF4Threads = 128;
 
 template <int M, int R>
 __device__ __forceinline__ void f4_stage(double2* buf, int Ns, int N, const double2* tw) {
@@ -1292,7 +1293,7 @@ __device__ __forceinline__ void f4_stage(double2* buf, int Ns, int N, const doub
 // (multiplied by W_N^(c k) when twiddle).  Lines are contiguous in memory
 // when c_in = 1 (columns) and elements are when s_in = 1 (rows).
 template <int M>
-__global__ __launch_bounds__(256) void mt_fft4_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+__global__ __launch_bounds__(kF4Threads) void mt_fft4_kernel(const double2* __restrict__ in, double2* __restrict__ out,
                                                     int logN, int groups_per_tr, int s_in, int c_in, int s_out,
                                                     int twiddle, const double2* __restrict__ tw) {
     __shared__ double2 buf[kF4Cols * (M + 1)];
@@ -1302,7 +1303,7 @@ __global__ __launch_bounds__(256) void mt_fft4_kernel(const double2* __restrict_
     const int c0 = (int)(blockIdx.x - tr * groups_per_tr) * kF4Cols;
     const double2* src = in + tr * N;
     double2* dst = out + tr * N;
-    for (int idx = t; idx < kF4Cols * M; idx += 256) {
+    for (int idx = t; idx < kF4Cols * M; idx += kF4Threads) {
         const int i = c_in == 1 ? idx / kF4Cols : idx % M;
         const int c = c_in == 1 ? idx % kF4Cols : idx / M;
         buf[c * (M + 1) + i] = src[i * s_in + (c0 + c) * c_in];
@@ -1310,7 +1311,7 @@ __global__ __launch_bounds__(256) void mt_fft4_kernel(const double2* __restrict_
     __syncthreads();
     f4_stage<M, 16>(buf, 1, N, tw);
     f4_stage<M, M / 16>(buf, 16, N, tw);
-    for (int idx = t; idx < kF4Cols * M; idx += 256) {
+    for (int idx = t; idx < kF4Cols * M; idx += kF4Threads) {
         const int k = idx / kF4Cols, c = idx % kF4Cols;
         double2 v = buf[c * (M + 1) + k];
         if (twiddle) v = cmul(v, twiddle_rt(tw, ((c0 + c) * k) & (N - 1), N / 4));
@@ -1560,7 +1561,7 @@ hipError_t long_convolve(double2*& cur, double2*& nxt, int logN, int64_t count, 
     auto transform4 = [&]() -> hipError_t {
         const int N2 = 1 << (logN - 7);
         timing_before(pass_name, st);
-        hipLaunchKernelGGL(mt_fft4_kernel<128>, dim3((unsigned)(count * (N2 / kF4Cols))), dim3(256), 0, st, cur,
+        hipLaunchKernelGGL(mt_fft4_kernel<128>, dim3((unsigned)(count * (N2 / kF4Cols))), dim3(kF4Threads), 0, st, cur,
                            nxt, logN, N2 / kF4Cols, N2, 1, N2, 1, tw);
         timing_after(st);
         hipError_t pe = hipGetLastError();
@@ -1568,10 +1569,10 @@ hipError_t long_convolve(double2*& cur, double2*& nxt, int logN, int64_t count, 
         swap();
         timing_before(pass_name, st);
         if (N2 == 128)
-            hipLaunchKernelGGL(mt_fft4_kernel<128>, dim3((unsigned)(count * (128 / kF4Cols))), dim3(256), 0, st,
+            hipLaunchKernelGGL(mt_fft4_kernel<128>, dim3((unsigned)(count * (128 / kF4Cols))), dim3(kF4Threads), 0, st,
                                cur, nxt, logN, 128 / kF4Cols, 1, N2, 128, 0, tw);
         else
-            hipLaunchKernelGGL(mt_fft4_kernel<64>, dim3((unsigned)(count * (128 / kF4Cols))), dim3(256), 0, st, cur,
+            hipLaunchKernelGGL(mt_fft4_kernel<64>, dim3((unsigned)(count * (128 / kF4Cols))), dim3(kF4Threads), 0, st, cur,
                                nxt, logN, 128 / kF4Cols, 1, N2, 128, 0, tw);
         timing_after(st);
         pe = hipGetLastError();
