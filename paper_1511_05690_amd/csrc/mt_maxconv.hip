@@ -1124,8 +1124,12 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
         const uint32_t nlo = (uint32_t)nm, nhi = (uint32_t)(nm >> 32);
         const int h0 = nlo ? 31 - __clz(nlo) : -1, h1 = nhi ? 31 - __clz(nhi) : -1;
         const int l0 = h0 >= 0 ? h0 : 0, l1 = h1 >= 0 ? 32 + h1 : 32;
-        const double e0 = h0 >= 0 ? log(readlane_f64(s, l0)) * readlane_f64(ipw, l0) : -INFINITY;
-        const double e1 = h1 >= 0 ? log(readlane_f64(s, l1)) * readlane_f64(ipw, l1) : -INFINITY;
+        // both runs' new roots in one log: half 0 takes run 0's sum, half 1 run 1's
+        const double sh = half ? readlane_f64(s, l1) : readlane_f64(s, l0);
+        const double ih = half ? readlane_f64(ipw, l1) : readlane_f64(ipw, l0);
+        const double lr = log(sh) * ih;
+        const double e0 = h0 >= 0 ? readlane_f64(lr, 0) : -INFINITY;
+        const double e1 = h1 >= 0 ? readlane_f64(lr, 32) : -INFINITY;
         if (lane == 0) {
             values[r] = acc ? xi + yj : shift + la0;
             if (diag) diag[r] = m1;
