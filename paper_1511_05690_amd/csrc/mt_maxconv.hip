@@ -952,17 +952,18 @@ __global__ __launch_bounds__(kSelThreads) void mt_xy_select_kernel(const double*
 
 __device__ __forceinline__ int diag_len(int m, int n) { return (m < 2 * n - 2 - m ? m : 2 * n - 2 - m) + 1; }
 
-// A lane's candidate slots held in registers (slot u * 64 + lane in entry u):
-// the largest log psi, the first valid slot on ties and all -inf.
+// A lane's candidate slots held in registers (slot u * 32 + q of its run in
+// entry u, q = lane % 32): the largest log psi, the first valid slot on ties
+// and all -inf.
 template <int kS>
-__device__ __forceinline__ void slots_best(const double (&rv)[kS], const int (&rm)[kS], int lane, int K, double& bv,
+__device__ __forceinline__ void slots_best(const double (&rv)[kS], const int (&rm)[kS], int q, int K, double& bv,
                                            int& bs, int& bm) {
     bv = -INFINITY;
     bs = K;
     bm = 0;
 #pragma unroll
     for (int u = 0; u < kS; ++u) {
-        const int s = u * 64 + lane;
+        const int s = u * 32 + q;
         if (s < K && (bs == K || rv[u] > bv)) {
             bv = rv[u];
             bs = s;
@@ -978,6 +979,37 @@ __device__ __forceinline__ void slots_set(double (&rv)[kS], int u, double e) {
         if (w == u) rv[w] = e;
 }
 
+// The largest v of each half wave (lanes 0..31 and 32..63) and, among the
+// lanes of that half holding it, the smallest s: row_shr 1, 2, 4, 8 leave
+// each row's maximum in its lane 15, row_bcast:15 into rows 1 and 3 brings
+// the two rows of a half together in lanes 31 and 63.  v must not be NaN.
+__device__ __forceinline__ void half_argmax(double v, int s, double& a0, int& s0, double& a1, int& s1) {
+    double m = v;
+    m = fmax(m, dpp_f64<0x111, 0xf>(m));
+    m = fmax(m, dpp_f64<0x112, 0xf>(m));
+    m = fmax(m, dpp_f64<0x114, 0xf>(m));
+    m = fmax(m, dpp_f64<0x118, 0xf>(m));
+    m = fmax(m, dpp_f64<0x142, 0xa>(m));
+    a0 = readlane_f64(m, 31);
+    a1 = readlane_f64(m, 63);
+    const bool tie = v == ((threadIdx.x & 32) ? a1 : a0);
+    const uint64_t t = __ballot(tie);
+    const uint32_t t0 = (uint32_t)t, t1 = (uint32_t)(t >> 32);
+    if (__popc(t0) == 1 && __popc(t1) == 1) {
+        s0 = __builtin_amdgcn_readlane(s, __ffs(t0) - 1);
+        s1 = __builtin_amdgcn_readlane(s, 32 + __ffs(t1) - 1);
+        return;
+    }
+    int w = tie ? s : INT_MAX;
+    w = min(w, dpp_i32<0x111, 0xf>(w));
+    w = min(w, dpp_i32<0x112, 0xf>(w));
+    w = min(w, dpp_i32<0x114, 0xf>(w));
+    w = min(w, dpp_i32<0x118, 0xf>(w));
+    w = min(w, dpp_i32<0x142, 0xa>(w));
+    s0 = __builtin_amdgcn_readlane(w, 31);
+    s1 = __builtin_amdgcn_readlane(w, 63);
+}
+
 // Both runs' NormQueues in lockstep, one wave, over the candidates: each
 // rank pops run 0 (diagonals i + j) and run 1 (anti-diagonals
 // i + n - 1 - j) together.  Plain (Sec. 2.3): each run subtracts its own
@@ -989,10 +1021,11 @@ __device__ __forceinline__ void slots_set(double (&rv)[kS], int u, double e) {
 // norms admit; none on a diagonal without a stable p); an accurate rank
 // reports x_i + y_j and (i, j) and subtracts v^p from both runs, any other
 // reports run 0's estimate and i = j = -1, and each run subtracts its own
-// estimate.  Lanes 0..31 hold run 0's powers, lanes 32..63 run 1's;
-// candidate slot s of a run belongs to lane s % 64.  The candidates' sigma
+// estimate.  Lanes 0..31 hold run 0's powers and candidates, lanes 32..63
+// run 1's; candidate slot s of run t belongs to lane 32 t + s % 32.  The
+// candidates' sigma
 // columns are updated in LDS when they fit (kColsLds), else in the
-// workspace copy; with kRegS > 0 (K <= 64 kRegS) a lane's slots, estimates
+// workspace copy; with kRegS > 0 (K <= 32 kRegS) a lane's slots, estimates
 // and diagonals, stay in registers.
 template <typename T, bool kPaired, bool kColsLds, int kRegS>
 __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict__ x, const T* __restrict__ y,
@@ -1036,16 +1069,18 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
     if (kColsLds)
         for (int s = lane; s < 2 * np * K; s += 64) cols[s] = cand_cols[s];
     __syncthreads();
-    const int S = (K + 63) / 64;
-    // the lane's largest log psi and its slot (the first valid slot always
-    // counts, so a run whose estimates are all -inf still names its lowest)
-    auto lane_best = [&](int t, double& bv, int& bs) {
+    const int half = lane >> 5, q = lane & 31;
+    const int S = (K + 31) / 32;
+    // the lane's largest log psi of its run and its slot (the first valid
+    // slot always counts, so a run whose estimates are all -inf still names
+    // its lowest)
+    auto lane_best = [&](double& bv, int& bs) {
         bv = -INFINITY;
         bs = K;
         for (int u = 0; u < S; ++u) {
-            const int s = u * 64 + lane;
+            const int s = u * 32 + q;
             if (s < K) {
-                const double e = cv[t * K + s];
+                const double e = cv[half * K + s];
                 if (bs == K || e > bv) {
                     bv = e;
                     bs = s;
@@ -1054,37 +1089,30 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
         }
     };
     constexpr int kSR = kRegS > 0 ? kRegS : 1;
-    double rv0[kSR], rv1[kSR];
-    int rm0[kSR], rm1[kSR];
-    double bv0, bv1;
-    int bs0, bs1, bm0, bm1;
+    double rv[kSR];
+    int rm[kSR];
+    double bv;
+    int bs, bm;
     if (kRegS > 0) {
 #pragma unroll
         for (int u = 0; u < kSR; ++u) {
-            const int s = u * 64 + lane;
-            rv0[u] = s < K ? cv[s] : -INFINITY;
-            rv1[u] = s < K ? cv[K + s] : -INFINITY;
-            rm0[u] = s < K ? cm[s] : 0;
-            rm1[u] = s < K ? cm[K + s] : 0;
+            const int s = u * 32 + q;
+            rv[u] = s < K ? cv[half * K + s] : -INFINITY;
+            rm[u] = s < K ? cm[half * K + s] : 0;
         }
-        slots_best(rv0, rm0, lane, K, bv0, bs0, bm0);
-        slots_best(rv1, rm1, lane, K, bv1, bs1, bm1);
+        slots_best(rv, rm, q, K, bv, bs, bm);
     } else {
-        lane_best(0, bv0, bs0);
-        lane_best(1, bv1, bs1);
-        bm0 = bs0 < K ? cm[bs0] : 0;
-        bm1 = bs1 < K ? cm[K + bs1] : 0;
+        lane_best(bv, bs);
+        bm = bs < K ? cm[half * K + bs] : 0;
     }
-    const int half = lane >> 5, q = lane & 31;
     const bool mine = q < np;
     // this lane's power and its reciprocal; a rank picks other lanes' by readlane
     const double pw = mine ? (double)spec.p[q] : 1.0, ipw = 1.0 / pw;
     for (int r = 0; r < k; ++r) {
-        double a0 = bv0, a1 = bv1;
-        int s0 = bs0, s1 = bs1;
-        wave_argmax(a0, s0);
-        wave_argmax(a1, s1);
-        const int m1 = __builtin_amdgcn_readlane(bm0, s0 & 63), m2 = __builtin_amdgcn_readlane(bm1, s1 & 63);
+        double a0, a1;
+        int s0, s1;
+        half_argmax(bv, bs, a0, s0, a1, s1);
+        const int m1 = __builtin_amdgcn_readlane(bm, s0 & 31), m2 = __builtin_amdgcn_readlane(bm, 32 + (s1 & 31));
         const int sd = m1 + m2 - (nn - 1);
         const int i = sd >> 1, j = m1 - i;
         bool valid = (sd & 1) == 0 && sd >= 0 && i < nn && j >= 0 && j < nn;
@@ -1140,25 +1168,18 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
             if (kPaired && acc) done[n_done] = id;
         }
         n_done += acc ? 1 : 0;
-        if (kRegS > 0) {
-            if (lane == (s0 & 63)) {
-                slots_set(rv0, s0 >> 6, e0);
-                slots_best(rv0, rm0, lane, K, bv0, bs0, bm0);
-            }
-            if (lane == (s1 & 63)) {
-                slots_set(rv1, s1 >> 6, e1);
-                slots_best(rv1, rm1, lane, K, bv1, bs1, bm1);
-            }
-        } else {
-            if (lane == (s0 & 63)) {
-                cv[s0] = e0;
-                lane_best(0, bv0, bs0);
-                bm0 = cm[bs0];
-            }
-            if (lane == (s1 & 63)) {
-                cv[K + s1] = e1;
-                lane_best(1, bv1, bs1);
-                bm1 = cm[K + bs1];
+        // the owner of each popped slot (one lane per half) takes its new
+        // estimate and rescans its slots
+        const int so = half ? s1 : s0;
+        if (q == (so & 31)) {
+            const double e = half ? e1 : e0;
+            if (kRegS > 0) {
+                slots_set(rv, so >> 5, e);
+                slots_best(rv, rm, q, K, bv, bs, bm);
+            } else {
+                cv[half * K + so] = e;
+                lane_best(bv, bs);
+                bm = cm[half * K + bs];
             }
         }
     }
@@ -1709,15 +1730,15 @@ hipError_t launch_xy_candidates(const T* x, const T* y, int64_t n, int32_t k, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // K <= 256: the columns always fit (at most 2 x 32 x 256 x 8 B plus
-    // 40 K + 4 k bytes), and a lane's 4 slots per run stay in registers
+    // 40 K + 4 k bytes), and a lane's 8 slots of its run stay in registers
     const bool cols = lockstep_lds(K, k, spec.n, true) <= kLdsBytes;
     const bool regs = K <= 256 && cols;
     if (paired) {
-        if (regs) return launch_lockstep<T, true, true, 4>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+        if (regs) return launch_lockstep<T, true, true, 8>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
         return cols ? launch_lockstep<T, true, true, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
                     : launch_lockstep<T, true, false, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
     }
-    if (regs) return launch_lockstep<T, false, true, 4>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+    if (regs) return launch_lockstep<T, false, true, 8>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
     return cols ? launch_lockstep<T, false, true, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
                 : launch_lockstep<T, false, false, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
 }
