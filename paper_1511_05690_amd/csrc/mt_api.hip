@@ -422,7 +422,7 @@ struct BwdLayout {
     int64_t m_out, k_out, n_out;  // output rows / cols padded to the adjoint tile
     int64_t m_in, n_in;           // inner lengths padded to the K step
     int32_t g_planes;             // adjoint planes per batch item
-    size_t hdr, r, c, xa, yb, pa, pb, total;
+    size_t hdr, r, c, ex, xa, yb, pa, pb, total;
 };
 
 BwdLayout backward_layout(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
@@ -441,6 +441,7 @@ BwdLayout backward_layout(const Family& f, int64_t b, int64_t m, int64_t k, int6
     L.hdr = off; off += align_up(sizeof(WsHeader));
     L.r = off;   off += align_up((size_t)(b * m) * 8);
     L.c = off;   off += align_up((size_t)(b * n) * 8);
+    L.ex = off;  off += align_up((size_t)(2 * b) * 4);
     L.xa = off;  off += align_up((size_t)b * L.g_planes * L.m_out * L.n_in * es);
     L.yb = off;  off += align_up((size_t)b * L.g_planes * L.n_out * L.m_in * es);
     L.pa = off;  off += align_up((size_t)b * pw_planes * L.k_out * L.n_in * es);
@@ -780,7 +781,11 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
     sp.xa_cols_pad = L.n_in;
     sp.yb_rows_pad = L.n_out;
     sp.yb_cols_pad = L.m_in;
-    MT_TRY(launch_adjoint_prep(G, C, p_star, f64, r, c, b, m, n, sp, hist, f.bf16, ws + L.xa, ws + L.yb, st),
+    // BF16 planes carry r_i and c_j divided by a power of two per batch item
+    // (their largest value then fits in (0, 1]); the adjoint GEMMs scale back
+    int32_t* ex = f.bf16 ? (int32_t*)(ws + L.ex) : nullptr;
+    if (ex) MT_TRY(launch_scale_exp(r, c, b, m, n, ex, st), "scale exponents");
+    MT_TRY(launch_adjoint_prep(G, C, p_star, f64, r, c, ex, b, m, n, sp, hist, f.bf16, ws + L.xa, ws + L.yb, st),
            "adjoint planes");
 
     // every power split into hi + lo on the BF16 path (G has mixed signs)
@@ -829,6 +834,7 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
         aa.hist = hist;
         aa.out = dA;
         aa.out_f64 = f64;
+        aa.post_exp = ex ? ex + b : nullptr;  // the Gt planes carry c_j / 2^ex
         if (f.bf16)
             MT_TRY(launch_adjoint_gemm_bf16((const uint16_t*)(ws + L.xa), (const uint16_t*)(ws + L.pa), b, m, k,
                                             L.m_out, L.k_out, L.n_in, L.g_planes, ps.n_planes, plan, aa, st),
@@ -851,6 +857,7 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
         ab.hist = hist;
         ab.out = dB;
         ab.out_f64 = f64;
+        ab.post_exp = ex;  // the Gt' planes carry r_i / 2^ex
         if (f.bf16)
             MT_TRY(launch_adjoint_gemm_bf16((const uint16_t*)(ws + L.pb), (const uint16_t*)(ws + L.yb), b, k, n,
                                             L.k_out, L.n_out, L.m_in, ps.n_planes, L.g_planes, plan, ab, st),

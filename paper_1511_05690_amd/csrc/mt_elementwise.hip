@@ -252,10 +252,12 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
         double sc = 1.0;
         if (scale_rows != nullptr && t < rows) sc = scale_rows[bi * rows + t];
         const bool zero_row = (t >= rows) || (sc == 0.0);
-        if (scale_cols == nullptr && !zero_row && u + 8 <= cols && (kTranspose || (cols & 3) == 0)) {
+        if (scale_cols == nullptr && !zero_row && sc >= DBL_MIN && u + 8 <= cols &&
+            (kTranspose || (cols & 3) == 0)) {
             // whole chunk inside the row and (untransposed) 16-byte aligned:
             // vector loads and one reciprocal per row instead of 8 divisions
-            // (the scaled value may differ from src / scale by one FP64 ulp)
+            // (the scaled value may differ from src / scale by one FP64 ulp;
+            // a subnormal scale, whose reciprocal overflows, divides below)
             TS v[8];
             if (kTranspose) {
 #pragma unroll

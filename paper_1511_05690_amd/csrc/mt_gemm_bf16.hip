@@ -48,6 +48,31 @@ __device__ __forceinline__ int swz(int row) { return (row >> 1) & 7; }
 
 
 
+// A row or column scale as mantissa x 2^exp, mantissa in [0.5, 1) (0 for a
+// zero scale).  The epilogues multiply the FP32 mantissas with the root and
+// apply the summed exponent with one ldexp in the output's precision, so
+// r_i c_j S^(1/p) over- or underflows only where the result itself does,
+// whatever the range of r and c (FP64 inputs may hold scales far outside
+// FP32; FP32 inputs may have r_i c_j beyond FP32 with a finite result).
+struct ScaleSplit {
+    float m;
+    int e;
+};
+__device__ __forceinline__ ScaleSplit split_scale(double v) {
+    if (!(v > 0.0)) return ScaleSplit{0.f, 0};
+    int e = 0;
+    const double m = frexp(v, &e);
+    return ScaleSplit{(float)m, e};
+}
+// v * 2^e in the output type, rounded once.
+template <typename TO>
+__device__ __forceinline__ TO scale_out(float v, int e) {
+    if constexpr (sizeof(TO) == 8)
+        return __builtin_amdgcn_ldexp((double)v, e);
+    else
+        return __builtin_amdgcn_ldexpf(v, e);
+}
+
 // S^(1/p) in FP32 with the hardware log2 / exp2 (about 1 ulp each); S = 0
 // gives 0 (log2 0 = -inf, 2^-inf = 0), denormal S is rescaled first.
 __device__ __forceinline__ float root_f32(float S, float inv_p) {
@@ -101,7 +126,8 @@ struct SelectEpi {
     static constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
     static constexpr int NDEC = (WT_M * WT_N * 16 + 31) / 32;
     static constexpr int STG = 32 * 33;  // floats of one wave's staging tile
-    static constexpr int LDS_BYTES = (C::BM + C::BN) * 4;
+    // row and column scales: FP32 mantissas, then int exponents
+    static constexpr int LDS_BYTES = (C::BM + C::BN) * 8;
     static_assert(C::NW * STG * 4 <= C::BUF_BYTES, "staging must fit in one pipeline buffer");
 
     using Args = EpiArgs;
@@ -111,8 +137,10 @@ struct SelectEpi {
     // r = 1 projection: entries whose p* was found at the previous p and
     // whose S_{p*} is parked in `out` until S at this (next smaller) p is known
     uint32_t pending[NDEC];
-    float* rs;
+    float* rs;  // mantissas of the row scales (BM), then of the column scales (BN)
     float* cs;
+    int* res;   // their exponents
+    int* ces;
     int lr0, lc0;
     int64_t out_lane;
     int32_t rows_left, cols_left, diag_off;
@@ -180,6 +208,8 @@ struct SelectEpi {
         n = g.cols;
         rs = (float*)lds;
         cs = rs + C::BM;
+        res = (int*)(rs + C::BM + C::BN);
+        ces = res + C::BM;
         // Row / column scales of this tile (1 where absent or padding).
         for (int i = tid; i < C::BM + C::BN; i += C::THREADS) {
             double v = 1.0;
@@ -189,7 +219,9 @@ struct SelectEpi {
                 const int64_t cc = t.col0 + (i - C::BM);
                 if (a.c && cc < n) v = a.c[(int64_t)t.bi * n + cc];
             }
-            rs[i] = (float)v;
+            const ScaleSplit sp = split_scale(v);
+            rs[i] = sp.m;
+            res[i] = sp.e;
         }
         // Tile (i, j) of this wave is staged through LDS as a 32 x 32 block;
         // lane l then handles rows 2q + l/32 (q = 0..15) of column l%32, so
@@ -290,10 +322,11 @@ struct SelectEpi {
     // Final output of entry (roff, j) from its ring result S at a p with
     // root factor inv_p (p_is_1: no root) and norm correction corr.
     __device__ void put(TO* out, int roff, int j, int64_t o, float S, bool p_is_1, float inv_p, float corr) {
-        float v = rs[lr0 + roff] * cs[lc0 + j * 32] * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
-        if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
-        if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) v = 1.f;
-        out[o] = (TO)v;
+        const float v = rs[lr0 + roff] * cs[lc0 + j * 32] * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
+        TO w = scale_out<TO>(v, res[lr0 + roff] + ces[lc0 + j * 32]);
+        if (MODE == EPI_APSP_X || a.clamp) w = w < TO(1) ? w : TO(1);
+        if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) w = TO(1);
+        out[o] = w;
     }
 
     // stage: a free pipeline buffer (C::NW staging tiles of STG floats).
@@ -411,7 +444,8 @@ struct SelectEpi {
 template <class C, typename TM>
 struct AdjointEpi {
     static constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
-    static constexpr int LDS_BYTES = (C::BM + C::BN) * 4;
+    // inverse mantissas of the row and column scales, then their exponents
+    static constexpr int LDS_BYTES = (C::BM + C::BN) * 8;
 
     using Args = AdjArgs;
     AdjArgs a;
@@ -419,6 +453,8 @@ struct AdjointEpi {
     f32x16 tot[WT_M][WT_N];
     float* rs;
     float* cs;
+    int* res;
+    int* ces;
     int lr0, lc0;
     int64_t lane_off;
     int32_t rows_left, cols_left;
@@ -437,6 +473,11 @@ struct AdjointEpi {
         cols = g.cols;
         rs = (float*)lds;
         cs = rs + C::BM;
+        res = (int*)(rs + C::BM + C::BN);
+        ces = res + C::BM;
+        // scale v = m 2^e: M / v is formed as (M 2^-e) / m, so neither a
+        // scale outside FP32 nor an FP64 entry beyond it overflows (the
+        // scaled value is in [0, 1])
         for (int i = tid; i < C::BM + C::BN; i += C::THREADS) {
             double v = 1.0;
             if (i < C::BM) {
@@ -445,7 +486,9 @@ struct AdjointEpi {
                 const int64_t cc = t.col0 + (i - C::BM);
                 if (a.scale_cols && cc < cols) v = a.scale_cols[(int64_t)t.bi * cols + cc];
             }
-            rs[i] = v > 0.0 ? (float)(1.0 / v) : 0.f;
+            const ScaleSplit sp = split_scale(v);
+            rs[i] = sp.m > 0.f ? 1.f / sp.m : 0.f;
+            res[i] = sp.e;
         }
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
@@ -470,13 +513,22 @@ struct AdjointEpi {
             for (int j = 0; j < WT_N; ++j) {
                 const bool col_ok = j * 32 < cols_left;
                 const float cinv = cs[lc0 + j * 32];
+                const int cexp = ces[lc0 + j * 32];
                 float x[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int roff = i * 32 + (r >> 2) * 8 + (r & 3);
-                    x[r] = (col_ok && roff < rows_left)
-                               ? (float)((double)src[(int64_t)roff * cols + j * 32]) * rs[lr0 + roff] * cinv
-                               : 0.f;
+                    float v = 0.f;
+                    if (col_ok && roff < rows_left) {
+                        const int ex = -(res[lr0 + roff] + cexp);
+                        const TM mv = src[(int64_t)roff * cols + j * 32];
+                        if constexpr (sizeof(TM) == 8)
+                            v = (float)__builtin_amdgcn_ldexp(mv, ex);
+                        else
+                            v = __builtin_amdgcn_ldexpf(mv, ex);
+                        v = v * rs[lr0 + roff] * cinv;
+                    }
+                    x[r] = v;
                 }
                 // x^(p-1) by binary powering (p uniform); 0^0 = 1
                 float pw[16];
@@ -495,7 +547,9 @@ struct AdjointEpi {
             }
     }
 
-    __device__ void finish(const TileCtx&) {
+    __device__ void finish(const TileCtx& t) {
+        // the adjoint planes carry the scales divided by 2^post (per batch item)
+        const int post = a.post_exp ? a.post_exp[t.bi] : 0;
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
@@ -507,9 +561,9 @@ struct AdjointEpi {
                     if (roff < rows_left) {
                         const int64_t o = lane_off + (int64_t)roff * cols + j * 32;
                         if (a.out_f64)
-                            ((double*)a.out)[o] = (double)tot[i][j][r];
+                            ((double*)a.out)[o] = scale_out<double>(tot[i][j][r], post);
                         else
-                            ((float*)a.out)[o] = tot[i][j][r];
+                            ((float*)a.out)[o] = scale_out<float>(tot[i][j][r], post);
                     }
                 }
             }
@@ -948,7 +1002,7 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
         w += gn;
         const int16_t state = te[0].state;
         const uint16_t* xr = g.X + (int64_t)te[0].bi * g.x_batch_elems + (int64_t)te[0].i * g.kp;
-        const float r_i = a.r ? (float)a.r[(int64_t)te[0].bi * g.rows + te[0].i] : 1.f;
+        const ScaleSplit r_i = split_scale(a.r ? a.r[(int64_t)te[0].bi * g.rows + te[0].i] : 1.0);
         const uint16_t* yr[G];
         int64_t o[G];
         float Sh[G], S[G];
@@ -965,10 +1019,11 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
         }
         // final value of entry q: the scales, clamp and APSP diagonal
         auto put = [&](int q, float v) {
-            v *= r_i * (a.c ? (float)a.c[(int64_t)te[q].bi * g.cols + te[q].j] : 1.f);
-            if (MODE == EPI_APSP_X || a.clamp) v = fminf(v, 1.f);
-            if (MODE == EPI_APSP_X && te[q].i == te[q].j) v = 1.f;
-            if (lane == 0) out[o[q]] = (TO)v;
+            const ScaleSplit c_j = split_scale(a.c ? a.c[(int64_t)te[q].bi * g.cols + te[q].j] : 1.0);
+            TO w = scale_out<TO>(v * r_i.m * c_j.m, r_i.e + c_j.e);
+            if (MODE == EPI_APSP_X || a.clamp) w = w < TO(1) ? w : TO(1);
+            if (MODE == EPI_APSP_X && te[q].i == te[q].j) w = TO(1);
+            if (lane == 0) out[o[q]] = w;
             live[q] = false;
         };
         if (!R1 && state == kTailRise) {

@@ -288,7 +288,8 @@ struct StoreAllEpi {
 template <class C, typename TM>
 struct AdjointEpiF64 {
     static constexpr int WT = C::WT;
-    static constexpr int LDS_BYTES = 2 * C::BM * 8;
+    // inverse mantissas of the row and column scales, then their exponents
+    static constexpr int LDS_BYTES = 2 * C::BM * 8 + 2 * C::BM * 4;
     using Args = AdjArgs;
     static constexpr bool kCanStop = false;
     AdjArgs a;
@@ -296,6 +297,8 @@ struct AdjointEpiF64 {
     f64x4 tot[WT][WT];
     double* rs;
     double* cs;
+    int* res;
+    int* ces;
     int lr0, lc0;
     int64_t lane_off;
     int32_t rows_left, cols_left;
@@ -312,6 +315,10 @@ struct AdjointEpiF64 {
         cols = g.cols;
         rs = (double*)lds;
         cs = rs + C::BM;
+        res = (int*)(rs + 2 * C::BM);
+        ces = res + C::BM;
+        // scale v = m 2^e: M / v is formed as (M 2^-e) / m, finite also for
+        // a subnormal scale (whose reciprocal is not)
         for (int i = tid; i < 2 * C::BM; i += kThreads) {
             double v = 1.0;
             if (i < C::BM) {
@@ -320,7 +327,10 @@ struct AdjointEpiF64 {
                 const int64_t cc = t.col0 + (i - C::BM);
                 if (a.scale_cols && cc < cols) v = a.scale_cols[(int64_t)t.bi * cols + cc];
             }
-            rs[i] = v > 0.0 ? 1.0 / v : 0.0;
+            int e = 0;
+            const double m = v > 0.0 ? frexp(v, &e) : 0.0;
+            rs[i] = m > 0.0 ? 1.0 / m : 0.0;
+            res[i] = e;
         }
 #pragma unroll
         for (int i = 0; i < WT; ++i)
@@ -342,12 +352,15 @@ struct AdjointEpiF64 {
             for (int j = 0; j < WT; ++j) {
                 const bool col_ok = j * 16 < cols_left;
                 const double cinv = cs[lc0 + j * 16];
+                const int cexp = ces[lc0 + j * 16];
                 double x[4], pw[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int roff = i * 16 + 4 * r;
                     x[r] = (col_ok && roff < rows_left)
-                               ? (double)src[(int64_t)roff * cols + j * 16] * rs[lr0 + roff] * cinv
+                               ? __builtin_amdgcn_ldexp((double)src[(int64_t)roff * cols + j * 16],
+                                                        -(res[lr0 + roff] + cexp)) *
+                                     rs[lr0 + roff] * cinv
                                : 0.0;
                     pw[r] = 1.0;
                 }

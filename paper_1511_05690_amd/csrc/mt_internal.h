@@ -123,6 +123,9 @@ struct AdjArgs {
     const int32_t* hist;      // per family index: number of entries using that p
     void* out;                // b x rows x cols (dA or dB)
     int32_t out_f64;
+    // nullable, per batch item: the result is multiplied by 2^post_exp (the
+    // BF16 adjoint planes hold c_j or r_i divided by that power of two)
+    const int32_t* post_exp;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -247,9 +250,13 @@ struct AdjPrepSpec {
     int64_t yb_rows_pad, yb_cols_pad;  // Gt' planes, transposed (rows n, inner m)
 };
 hipError_t launch_pstar_hist(const uint8_t* ps, int64_t total, int n_p, int32_t* hist, hipStream_t st);
+// ex (nullable, 2 b entries, from launch_scale_exp): the planes then carry
+// r_i / 2^ex[bi] and c_j / 2^ex[b + bi].
+hipError_t launch_scale_exp(const double* r, const double* c, int64_t b, int64_t m, int64_t n, int32_t* ex,
+                            hipStream_t st);
 hipError_t launch_adjoint_prep(const void* G, const void* C, const uint8_t* pstar, int io_f64,
-                               const double* r, const double* c, int64_t b, int64_t m, int64_t n,
-                               const AdjPrepSpec& spec, const int32_t* hist, int bf16, void* XA,
+                               const double* r, const double* c, const int32_t* ex, int64_t b, int64_t m,
+                               int64_t n, const AdjPrepSpec& spec, const int32_t* hist, int bf16, void* XA,
                                void* YB, hipStream_t st);
 
 // Adjoint GEMMs (rows x cols output, inner k_pad; X planes per batch item,

@@ -1026,8 +1026,10 @@ __device__ __forceinline__ void half_argmax(double v, int s, double& a0, int& s0
 // candidates' sigma
 // columns are updated in LDS when they fit (kColsLds), else in the
 // workspace copy; with kRegS > 0 (K <= 32 kRegS) a lane's slots, estimates
-// and diagonals, stay in registers.
-template <typename T, bool kPaired, bool kColsLds, int kRegS>
+// and diagonals, stay in registers.  The log diagonal lengths of the paired
+// acceptance test are kept in LDS when they fit (kLenLds), else taken from
+// the popped diagonals each rank (the same values).
+template <typename T, bool kPaired, bool kColsLds, int kRegS, bool kLenLds>
 __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict__ x, const T* __restrict__ y,
                                                           int64_t n, MaxconvSpec spec,
                                                           const int32_t* __restrict__ cand_m,
@@ -1036,18 +1038,19 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
                                                           double* __restrict__ values, int32_t* __restrict__ diag,
                                                           int32_t* __restrict__ anti, int32_t* __restrict__ ii,
                                                           int32_t* __restrict__ jj) {
-    // LDS: 2K log estimates, 2K log diagonal lengths, [2 np K column cells],
-    // 2K diagonals, k reported pairs.  The queue keeps log psi: the argmax
+    // LDS: 2K log estimates, [2K log diagonal lengths], [2 np K column
+    // cells], 2K diagonals, [k reported pairs (paired)].  The queue keeps log psi: the argmax
     // order is psi's, the reported value needs the log, the subtraction
     // exp(p log psi) and the new root exp(log S / p) then need no log or exp
     // of their own.
     extern __shared__ double cv[];
     const int lane = threadIdx.x;
     const int np = spec.n, nn = (int)n;
-    double* cl = cv + 2 * K;
-    double* cols = kColsLds ? cv + 4 * K : cand_cols;
-    int* cm = (int*)(cv + 4 * K + (kColsLds ? 2 * np * K : 0));
-    int* done = cm + 2 * K;
+    constexpr int kLen = kPaired && kLenLds ? 1 : 0;
+    double* cl = cv + 2 * K;  // used when kLen
+    double* cols = kColsLds ? cv + (2 + 2 * kLen) * K : cand_cols;
+    int* cm = (int*)(cv + (2 + 2 * kLen) * K + (kColsLds ? 2 * np * K : 0));
+    int* done = cm + 2 * K;  // paired only
     int n_done = 0;
     double mx = -INFINITY, my = -INFINITY;
     for (int i = lane; i < nn; i += 64) {
@@ -1063,7 +1066,7 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
         const double e = cand_psi[s];
         const int m = cand_m[s];
         cv[s] = e > 0.0 ? log(e) : -INFINITY;
-        cl[s] = log((double)diag_len(m, nn));
+        if (kLen) cl[s] = log((double)diag_len(m, nn));
         cm[s] = m;
     }
     if (kColsLds)
@@ -1137,8 +1140,10 @@ __global__ __launch_bounds__(64) void mt_xy_lockstep_kernel(const T* __restrict_
             const int q0 = lo_b ? 31 - __clz(lo_b) : -1, q1 = hi_b ? 31 - __clz(hi_b) : -1;
             // in logs: log v >= log psi - log(len) / p* on both diagonals
             lv = (xi - mx) + (yj - my);
-            acc = valid && q0 >= 0 && q1 >= 0 && lv >= la0 - cl[s0] * readlane_f64(ipw, q0 >= 0 ? q0 : 0) &&
-                  lv >= la1 - cl[K + s1] * readlane_f64(ipw, q1 >= 0 ? 32 + q1 : 32);
+            const double ll0 = kLen ? cl[s0] : log((double)diag_len(m1, nn));
+            const double ll1 = kLen ? cl[K + s1] : log((double)diag_len(m2, nn));
+            acc = valid && q0 >= 0 && q1 >= 0 && lv >= la0 - ll0 * readlane_f64(ipw, q0 >= 0 ? q0 : 0) &&
+                  lv >= la1 - ll1 * readlane_f64(ipw, q1 >= 0 ? 32 + q1 : 32);
         }
         const double la = acc ? lv : (half ? la1 : la0);
         double s = 0.0;
@@ -1684,20 +1689,23 @@ hipError_t launch_xy_long(const T* x, const T* y, int64_t n, const MaxconvSpec& 
     return hipGetLastError();
 }
 
-// LDS bytes of the lockstep queue: log estimates, log lengths and diagonals
-// of 2K candidates, the reported pairs, and the 2 |P| K column cells when
-// they are kept there.
-size_t lockstep_lds(int K, int k, int np, bool cols) {
-    return (size_t)2 * K * (2 * sizeof(double) + sizeof(int)) + (size_t)k * sizeof(int) +
+// LDS bytes of the lockstep queue: log estimates and diagonals of 2K
+// candidates; paired: the reported pairs and, when kept there, the log
+// lengths; the 2 |P| K column cells when they are kept there.
+size_t lockstep_lds(int K, int k, int np, bool paired, bool cols, bool lens) {
+    return (size_t)2 * K * (sizeof(double) + sizeof(int)) +
+           (paired ? (size_t)k * sizeof(int) + (lens ? (size_t)2 * K * sizeof(double) : 0) : 0) +
            (cols ? (size_t)2 * np * K * sizeof(double) : 0);
 }
 constexpr size_t kLdsBytes = 160 * 1024;
 
-template <typename T, bool kPaired, bool kColsLds, int kRegS>
+template <typename T, bool kPaired, bool kColsLds, int kRegS, bool kLenLds = true>
 hipError_t launch_lockstep(const T* x, const T* y, int64_t n, int32_t k, int K, const MaxconvSpec& spec,
                            double* values, int32_t* diag, int32_t* ii, int32_t* jj, const XyWorkspace& w,
                            hipStream_t st) {
-    auto queue = mt_xy_lockstep_kernel<T, kPaired, kColsLds, kRegS>;
+    auto queue = mt_xy_lockstep_kernel<T, kPaired, kColsLds, kRegS, kLenLds>;
+    const size_t lds = lockstep_lds(K, k, spec.n, kPaired, kColsLds, kLenLds);
+    if (lds > kLdsBytes) return hipErrorInvalidValue;
     static std::atomic<uint64_t> attr_set{0};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1709,7 +1717,7 @@ hipError_t launch_lockstep(const T* x, const T* y, int64_t n, int32_t k, int K, 
         attr_set.fetch_or(bit);
     }
     timing_before(kPaired ? "mt_xy_paired" : "mt_xy_queue", st);
-    hipLaunchKernelGGL(queue, dim3(1), dim3(64), lockstep_lds(K, k, spec.n, kColsLds), st, x, y, n, spec, w.cand_m,
+    hipLaunchKernelGGL(queue, dim3(1), dim3(64), lds, st, x, y, n, spec, w.cand_m,
                        w.cand_psi, w.cand_cols, K, k, values, diag, w.diag1, ii, jj);
     timing_after(st);
     return hipGetLastError();
@@ -1730,13 +1738,17 @@ hipError_t launch_xy_candidates(const T* x, const T* y, int64_t n, int32_t k, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // K <= 256: the columns always fit (at most 2 x 32 x 256 x 8 B plus
-    // 40 K + 4 k bytes), and a lane's 8 slots of its run stay in registers
-    const bool cols = lockstep_lds(K, k, spec.n, true) <= kLdsBytes;
+    // 40 K + 4 k bytes), and a lane's 8 slots of its run stay in registers.
+    // The largest case, K = k = 4096, needs 40 K = 160 KiB plain and
+    // 24 K + 4 k paired with the log lengths taken per rank.
+    const bool cols = lockstep_lds(K, k, spec.n, paired, true, true) <= kLdsBytes;
     const bool regs = K <= 256 && cols;
     if (paired) {
         if (regs) return launch_lockstep<T, true, true, 8>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
-        return cols ? launch_lockstep<T, true, true, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)
-                    : launch_lockstep<T, true, false, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+        if (cols) return launch_lockstep<T, true, true, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+        if (lockstep_lds(K, k, spec.n, true, false, true) <= kLdsBytes)
+            return launch_lockstep<T, true, false, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
+        return launch_lockstep<T, true, false, 0, false>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
     }
     if (regs) return launch_lockstep<T, false, true, 8>(x, y, n, k, K, spec, values, diag, ii, jj, w, st);
     return cols ? launch_lockstep<T, false, true, 0>(x, y, n, k, K, spec, values, diag, ii, jj, w, st)

@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 from parity import TAU, compare_estimate
-from workloads import lognormal_product, rgg_graph, er_graph
+from workloads import crossed_product, lognormal_product, rgg_graph, er_graph
 
 pytestmark = pytest.mark.gpu
 
@@ -46,13 +46,14 @@ def _dev(x):
 @pytest.mark.parametrize("path", ["bf16", "fp64"])
 def test_every_start_parity(knobs, path, thr):
     """Log-normal terms spread p* over the family; a second batch item of
-    sixth powers (a log-normal six times as wide, scaled into (0, 1] so that
-    r c stays in FP32 range) moves it further down."""
+    sixth powers (a log-normal six times as wide) moves it further down; a
+    third, unscaled, has r c beyond FP32 (about 1e40) with outputs near 1e25."""
     A, B = lognormal_product(300, 1000, 290, seed=78)
     A = A.astype(np.float64)
     B = B.astype(np.float64)
-    A = np.stack([A, (A[::-1] / A.max()) ** 6])
-    B = np.stack([B, (B[:, ::-1] / B.max()) ** 6])
+    Ax, Bx = crossed_product(300, 1000, 290, seed=80, big=1e20, small=1e5, dtype=np.float64)
+    A = np.stack([A, (A[::-1] / A.max()) ** 6, Ax])
+    B = np.stack([B, (B[:, ::-1] / B.max()) ** 6, Bx])
     if path == "bf16":
         A, B = A.astype(np.float32), B.astype(np.float32)
     knobs.set_tail_threshold(thr)

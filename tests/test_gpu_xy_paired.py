@@ -125,3 +125,24 @@ def test_paired_rejects_large_k(gpu_lib):
     x = torch.zeros(16, dtype=torch.float64, device="cuda")
     with pytest.raises(gpu_lib.MaxTimesError, match="k <= 4096"):
         gpu_lib.xy_topk(x, x, 4097, paired=True)
+
+
+def test_paired_largest_k_at_the_largest_n(gpu_lib):
+    """n = 8192, k = 4096: 2 x 4096 candidates, the reported pairs and the
+    estimates exceed LDS with the log lengths, which are then taken per rank.
+    The first 256 ranks against the oracle (the depth the k = 256 case
+    checks; candidates are exact, so ranks do not depend on k), every rank's
+    properties, and the first 1000 ranks equal to a k = 1000 call (log
+    lengths kept in LDS there)."""
+    rng = np.random.default_rng(5005)
+    x = rng.uniform(0, 40, 8192)
+    y = rng.uniform(0, 40, 8192)
+    print("[xy] paired n=8192 k=4096", flush=True)
+    v, i, j, d = _run(gpu_lib, x, y, 4096)
+    o = xy_topk_paired(x, y, P24, 256)
+    _check(v[:256], i[:256], j[:256], d[:256], o)
+    _check_properties(x, y, v, i, j, d)
+    v2, i2, j2, d2 = _run(gpu_lib, x, y, 1000)
+    np.testing.assert_array_equal(i[:1000], i2)
+    np.testing.assert_array_equal(d[:1000], d2)
+    np.testing.assert_array_equal(v[:1000], v2)

@@ -186,3 +186,26 @@ def test_queue_over_every_diagonal_matches_the_candidate_queue(gpu_lib):
     o = xy_topk_estimate(xn, yn, P24, 1)
     np.testing.assert_allclose(b[0].cpu().numpy()[0], o["values"][0], rtol=0, atol=1e-9)
     assert b[3].cpu().numpy()[0] == o["diag"][0]
+
+
+def test_largest_k_at_the_largest_n(gpu_lib):
+    """n = 8192, k = 4096 (the sizes of Sec. 3 with the largest k of the
+    candidate queue: K = 4096 candidates per run, 160 KiB of LDS): the first
+    128 ranks of uniform lists on [0, 1] against the oracle (the depth whose
+    sequence does not depend on rounding), and every rank the same as a call
+    with a smaller k gives (the candidates are exact at every rank)."""
+    rng = np.random.default_rng(9800)
+    x = rng.uniform(0, 1, 8192)
+    y = rng.uniform(0, 1, 8192)
+    print("[xy] plain n=8192 k=4096", flush=True)
+    v, i, j, d = gpu_lib.xy_topk(_dev(x), _dev(y), 4096, P24, return_diag=True)
+    v, i, j, d = (t.cpu().numpy() for t in (v, i, j, d))
+    ref = xy_topk_estimate(x, y, P24, 128)
+    np.testing.assert_array_equal(d[:128], ref["diag"])
+    np.testing.assert_allclose(v[:128], ref["values"], rtol=0, atol=1e-6)
+    np.testing.assert_array_equal(i[:128], ref["i"])
+    np.testing.assert_array_equal(j[:128], ref["j"])
+    v2, i2, j2, d2 = (t.cpu().numpy() for t in gpu_lib.xy_topk(_dev(x), _dev(y), 1000, P24, return_diag=True))
+    np.testing.assert_array_equal(d[:1000], d2)
+    np.testing.assert_array_equal(i[:1000], i2)
+    np.testing.assert_allclose(v[:1000], v2, rtol=1e-12, atol=0)

@@ -17,6 +17,12 @@ dense graphs, Sec. 3 Table 1, so every input here is synthetic):
                      scale * Euclidean length, FP32, +inf = no edge
   dense_graph        complete digraph with U[lo, hi) weights (the shape of
                      the paper's Table 1 instances)
+  crossed_product    log-normal A, B whose inner index halves are scaled by a
+                     large and a small factor in opposite order (every term
+                     is about big * small, the row and column maxima about
+                     big): scales beyond FP32 with moderate products
+  wide_scale_product FP64 log-normal A, B with rows of A and columns of B
+                     scaled by 10^(+-decades)
   maxconv_vectors    b pairs of nonnegative vectors (x of length n, y of
                      length m) for the max-convolution of Sec. 1: "uniform"
                      (1 - U[0, 1)), "lognormal" (exp(N(0, 2^2))), "sparse"
@@ -143,3 +149,29 @@ def config(i):
         return {"W": rgg_graph(16384, 0.02, 100.0, seed), "s": 0.35, "T": 14,
                 "P": pfamily(128), "path": "bf16"}
     raise ValueError(i)
+
+
+def crossed_product(m, k, n, seed, big, small, dtype):
+    """A's first half of the inner index is `big`, its second `small`; B the
+    other way round.  Every term is about big * small, while r_i c_j is
+    about big^2."""
+    rng = np.random.default_rng(seed)
+    h = k // 2
+    A = np.exp(rng.normal(0.0, 1.0, (m, k)))
+    B = np.exp(rng.normal(0.0, 1.0, (k, n)))
+    A[:, :h] *= big
+    A[:, h:] *= small
+    B[:h] *= small
+    B[h:] *= big
+    return A.astype(dtype), B.astype(dtype)
+
+
+def wide_scale_product(m, k, n, seed, decades):
+    """FP64 log-normal A, B with row i of A scaled by 10^(+-decades) and
+    column j of B by 10^(+-decades), signs at random."""
+    rng = np.random.default_rng(seed)
+    A = np.minimum(np.exp(rng.normal(0.0, 1.5, (m, k))), 1e6)
+    B = np.minimum(np.exp(rng.normal(0.0, 1.5, (k, n))), 1e6)
+    A *= (10.0 ** (decades * rng.choice([-1.0, 1.0], m)))[:, None]
+    B *= (10.0 ** (decades * rng.choice([-1.0, 1.0], n)))[None, :]
+    return A, B
