@@ -408,8 +408,10 @@ mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* la
  * most, and often less than, 2 * rows_pad * cols_pad * k_pad per segment of
  * the family.  The max-convolution counts 10 N log2 N flops (two complex FFTs
  * of N points, 5 N log2 N each by the usual count) per pair and p visited.
- * Counters live in device memory that the timing facility allocates on first
- * use; reset waits for the recorded launches and clears them.
+ * The counters are a static device array of the library (8192 launches per
+ * reset, on the device current at the first timed launch that counts work;
+ * nothing is allocated); reset waits for the recorded launches and clears
+ * them.
  */
 mt_status maxtimes_timing_work(const char* prefix, double* flops);
 

@@ -52,9 +52,12 @@ struct TimedLaunch {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_launches;
-// Executed-flop counters of timed launches (device memory, one per launch,
-// allocated on first use, zeroed at reset).
+// Executed-flop counters of timed launches (one per launch, zeroed at
+// reset): a device array of the library, so that timing allocates nothing;
+// g_work is its address on the device that was current at the first timed
+// launch that counts work.
 constexpr int kWorkSlots = 8192;
+__device__ __align__(256) unsigned long long timing_work_counters[kWorkSlots];
 unsigned long long* g_work = nullptr;
 int g_work_used = 0;
 }  // namespace
@@ -80,12 +83,10 @@ unsigned long long* timing_work_slot() {
     if (!g_timing || g_launches.empty() || g_work_used >= kWorkSlots) return nullptr;
     if (!g_work) {
         void* p = nullptr;
-        if (hipMalloc(&p, kWorkSlots * sizeof(unsigned long long)) != hipSuccess) return nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(timing_work_counters)) != hipSuccess) return nullptr;
         if (hipMemset(p, 0, kWorkSlots * sizeof(unsigned long long)) != hipSuccess ||
-            hipDeviceSynchronize() != hipSuccess) {
-            (void)hipFree(p);
+            hipDeviceSynchronize() != hipSuccess)
             return nullptr;
-        }
         g_work = (unsigned long long*)p;
     }
     g_launches.back().work_slot = g_work_used;
