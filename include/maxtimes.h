@@ -201,6 +201,27 @@ mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype,
                             const mt_options* opt, void* C, uint8_t* p_star,
                             void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * maxtimes_estimate without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * maxtimes_estimate; the workspace is a static device array of the library
+ * of MT_NOALLOC_SCRATCH_BYTES bytes (one per GPU, on the device current at
+ * the call, which must hold A, B, C and p_star; each GPU keeps it until the
+ * process ends).  The call allocates nothing.  A product whose workspace
+ * (maxtimes_workspace_size) exceeds the scratch returns MT_ERR_WORKSPACE
+ * before anything is enqueued.  Every call on one GPU shares that GPU's
+ * scratch: calls whose stream work overlaps on one GPU (two streams, or two
+ * threads) race on it and give undefined results; calls in order on one
+ * stream are safe.  The call clears with kernels what its kernels need at
+ * zero; the scratch otherwise keeps the last call's contents.
+ */
+#define MT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mt_status maxtimes_estimate_noalloc(const void* A, const void* B, mt_dtype dtype,
+                                    int64_t b, int64_t m, int64_t k, int64_t n,
+                                    const mt_options* opt, void* C, uint8_t* p_star,
+                                    void* stream);
+
 /* Workspace bytes needed by maxtimes_estimate_backward. */
 mt_status maxtimes_backward_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n,
                                            const mt_options* opt, size_t* bytes);

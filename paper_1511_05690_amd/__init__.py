@@ -37,6 +37,7 @@ PATHS = {"fp64": 0, "bf16": 1}
 F32, F64 = 0, 1
 FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT, FLAG_PROJECT_R1, FLAG_PROJECT_R2 = 1, 2, 4, 8, 16, 32
 FLAG_XY_PAIRED = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20  # MT_NOALLOC_SCRATCH_BYTES
 PROJECTIONS = {None: 0, "r1": FLAG_PROJECT_R1, "r2": FLAG_PROJECT_R2}
 STATUS = {0: "MT_OK", 1: "MT_ERR_INVALID_ARG", 2: "MT_ERR_DOMAIN", 3: "MT_ERR_WORKSPACE",
           4: "MT_ERR_DEVICE", 5: "MT_ERR_UNSUPPORTED"}
@@ -92,6 +93,7 @@ def load_library():
         "maxtimes_workspace_size": [i64, i64, i64, i64, opt, ctypes.POINTER(sz)],
         "maxtimes_workspace_map": [i64, i64, i64, i64, opt, ctypes.POINTER(_WorkspaceMap)],
         "maxtimes_estimate": [vp, vp, ctypes.c_int, i64, i64, i64, i64, opt, vp, vp, vp, sz, vp],
+        "maxtimes_estimate_noalloc": [vp, vp, ctypes.c_int, i64, i64, i64, i64, opt, vp, vp, vp],
         "maxtimes_backward_workspace_size": [i64, i64, i64, i64, opt, ctypes.POINTER(sz)],
         "maxtimes_estimate_backward": [vp, vp, vp, vp, vp, ctypes.c_int, i64, i64, i64, i64, opt,
                                        vp, vp, vp, sz, vp],
@@ -250,6 +252,33 @@ def _forward(A, B, P, path, tau, split_max_p, flags, want_pstar, workspace=None)
     ps = torch.empty(shape, dtype=torch.uint8, device=A.device) if want_pstar else None
     _check(lib.maxtimes_estimate(_ptr(A), _ptr(B), _dtype_code(A), b, m, k, n, ctypes.byref(o),
                                  _ptr(C), _ptr(ps), _ptr(ws), need.value, _stream(A.device)))
+    return C, ps
+
+
+def estimate_noalloc(A, B, P=(1, 2, 4, 8, 16, 32, 64), tau=None, path="bf16", split_max_p=None, flags=0,
+                     out=None, p_star=None):
+    """maxtimes_estimate_noalloc: the estimate on the library's static scratch
+    (no workspace).  `out` and `p_star` may be preallocated tensors of the
+    output shape (C's dtype is the inputs'); returns (C, p_star)."""
+    lib = load_library()
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("A and B must be device tensors")
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    A = A.contiguous()
+    B = B.contiguous()
+    b, m, k, n, batched = _shape3(A, B)
+    o = _options(P, path, tau, split_max_p, flags)
+    shape = (b, m, n) if batched else (m, n)
+    C = out if out is not None else torch.empty(shape, dtype=A.dtype, device=A.device)
+    ps = p_star if p_star is not None else torch.empty(shape, dtype=torch.uint8, device=A.device)
+    if tuple(C.shape) != shape or C.dtype != A.dtype or not C.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of the output shape and the inputs' dtype")
+    if tuple(ps.shape) != shape or ps.dtype != torch.uint8 or not ps.is_contiguous():
+        raise ValueError("p_star must be a contiguous uint8 tensor of the output shape")
+    with torch.cuda.device(A.device):
+        _check(lib.maxtimes_estimate_noalloc(_ptr(A), _ptr(B), _dtype_code(A), b, m, k, n, ctypes.byref(o),
+                                             _ptr(C), _ptr(ps), _stream(A.device)))
     return C, ps
 
 

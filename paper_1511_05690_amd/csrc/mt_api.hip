@@ -625,9 +625,42 @@ mt_status maxtimes_workspace_map(int64_t b, int64_t m, int64_t k, int64_t n, con
     return MT_OK;
 }
 
-mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,
-                            int64_t k, int64_t n, const mt_options* opt, void* C, uint8_t* p_star,
-                            void* workspace, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace mt {
+namespace {
+
+// ------------------------------------------------------------------ static scratch
+// The workspace of maxtimes_estimate_noalloc: a device array of the library.
+// Every GPU the library runs on holds its own copy, at its own address, until
+// the process ends.  In host code the array's name is not a device address:
+// host code uses only the address hipGetSymbolAddress gives for the current
+// device, kept per device.
+constexpr size_t kScratchBytes = MT_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+mt_status scratch_of_current_device(void** out) {
+    int dev = 0;
+    MT_TRY(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MT_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        MT_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MT_OK;
+}
+
+// maxtimes_estimate on a caller workspace, or (workspace == nullptr and
+// use_scratch) on the static scratch of the current device.
+mt_status estimate_impl(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m, int64_t k, int64_t n,
+                        const mt_options* opt, void* C, uint8_t* p_star, void* workspace, size_t ws_bytes,
+                        void* stream, bool use_scratch) {
     g_last_error.clear();
     Family f;
     mt_status s = parse_options(opt, &f);
@@ -642,12 +675,24 @@ mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype, int64_
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, b, m, k, n);
     const Layout L = product_layout(f, ps, g, b, m, n, 0);
+    if (use_scratch) {
+        if (L.total > kScratchBytes)
+            return fail(MT_ERR_WORKSPACE,
+                        "this product needs %zu bytes of workspace; the static scratch of "
+                        "maxtimes_estimate_noalloc holds %zu (call maxtimes_estimate with a workspace)",
+                        L.total, kScratchBytes);
+        if ((s = scratch_of_current_device(&workspace)) != MT_OK) return s;
+        ws_bytes = kScratchBytes;
+    }
     if ((s = check_ws(workspace, ws_bytes, L.total)) != MT_OK) return s;
 
     hipStream_t st = (hipStream_t)stream;
     uint8_t* ws = (uint8_t*)workspace;
     const int f64 = dtype == MT_F64;
     int32_t* flag = (int32_t*)(ws + L.hdr);
+    // everything the kernels expect at zero is cleared by kernels of the
+    // call itself (the header: domain flag, tail count, p* histogram), so a
+    // workspace that holds an earlier call's contents is fine
     MT_TRY(launch_fill_zero_u32(ws + L.hdr, sizeof(WsHeader) / 4, st), "clear header");
     MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
     MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st), "column max");
@@ -656,6 +701,22 @@ mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype, int64_
     }
     return run_product(A, B, f64, b, m, k, n, f, ps, g, L, ws, true, EPI_PLAIN,
                        (f.flags & MT_FLAG_CLAMP) ? 1 : 0, C, f64, p_star, st);
+}
+
+}  // namespace
+}  // namespace mt
+
+extern "C" {
+
+mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m,
+                            int64_t k, int64_t n, const mt_options* opt, void* C, uint8_t* p_star,
+                            void* workspace, size_t ws_bytes, void* stream) {
+    return estimate_impl(A, B, dtype, b, m, k, n, opt, C, p_star, workspace, ws_bytes, stream, false);
+}
+
+mt_status maxtimes_estimate_noalloc(const void* A, const void* B, mt_dtype dtype, int64_t b, int64_t m, int64_t k,
+                                    int64_t n, const mt_options* opt, void* C, uint8_t* p_star, void* stream) {
+    return estimate_impl(A, B, dtype, b, m, k, n, opt, C, p_star, nullptr, 0, stream, true);
 }
 
 mt_status apsp_workspace_size(int64_t n, const mt_options* opt, size_t* bytes) {

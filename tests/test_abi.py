@@ -111,6 +111,23 @@ def test_null_pointers_and_small_workspace_rejected_before_launch():
     assert st == 1
 
 
+def test_noalloc_rejects_before_launch():
+    """maxtimes_estimate_noalloc checks its arguments, and that the product's
+    workspace fits the static scratch, before any device call."""
+    lib = mt.load_library()
+    o = _opts([1, 2, 4, 8, 16, 32, 64, 128])
+    fake = ctypes.c_void_p(0x100000)
+    null = ctypes.c_void_p(0)
+    st = lib.maxtimes_estimate_noalloc(fake, fake, 0, 1, 8, 8, 8, ctypes.byref(o), null, null, null)
+    assert st == 1 and b"C is NULL" in lib.maxtimes_last_error()
+    st = lib.maxtimes_estimate_noalloc(fake, fake, 0, 1, 4096, 4096, 4096, ctypes.byref(o), fake, null, null)
+    assert st == 3 and b"static scratch" in lib.maxtimes_last_error()
+    need = mt.workspace_size(1, 4096, 4096, 4096, [1, 2, 4, 8, 16, 32, 64, 128])
+    assert need > mt.NOALLOC_SCRATCH_BYTES
+    st = lib.maxtimes_estimate_noalloc(null, null, 0, 1, 0, 8, 8, ctypes.byref(o), null, null, null)
+    assert st == 0
+
+
 def test_apsp_argument_errors():
     lib = mt.load_library()
     o = _opts([1, 2, 4], path=0)
