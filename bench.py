@@ -286,13 +286,58 @@ def run_legs(mt, torch, np):
     del xs, ys
     torch.cuda.empty_cache()
 
+    # APSP on the 16384-vertex random geometric graph (radius 0.02, weights
+    # 100 x length, s = 0.35, 14 squarings, P = {1..128}) on the BF16 path,
+    # and once on the FP64 path for comparison; errors against exact rows
+    # from 64 sampled sources (Bellman-Ford on the GPU, the library's
+    # apsp_exact_rows)
     c5 = config(5)
     W5 = torch.from_numpy(c5["W"]).cuda()
     del c5["W"]
-    ms = time_call(lambda: mt.apsp(W5, s=c5["s"], P=c5["P"], path="bf16", n_squarings=c5["T"]), 1, torch)
-    legs["apsp_rgg16384_bf16"] = {"ms": ms, "squarings": c5["T"], "P": c5["P"],
-                                  "ops_per_s": c5["T"] * 16384.0 ** 3 / (ms / 1e3)}
+    n5 = W5.shape[0]
+    src5 = np.sort(np.random.default_rng(5006).choice(n5, 64, replace=False)).astype(np.int32)
+    ex5, rounds5 = mt.apsp_exact_rows(W5, src5)
+    si = torch.from_numpy(src5.astype(np.int64)).cuda()
+    for path in ("bf16", "fp64"):
+        if path == "bf16":  # one untimed call first; the FP64 run (seconds) is timed once, cold
+            mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        D5 = mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        legs["apsp_rgg16384_" + path] = {
+            "ms": ms, "squarings": c5["T"], "P": c5["P"], "s": c5["s"],
+            "ops_per_s": c5["T"] * float(n5) ** 3 / (ms / 1e3),
+            "vs_exact_64_sources": apsp_errors(D5[si], ex5, c5["s"], torch),
+            "exact_rows": {"sources": len(src5), "bellman_ford_rounds": rounds5}}
+        del D5
+        torch.cuda.empty_cache()
     return legs
+
+
+def apsp_errors(D, E, s, torch):
+    """Errors of estimated distances D against exact ones E (same shape, FP64
+    on the device): distance MSE, mean and largest absolute error over
+    pairs with a finite exact distance (the paper's MSE, Table 1); the
+    largest relative error in (x, max) space, |e^(-s d) / e^(-s d_exact) - 1|;
+    pairs at a positive exact distance estimated at 0 (the clamp X <= 1);
+    pairs with a finite exact distance estimated unreachable, and the
+    reverse."""
+    fin = torch.isfinite(E)
+    est_fin = torch.isfinite(D)
+    both = fin & est_fin
+    err = (D - E)[both]
+    xrel = (torch.exp(-s * (D[both] - E[both])) - 1.0).abs()
+    off = E > 0
+    return {"pairs": int(fin.sum()), "distance_mse": float((err ** 2).mean()),
+            "mean": float(err.mean()), "max_abs": float(err.abs().max()),
+            "max_rel_x": float(xrel.max()), "median_rel_x": float(xrel.median()),
+            "clamped_to_zero": int((off & fin & (D == 0)).sum()),
+            "finite_estimated_inf": int((fin & ~est_fin).sum()),
+            "inf_estimated_finite": int((~fin & est_fin).sum())}
 
 
 def main():

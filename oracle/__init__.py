@@ -32,6 +32,8 @@ from .pnorm import (  # noqa: F401
     exact_maxtimes,
     exact_maxtimes_loops,
     scale_factors,
+    balance_factors,
+    balanced,
     norm_power_sequence,
     select_pstar,
     pnorm_estimate,

@@ -52,6 +52,16 @@ design notes of the repository):
       p*/2 in P, a norm is 0, the Hankel matrix has rank 1 (a single
       distinct value), or no root is real and positive, the r = 1
       projection (R6) is used instead.
+  R8  Inner-index balancing (the Discussion's remark on scaling a problem
+      into a bounded range; the paper gives no formula).  The product is
+      unchanged when column k of A is multiplied by d_k > 0 and row k of B
+      divided by it, since each term A_ik B_kj is; only the scales r_i, c_j
+      and hence which p are stable change.  Read as: d_k = sqrt(b_k / a_k)
+      with a_k = max_i A_ik and b_k = max_j B_kj (d_k = 1 where either is
+      0), which makes the largest entry of column k of A D equal to the
+      largest entry of row k of D^-1 B, and makes the balanced estimate
+      independent of any inner-index rescaling of the inputs.  The
+      estimate is then the plain one of (A D, D^-1 B).
 """
 
 import numpy as np
@@ -241,13 +251,36 @@ def _project_r2(S, P, idx, fallback, S_aux, aux):
     return out
 
 
-def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None):
+def balance_factors(A, B):
+    """Reading R8: d_k = sqrt(b_k / a_k), a_k = max_i A_ik (over the rows of
+    A), b_k = max_j B_kj (over the columns of B); 1 where a_k or b_k is 0.
+    Batched over leading dimensions: shape (..., k)."""
+    A = _f64(A)
+    B = _f64(B)
+    a = np.max(A, axis=-2, initial=0.0)
+    b = np.max(B, axis=-1, initial=0.0)
+    ok = (a > 0) & (b > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(ok, np.sqrt(np.where(ok, b, 1.0) / np.where(ok, a, 1.0)), 1.0)
+
+
+def balanced(A, B):
+    """(A D, D^-1 B, d) with d from balance_factors (reading R8)."""
+    A = _f64(A)
+    B = _f64(B)
+    d = balance_factors(A, B)
+    return A * d[..., None, :], B / d[..., :, None], d
+
+
+def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None, balance=False):
     """The p-norm estimate of the (max, x) product (Alg. 5, Sec. 2.1-2.2).
 
     C_ij = r_i c_j S_{p*}^(1/p*), p* = max{p in P : S_p[i, j] >= tau}.
     With norm_correct, C is divided by k^(1/p*) (Sec. 1, centred error).
     With projection="r1" the max is taken from the r = 1 projection of the
     norm sequence instead of the plain root (Sec. 1; reading R6).
+    With balance, the estimate of the balanced pair (A D, D^-1 B) (reading
+    R8); r and c are then those of the balanced pair, and d is returned.
 
     Returns a dict: C, pstar_idx (uint8, index into P, 255 = none stable),
     r, c, S (the whole norm power sequence), pstar (the p used per entry).
@@ -262,6 +295,9 @@ def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None):
     A = _f64(A)
     B = _f64(B)
     k = A.shape[-1]
+    d = None
+    if balance:
+        A, B, d = balanced(A, B)
     S, r, c = norm_power_sequence(A, B, P)
     idx = select_pstar(S, tau)
     root, psel, _ = _root(S, P, idx)
@@ -277,17 +313,25 @@ def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None):
     if norm_correct and k > 0:
         C = C / np.power(float(k), 1.0 / psel)
     out = {"C": C, "pstar_idx": idx, "pstar": psel, "r": r, "c": c, "S": S}
+    if d is not None:
+        out["d"] = d
     out.update(out_aux)
     return out
 
 
-def pnorm_estimate_rows(A, B, P, tau, rows, norm_correct=False, projection=None):
+def pnorm_estimate_rows(A, B, P, tau, rows, norm_correct=False, projection=None, balance=False):
     """The estimate restricted to output rows ``rows``: row i of C depends
     only on row i of A (through r_i and A'_i) and on all of B, so this is
-    pnorm_estimate(A[rows], B)."""
+    pnorm_estimate(A[rows], B).  Balancing (R8) takes its factors from the
+    whole of A and B first."""
     A = _f64(A)
-    return pnorm_estimate(A[..., rows, :], B, P, tau, norm_correct=norm_correct,
-                          projection=projection)
+    d = None
+    if balance:
+        A, B, d = balanced(A, B)
+    out = pnorm_estimate(A[..., rows, :], B, P, tau, norm_correct=norm_correct, projection=projection)
+    if d is not None:
+        out["d"] = d
+    return out
 
 
 def pnorm_forward_fixed(A, B, P, pstar_idx):
