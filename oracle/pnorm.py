@@ -334,10 +334,14 @@ def pnorm_estimate_rows(A, B, P, tau, rows, norm_correct=False, projection=None,
     return out
 
 
-def pnorm_forward_fixed(A, B, P, pstar_idx):
+def pnorm_forward_fixed(A, B, P, pstar_idx, balance=False):
     """C_ij = (sum_k A_ik^p B_kj^p)^(1/p) with p = P[pstar_idx[i, j]] given
     per entry (PSTAR_NONE -> P[0]); the forward with p* frozen, for finite
-    differences of the gradient."""
+    differences of the gradient.  With balance, formed from the balanced
+    pair (reading R8; the same function, scaled so that it does not
+    underflow where the inner index carries a scaling)."""
+    if balance:
+        A, B, _ = balanced(A, B)
     S, r, c = norm_power_sequence(A, B, P)
     root, _, _ = _root(S, P, np.asarray(pstar_idx, dtype=np.uint8))
     return r[..., :, None] * c[..., None, :] * root
@@ -346,7 +350,7 @@ def pnorm_forward_fixed(A, B, P, pstar_idx):
 # --------------------------------------------------------------------------
 # O-10: analytic gradient with p* frozen
 # --------------------------------------------------------------------------
-def pnorm_grad(A, B, G, P, pstar_idx):
+def pnorm_grad(A, B, G, P, pstar_idx, balance=False):
     """Gradient of L = sum(G * C) for the estimate with p = p*_ij frozen per
     entry.  The paper only notes that the p-norm rings are continuous and
     differentiable (Sec. 4); the derivative follows from
@@ -357,10 +361,19 @@ def pnorm_grad(A, B, G, P, pstar_idx):
         dL/dA_ik = sum_p A'_ik^(p-1) sum_{j: p*_ij = p} G_ij c_j C'_ij^(1-p) B'_kj^p
         dL/dB_kj = sum_p B'_kj^(p-1) sum_{i: p*_ij = p} A'_ik^p G_ij r_i C'_ij^(1-p)
     Entries whose S is 0 contribute nothing.
+    With balance (reading R8) the same formula is evaluated on the balanced
+    pair (A D, D^-1 B), whose scaled quantities stay in range where the
+    inner index of the inputs carries a scaling, and taken back by the chain
+    rule: dL/dA_ik = d_k dL/d(AD)_ik, dL/dB_kj = dL/d(D^-1 B)_kj / d_k.  The
+    function C with p* frozen does not depend on d, so d is a constant here.
     """
     A = _f64(A)
     B = _f64(B)
     G = _f64(G)
+    if balance:
+        Ab, Bb, d = balanced(A, B)
+        gA, gB = pnorm_grad(Ab, Bb, G, P, pstar_idx)
+        return gA * d[..., None, :], gB / d[..., :, None]
     P = [int(p) for p in P]
     Ap, Bp, r, c = _scaled(A, B)
     idx = np.asarray(pstar_idx, dtype=np.uint8)

@@ -159,3 +159,53 @@ def test_rows_take_the_factors_from_the_whole_inputs():
     part = oracle.pnorm_estimate_rows(A, B, P128, TAU, rows, balance=True)
     np.testing.assert_array_equal(part["C"], full["C"][rows])
     np.testing.assert_array_equal(part["d"], full["d"])
+
+
+def _fd_directional(A, B, G, P, idx, dirA, dirB, h):
+    """Central difference of L = sum(G C) along (dirA, dirB), p* frozen, on
+    the balanced forward (the factors are recomputed at each point; C with
+    p* frozen does not depend on them)."""
+    lp = (G * oracle.pnorm_forward_fixed(A + h * dirA, B + h * dirB, P, idx, balance=True)).sum()
+    lm = (G * oracle.pnorm_forward_fixed(A - h * dirA, B - h * dirB, P, idx, balance=True)).sum()
+    return (lp - lm) / (2 * h)
+
+
+def test_balanced_gradient_equals_plain_where_both_are_in_range():
+    """On uniform inputs (no inner scaling) both forms are accurate: the
+    balanced gradient is the plain one to rounding."""
+    rng = np.random.default_rng(90)
+    A = 1.0 - rng.random((12, 17))
+    B = 1.0 - rng.random((17, 9))
+    G = rng.standard_normal((12, 9))
+    P = [1, 2, 4, 8, 16, 32, 64]
+    idx = oracle.pnorm_estimate(A, B, P, 1e-290, balance=True)["pstar_idx"]
+    g0 = oracle.pnorm_grad(A, B, G, P, idx)
+    g1 = oracle.pnorm_grad(A, B, G, P, idx, balance=True)
+    for a, b in zip(g1, g0):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+
+
+def test_balanced_gradient_finite_differences_on_inner_scaled_inputs():
+    """Inner-scaled inputs (6 decades) at p* = 64: the plain scaled form
+    underflows (C' ~ 1e-6, C'^63 below FP64), the balanced one matches
+    central differences (h relative to each coordinate's scale) and Euler's
+    identity."""
+    U, V, s = _inner_scaled(91, m=10, k=14, n=8, decades=3)
+    A, B = U * s[None, :], V / s[:, None]
+    rng = np.random.default_rng(92)
+    G = rng.standard_normal((10, 8))
+    P = [1, 2, 4, 8, 16, 32, 64]
+    ref = oracle.pnorm_estimate(A, B, P, 1e-290, balance=True)
+    idx = ref["pstar_idx"]
+    assert (idx == 6).all()
+    gA, gB = oracle.pnorm_grad(A, B, G, P, idx, balance=True)
+    assert np.isfinite(gA).all() and np.isfinite(gB).all() and np.abs(gA).max() > 0
+    for t in range(6):
+        dA = rng.standard_normal(A.shape) * A
+        dB = rng.standard_normal(B.shape) * B
+        fd = _fd_directional(A, B, G, P, idx, dA, dB, 1e-6)
+        an = (gA * dA).sum() + (gB * dB).sum()
+        assert abs(fd - an) <= 1e-6 * (abs(an) + np.abs(G * ref["C"]).sum())
+    GC = G * ref["C"]
+    np.testing.assert_allclose((A * gA).sum(1), GC.sum(1), rtol=1e-10, atol=1e-12 * np.abs(GC).sum())
+    np.testing.assert_allclose((B * gB).sum(0), GC.sum(0), rtol=1e-10, atol=1e-12 * np.abs(GC).sum())
