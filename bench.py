@@ -132,6 +132,10 @@ def hbm_kernels(kern_ms, n, P, path, in_bytes=4):
     return out
 
 
+def pfamily_128():
+    return [1, 2, 4, 8, 16, 32, 64, 128]
+
+
 def time_call(fn, reps, torch):
     fn()
     torch.cuda.synchronize()
@@ -209,6 +213,30 @@ def run_legs(mt, torch, np):
             mt.estimate_backward(A4, B4, G4, C, ps, P, path="bf16")
         ms = time_call(fwd_bwd, 5, torch)
         legs[name] = {"ms_fwd_bwd": ms, "P": P, "ops_per_s": 64 * 512.0 ** 3 / (ms / 1e3)}
+
+    # inner-index balancing on inputs whose inner index carries a scaling:
+    # A = U diag(s), B = diag(s)^-1 V, U, V uniform on (0, 1], log10 s
+    # uniform on [-8, 8], 4096^3, P = {1..128}, BF16; error against the exact
+    # product on 256 sampled rows, plain and balanced
+    nb = 4096
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6006)
+    sc = torch.pow(10.0, torch.rand(nb, generator=g, device="cuda", dtype=torch.float64) * 16 - 8)
+    Ab = ((1.0 - torch.rand(nb, nb, generator=g, device="cuda", dtype=torch.float64)) * sc[None, :]).float()
+    Bb = ((1.0 - torch.rand(nb, nb, generator=g, device="cuda", dtype=torch.float64)) / sc[:, None]).float()
+    rb = torch.from_numpy(np.sort(np.random.default_rng(6007).choice(nb, 256, replace=False))).cuda()
+    Eb = mt.exact(Ab[rb].contiguous(), Bb).double()
+    leg = {"n": nb, "P": pfamily_128(), "inner_scale_decades": 16}
+    for tag, balance in (("plain", False), ("balanced", True)):
+        ms = time_call(lambda: mt.estimate(Ab, Bb, P=pfamily_128(), path="bf16", balance=balance), 3, torch)
+        C, ps = mt.estimate(Ab, Bb, P=pfamily_128(), path="bf16", balance=balance, return_pstar=True)
+        rel = (C[rb].double() / Eb - 1.0).abs()
+        psel = ps[rb].flatten().long()
+        leg[tag] = {"ms": ms, "max_rel_vs_exact": float(rel.max()), "median_rel_vs_exact": float(rel.median()),
+                    "pstar_hist": torch.bincount(psel, minlength=256)[:8].tolist()}
+    legs["balance_inner_scaled_4096_bf16"] = leg
+    del Ab, Bb, Eb, C, ps
+    torch.cuda.empty_cache()
 
     # max-convolution (Sec. 1): 8192 pairs of 2048-point probability vectors
     # (Dirichlet(1) rows), P = {1, ..., 64}, FFT convolution in FP64
@@ -298,22 +326,33 @@ def run_legs(mt, torch, np):
     src5 = np.sort(np.random.default_rng(5006).choice(n5, 64, replace=False)).astype(np.int32)
     ex5, rounds5 = mt.apsp_exact_rows(W5, src5)
     si = torch.from_numpy(src5.astype(np.int64)).cuda()
-    for path in ("bf16", "fp64"):
+    # the plain estimate's far pairs sit at small p* (e^(-s d) to the power p
+    # must stay above tau), so its error grows with the distance; the r = 1
+    # projection (exact for tied top terms) and the affine correction fitted
+    # on the same exact rows are reported beside it
+    for path, proj in (("bf16", None), ("bf16", "r1"), ("fp64", None)):
         if path == "bf16":  # one untimed call first; the FP64 run (seconds) is timed once, cold
-            mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64)
+            mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64,
+                    projection=proj)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
-        D5 = mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64)
+        D5 = mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64,
+                     projection=proj)
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
-        legs["apsp_rgg16384_" + path] = {
-            "ms": ms, "squarings": c5["T"], "P": c5["P"], "s": c5["s"],
-            "ops_per_s": c5["T"] * float(n5) ** 3 / (ms / 1e3),
-            "vs_exact_64_sources": apsp_errors(D5[si], ex5, c5["s"], torch),
-            "exact_rows": {"sources": len(src5), "bellman_ford_rounds": rounds5}}
-        del D5
+        leg = {"ms": ms, "squarings": c5["T"], "P": c5["P"], "s": c5["s"], "projection": proj or "plain",
+               "ops_per_s": c5["T"] * float(n5) ** 3 / (ms / 1e3),
+               "vs_exact_64_sources": apsp_errors(D5[si], ex5, c5["s"], torch),
+               "exact_rows": {"sources": len(src5), "bellman_ford_rounds": rounds5}}
+        Dc = D5.clone()
+        ab = mt.apsp_affine_correct(Dc, src5, ex5)
+        leg["affine_64_sources"] = dict(apsp_errors(Dc[si], ex5, c5["s"], torch),
+                                        a=float(ab[0]), b=float(ab[1]),
+                                        note="fitted on the same 64 rows it is scored on")
+        legs["apsp_rgg16384_" + path + ("_" + proj if proj else "")] = leg
+        del D5, Dc
         torch.cuda.empty_cache()
     return legs
 
@@ -425,6 +464,24 @@ def main():
         del ws
         log(f"[bench] {path}: {ms:.3f} ms/step, GEMM {gemm_ms / max(gemm_n, 1):.3f} ms")
 
+    # the BF16 path with inner-index balancing (MT_FLAG_BALANCE), timed the
+    # same way, for its error column
+    bal = None
+    if "bf16" in res:
+        ws = torch.empty(mt.workspace_size(1, n, n, n, P, path="bf16", flags=mt.FLAG_BALANCE), dtype=torch.uint8,
+                         device="cuda")
+        holder = {}
+
+        def step_bal():
+            holder["C"] = mt.estimate(Ad, Bd, P=P, path="bf16", workspace=ws, balance=True)
+
+        for _ in range(args.warmup):
+            step_bal()
+        ms_bal, _ = time_steps(step_bal, max(3, args.steps // 4), 0, torch)
+        bal = {"ms_per_step": ms_bal, "value": ops / (ms_bal / 1e3), "C": holder["C"]}
+        del ws
+        log(f"[bench] bf16 balanced: {ms_bal:.3f} ms/step")
+
     # error against the exact product on sampled rows (exact kernel on the GPU)
     rows = np.sort(np.random.default_rng(3003).choice(n, 256, replace=False))
     ri = torch.from_numpy(rows).cuda()
@@ -443,6 +500,9 @@ def main():
         rel = (res[path]["C"][ri].double() / E64 - 1.0).abs()
         errs[path] = {"max": float(rel.max()), "median": float(rel.median())}
         del res[path]["C"]
+    if bal is not None:
+        rel = (bal.pop("C")[ri].double() / E64 - 1.0).abs()
+        errs["bf16_balanced"] = {"max": float(rel.max()), "median": float(rel.median())}
 
     bf = res.get("bf16") or res[paths[0]]
     main_path = "bf16" if "bf16" in res else paths[0]
@@ -490,6 +550,9 @@ def main():
         "exact_valu": {"rows": len(rows), "ms": exact_ms,
                        "ops_per_s": len(rows) * float(n) * n / (exact_ms / 1e3)},
     }
+    if bal is not None:
+        out["bf16_balanced"] = {"ms_per_step": bal["ms_per_step"], "value": bal["value"],
+                                "flag": "MT_FLAG_BALANCE (inner-index balancing, A D and D^-1 B)"}
     if "fp64" in res and main_path == "bf16":
         f = res["fp64"]
         fval = ops / (f["ms_per_step"] / 1e3)

@@ -131,6 +131,23 @@ typedef enum { MT_PATH_FP64 = 0, MT_PATH_BF16_SPLIT = 1 } mt_path;
  * plain queue's update).  Needs k <= 4096 (MT_ERR_UNSUPPORTED above).
  */
 #define MT_FLAG_XY_PAIRED   64u
+/*
+ * Inner-index balancing (maxtimes_estimate only).  The Discussion (Sec. 4)
+ * remarks that a problem can be scaled into a bounded range.  Every term
+ * A_ik B_kj, hence the product and each p-norm of the terms, is unchanged
+ * when column k of A is multiplied by d_k > 0 and row k of B divided by it;
+ * what changes are the scales r_i, c_j of the scaled call H' (Sec. 2.1) and
+ * with them which p are stable.  With this flag the estimate is that of
+ * (A D, D^-1 B), d_k = sqrt(b_k / a_k), a_k = max_i A_ik, b_k = max_j B_kj
+ * (d_k = 1 where either is 0): column k of A D and row k of D^-1 B then have
+ * the same largest entry, and the estimate no longer depends on how the
+ * inner index of the inputs is scaled.  Where the inputs carry such a
+ * scaling, r_i c_j tightens and p* rises.  p_star refers to the balanced
+ * estimate; the backward accepts the flag and differentiates the estimate
+ * at the given p* (balancing does not change the p-norm of the terms).
+ * Costs two more reductions over A and B; workspace grows by 32 b k bytes.
+ */
+#define MT_FLAG_BALANCE    128u
 
 #define MT_PSTAR_NONE 255  /* p_star value when no p of the family was stable */
 #define MT_MAX_P 32        /* largest family size */

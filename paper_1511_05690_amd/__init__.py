@@ -37,6 +37,7 @@ PATHS = {"fp64": 0, "bf16": 1}
 F32, F64 = 0, 1
 FLAG_VALIDATE, FLAG_NORM_CORRECT, FLAG_CLAMP, FLAG_RAW_OUTPUT, FLAG_PROJECT_R1, FLAG_PROJECT_R2 = 1, 2, 4, 8, 16, 32
 FLAG_XY_PAIRED = 64
+FLAG_BALANCE = 128
 NOALLOC_SCRATCH_BYTES = 64 << 20  # MT_NOALLOC_SCRATCH_BYTES
 PROJECTIONS = {None: 0, "r1": FLAG_PROJECT_R1, "r2": FLAG_PROJECT_R2}
 STATUS = {0: "MT_OK", 1: "MT_ERR_INVALID_ARG", 2: "MT_ERR_DOMAIN", 3: "MT_ERR_WORKSPACE",
@@ -333,7 +334,7 @@ def _projection_flag(projection):
 
 def estimate(A, B, P=(1, 2, 4, 8, 16, 32, 64), tau=None, path="bf16", split_max_p=None,
              norm_correct=False, clamp=False, validate=False, return_pstar=False, workspace=None,
-             projection=None):
+             projection=None, balance=False):
     """Estimate C_ij = max_k A_ik B_kj for nonnegative A (.., m, k), B (.., k, n).
 
     path "bf16": BF16 MFMA ring products with hi/lo split for p <= split_max_p;
@@ -342,10 +343,12 @@ def estimate(A, B, P=(1, 2, 4, 8, 16, 32, 64), tau=None, path="bf16", split_max_
     projection (S_{p*} / S_{p_lo})^(1/(p* - p_lo)) (MT_FLAG_PROJECT_R1);
     "r2": the r = 2 projection from S at p*/4, p*/2, 3p*/4, p*
     (MT_FLAG_PROJECT_R2, FP64 path only).
+    balance: the estimate of (A D, D^-1 B) with the inner-index balancing
+    factors d_k = sqrt(max_j B_kj / max_i A_ik) (MT_FLAG_BALANCE).
     Differentiable (p* held fixed) when A or B requires grad (plain root only).
     """
     flags = (FLAG_VALIDATE if validate else 0) | (FLAG_NORM_CORRECT if norm_correct else 0) | \
-        (FLAG_CLAMP if clamp else 0) | _projection_flag(projection)
+        (FLAG_CLAMP if clamp else 0) | _projection_flag(projection) | (FLAG_BALANCE if balance else 0)
     if torch.is_grad_enabled() and (A.requires_grad or B.requires_grad):
         if projection is not None:
             raise ValueError("the projections have no backward; use projection=None for gradients")

@@ -120,7 +120,7 @@ mt_status parse_options(const mt_options* opt, Family* f, bool xy = false) {
     if (opt->path != MT_PATH_FP64 && opt->path != MT_PATH_BF16_SPLIT)
         return fail(MT_ERR_INVALID_ARG, "unknown path %d", opt->path);
     const uint32_t known = MT_FLAG_VALIDATE | MT_FLAG_NORM_CORRECT | MT_FLAG_CLAMP | MT_FLAG_RAW_OUTPUT |
-                           MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2 | MT_FLAG_XY_PAIRED;
+                           MT_FLAG_PROJECT_R1 | MT_FLAG_PROJECT_R2 | MT_FLAG_XY_PAIRED | MT_FLAG_BALANCE;
     if (opt->flags & ~known) return fail(MT_ERR_INVALID_ARG, "unknown flag bits 0x%x", opt->flags & ~known);
     if ((opt->flags & MT_FLAG_XY_PAIRED) && !xy)
         return fail(MT_ERR_INVALID_ARG, "MT_FLAG_XY_PAIRED is for xy_topk_estimate only");
@@ -314,7 +314,7 @@ Geom product_geom(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
 }
 
 struct Layout {
-    size_t hdr, r, c, ap, bp, s, s2, code, tail, tail_sorted, tail_bucket, pilot, x, total;
+    size_t hdr, r, c, bal, ap, bp, s, s2, code, tail, tail_sorted, tail_bucket, pilot, x, total;
     int32_t tail_max;  // sparse-tail threshold the layout was sized for (0: no tail)
     int32_t tail_shift, tail_buckets;  // row buckets of the tail sort
 };
@@ -333,12 +333,14 @@ constexpr int32_t kPilotKParts = kMaxPilotKParts;
 
 // The workspace of one product (plus an APSP X buffer when x_bytes > 0).
 Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64_t b, int64_t m,
-                      int64_t n, size_t x_bytes) {
+                      int64_t k, int64_t n, size_t x_bytes) {
     Layout L;
     size_t off = 0;
     L.hdr = off; off += align_up(sizeof(WsHeader));
     L.r = off;   off += align_up((size_t)(b * m) * 8);
     L.c = off;   off += align_up((size_t)(b * n) * 8);
+    // inner-index balancing: column maxima of A, row maxima of B, d, 1 / d
+    L.bal = off; off += (f.flags & MT_FLAG_BALANCE) ? 4 * align_up((size_t)(b * k) * 8) : 0;
     L.ap = off;  off += align_up((size_t)b * ps.n_planes * g.mp * g.kp * g.esize);
     L.bp = off;  off += align_up((size_t)b * ps.n_planes * g.np * g.kp * g.esize);
     L.s = L.s2 = L.code = 0;
@@ -423,7 +425,7 @@ struct BwdLayout {
     int64_t m_out, k_out, n_out;  // output rows / cols padded to the adjoint tile
     int64_t m_in, n_in;           // inner lengths padded to the K step
     int32_t g_planes;             // adjoint planes per batch item
-    size_t hdr, r, c, ex, xa, yb, pa, pb, total;
+    size_t hdr, r, c, bal, ex, xa, yb, pa, pb, total;
 };
 
 BwdLayout backward_layout(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
@@ -442,6 +444,8 @@ BwdLayout backward_layout(const Family& f, int64_t b, int64_t m, int64_t k, int6
     L.hdr = off; off += align_up(sizeof(WsHeader));
     L.r = off;   off += align_up((size_t)(b * m) * 8);
     L.c = off;   off += align_up((size_t)(b * n) * 8);
+    // balanced forward: column maxima of A, row maxima of B, d, 1 / d
+    L.bal = off; off += (f.flags & MT_FLAG_BALANCE) ? 4 * align_up((size_t)(b * k) * 8) : 0;
     L.ex = off;  off += align_up((size_t)(2 * b) * 4);
     L.xa = off;  off += align_up((size_t)b * L.g_planes * L.m_out * L.n_in * es);
     L.yb = off;  off += align_up((size_t)b * L.g_planes * L.n_out * L.m_in * es);
@@ -461,9 +465,13 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     double* c = scale ? (double*)(ws + L.c) : nullptr;
     void* ap = ws + L.ap;
     void* bp = ws + L.bp;
-    MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps, f.bf16, ap, st),
+    // balanced inputs: A D and D^-1 B, d and 1 / d per inner index
+    const bool bal = scale && (f.flags & MT_FLAG_BALANCE);
+    const double* d = bal ? (const double*)(ws + L.bal + 2 * align_up((size_t)(b * k) * 8)) : nullptr;
+    const double* dinv = bal ? (const double*)(ws + L.bal + 3 * align_up((size_t)(b * k) * 8)) : nullptr;
+    MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps, f.bf16, ap, st, d),
            "power planes (A)");
-    MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, nullptr, ps, f.bf16, bp, st),
+    MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, nullptr, ps, f.bf16, bp, st, dinv),
            "power planes (B)");
     const FamilyPlan plan = family_plan(f, ps, k);
     EpiArgs epi;
@@ -590,7 +598,7 @@ mt_status maxtimes_workspace_size(int64_t b, int64_t m, int64_t k, int64_t n, co
     if ((s = check_bf16_inner(f, k)) != MT_OK) return s;
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, b, m, k, n);
-    *bytes = product_layout(f, ps, g, b, m, n, 0).total;
+    *bytes = product_layout(f, ps, g, b, m, k, n, 0).total;
     return MT_OK;
 }
 
@@ -605,7 +613,7 @@ mt_status maxtimes_workspace_map(int64_t b, int64_t m, int64_t k, int64_t n, con
     if ((s = check_bf16_inner(f, k)) != MT_OK) return s;
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, b, m, k, n);
-    const Layout L = product_layout(f, ps, g, b, m, n, 0);
+    const Layout L = product_layout(f, ps, g, b, m, k, n, 0);
     memset(map, 0, sizeof *map);
     map->r_offset = L.r;
     map->c_offset = L.c;
@@ -674,7 +682,7 @@ mt_status estimate_impl(const void* A, const void* B, mt_dtype dtype, int64_t b,
     if (k > 0 && (!A || !B)) return fail(MT_ERR_INVALID_ARG, "A or B is NULL");
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, b, m, k, n);
-    const Layout L = product_layout(f, ps, g, b, m, n, 0);
+    const Layout L = product_layout(f, ps, g, b, m, k, n, 0);
     if (use_scratch) {
         if (L.total > kScratchBytes)
             return fail(MT_ERR_WORKSPACE,
@@ -694,8 +702,23 @@ mt_status estimate_impl(const void* A, const void* B, mt_dtype dtype, int64_t b,
     // call itself (the header: domain flag, tail count, p* histogram), so a
     // workspace that holds an earlier call's contents is fine
     MT_TRY(launch_fill_zero_u32(ws + L.hdr, sizeof(WsHeader) / 4, st), "clear header");
-    MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
-    MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st), "column max");
+    if ((f.flags & MT_FLAG_BALANCE) && k > 0) {
+        // inner-index balancing: a_k = max_i A_ik, b_k = max_j B_kj,
+        // d_k = sqrt(b_k / a_k); then r_i = max_k A_ik d_k, c_j = max_k B_kj / d_k
+        const size_t sec = align_up((size_t)(b * k) * 8);
+        double* amax = (double*)(ws + L.bal);
+        double* bmax = (double*)(ws + L.bal + sec);
+        double* d = (double*)(ws + L.bal + 2 * sec);
+        double* dinv = (double*)(ws + L.bal + 3 * sec);
+        MT_TRY(launch_colmax(A, f64, b, m, k, amax, flag, st), "column max of A (balancing)");
+        MT_TRY(launch_rowmax(B, f64, b * k, n, bmax, flag, st), "row max of B (balancing)");
+        MT_TRY(launch_balance(amax, bmax, b * k, d, dinv, st), "balancing factors");
+        MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st, d, m), "row max");
+        MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st, dinv), "column max");
+    } else {
+        MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
+        MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st), "column max");
+    }
     if (f.flags & MT_FLAG_VALIDATE) {
         if ((s = read_domain_flag(ws + L.hdr, st)) != MT_OK) return s;
     }
@@ -727,9 +750,10 @@ mt_status apsp_workspace_size(int64_t n, const mt_options* opt, size_t* bytes) {
     if (s != MT_OK) return s;
     if ((s = check_dims(1, n, n, n)) != MT_OK) return s;
     if ((s = check_bf16_inner(f, n)) != MT_OK) return s;
+    if (f.flags & MT_FLAG_BALANCE) return fail(MT_ERR_INVALID_ARG, "MT_FLAG_BALANCE is for maxtimes_estimate");
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, 1, n, n, n);
-    *bytes = product_layout(f, ps, g, 1, n, n, (size_t)(n * n) * (f.bf16 ? 4 : 8)).total;
+    *bytes = product_layout(f, ps, g, 1, n, n, n, (size_t)(n * n) * (f.bf16 ? 4 : 8)).total;
     return MT_OK;
 }
 
@@ -741,6 +765,9 @@ mt_status apsp_estimate(const float* W, int64_t n, double s_scale, int32_t n_squ
     mt_status s = parse_options(opt, &f);
     if (s != MT_OK) return s;
     if (f.flags & MT_FLAG_NORM_CORRECT) return fail(MT_ERR_UNSUPPORTED, "MT_FLAG_NORM_CORRECT is not defined for APSP");
+    if (f.flags & MT_FLAG_BALANCE)
+        return fail(MT_ERR_INVALID_ARG,
+                    "MT_FLAG_BALANCE is for maxtimes_estimate (an APSP operand has row and column maxima 1)");
     if (d_dtype != MT_F32 && d_dtype != MT_F64) return fail(MT_ERR_INVALID_ARG, "unknown dtype %d", (int)d_dtype);
     if ((s = check_dims(1, n, n, n)) != MT_OK) return s;
     if ((s = check_bf16_inner(f, n)) != MT_OK) return s;
@@ -756,7 +783,7 @@ mt_status apsp_estimate(const float* W, int64_t n, double s_scale, int32_t n_squ
     const PlaneSpec ps = plane_spec(f);
     const Geom g = product_geom(f, 1, n, n, n);
     const int x_f64 = f.bf16 ? 0 : 1;
-    const Layout L = product_layout(f, ps, g, 1, n, n, (size_t)(n * n) * (x_f64 ? 8 : 4));
+    const Layout L = product_layout(f, ps, g, 1, n, n, n, (size_t)(n * n) * (x_f64 ? 8 : 4));
     if ((s = check_ws(workspace, ws_bytes, L.total)) != MT_OK) return s;
 
     hipStream_t st = (hipStream_t)stream;
@@ -830,8 +857,26 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
     double* r = (double*)(ws + L.r);
     double* c = (double*)(ws + L.c);
     MT_TRY(launch_fill_zero_u32(ws + L.hdr, sizeof(WsHeader) / 4, st), "clear header");
-    MT_TRY(launch_rowmax(A, f64, b * m, k, r, flag, st), "row max");
-    MT_TRY(launch_colmax(B, f64, b, k, n, c, flag, st), "column max");
+    // A balanced forward (MT_FLAG_BALANCE) is differentiated on the balanced
+    // pair (A D, D^-1 B), whose scaled quantities stay in range, and taken
+    // back by the chain rule (columns of dA times d_k, rows of dB over d_k);
+    // with p* given, C does not depend on d
+    const bool bal = (f.flags & MT_FLAG_BALANCE) != 0;
+    const size_t bsec = align_up((size_t)(b * k) * 8);
+    double* dfac = bal ? (double*)(ws + L.bal + 2 * bsec) : nullptr;
+    double* dinv = bal ? (double*)(ws + L.bal + 3 * bsec) : nullptr;
+    if (bal) {
+        double* amax = (double*)(ws + L.bal);
+        double* bmax = (double*)(ws + L.bal + bsec);
+        MT_TRY(launch_colmax(A, f64, b, m, k, amax, flag, st), "column max of A (balancing)");
+        MT_TRY(launch_rowmax(B, f64, b * k, n, bmax, flag, st), "row max of B (balancing)");
+        MT_TRY(launch_balance(amax, bmax, b * k, dfac, dinv, st), "balancing factors");
+        MT_TRY(launch_rowmax(A, f64, b * m, k, r, flag, st, dfac, m), "row max");
+        MT_TRY(launch_colmax(B, f64, b, k, n, c, flag, st, dinv), "column max");
+    } else {
+        MT_TRY(launch_rowmax(A, f64, b * m, k, r, flag, st), "row max");
+        MT_TRY(launch_colmax(B, f64, b, k, n, c, flag, st), "column max");
+    }
     MT_TRY(launch_pstar_hist(p_star, b * m * n, f.n, hist, st), "p* histogram");
 
     AdjPrepSpec sp;
@@ -886,13 +931,15 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
     if (dA) {
         // dA (m x k) = sum_p A'^(p-1) .* (Gt_p B'^p^T): X = Gt planes (rows m, inner n),
         // Y = B'^p planes (rows k, inner n; B row-major is already K-contiguous)
-        MT_TRY(launch_power_planes(B, f64, 0, b, k, n, L.k_out, L.n_in, nullptr, c, ps, f.bf16, ws + L.pa, st),
+        MT_TRY(launch_power_planes(B, f64, 0, b, k, n, L.k_out, L.n_in, dfac, c, ps, f.bf16, ws + L.pa, st),
                "power planes (B, adjoint)");
         AdjArgs aa;
         memset(&aa, 0, sizeof aa);
         aa.M = A;
         aa.m_f64 = f64;
         aa.scale_rows = r;
+        aa.scale_cols = dinv;   // balanced: A' = A d / r
+        aa.out_col_mul = dfac;  // dL/dA = d_k dL/d(A D)
         aa.hist = hist;
         aa.out = dA;
         aa.out_f64 = f64;
@@ -909,13 +956,15 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
     if (dB) {
         // dB (k x n) = sum_p B'^(p-1) .* (A'^p^T Gt'_p): X = A'^p transposed (rows k,
         // inner m), Y = Gt' planes transposed (rows n, inner m)
-        MT_TRY(launch_power_planes(A, f64, 1, b, k, m, L.k_out, L.m_in, nullptr, r, ps, f.bf16, ws + L.pb, st),
+        MT_TRY(launch_power_planes(A, f64, 1, b, k, m, L.k_out, L.m_in, dinv, r, ps, f.bf16, ws + L.pb, st),
                "power planes (A, adjoint)");
         AdjArgs ab;
         memset(&ab, 0, sizeof ab);
         ab.M = B;
         ab.m_f64 = f64;
         ab.scale_cols = c;
+        ab.scale_rows = dfac;   // balanced: B' = B / (d c)
+        ab.out_row_mul = dinv;  // dL/dB = dL/d(D^-1 B) / d_k
         ab.hist = hist;
         ab.out = dB;
         ab.out_f64 = f64;

@@ -109,15 +109,21 @@ __global__ void tail_scatter_kernel(const TailEntry* __restrict__ in, const uint
     }
 }
 
-// One wave per row: r[row] = max_k A[row, k]; flags invalid entries.
-template <typename T>
+// One wave per row: r[row] = max_k A[row, k] (times mul[batch, k] when
+// kMul: the balanced row maximum, rpb rows per batch item); flags invalid
+// entries.
+template <typename T, bool kMul = false>
 __global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict__ A, int64_t rows,
                                                              int64_t k, double* __restrict__ r,
-                                                             int32_t* __restrict__ flag) {
+                                                             int32_t* __restrict__ flag,
+                                                             const double* __restrict__ mul = nullptr,
+                                                             int64_t rpb = 1) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     if (row >= rows) return;
     const T* a = A + row * k;
+    const double* mu = kMul ? mul + (row / rpb) * k : nullptr;
+    auto val = [&](T v, int64_t j) { return kMul ? (double)v * mu[j] : (double)v; };
     double mx = 0.0;
     bool bad = false;
     int64_t j = lane;
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 bad |= bad_value(v[q]);
-                mx = fmax(mx, (double)v[q]);
+                mx = fmax(mx, val(v[q], j0 + q));
             }
         }
         j = k;
@@ -138,25 +144,27 @@ __global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict
     for (; j + 192 < k; j += 256) {
         T v0 = a[j], v1 = a[j + 64], v2 = a[j + 128], v3 = a[j + 192];
         bad |= bad_value(v0) | bad_value(v1) | bad_value(v2) | bad_value(v3);
-        mx = fmax(mx, fmax(fmax((double)v0, (double)v1), fmax((double)v2, (double)v3)));
+        mx = fmax(mx, fmax(fmax(val(v0, j), val(v1, j + 64)), fmax(val(v2, j + 128), val(v3, j + 192))));
     }
     for (; j < k; j += 64) {
         T v = a[j];
         bad |= bad_value(v);
-        mx = fmax(mx, (double)v);
+        mx = fmax(mx, val(v, j));
     }
     mx = wave_max(mx);
     if (lane == 0) r[row] = mx;
     if (bad) atomicOr(flag, 1);
 }
 
-// c[b, j] = max_k B[b, k, j]: each thread owns kColVec consecutive columns
-// (one 16-byte load per row when n allows it), 64 rows per block, combined
-// with an integer atomic max on the bit pattern (exact for >= 0).
-template <typename T>
+// c[b, j] = max_k B[b, k, j] (times mul[b, k] when kMul: the balanced column
+// maximum): each thread owns kColVec consecutive columns (one 16-byte load
+// per row when n allows it), 64 rows per block, combined with an integer
+// atomic max on the bit pattern (exact for >= 0).
+template <typename T, bool kMul = false>
 __global__ __launch_bounds__(kThreads) void mt_colmax_kernel(const T* __restrict__ B, int64_t k,
                                                              int64_t n, double* __restrict__ c,
-                                                             int32_t* __restrict__ flag) {
+                                                             int32_t* __restrict__ flag,
+                                                             const double* __restrict__ mul = nullptr) {
     constexpr int V = 16 / sizeof(T);
     const int64_t j0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * V;
     const int64_t k0 = (int64_t)blockIdx.y * 64;
@@ -173,27 +181,43 @@ __global__ __launch_bounds__(kThreads) void mt_colmax_kernel(const T* __restrict
 #pragma unroll 8
         for (int64_t kk = k0; kk < k1; ++kk) {
             const vecT v = *(const vecT*)(bb + kk * n);
+            const double f = kMul ? mul[bi * k + kk] : 1.0;
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 bad |= bad_value(v[q]);
-                mx[q] = fmax(mx[q], (double)v[q]);
+                mx[q] = fmax(mx[q], kMul ? (double)v[q] * f : (double)v[q]);
             }
         }
     } else {
-        for (int64_t kk = k0; kk < k1; ++kk)
+        for (int64_t kk = k0; kk < k1; ++kk) {
+            const double f = kMul ? mul[bi * k + kk] : 1.0;
 #pragma unroll
             for (int q = 0; q < V; ++q)
                 if (j0 + q < n) {
                     const T v = bb[kk * n + q];
                     bad |= bad_value(v);
-                    mx[q] = fmax(mx[q], (double)v);
+                    mx[q] = fmax(mx[q], kMul ? (double)v * f : (double)v);
                 }
+        }
     }
     if (bad) atomicOr(flag, 1);
 #pragma unroll
     for (int q = 0; q < V; ++q)
         if (j0 + q < n && (mx[q] > 0.0 || mx[q] != mx[q]))
             atomicMax((unsigned long long*)(c + bi * n + j0 + q), (unsigned long long)__double_as_longlong(mx[q]));
+}
+
+// Inner-index balancing: d = sqrt(b / a) per inner index (a = largest entry
+// of the column of A, b = of the row of B), 1 where either is 0; dinv = 1 / d.
+__global__ void mt_balance_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t count,
+                                  double* __restrict__ d, double* __restrict__ dinv) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double av = a[i], bv = b[i];
+        const double f = (av > 0.0 && bv > 0.0) ? sqrt(bv / av) : 1.0;
+        d[i] = f;
+        dinv[i] = 1.0 / f;
+    }
 }
 
 template <typename T>
@@ -217,8 +241,8 @@ __device__ inline T ipow(T x, int p) {
 template <typename TS, bool kBf16, bool kTranspose>
 __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
     const TS* __restrict__ src, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
-    const double* __restrict__ scale_rows, const double* __restrict__ scale_cols, PlaneSpec spec,
-    void* __restrict__ planes) {
+    const double* __restrict__ scale_rows, const double* __restrict__ scale_cols,
+    const double* __restrict__ col_mul, PlaneSpec spec, void* __restrict__ planes) {
     __shared__ TS tile[64][64 + 1];
     const int64_t bi = blockIdx.z;
     // A workgroup covers kPlaneRows x kPlaneCols of a plane: 64 x 64 through
@@ -273,14 +297,23 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
                 }
             }
             const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+            if (col_mul != nullptr) {
+                // balanced input: (src d_u) / scale_rows, the product first
+                // (it is at most the row's balanced maximum)
+                const double* cm = col_mul + bi * cols + u;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) x[i] = (TC)((double)v[i] * inv);
+                for (int i = 0; i < 8; ++i) x[i] = (TC)(((double)v[i] * cm[i]) * inv);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[i] = (TC)((double)v[i] * inv);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 double v = 0.0;
                 if (!zero_row && u + i < cols) {
                     v = kTranspose ? (double)tile[tt][ch * 8 + i] : (double)s[t * cols + u + i];
+                    if (col_mul != nullptr) v *= col_mul[bi * cols + u + i];
                     double d = sc;
                     if (scale_cols != nullptr) d *= scale_cols[bi * cols + u + i];
                     v = d > 0.0 ? v / d : 0.0;
@@ -515,33 +548,48 @@ hipError_t launch_tail_sort(const EpiArgs& epi, int64_t rows, int64_t cap, hipSt
 }
 
 hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r, int32_t* flag,
-                         hipStream_t st) {
+                         hipStream_t st, const double* mul, int64_t rows_per_batch) {
     if (rows <= 0) return hipSuccess;
     const dim3 grid((unsigned)((rows + 3) / 4));
     timing_before("mt_rowmax", st);
-    if (f64)
-        hipLaunchKernelGGL(mt_rowmax_kernel<double>, grid, dim3(kThreads), 0, st, (const double*)A,
-                           rows, k, r, flag);
-    else
-        hipLaunchKernelGGL(mt_rowmax_kernel<float>, grid, dim3(kThreads), 0, st, (const float*)A,
-                           rows, k, r, flag);
+#define MT_ROWMAX(T, M)                                                                        \
+    hipLaunchKernelGGL((mt_rowmax_kernel<T, M>), grid, dim3(kThreads), 0, st, (const T*)A, rows, k, r, flag, \
+                       mul, rows_per_batch)
+    if (f64) {
+        if (mul) MT_ROWMAX(double, true); else MT_ROWMAX(double, false);
+    } else {
+        if (mul) MT_ROWMAX(float, true); else MT_ROWMAX(float, false);
+    }
+#undef MT_ROWMAX
     timing_after(st);
     return hipGetLastError();
 }
 
 hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n, double* c,
-                         int32_t* flag, hipStream_t st) {
+                         int32_t* flag, hipStream_t st, const double* mul) {
     hipError_t e = launch_fill_zero_u32(c, b * n * 2, st);
     if (e != hipSuccess || k <= 0) return e;
     const int64_t per_block = (int64_t)kThreads * (f64 ? 2 : 4);  // columns per block
     const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)((k + 63) / 64), (unsigned)b);
     timing_before("mt_colmax", st);
-    if (f64)
-        hipLaunchKernelGGL(mt_colmax_kernel<double>, grid, dim3(kThreads), 0, st, (const double*)B,
-                           k, n, c, flag);
-    else
-        hipLaunchKernelGGL(mt_colmax_kernel<float>, grid, dim3(kThreads), 0, st, (const float*)B, k,
-                           n, c, flag);
+#define MT_COLMAX(T, M) \
+    hipLaunchKernelGGL((mt_colmax_kernel<T, M>), grid, dim3(kThreads), 0, st, (const T*)B, k, n, c, flag, mul)
+    if (f64) {
+        if (mul) MT_COLMAX(double, true); else MT_COLMAX(double, false);
+    } else {
+        if (mul) MT_COLMAX(float, true); else MT_COLMAX(float, false);
+    }
+#undef MT_COLMAX
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_balance(const double* a, const double* b, int64_t count, double* d, double* dinv,
+                          hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    timing_before("mt_balance", st);
+    hipLaunchKernelGGL(mt_balance_kernel, dim3(grid_for(count, kThreads, 1024)), dim3(kThreads), 0, st, a, b,
+                       count, d, dinv);
     timing_after(st);
     return hipGetLastError();
 }
@@ -549,7 +597,8 @@ hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n
 hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int64_t b, int64_t rows,
                                int64_t cols, int64_t rows_pad, int64_t cols_pad,
                                const double* scale_rows, const double* scale_cols,
-                               const PlaneSpec& spec, int bf16, void* planes, hipStream_t st) {
+                               const PlaneSpec& spec, int bf16, void* planes, hipStream_t st,
+                               const double* col_mul) {
     if (rows_pad <= 0 || cols_pad <= 0) return hipSuccess;
     // 64 x 64 tiles through LDS for the transposed operand, 16 x 256 otherwise
     const dim3 grid = transpose
@@ -557,7 +606,7 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
         : dim3((unsigned)((cols_pad + 255) / 256), (unsigned)((rows_pad + 15) / 16), (unsigned)b);
 #define MT_PLANES(TS, BF, TR)                                                                   \
     hipLaunchKernelGGL((mt_power_planes_kernel<TS, BF, TR>), grid, dim3(kThreads), 0, st,      \
-                       (const TS*)src, rows, cols, rows_pad, cols_pad, scale_rows, scale_cols, spec,  \
+                       (const TS*)src, rows, cols, rows_pad, cols_pad, scale_rows, scale_cols, col_mul, spec,  \
                        planes)
     timing_before(bf16 ? "mt_power_planes_bf16" : "mt_power_planes_f64", st);
     if (src_f64) {

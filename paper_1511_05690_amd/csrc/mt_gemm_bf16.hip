@@ -550,20 +550,33 @@ struct AdjointEpi {
     __device__ void finish(const TileCtx& t) {
         // the adjoint planes carry the scales divided by 2^post (per batch item)
         const int post = a.post_exp ? a.post_exp[t.bi] : 0;
+        const bool mul = a.out_row_mul || a.out_col_mul;
+        const int64_t row_base = (int64_t)t.bi * rows + t.row0 + lr0;
+        const int64_t col_base = (int64_t)t.bi * cols + t.col0 + lc0;
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
             for (int j = 0; j < WT_N; ++j) {
                 if (!(j * 32 < cols_left)) continue;
+                const double cm = a.out_col_mul ? a.out_col_mul[col_base + j * 32] : 1.0;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int roff = i * 32 + (r >> 2) * 8 + (r & 3);
                     if (roff < rows_left) {
                         const int64_t o = lane_off + (int64_t)roff * cols + j * 32;
-                        if (a.out_f64)
+                        if (mul) {
+                            // chain factors of a balanced forward, in FP64
+                            const double rm = a.out_row_mul ? a.out_row_mul[row_base + roff] : 1.0;
+                            const double w = __builtin_amdgcn_ldexp((double)tot[i][j][r] * rm * cm, post);
+                            if (a.out_f64)
+                                ((double*)a.out)[o] = w;
+                            else
+                                ((float*)a.out)[o] = (float)w;
+                        } else if (a.out_f64) {
                             ((double*)a.out)[o] = scale_out<double>(tot[i][j][r], post);
-                        else
+                        } else {
                             ((float*)a.out)[o] = scale_out<float>(tot[i][j][r], post);
+                        }
                     }
                 }
             }

@@ -377,7 +377,9 @@ struct AdjointEpiF64 {
             }
     }
 
-    __device__ void finish(const TileCtx&) {
+    __device__ void finish(const TileCtx& t) {
+        const int64_t row_base = (int64_t)t.bi * rows + t.row0 + lr0;
+        const int64_t col_base = (int64_t)t.bi * cols + t.col0 + lc0;
 #pragma unroll
         for (int i = 0; i < WT; ++i)
 #pragma unroll
@@ -388,10 +390,14 @@ struct AdjointEpiF64 {
                     const int roff = i * 16 + 4 * r;
                     if (roff < rows_left) {
                         const int64_t o = lane_off + (int64_t)roff * cols + j * 16;
+                        double w = tot[i][j][r];
+                        // chain factors of a balanced forward
+                        if (a.out_row_mul) w *= a.out_row_mul[row_base + roff];
+                        if (a.out_col_mul) w *= a.out_col_mul[col_base + j * 16];
                         if (a.out_f64)
-                            ((double*)a.out)[o] = tot[i][j][r];
+                            ((double*)a.out)[o] = w;
                         else
-                            ((float*)a.out)[o] = (float)tot[i][j][r];
+                            ((float*)a.out)[o] = (float)w;
                     }
                 }
             }

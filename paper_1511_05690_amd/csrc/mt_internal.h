@@ -126,6 +126,11 @@ struct AdjArgs {
     // nullable, per batch item: the result is multiplied by 2^post_exp (the
     // BF16 adjoint planes hold c_j or r_i divided by that power of two)
     const int32_t* post_exp;
+    // nullable, b x rows and b x cols: the result is multiplied by
+    // out_row_mul[row] out_col_mul[col] (the chain factors of a balanced
+    // forward: d_k for the columns of dA, 1 / d_k for the rows of dB)
+    const double* out_row_mul;
+    const double* out_col_mul;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -174,10 +179,16 @@ hipError_t launch_affine_correct(void* D, int f64, int64_t n, const int32_t* src
 // Counting sort of the sparse-tail list (length *count, read on the device)
 // into epi.tail_sorted by row bucket; rows = rows of the output per batch item.
 hipError_t launch_tail_sort(const EpiArgs& epi, int64_t rows, int64_t cap, hipStream_t st);
+// Row maxima of A (rows x k; with mul, of A_rj mul[r / rows_per_batch][j])
+// and column maxima of B (b x k x n; with mul, of B_bkj mul[b][k]).
 hipError_t launch_rowmax(const void* A, int f64, int64_t rows, int64_t k, double* r,
-                         int32_t* flag, hipStream_t st);
+                         int32_t* flag, hipStream_t st, const double* mul = nullptr,
+                         int64_t rows_per_batch = 1);
 hipError_t launch_colmax(const void* B, int f64, int64_t b, int64_t k, int64_t n, double* c,
-                         int32_t* flag, hipStream_t st);
+                         int32_t* flag, hipStream_t st, const double* mul = nullptr);
+// Inner-index balancing factors d = sqrt(b / a) (1 where a or b is 0) and 1 / d.
+hipError_t launch_balance(const double* a, const double* b, int64_t count, double* d, double* dinv,
+                          hipStream_t st);
 hipError_t launch_apsp_transform(const float* W, int64_t n, double s, void* X, int x_f64,
                                  int32_t* flag, hipStream_t st);
 hipError_t launch_apsp_to_dist(const void* X, int x_f64, int64_t n, double s, void* D,
@@ -186,8 +197,9 @@ hipError_t launch_apsp_to_dist(const void* X, int x_f64, int64_t n, double s, vo
 // Power planes.  src is b x rows x cols (row-major, element f64 ? double :
 // float) when !transpose, or b x cols x rows when transpose (then planes hold
 // the transpose).  Output planes: [b][plane][rows_pad][cols_pad] of bf16
-// (bf16 != 0) or double.  Plane element (t, u) is src / (scale_rows[t] *
-// scale_cols[u]); scale_rows is b x rows, scale_cols b x cols, each nullable.
+// (bf16 != 0) or double.  Plane element (t, u) is src col_mul[u] /
+// (scale_rows[t] * scale_cols[u]); scale_rows is b x rows, scale_cols and
+// col_mul b x cols, each nullable.
 // powers: ascending list; split[q] says whether power q gets a hi/lo pair
 // (bf16 only).
 struct PlaneSpec {
@@ -200,7 +212,8 @@ struct PlaneSpec {
 hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int64_t b,
                                int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
                                const double* scale_rows, const double* scale_cols,
-                               const PlaneSpec& spec, int bf16, void* planes, hipStream_t st);
+                               const PlaneSpec& spec, int bf16, void* planes, hipStream_t st,
+                               const double* col_mul = nullptr);
 
 // Fused p-family GEMM + selection epilogue.
 hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m,

@@ -128,6 +128,20 @@ def test_noalloc_rejects_before_launch():
     assert st == 0
 
 
+def test_balance_flag_workspace_and_scope():
+    """MT_FLAG_BALANCE adds 4 b k FP64 values (column maxima of A, row maxima
+    of B, d, 1 / d) to the product workspace and is refused by APSP."""
+    lib = mt.load_library()
+    P = [1, 2, 4, 8]
+    w0 = mt.workspace_size(3, 100, 777, 90, P)
+    w1 = mt.workspace_size(3, 100, 777, 90, P, flags=mt.FLAG_BALANCE)
+    assert w1 - w0 == 4 * ((3 * 777 * 8 + 255) // 256 * 256)
+    o = _opts(P, flags=mt.FLAG_BALANCE)
+    out = ctypes.c_size_t(0)
+    assert lib.apsp_workspace_size(64, ctypes.byref(o), ctypes.byref(out)) == 1
+    assert b"MT_FLAG_BALANCE" in lib.maxtimes_last_error()
+
+
 def test_apsp_argument_errors():
     lib = mt.load_library()
     o = _opts([1, 2, 4], path=0)
