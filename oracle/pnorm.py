@@ -49,9 +49,21 @@ design notes of the repository):
       the added norms 3q).  The estimate is the largest of the two
       projected values, i.e. of the positive roots x = alpha^q of the
       null-space polynomial.  Where p* is not a multiple of 4 with p*/4 and
-      p*/2 in P, a norm is 0, the Hankel matrix has rank 1 (a single
-      distinct value), or no root is real and positive, the r = 1
-      projection (R6) is used instead.
+      p*/2 in P, a norm is 0, the Hankel matrix is numerically of rank 1,
+      or no root is real and positive, the r = 1 projection (R6) is used
+      instead.
+      Rank 1, from the rounding of the norms: each norm S_kq is a sum of K
+      nonnegative terms whose powers come from p*-fold products, so its
+      relative rounding is at most eps = (K + 4 p* + L) u (u = 2^-53;
+      L = max_k |ln S_kq| covers the rounding of the logarithms that
+      normalise the norms).  A relative perturbation eps of the Hankel
+      matrix moves its null vector by about eps / rho (rho = sigma_2 /
+      sigma_1) and the projected value alpha = x^(1/q) by about
+      eps / (q rho).  The projection is used where that is at most
+      delta = 2.5e-6, a quarter of the FP64 path's stated accuracy 1e-5,
+      i.e. where rho > theta = eps / (q delta); below, rounding decides
+      the root and the r = 1 projection (well conditioned: a ratio of two
+      norms) is used.
   R8  Inner-index balancing (the Discussion's remark on scaling a problem
       into a bounded range; the paper gives no formula).  The product is
       unchanged when column k of A is multiplied by d_k > 0 and row k of B
@@ -192,7 +204,18 @@ def r2_aux_powers(P):
     return sorted({3 * p // 4 for p in Ps if p % 4 == 0 and p // 4 in Ps and p // 2 in Ps} - Ps)
 
 
-def _project_r2(S, P, idx, fallback, S_aux, aux):
+R2_DELTA = 2.5e-6
+U64 = 2.0 ** -53
+
+
+def r2_threshold(k, pstar, lmax):
+    """Reading R7: the rank-1 threshold theta on sigma_2 / sigma_1 for inner
+    length k, p* = 4q and L = max |ln S| of the four norms."""
+    q = pstar // 4
+    return (k + 4.0 * pstar + lmax) * U64 / (q * R2_DELTA)
+
+
+def _project_r2(S, P, idx, fallback, S_aux, aux, k, info=None):
     """The r = 2 projection of Sec. 1 (reading R7): with p* = P[q] = 4t and
     the ring results S_t, S_2t, S_3t, S_4t, a null vector g of the Hankel
     matrix [[S_t, S_2t, S_3t], [S_2t, S_3t, S_4t]] (taken from the SVD) gives
@@ -202,8 +225,13 @@ def _project_r2(S, P, idx, fallback, S_aux, aux):
     scales the roots by c.  Where the four norms are not all positive and
     available, the Hankel matrix has rank below 2 (sigma_2 <= 1e-8
     sigma_1: one distinct value, or so close to one that rounding in the
-    norms, about 1e-16 relative, would decide the roots), or the roots are
-    complex or not positive, ``fallback`` (the r = 1 projection) is used."""
+    norms, would decide the roots: sigma_2 / sigma_1 <= r2_threshold), or
+    the roots are complex or not positive, ``fallback`` (the r = 1
+    projection) is used.  k is the inner length of the product.  With a
+    dict ``info``, per entry: rho (sigma_2 / sigma_1), theta, and alt, the
+    value the other rank decision gives (the projected root where the
+    threshold chose the fallback, the fallback where it chose the root;
+    NaN where the decision had no alternative)."""
     P = [int(p) for p in P]
     pos = {p: ("P", i) for i, p in enumerate(P)}
     pos.update({p: ("A", i) for i, p in enumerate(aux)})
@@ -213,6 +241,10 @@ def _project_r2(S, P, idx, fallback, S_aux, aux):
     flatS = S.reshape(S.shape[0], -1)
     flatA = S_aux.reshape(S_aux.shape[0], -1) if len(aux) else None
     flat_out = out.reshape(-1)
+    fb = np.asarray(fallback, dtype=np.float64).reshape(-1)
+    rho_a = np.full(flat_idx.size, np.nan)
+    theta_a = np.full(flat_idx.size, np.nan)
+    alt_a = np.full(flat_idx.size, np.nan)
     for e in range(flat_idx.size):
         q = int(flat_idx[e])
         if q == PSTAR_NONE:
@@ -231,12 +263,11 @@ def _project_r2(S, P, idx, fallback, S_aux, aux):
         Sk = np.array(vals, dtype=np.float64)
         if np.any(Sk <= 0):
             continue
-        logc = (np.log(Sk[3]) - np.log(Sk[0])) / 3.0
-        tk = np.exp(np.log(Sk) - np.arange(1, 5) * logc)
+        lS = np.log(Sk)
+        logc = (lS[3] - lS[0]) / 3.0
+        tk = np.exp(lS - np.arange(1, 5) * logc)
         H = np.array([[tk[0], tk[1], tk[2]], [tk[1], tk[2], tk[3]]])
         _, sv, Vh = np.linalg.svd(H)
-        if sv[1] <= 1e-8 * sv[0]:
-            continue
         g0, g1, g2 = Vh[-1]
         if g2 == 0:
             continue
@@ -247,7 +278,19 @@ def _project_r2(S, P, idx, fallback, S_aux, aux):
         ymax = max(roots)
         if not ymax > 0:
             continue
-        flat_out[e] = np.exp((np.log(ymax) + logc) / t)
+        root_val = np.exp((np.log(ymax) + logc) / t)
+        rho = sv[1] / sv[0]
+        theta = r2_threshold(k, ps, np.abs(lS).max())
+        rho_a[e], theta_a[e] = rho, theta
+        if rho > theta:
+            flat_out[e] = root_val
+            alt_a[e] = fb[e]
+        else:
+            alt_a[e] = root_val
+    if info is not None:
+        info["rho"] = rho_a.reshape(shp)
+        info["theta"] = theta_a.reshape(shp)
+        info["alt"] = alt_a.reshape(shp)
     return out
 
 
@@ -307,8 +350,11 @@ def pnorm_estimate(A, B, P, tau, norm_correct=False, projection=None, balance=Fa
     if projection == "r2":
         aux = r2_aux_powers(P)
         S_aux = norm_power_sequence(A, B, aux)[0] if aux else np.zeros((0,) + S.shape[1:])
-        root = _project_r2(S, P, idx, root, S_aux, aux)
-        out_aux = {"S_aux": S_aux, "aux": aux}
+        info = {}
+        root = _project_r2(S, P, idx, root, S_aux, aux, k, info)
+        rc = r[..., :, None] * c[..., None, :]
+        out_aux = {"S_aux": S_aux, "aux": aux, "k": k, "r2_rho": info["rho"], "r2_theta": info["theta"],
+                   "C_alt": rc * info["alt"]}
     C = r[..., :, None] * c[..., None, :] * root
     if norm_correct and k > 0:
         C = C / np.power(float(k), 1.0 / psel)

@@ -252,7 +252,7 @@ FamilyPlan family_plan(const Family& f, const PlaneSpec& ps, int64_t k) {
 }
 
 // The r = 2 selection over the S stack (planes in the order of ps).
-R2Spec r2_spec(const Family& f, const PlaneSpec& ps, int mode, int clamp) {
+R2Spec r2_spec(const Family& f, const PlaneSpec& ps, int mode, int clamp, int64_t k) {
     R2Spec r;
     memset(&r, 0, sizeof r);
     auto plane_of = [&](int32_t v) {
@@ -272,6 +272,7 @@ R2Spec r2_spec(const Family& f, const PlaneSpec& ps, int mode, int clamp) {
     r.tau = f.tau;
     r.mode = mode;
     r.clamp = clamp;
+    r.k_inner = (double)k;
     return r;
 }
 
@@ -487,7 +488,7 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
         MT_TRY(launch_pfamily_gemm_f64((const double*)ap, (const double*)bp, b, m, n, g.mp, g.np, g.kp,
                                        ps.n_planes, g.bm, plan, epi, st),
                "p-family GEMM (FP64, every ring result)");
-        const R2Spec rs = r2_spec(f, ps, mode, clamp);
+        const R2Spec rs = r2_spec(f, ps, mode, clamp, k);
         MT_TRY(launch_select_r2_f64((const double*)(ws + L.s), b * m * n, b, m, n, r, c, rs, out, out_f64, pstar,
                                     st),
                "select and r = 2 projection");

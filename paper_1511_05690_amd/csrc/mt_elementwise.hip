@@ -444,11 +444,17 @@ __global__ __launch_bounds__(kThreads) void mt_select_root_f64_kernel(
 // c^k, c = (S_4q / S_q)^(1/3), which scales the roots by c) is the cross
 // product of its rows, g = (t2 t4 - t3^2, t2 t3 - t1 t4, t1 t3 - t2^2), and
 // the estimate is the largest root x of g0 + g1 x + g2 x^2 (x = alpha^q / c)
-// as alpha = (c x)^(1/q).  Rank 1 (|g| <= 1e-8 (|row1|^2 + |row2|^2): one
-// distinct value, or so close to it that rounding decides), complex or
-// nonpositive roots, or a missing norm: the r = 1
-// projection with the next smaller family p; no such p or S_lo = 0: the
-// plain root.
+// as alpha = (c x)^(1/q).  Numerical rank 1, complex or nonpositive roots, or
+// a missing norm: the r = 1 projection with the next smaller family p; no
+// such p or S_lo = 0: the plain root.  Rank 1: rho = sigma_2 / sigma_1 of
+// the 2 x 3 matrix (from |g| = sigma_1 sigma_2 and the squared Frobenius
+// norm sigma_1^2 + sigma_2^2) at most theta = eps / (q delta): the norms'
+// relative rounding eps = (K + 4 p* + max |ln S|) 2^-53 (K terms, p*-fold
+// products, the logarithms) moves the projected value by about
+// eps / (q rho), and the projection is used where that stays below
+// delta = 2.5e-6 (a quarter of the path's 1e-5).
+constexpr double kR2Delta = 2.5e-6;
+
 template <typename TO>
 __global__ __launch_bounds__(kThreads) void mt_select_r2_kernel(const double* __restrict__ stack, int64_t stride,
                                                                 int64_t rows, int64_t m, int64_t n,
@@ -494,8 +500,16 @@ __global__ __launch_bounds__(kThreads) void mt_select_r2_kernel(const double* __
                     const double g2 = t[0] * t[2] - t[1] * t[1];
                     const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
                     const double rn = t[0] * t[0] + 2 * t[1] * t[1] + 2 * t[2] * t[2] + t[3] * t[3];
+                    // y = sigma_1 sigma_2 / (sigma_1^2 + sigma_2^2) = rho / (1 + rho^2)
+                    const double y = fmin(gn / rn, 0.5);
+                    const double rho = 2.0 * y / (1.0 + sqrt(fmax(1.0 - 4.0 * y * y, 0.0)));
+                    double lmax = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) lmax = fmax(lmax, fabs(lS[k]));
+                    const double theta =
+                        (spec.k_inner + 4.0 * p + lmax) * 0x1p-53 / ((double)(p / 4) * kR2Delta);
                     const double disc = g1 * g1 - 4.0 * g2 * g0;
-                    if (gn > 1e-8 * rn && g2 != 0.0 && disc >= 0.0) {
+                    if (rho > theta && g2 != 0.0 && disc >= 0.0) {
                         const double sq = sqrt(disc);
                         const double x1 = (-g1 + sq) / (2.0 * g2), x2 = (-g1 - sq) / (2.0 * g2);
                         const double xm = x1 > x2 ? x1 : x2;

@@ -245,6 +245,7 @@ struct R2Spec {
     double tau;
     int32_t mode;
     int32_t clamp;
+    double k_inner;  // inner length K of the product (the rank-1 threshold)
 };
 hipError_t launch_select_r2_f64(const double* stack, int64_t stride, int64_t b, int64_t m, int64_t n,
                                 const double* r, const double* c, const R2Spec& spec, void* out, int out_f64,

@@ -46,7 +46,22 @@ def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, ma
     denom = np.maximum(np.abs(C_ref), 1e-300)
     rel = np.abs(C_gpu - C_ref) / denom
     bad = same & (rel > tol)
-    assert not bad.any(), f"{bad.sum()} entries exceed rel tol {tol}: max {rel[same].max():.3e}"
+    n_rank_flip = 0
+    if projection == "r2" and "r2_rho" in ref and bad.any():
+        # the r = 2 rank decision (reading R7) near its threshold: the two
+        # sides' rounding may decide differently where the oracle's
+        # sigma_2 / sigma_1 is within 10 % of theta (their estimates of it
+        # differ by the rounding of the norms, far less); the GPU value must
+        # then be the oracle's value under the other decision
+        rho, theta = ref["r2_rho"], ref["r2_theta"]
+        C_alt = np.minimum(ref["C_alt"], 1.0) if clamp else ref["C_alt"]
+        with np.errstate(invalid="ignore"):
+            in_band = np.isfinite(rho) & (np.abs(rho / theta - 1.0) <= 0.1)
+            alt_ok = np.abs(C_gpu - C_alt) <= tol * np.maximum(np.abs(C_alt), 1e-300)
+        arbitrated = bad & in_band & alt_ok
+        n_rank_flip = int(arbitrated.sum())
+        bad &= ~arbitrated
+    assert not bad.any(), f"{bad.sum()} entries exceed rel tol {tol}: max {rel[bad].max():.3e}"
 
     flips = (ps_gpu != q_ref) & keep
     n_flip = int(flips.sum())
@@ -71,7 +86,7 @@ def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, ma
             root_g = oracle.pnorm._root(S, P, idx_g)[0]
             proj = oracle.pnorm._project_r1(S, P, idx_g, root_g)
             if projection == "r2":
-                proj = oracle.pnorm._project_r2(S, P, idx_g, proj, ref["S_aux"], ref["aux"])
+                proj = oracle.pnorm._project_r2(S, P, idx_g, proj, ref["S_aux"], ref["aux"], ref["k"])
             C_at = rc[flips] * proj[flips]
         if norm_k is not None:
             C_at = C_at / np.power(float(norm_k), 1.0 / P[qg_used])
@@ -91,5 +106,7 @@ def compare_estimate(C_gpu, ps_gpu, ref, P, path, split_max_p=4, norm_k=None, ma
             cap = cap / np.power(float(norm_k), 1.0 / P[0])
         assert (C_gpu[both_none] <= cap[both_none] + 1e-300).all()
         assert (C_gpu[both_none] >= 0).all()
-    return {"max_rel": float(rel[same].max()) if same.any() else 0.0,
-            "flips": n_flip, "none": int(both_none.sum()), "n": int(C_ref.size)}
+    ok_same = same & (rel <= tol)
+    return {"max_rel": float(rel[ok_same].max()) if ok_same.any() else 0.0,
+            "flips": n_flip, "none": int(both_none.sum()), "n": int(C_ref.size),
+            "r2_rank_flips": n_rank_flip}
