@@ -33,6 +33,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 matrix
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pfamily_gemm_bf16_8192_pmc.md")
+TRACE_SUMMARY = os.path.join(ROOT, "profiles", "pfamily_gemm_bf16_8192_kernel_trace.md")
 GEMM_SRC = os.path.join(ROOT, "paper_1511_05690_amd", "csrc", "mt_gemm_bf16.hip")
 MAXCONV_PMC = os.path.join(ROOT, "profiles", "maxconv_fft_8192x2048_pmc.md")
 MAXCONV_SRC = os.path.join(ROOT, "paper_1511_05690_amd", "csrc", "mt_maxconv.hip")
@@ -58,6 +59,19 @@ def traffic_from_profile(summary=PMC_SUMMARY, src=GEMM_SRC):
     if not m_hash or not m_bytes or m_hash.group(1) != source_hash(src):
         return None
     return float(m_bytes.group(1))
+
+
+def trace_from_profile(summary, src, kernel):
+    """Average duration (ms) of `kernel` in a committed rocprofv3 kernel-trace
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(summary):
+        return None
+    text = open(summary).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_avg = re.search(r"^" + re.escape(kernel) + r"_avg_ms:\s*([0-9.eE+-]+)", text, re.M)
+    if not m_hash or not m_avg or m_hash.group(1) != source_hash(src):
+        return None
+    return float(m_avg.group(1))
 
 
 def gemm_segments(P, split_max_p=4):
@@ -149,211 +163,222 @@ def time_call(fn, reps, torch):
     return ev0.elapsed_time(ev1) / reps
 
 
-def run_legs(mt, torch, np):
+def run_legs(mt, torch, np, sections=None):
     """The other rows of the hot path, each on its own workload: APSP on the
     FP64 and BF16 paths, the differentiable form, and the small FP64 product.
     Effective max-times ops: T n^3 for APSP, b m k n per product."""
     from workloads import config
 
+    def want(name):
+        return sections is None or name in sections
+
     legs = {}
-    c1 = config(1)
-    A1, B1 = torch.from_numpy(c1["A"]).cuda(), torch.from_numpy(c1["B"]).cuda()
-    ms = time_call(lambda: mt.estimate(A1, B1, P=c1["P"], path="fp64"), 20, torch)
-    legs["product_256_fp64"] = {"ms": ms, "ops_per_s": 256.0 ** 3 / (ms / 1e3), "P": c1["P"]}
+    if want("small"):
+        c1 = config(1)
+        A1, B1 = torch.from_numpy(c1["A"]).cuda(), torch.from_numpy(c1["B"]).cuda()
+        ms = time_call(lambda: mt.estimate(A1, B1, P=c1["P"], path="fp64"), 20, torch)
+        legs["product_256_fp64"] = {"ms": ms, "ops_per_s": 256.0 ** 3 / (ms / 1e3), "P": c1["P"]}
 
-    c2 = config(2)
-    W2 = torch.from_numpy(c2["W"]).cuda()
-    n2 = c2["W"].shape[0]
-    # exact APSP on the GPU for the error columns: T squarings of the exact
-    # (max, x) product (the library's VALU kernel) on X = exp(-s W)
-    X = torch.exp(-c2["s"] * W2.double())
-    X.fill_diagonal_(1.0)
-    for _ in range(c2["T"]):
-        X = mt.exact(X, X)
+    if want("apsp2048"):
+        c2 = config(2)
+        W2 = torch.from_numpy(c2["W"]).cuda()
+        n2 = c2["W"].shape[0]
+        # exact APSP on the GPU for the error columns: T squarings of the exact
+        # (max, x) product (the library's VALU kernel) on X = exp(-s W)
+        X = torch.exp(-c2["s"] * W2.double())
         X.fill_diagonal_(1.0)
-    D_ex = -torch.log(X) / c2["s"]
-    fin = torch.isfinite(D_ex)
-    for proj in (None, "r1", "r2"):
-        ms = time_call(lambda: mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"],
-                                       out_dtype=torch.float64, projection=proj), 3, torch)
-        D = mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"], out_dtype=torch.float64,
-                    projection=proj)
-        err = (D - D_ex)[fin]
-        xrel = (torch.exp(-c2["s"] * D[fin]) / torch.exp(-c2["s"] * D_ex[fin]) - 1.0).abs()
-        name = "apsp_er2048_fp64" + ("_" + proj if proj else "")
-        legs[name] = {"ms": ms, "squarings": c2["T"], "P": c2["P"], "projection": proj or "plain",
-                      "ops_per_s": c2["T"] * float(n2) ** 3 / (ms / 1e3),
-                      "vs_exact": {"distance_mse": float((err ** 2).mean()), "max_abs": float(err.abs().max()),
-                                   "mean": float(err.mean()), "max_rel_x": float(xrel.max()),
-                                   "reachability_equal": bool(torch.equal(torch.isfinite(D), fin))}}
-        # the affine correction (Sec. 4) fitted on the exact rows of 64
-        # sampled sources (Bellman-Ford on the GPU), timed with them
-        src = np.random.default_rng(2002).choice(n2, 64, replace=False).astype(np.int32)
+        for _ in range(c2["T"]):
+            X = mt.exact(X, X)
+            X.fill_diagonal_(1.0)
+        D_ex = -torch.log(X) / c2["s"]
+        fin = torch.isfinite(D_ex)
+        for proj in (None, "r1", "r2"):
+            ms = time_call(lambda: mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"],
+                                           out_dtype=torch.float64, projection=proj), 3, torch)
+            D = mt.apsp(W2, s=c2["s"], P=c2["P"], path="fp64", n_squarings=c2["T"], out_dtype=torch.float64,
+                        projection=proj)
+            err = (D - D_ex)[fin]
+            xrel = (torch.exp(-c2["s"] * D[fin]) / torch.exp(-c2["s"] * D_ex[fin]) - 1.0).abs()
+            name = "apsp_er2048_fp64" + ("_" + proj if proj else "")
+            legs[name] = {"ms": ms, "squarings": c2["T"], "P": c2["P"], "projection": proj or "plain",
+                          "ops_per_s": c2["T"] * float(n2) ** 3 / (ms / 1e3),
+                          "vs_exact": {"distance_mse": float((err ** 2).mean()), "max_abs": float(err.abs().max()),
+                                       "mean": float(err.mean()), "max_rel_x": float(xrel.max()),
+                                       "reachability_equal": bool(torch.equal(torch.isfinite(D), fin))}}
+            # the affine correction (Sec. 4) fitted on the exact rows of 64
+            # sampled sources (Bellman-Ford on the GPU), timed with them
+            src = np.random.default_rng(2002).choice(n2, 64, replace=False).astype(np.int32)
 
-        def correct():
-            rows, _ = mt.apsp_exact_rows(W2, src)
-            return rows, mt.apsp_affine_correct(D, src, rows, apply=False)
-        ms_fit = time_call(correct, 3, torch)
-        rows, ab = correct()
-        Dc = D.clone()
-        ab = mt.apsp_affine_correct(Dc, src, rows)
-        errc = (Dc - D_ex)[fin]
-        a_, b_ = [float(x) for x in ab.cpu()]
-        legs[name]["affine_64_sources"] = {"ms_exact_rows_and_fit": ms_fit, "a": a_, "b": b_,
-                                           "distance_mse": float((errc ** 2).mean()),
-                                           "max_abs": float(errc.abs().max()), "mean": float(errc.mean())}
+            def correct():
+                rows, _ = mt.apsp_exact_rows(W2, src)
+                return rows, mt.apsp_affine_correct(D, src, rows, apply=False)
+            ms_fit = time_call(correct, 3, torch)
+            rows, ab = correct()
+            Dc = D.clone()
+            ab = mt.apsp_affine_correct(Dc, src, rows)
+            errc = (Dc - D_ex)[fin]
+            a_, b_ = [float(x) for x in ab.cpu()]
+            legs[name]["affine_64_sources"] = {"ms_exact_rows_and_fit": ms_fit, "a": a_, "b": b_,
+                                               "distance_mse": float((errc ** 2).mean()),
+                                               "max_abs": float(errc.abs().max()), "mean": float(errc.mean())}
 
-    c4 = config(4)
-    A4 = torch.from_numpy(c4["A"]).cuda()
-    B4 = torch.from_numpy(c4["B"]).cuda()
-    G4 = torch.from_numpy(c4["G"]).cuda()
-    for name, P in (("grad_64x512_p16_bf16", c4["P_fixed"]), ("grad_64x512_bf16", c4["P"])):
-        def fwd_bwd():
-            C, ps = mt.estimate(A4, B4, P=P, path="bf16", split_max_p=4096, return_pstar=True)
-            mt.estimate_backward(A4, B4, G4, C, ps, P, path="bf16")
-        ms = time_call(fwd_bwd, 5, torch)
-        legs[name] = {"ms_fwd_bwd": ms, "P": P, "ops_per_s": 64 * 512.0 ** 3 / (ms / 1e3)}
+    if want("grad"):
+        c4 = config(4)
+        A4 = torch.from_numpy(c4["A"]).cuda()
+        B4 = torch.from_numpy(c4["B"]).cuda()
+        G4 = torch.from_numpy(c4["G"]).cuda()
+        for name, P in (("grad_64x512_p16_bf16", c4["P_fixed"]), ("grad_64x512_bf16", c4["P"])):
+            def fwd_bwd():
+                C, ps = mt.estimate(A4, B4, P=P, path="bf16", split_max_p=4096, return_pstar=True)
+                mt.estimate_backward(A4, B4, G4, C, ps, P, path="bf16")
+            ms = time_call(fwd_bwd, 5, torch)
+            legs[name] = {"ms_fwd_bwd": ms, "P": P, "ops_per_s": 64 * 512.0 ** 3 / (ms / 1e3)}
 
-    # inner-index balancing on inputs whose inner index carries a scaling:
-    # A = U diag(s), B = diag(s)^-1 V, U, V uniform on (0, 1], log10 s
-    # uniform on [-8, 8], 4096^3, P = {1..128}, BF16; error against the exact
-    # product on 256 sampled rows, plain and balanced
-    nb = 4096
-    g = torch.Generator(device="cuda")
-    g.manual_seed(6006)
-    sc = torch.pow(10.0, torch.rand(nb, generator=g, device="cuda", dtype=torch.float64) * 16 - 8)
-    Ab = ((1.0 - torch.rand(nb, nb, generator=g, device="cuda", dtype=torch.float64)) * sc[None, :]).float()
-    Bb = ((1.0 - torch.rand(nb, nb, generator=g, device="cuda", dtype=torch.float64)) / sc[:, None]).float()
-    rb = torch.from_numpy(np.sort(np.random.default_rng(6007).choice(nb, 256, replace=False))).cuda()
-    Eb = mt.exact(Ab[rb].contiguous(), Bb).double()
-    leg = {"n": nb, "P": pfamily_128(), "inner_scale_decades": 16}
-    for tag, balance in (("plain", False), ("balanced", True)):
-        ms = time_call(lambda: mt.estimate(Ab, Bb, P=pfamily_128(), path="bf16", balance=balance), 3, torch)
-        C, ps = mt.estimate(Ab, Bb, P=pfamily_128(), path="bf16", balance=balance, return_pstar=True)
-        rel = (C[rb].double() / Eb - 1.0).abs()
-        psel = ps[rb].flatten().long()
-        leg[tag] = {"ms": ms, "max_rel_vs_exact": float(rel.max()), "median_rel_vs_exact": float(rel.median()),
-                    "pstar_hist": torch.bincount(psel, minlength=256)[:8].tolist()}
-    legs["balance_inner_scaled_4096_bf16"] = leg
-    del Ab, Bb, Eb, C, ps
-    torch.cuda.empty_cache()
+    if want("balance"):
+        # inner-index balancing on inputs whose inner index carries a scaling:
+        # A = U diag(s), B = diag(s)^-1 V, U, V uniform on (0, 1], log10 s
+        # uniform on [-8, 8], 4096^3, P = {1..128}, BF16; error against the exact
+        # product on 256 sampled rows, plain and balanced
+        nb = 4096
+        g = torch.Generator(device="cuda")
+        g.manual_seed(6006)
+        sc = torch.pow(10.0, torch.rand(nb, generator=g, device="cuda", dtype=torch.float64) * 16 - 8)
+        Ab = ((1.0 - torch.rand(nb, nb, generator=g, device="cuda", dtype=torch.float64)) * sc[None, :]).float()
+        Bb = ((1.0 - torch.rand(nb, nb, generator=g, device="cuda", dtype=torch.float64)) / sc[:, None]).float()
+        rb = torch.from_numpy(np.sort(np.random.default_rng(6007).choice(nb, 256, replace=False))).cuda()
+        Eb = mt.exact(Ab[rb].contiguous(), Bb).double()
+        leg = {"n": nb, "P": pfamily_128(), "inner_scale_decades": 16}
+        for tag, balance in (("plain", False), ("balanced", True)):
+            ms = time_call(lambda: mt.estimate(Ab, Bb, P=pfamily_128(), path="bf16", balance=balance), 3, torch)
+            C, ps = mt.estimate(Ab, Bb, P=pfamily_128(), path="bf16", balance=balance, return_pstar=True)
+            rel = (C[rb].double() / Eb - 1.0).abs()
+            psel = ps[rb].flatten().long()
+            leg[tag] = {"ms": ms, "max_rel_vs_exact": float(rel.max()), "median_rel_vs_exact": float(rel.median()),
+                        "pstar_hist": torch.bincount(psel, minlength=256)[:8].tolist()}
+        legs["balance_inner_scaled_4096_bf16"] = leg
+        del Ab, Bb, Eb, C, ps
+        torch.cuda.empty_cache()
 
-    # max-convolution (Sec. 1): 8192 pairs of 2048-point probability vectors
-    # (Dirichlet(1) rows), P = {1, ..., 64}, FFT convolution in FP64
-    from workloads import maxconv_vectors, pfamily
-    bm, nm = 8192, 2048
-    xc, yc = maxconv_vectors(bm, nm, nm, seed=4004, kind="distribution")
-    xd, yd = torch.from_numpy(xc).cuda(), torch.from_numpy(yc).cuda()
-    del xc, yc
-    Pm = pfamily(64)
-    mt.timing_reset()
-    mt.timing_enable(True)
-    ms = time_call(lambda: mt.maxconv(xd, yd, Pm), 5, torch)
-    kms, kn = mt.timing_read("mt_maxconv")
-    kflop = mt.timing_work("mt_maxconv")
-    mt.timing_reset()
-    ms_exact = time_call(lambda: mt.maxconv_exact(xd, yd), 1, torch)
-    mt.timing_enable(False)
-    z, ps = mt.maxconv(xd, yd, Pm, return_pstar=True)
-    E = mt.maxconv_exact(xd, yd)
-    pos = E > 0
-    rel = (z[pos] / E[pos] - 1.0).abs()
-    hist = torch.bincount(ps.flatten().long(), minlength=256)[:len(Pm)].tolist()
-    achieved = kflop / kn / (kms / kn / 1e3) / 1e12
-    legs["maxconv_8192x2048_fp64"] = {
-        "ms": ms, "pairs": bm, "n": nm, "m": nm, "P": Pm,
-        "ops_per_s": bm * float(nm) * nm / (ms / 1e3),
-        "roofline": {"bound": "alu", "kernel": "mt_maxconv", "achieved": achieved,
-                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic_from_profile(MAXCONV_PMC, MAXCONV_SRC),
-                     "flop_per_launch": kflop / kn, "avg_launch_ms": kms / kn,
-                     "flop_count": "10 N log2 N per pair and p visited (two complex FFTs), N = 4096"},
-        "exact_ms": ms_exact, "speedup_vs_exact": ms_exact / ms,
-        "vs_exact": {"max_rel": float(rel.max()), "median_rel": float(rel.median())},
-        "pstar_hist": hist,
-    }
-    del xd, yd, z, ps, E, pos, rel
-    torch.cuda.empty_cache()
-
-    # top k of x + y (Sec. 2.3, the n = 8192, k = 256 case of Sec. 3): uniform
-    # lists on [0, 1] and on [0, 40], the 24-power family up to 4096, the
-    # plain queue and the paired one (Discussion); exact top k on the GPU by
-    # torch over all n^2 sums, for the accuracy columns
-    nx, kx = 8192, 256
-
-    def lists(spread):
-        rng = np.random.default_rng(5005)
-        return (torch.from_numpy(rng.uniform(0, spread, nx)).cuda(),
-                torch.from_numpy(rng.uniform(0, spread, nx)).cuda())
-
-    def accuracy(xs, ys, paired):
-        v, ii, jj = mt.xy_topk(xs, ys, kx, paired=paired)
-        ev, eidx = torch.topk((xs[:, None] + ys[None, :]).flatten(), kx)
-        ei, ej = (eidx // nx).int(), (eidx % nx).int()
-        return {"indices_found_at_rank": int(((ii == ei) & (jj == ej)).sum()),
-                "true_top_k_pairs_found": int(torch.isin(ii.long() * nx + jj.long(), eidx).sum()), "k": kx,
-                "max_abs_value_err_first_16": float((v[:16] - ev[:16]).abs().max()),
-                "max_abs_value_err": float((v - ev).abs().max())}
-
-    xs, ys = lists(1)
-    leg = {"n": nx, "k": kx, "P": list(mt.XY_FAMILY)}
-    for paired, tag in ((False, ""), (True, "paired_")):
+    if want("maxconv"):
+        # max-convolution (Sec. 1): 8192 pairs of 2048-point probability vectors
+        # (Dirichlet(1) rows), P = {1, ..., 64}, FFT convolution in FP64
+        from workloads import maxconv_vectors, pfamily
+        bm, nm = 8192, 2048
+        xc, yc = maxconv_vectors(bm, nm, nm, seed=4004, kind="distribution")
+        xd, yd = torch.from_numpy(xc).cuda(), torch.from_numpy(yc).cuda()
+        del xc, yc
+        Pm = pfamily(64)
         mt.timing_reset()
         mt.timing_enable(True)
-        leg[tag + "ms"] = time_call(lambda: mt.xy_topk(xs, ys, kx, paired=paired), 3, torch)
-        names = ("mt_xy_sigma", "mt_xy_psi", "mt_xy_select", "mt_xy_paired" if paired else "mt_xy_queue")
-        leg[tag + "kernel_ms"] = {name: mt.timing_read(name)[0] / 4 for name in names}
+        ms = time_call(lambda: mt.maxconv(xd, yd, Pm), 5, torch)
+        kms, kn = mt.timing_read("mt_maxconv")
+        kflop = mt.timing_work("mt_maxconv")
+        mt.timing_reset()
+        ms_exact = time_call(lambda: mt.maxconv_exact(xd, yd), 1, torch)
         mt.timing_enable(False)
-    leg["naive_gpu_topk_ms"] = time_call(lambda: torch.topk((xs[:, None] + ys[None, :]).flatten(), kx), 3, torch)
-    for spread in (1, 40):
-        xs, ys = lists(spread)
-        for paired, tag in ((False, ""), (True, "paired_")):
-            leg[f"{tag}vs_exact_uniform_0_{spread}"] = accuracy(xs, ys, paired)
-    legs["xy_topk_8192_k256_fp64"] = leg
-    del xs, ys
-    torch.cuda.empty_cache()
-
-    # APSP on the 16384-vertex random geometric graph (radius 0.02, weights
-    # 100 x length, s = 0.35, 14 squarings, P = {1..128}) on the BF16 path,
-    # and once on the FP64 path for comparison; errors against exact rows
-    # from 64 sampled sources (Bellman-Ford on the GPU, the library's
-    # apsp_exact_rows)
-    c5 = config(5)
-    W5 = torch.from_numpy(c5["W"]).cuda()
-    del c5["W"]
-    n5 = W5.shape[0]
-    src5 = np.sort(np.random.default_rng(5006).choice(n5, 64, replace=False)).astype(np.int32)
-    ex5, rounds5 = mt.apsp_exact_rows(W5, src5)
-    si = torch.from_numpy(src5.astype(np.int64)).cuda()
-    # the plain estimate's far pairs sit at small p* (e^(-s d) to the power p
-    # must stay above tau), so its error grows with the distance; the r = 1
-    # projection (exact for tied top terms) and the affine correction fitted
-    # on the same exact rows are reported beside it
-    for path, proj in (("bf16", None), ("bf16", "r1"), ("fp64", None)):
-        if path == "bf16":  # one untimed call first; the FP64 run (seconds) is timed once, cold
-            mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64,
-                    projection=proj)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        D5 = mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64,
-                     projection=proj)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1)
-        leg = {"ms": ms, "squarings": c5["T"], "P": c5["P"], "s": c5["s"], "projection": proj or "plain",
-               "ops_per_s": c5["T"] * float(n5) ** 3 / (ms / 1e3),
-               "vs_exact_64_sources": apsp_errors(D5[si], ex5, c5["s"], torch),
-               "exact_rows": {"sources": len(src5), "bellman_ford_rounds": rounds5}}
-        Dc = D5.clone()
-        ab = mt.apsp_affine_correct(Dc, src5, ex5)
-        leg["affine_64_sources"] = dict(apsp_errors(Dc[si], ex5, c5["s"], torch),
-                                        a=float(ab[0]), b=float(ab[1]),
-                                        note="fitted on the same 64 rows it is scored on")
-        legs["apsp_rgg16384_" + path + ("_" + proj if proj else "")] = leg
-        del D5, Dc
+        z, ps = mt.maxconv(xd, yd, Pm, return_pstar=True)
+        E = mt.maxconv_exact(xd, yd)
+        pos = E > 0
+        rel = (z[pos] / E[pos] - 1.0).abs()
+        hist = torch.bincount(ps.flatten().long(), minlength=256)[:len(Pm)].tolist()
+        achieved = kflop / kn / (kms / kn / 1e3) / 1e12
+        legs["maxconv_8192x2048_fp64"] = {
+            "ms": ms, "pairs": bm, "n": nm, "m": nm, "P": Pm,
+            "ops_per_s": bm * float(nm) * nm / (ms / 1e3),
+            "roofline": {"bound": "alu", "kernel": "mt_maxconv", "achieved": achieved,
+                         "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                         "traffic": traffic_from_profile(MAXCONV_PMC, MAXCONV_SRC),
+                         "flop_per_launch": kflop / kn, "avg_launch_ms": kms / kn,
+                         "flop_count": "10 N log2 N per pair and p visited (two complex FFTs), N = 4096"},
+            "exact_ms": ms_exact, "speedup_vs_exact": ms_exact / ms,
+            "vs_exact": {"max_rel": float(rel.max()), "median_rel": float(rel.median())},
+            "pstar_hist": hist,
+        }
+        del xd, yd, z, ps, E, pos, rel
         torch.cuda.empty_cache()
+
+    if want("xy"):
+        # top k of x + y (Sec. 2.3, the n = 8192, k = 256 case of Sec. 3): uniform
+        # lists on [0, 1] and on [0, 40], the 24-power family up to 4096, the
+        # plain queue and the paired one (Discussion); exact top k on the GPU by
+        # torch over all n^2 sums, for the accuracy columns
+        nx, kx = 8192, 256
+
+        def lists(spread):
+            rng = np.random.default_rng(5005)
+            return (torch.from_numpy(rng.uniform(0, spread, nx)).cuda(),
+                    torch.from_numpy(rng.uniform(0, spread, nx)).cuda())
+
+        def accuracy(xs, ys, paired):
+            v, ii, jj = mt.xy_topk(xs, ys, kx, paired=paired)
+            ev, eidx = torch.topk((xs[:, None] + ys[None, :]).flatten(), kx)
+            ei, ej = (eidx // nx).int(), (eidx % nx).int()
+            return {"indices_found_at_rank": int(((ii == ei) & (jj == ej)).sum()),
+                    "true_top_k_pairs_found": int(torch.isin(ii.long() * nx + jj.long(), eidx).sum()), "k": kx,
+                    "max_abs_value_err_first_16": float((v[:16] - ev[:16]).abs().max()),
+                    "max_abs_value_err": float((v - ev).abs().max())}
+
+        xs, ys = lists(1)
+        leg = {"n": nx, "k": kx, "P": list(mt.XY_FAMILY)}
+        for paired, tag in ((False, ""), (True, "paired_")):
+            mt.timing_reset()
+            mt.timing_enable(True)
+            leg[tag + "ms"] = time_call(lambda: mt.xy_topk(xs, ys, kx, paired=paired), 3, torch)
+            names = ("mt_xy_sigma", "mt_xy_psi", "mt_xy_select", "mt_xy_paired" if paired else "mt_xy_queue")
+            leg[tag + "kernel_ms"] = {name: mt.timing_read(name)[0] / 4 for name in names}
+            mt.timing_enable(False)
+        leg["naive_gpu_topk_ms"] = time_call(lambda: torch.topk((xs[:, None] + ys[None, :]).flatten(), kx), 3, torch)
+        for spread in (1, 40):
+            xs, ys = lists(spread)
+            for paired, tag in ((False, ""), (True, "paired_")):
+                leg[f"{tag}vs_exact_uniform_0_{spread}"] = accuracy(xs, ys, paired)
+        legs["xy_topk_8192_k256_fp64"] = leg
+        del xs, ys
+        torch.cuda.empty_cache()
+
+    if want("rgg"):
+        # APSP on the 16384-vertex random geometric graph (radius 0.02, weights
+        # 100 x length, s = 0.35, 14 squarings, P = {1..128}) on the BF16 path,
+        # and once on the FP64 path for comparison; errors against exact rows
+        # from 64 sampled sources (Bellman-Ford on the GPU, the library's
+        # apsp_exact_rows)
+        c5 = config(5)
+        W5 = torch.from_numpy(c5["W"]).cuda()
+        del c5["W"]
+        n5 = W5.shape[0]
+        src5 = np.sort(np.random.default_rng(5006).choice(n5, 64, replace=False)).astype(np.int32)
+        ex5, rounds5 = mt.apsp_exact_rows(W5, src5)
+        si = torch.from_numpy(src5.astype(np.int64)).cuda()
+        # the plain estimate's far pairs sit at small p* (e^(-s d) to the power p
+        # must stay above tau), so its error grows with the distance; the r = 1
+        # projection (exact for tied top terms) and the affine correction fitted
+        # on the same exact rows are reported beside it
+        for path, proj in (("bf16", None), ("bf16", "r1"), ("fp64", None)):
+            if path == "bf16":  # one untimed call first; the FP64 run (seconds) is timed once, cold
+                mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64,
+                        projection=proj)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            D5 = mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64,
+                         projection=proj)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            leg = {"ms": ms, "squarings": c5["T"], "P": c5["P"], "s": c5["s"], "projection": proj or "plain",
+                   "ops_per_s": c5["T"] * float(n5) ** 3 / (ms / 1e3),
+                   "vs_exact_64_sources": apsp_errors(D5[si], ex5, c5["s"], torch),
+                   "exact_rows": {"sources": len(src5), "bellman_ford_rounds": rounds5}}
+            Dc = D5.clone()
+            ab = mt.apsp_affine_correct(Dc, src5, ex5)
+            leg["affine_64_sources"] = dict(apsp_errors(Dc[si], ex5, c5["s"], torch),
+                                            a=float(ab[0]), b=float(ab[1]),
+                                            note="fitted on the same 64 rows it is scored on")
+            legs["apsp_rgg16384_" + path + ("_" + proj if proj else "")] = leg
+            del D5, Dc
+            torch.cuda.empty_cache()
+
     return legs
 
 
@@ -391,6 +416,10 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=128)
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the APSP / gradient / small-product legs")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated leg sections to run (small, apsp2048, grad, balance, maxconv, xy, rgg); "
+                         "with --only-legs, nothing else is timed (profiling runs)")
+    ap.add_argument("--only-legs", action="store_true", help="run only the legs (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -419,6 +448,10 @@ def main():
     from workloads import config
 
     mt.load_library()
+    sections = set(args.legs.split(",")) if args.legs else None
+    if args.only_legs:
+        print(json.dumps({"legs": run_legs(mt, torch, np, sections)}))
+        return
     log("[bench] generating the 8192^2 log-normal workload")
     cfg = config(3)
     A, B, P = cfg["A"], cfg["B"], cfg["P"]
@@ -443,10 +476,13 @@ def main():
         for _ in range(warm):
             step()
         torch.cuda.synchronize()
+        log(f"[bench] timing {path}: {steps} steps")
+        # the step time with the per-launch timing off, then the same steps
+        # again with it on for the per-kernel times and executed flops
+        ms, wall = time_steps(step, steps, 0, torch)
         mt.timing_reset()
         mt.timing_enable(True)
-        log(f"[bench] timing {path}: {steps} steps")
-        ms, wall = time_steps(step, steps, 0, torch)
+        time_steps(step, steps, 0, torch)
         mt.timing_enable(False)
         kname = "mt_pfamily_gemm_" + ("bf16" if path == "bf16" else "f64")
         gemm_ms, gemm_n = mt.timing_read(kname)
@@ -514,6 +550,8 @@ def main():
     achieved = flop / (bf["gemm_ms"] / 1e3) / 1e12
     peak = BF16_PEAK_TFLOPS if main_path == "bf16" else FP64_PEAK_TFLOPS
     traffic = traffic_from_profile() if main_path == "bf16" else None
+    # the same launch in the committed rocprofv3 kernel trace (same source)
+    rp_ms = trace_from_profile(TRACE_SUMMARY, GEMM_SRC, "mt_pfamily_gemm_bf16") if main_path == "bf16" else None
 
     value = ops / (bf["ms_per_step"] / 1e3)
     out = {
@@ -543,6 +581,8 @@ def main():
             "flop_per_launch": flop,
             "flop_per_launch_whole_family": flop_family,
             "avg_launch_ms": bf["gemm_ms"],
+            "rocprof_avg_launch_ms": rp_ms,
+            "frac_at_rocprof_avg": (flop / (rp_ms / 1e3) / 1e12 / peak) if rp_ms else None,
         },
         "kernel_ms_per_step": bf["kernel_ms_per_step"],
         "hbm_kernels": hbm_kernels(bf["kernel_ms_per_step"], n, P, main_path),
@@ -573,7 +613,7 @@ def main():
             "max-convolution 8192 x 2048, x + y top 256 at n = 8192")
         del Ad, Bd, E, E64, Asub
         torch.cuda.empty_cache()
-        out["legs"] = run_legs(mt, torch, np)
+        out["legs"] = run_legs(mt, torch, np, sections)
 
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_rows} rows")

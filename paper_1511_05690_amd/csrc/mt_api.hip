@@ -52,6 +52,21 @@ struct TimedLaunch {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_launches;
+// Events are taken from a pool, filled when timing is switched on and
+// refilled at reset, so that a timed launch costs the host two event records
+// and no event creation (a host slower than the GPU would otherwise leave the
+// GPU idle between an event and its kernel, and the idle time would count).
+std::vector<hipEvent_t> g_event_pool;
+constexpr size_t kEventPoolFill = 1024;
+hipEvent_t take_event() {
+    if (g_event_pool.empty()) {
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    }
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+}
 // Executed-flop counters of timed launches (one per launch, zeroed at
 // reset): a device array of the library, so that timing allocates nothing;
 // g_work is its address on the device that was current at the first timed
@@ -65,8 +80,8 @@ int g_work_used = 0;
 void timing_before(const char* name, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing) return;
-    TimedLaunch t{name, nullptr, nullptr, -1};
-    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
+    TimedLaunch t{name, take_event(), take_event(), -1};
+    if (!t.start || !t.stop) return;
     (void)hipEventRecord(t.start, st);
     g_launches.push_back(t);
 }
@@ -1276,6 +1291,11 @@ int32_t maxtimes_search_start(void) { return g_start_entry.load(); }
 mt_status maxtimes_timing_enable(int on) {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_timing = on != 0;
+    while (g_timing && g_event_pool.size() < kEventPoolFill) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        g_event_pool.push_back(e);
+    }
     return MT_OK;
 }
 
@@ -1284,8 +1304,8 @@ mt_status maxtimes_timing_reset(void) {
     std::lock_guard<std::mutex> lk(g_tmu);
     for (auto& t : g_launches) {
         if (t.stop) (void)hipEventSynchronize(t.stop);
-        if (t.start) (void)hipEventDestroy(t.start);
-        if (t.stop) (void)hipEventDestroy(t.stop);
+        if (t.start) g_event_pool.push_back(t.start);
+        if (t.stop) g_event_pool.push_back(t.stop);
     }
     g_launches.clear();
     if (g_work && g_work_used > 0) {
