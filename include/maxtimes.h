@@ -212,6 +212,10 @@ mt_status maxtimes_workspace_map(int64_t b, int64_t m, int64_t k, int64_t n, con
  * k above 2^23 on the BF16 path (m or n above 2^23 for its backward, n for
  * its APSP).
  * FP32 inputs are converted exactly on load for the FP64 path.
+ * Range: r_i c_j may lie outside the output type (it is applied as a
+ * mantissa product and one power-of-two scaling in the output precision),
+ * so an entry of C overflows or underflows only where its value
+ * r_i c_j S^(1/p*) itself lies outside the output type.
  */
 mt_status maxtimes_estimate(const void* A, const void* B, mt_dtype dtype,
                             int64_t b, int64_t m, int64_t k, int64_t n,
@@ -255,6 +259,14 @@ mt_status maxtimes_backward_workspace_size(int64_t b, int64_t m, int64_t k, int6
  * Entries whose C is 0 contribute nothing.  MT_FLAG_NORM_CORRECT is not
  * supported here (MT_ERR_UNSUPPORTED).  The BF16 path splits every power
  * and every Gt into hi + lo, because G has mixed signs.
+ * Range on the BF16 path: Gt is formed in FP32 with r and c carried over a
+ * per-item power of two (the exponent of the item's largest r, resp. c),
+ * so G C'^(1-p) must lie in FP32 (it does for every stable entry, where
+ * C'^p* >= tau, up to the range of G itself), and an r_i (c_j) more than
+ * about 2^126 below the item's largest contributes 0 to dB (dA).  The FP64
+ * path has the FP64 range.  With MT_FLAG_BALANCE (set as in the forward
+ * call) the backward runs on the balanced pair (A D, D^-1 B) and returns
+ * dA = D dA', dB = D^-1 dB': the derivative of the same estimate.
  */
 mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G,
                                      const void* C, const uint8_t* p_star, mt_dtype dtype,
@@ -446,12 +458,26 @@ mt_status maxtimes_timing_read(const char* prefix, double* total_ms, int64_t* la
  * most, and often less than, 2 * rows_pad * cols_pad * k_pad per segment of
  * the family.  The max-convolution counts 10 N log2 N flops (two complex FFTs
  * of N points, 5 N log2 N each by the usual count) per pair and p visited.
- * The counters are a static device array of the library (8192 launches per
+ * The counters are a static device array of the library (2048 launches per
  * reset, on the device current at the first timed launch that counts work;
  * nothing is allocated); reset waits for the recorded launches and clears
  * them.
  */
 mt_status maxtimes_timing_work(const char* prefix, double* flops);
+
+/*
+ * Device-side duration of the timed launches whose kernel name starts with
+ * `prefix`, for the kernels that count work (the p-family GEMMs and the
+ * max-convolution): each workgroup reads the device's constant-rate
+ * real-time counter when it starts and, after a barrier, when it ends; the
+ * launch's span is the latest end minus the earliest start, converted with
+ * the device's reported clock rate.  Returns the summed milliseconds and the
+ * number of launches.  Unlike the events of maxtimes_timing_read, the span
+ * excludes the command processor's time before the first workgroup starts
+ * and after the last one ends, and cannot include work queued before the
+ * launch; MT_ERR_UNSUPPORTED if the device reports no clock rate.
+ */
+mt_status maxtimes_timing_span(const char* prefix, double* total_ms, int64_t* launches);
 
 /*
  * Sparse tail.  The forward GEMMs visit the family from the largest p down

@@ -23,7 +23,7 @@ import torch
 __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
     "workspace_size", "workspace_map", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
-    "timing_reset", "timing_read", "timing_work", "set_tail_threshold", "tail_threshold",
+    "timing_reset", "timing_read", "timing_work", "timing_span", "set_tail_threshold", "tail_threshold",
     "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "maxconv", "maxconv_exact",
     "maxconv_workspace_size", "xy_topk", "xy_topk_workspace_size", "XY_FAMILY", "pfamily", "PSTAR_NONE", "PATHS",
 ]
@@ -117,6 +117,7 @@ def load_library():
         "maxtimes_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(i64)],
         "maxtimes_timing_work": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)],
+        "maxtimes_timing_span": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "maxtimes_set_tail_threshold": [ctypes.c_int32],
         "maxtimes_tail_threshold": [],
         "maxtimes_set_search_start": [ctypes.c_int32],
@@ -582,3 +583,14 @@ def timing_work(prefix):
     fl = ctypes.c_double(0.0)
     _check(load_library().maxtimes_timing_work(prefix.encode(), ctypes.byref(fl)))
     return fl.value
+
+
+def timing_span(prefix):
+    """(total milliseconds, launches) of the timed launches whose kernel name
+    starts with ``prefix``, measured on the device: from the first workgroup's
+    start to the last workgroup's end on the device's real-time counter (the
+    kernels that count work only)."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(load_library().maxtimes_timing_span(prefix.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

@@ -67,14 +67,23 @@ hipEvent_t take_event() {
     g_event_pool.pop_back();
     return e;
 }
-// Executed-flop counters of timed launches (one per launch, zeroed at
-// reset): a device array of the library, so that timing allocates nothing;
+// Timing slots of timed launches (kTimingSlotWords counters per launch:
+// executed work, first start and last end on the device clock), cleared at
+// reset: a device array of the library, so that timing allocates nothing;
 // g_work is its address on the device that was current at the first timed
 // launch that counts work.
-constexpr int kWorkSlots = 8192;
-__device__ __align__(256) unsigned long long timing_work_counters[kWorkSlots];
+constexpr int kWorkSlots = 2048;
+__device__ __align__(256) unsigned long long timing_work_counters[kWorkSlots * kTimingSlotWords];
 unsigned long long* g_work = nullptr;
 int g_work_used = 0;
+// cleared slots: no work, start at the largest value (minimum taken), end 0
+hipError_t clear_work_slots(int slots) {
+    std::vector<unsigned long long> init((size_t)slots * kTimingSlotWords, 0ull);
+    for (int i = 0; i < slots; ++i) init[(size_t)i * kTimingSlotWords + 1] = ~0ull;
+    hipError_t e = hipMemcpy(g_work, init.data(), init.size() * sizeof(unsigned long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e;
+}
 }  // namespace
 
 void timing_before(const char* name, hipStream_t st) {
@@ -99,13 +108,14 @@ unsigned long long* timing_work_slot() {
     if (!g_work) {
         void* p = nullptr;
         if (hipGetSymbolAddress(&p, HIP_SYMBOL(timing_work_counters)) != hipSuccess) return nullptr;
-        if (hipMemset(p, 0, kWorkSlots * sizeof(unsigned long long)) != hipSuccess ||
-            hipDeviceSynchronize() != hipSuccess)
-            return nullptr;
         g_work = (unsigned long long*)p;
+        if (clear_work_slots(kWorkSlots) != hipSuccess) {
+            g_work = nullptr;
+            return nullptr;
+        }
     }
     g_launches.back().work_slot = g_work_used;
-    return g_work + g_work_used++;
+    return g_work + (size_t)kTimingSlotWords * g_work_used++;
 }
 
 namespace {
@@ -1309,8 +1319,7 @@ mt_status maxtimes_timing_reset(void) {
     }
     g_launches.clear();
     if (g_work && g_work_used > 0) {
-        hipError_t e = hipMemset(g_work, 0, (size_t)g_work_used * sizeof(unsigned long long));
-        if (e == hipSuccess) e = hipDeviceSynchronize();
+        hipError_t e = clear_work_slots(g_work_used);
         if (e != hipSuccess) return device_fail(e, "clearing the work counters");
     }
     g_work_used = 0;
@@ -1351,13 +1360,50 @@ mt_status maxtimes_timing_work(const char* prefix, double* flops) {
         hipError_t e = hipEventSynchronize(t.stop);
         if (e != hipSuccess) return device_fail(e, "event sync");
     }
-    std::vector<unsigned long long> w((size_t)g_work_used);
+    std::vector<unsigned long long> w((size_t)g_work_used * kTimingSlotWords);
     hipError_t e = hipMemcpy(w.data(), g_work, w.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return device_fail(e, "reading the work counters");
     double sum = 0.0;
     for (auto& t : g_launches)
-        if (t.work_slot >= 0 && strncmp(t.name, prefix, pl) == 0) sum += (double)w[(size_t)t.work_slot];
+        if (t.work_slot >= 0 && strncmp(t.name, prefix, pl) == 0)
+            sum += (double)w[(size_t)t.work_slot * kTimingSlotWords];
     *flops = sum;
+    return MT_OK;
+}
+
+mt_status maxtimes_timing_span(const char* prefix, double* total_ms, int64_t* launches) {
+    g_last_error.clear();
+    if (!prefix || !total_ms || !launches) return fail(MT_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    *total_ms = 0.0;
+    *launches = 0;
+    if (!g_work || g_work_used == 0) return MT_OK;
+    const size_t pl = strlen(prefix);
+    for (auto& t : g_launches) {
+        if (strncmp(t.name, prefix, pl) != 0 || !t.stop) continue;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e != hipSuccess) return device_fail(e, "event sync");
+    }
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return device_fail(e, "reading the device clock rate");
+    if (khz <= 0) return fail(MT_ERR_UNSUPPORTED, "the device reports no real-time clock rate");
+    std::vector<unsigned long long> w((size_t)g_work_used * kTimingSlotWords);
+    e = hipMemcpy(w.data(), g_work, w.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(e, "reading the timing slots");
+    double ticks = 0.0;
+    int64_t cnt = 0;
+    for (auto& t : g_launches) {
+        if (t.work_slot < 0 || strncmp(t.name, prefix, pl) != 0) continue;
+        const unsigned long long t0 = w[(size_t)t.work_slot * kTimingSlotWords + 1];
+        const unsigned long long t1 = w[(size_t)t.work_slot * kTimingSlotWords + 2];
+        if (t1 < t0) continue;  // the kernel records no span
+        ticks += (double)(t1 - t0);
+        ++cnt;
+    }
+    *total_ms = ticks / (double)khz;
+    *launches = cnt;
     return MT_OK;
 }
 

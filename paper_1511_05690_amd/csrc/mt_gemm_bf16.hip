@@ -596,6 +596,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
     __shared__ uint32_t s_tail_base;
 
     const int tid = threadIdx.x;
+    if (g.work && tid == 0) timing_span_begin(g.work);
     TileCtx t;
     t.lane = tid & 63;
     t.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -908,7 +909,14 @@ __global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(Gem
         }
     }
     epi.finish(t);
-    if (g.work && tid == 0) atomicAdd(g.work, (unsigned long long)kunits * (2ull * C::BM * C::BN));
+    if (g.work) {
+        // timed launch: the work, and the end once every wave is done
+        __syncthreads();
+        if (tid == 0) {
+            atomicAdd(g.work, (unsigned long long)kunits * (2ull * C::BM * C::BN));
+            timing_span_end(g.work);
+        }
+    }
 }
 
 // ------------------------------------------------------------ the sparse tail

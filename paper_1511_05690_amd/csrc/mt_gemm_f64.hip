@@ -417,6 +417,7 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
     __shared__ uint32_t s_tail_base;
 
     const int tid = threadIdx.x;
+    if (g.work && tid == 0) timing_span_begin(g.work);
     TileCtx t;
     t.lane = tid & 63;
     t.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -613,8 +614,14 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
         }
     }
     epi.finish(t);
-    if (g.work && tid == 0)
-        atomicAdd(g.work, (unsigned long long)steps_done * (2ull * C::BM * C::BM * 16));
+    if (g.work) {
+        // timed launch: the work, and the end once every wave is done
+        __syncthreads();
+        if (tid == 0) {
+            atomicAdd(g.work, (unsigned long long)steps_done * (2ull * C::BM * C::BM * 16));
+            timing_span_end(g.work);
+        }
+    }
 }
 
 // ------------------------------------------------------------ the sparse tail

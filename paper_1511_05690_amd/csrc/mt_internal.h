@@ -345,8 +345,20 @@ hipError_t launch_exact_maxtimes(const void* A, const void* B, int f64, int64_t 
 // Per-kernel event timing (api.cpp).
 void timing_before(const char* name, hipStream_t st);
 void timing_after(hipStream_t st);
-// Device counter for the launch just opened by timing_before, into which a
-// kernel may add the MFMA flops it executed; nullptr when timing is off.
+// Timing slot of the launch just opened by timing_before (nullptr when
+// timing is off): kTimingSlotWords counters in device memory.  Word 0: the
+// work the kernel executed (it adds to it).  Words 1 and 2: the earliest
+// start and the latest end, over the kernel's workgroups, of the device's
+// constant-rate real-time counter, so that the launch's span on the device
+// is known independently of how the host-side events are stamped.
+constexpr int kTimingSlotWords = 4;
 unsigned long long* timing_work_slot();
+
+__device__ __forceinline__ void timing_span_begin(unsigned long long* slot) {
+    atomicMin(slot + 1, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+}
+__device__ __forceinline__ void timing_span_end(unsigned long long* slot) {
+    atomicMax(slot + 2, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+}
 
 }  // namespace mt

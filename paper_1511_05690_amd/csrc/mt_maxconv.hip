@@ -434,6 +434,7 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
     __shared__ double red[2][kConvThreads / 64];
     double2* tw = lds;  // kConvTwElems
     const int tid = threadIdx.x;
+    if (work && tid == 0) timing_span_begin(work);
     const int slot = tid / TP, tl0 = tid % TP;
     const int64_t item = (int64_t)blockIdx.x * F::G + slot;
     const bool active = item < b;
@@ -528,10 +529,15 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
             if (pstar) pstar[item * L + t] = (uint8_t)code;
         }
     }
-    if (work && tid == 0) {
-        // two complex transforms per p, 5 N log2 N flops each (the usual FFT count)
-        const int64_t pairs = b - (int64_t)blockIdx.x * F::G < F::G ? b - (int64_t)blockIdx.x * F::G : F::G;
-        atomicAdd(work, (unsigned long long)iters * (unsigned long long)pairs * (10ull * N * LOGN));
+    if (work) {
+        // timed launch: two complex transforms per p, 5 N log2 N flops each
+        // (the usual FFT count), and the end once every wave is done
+        __syncthreads();
+        if (tid == 0) {
+            const int64_t pairs = b - (int64_t)blockIdx.x * F::G < F::G ? b - (int64_t)blockIdx.x * F::G : F::G;
+            atomicAdd(work, (unsigned long long)iters * (unsigned long long)pairs * (10ull * N * LOGN));
+            timing_span_end(work);
+        }
     }
 }
 

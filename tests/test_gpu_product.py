@@ -185,6 +185,39 @@ def test_timing_facility_sees_kernels(gpu_lib):
     assert n == 1 and ms > 0
 
 
+def test_timing_span_on_the_device_clock(gpu_lib):
+    """The GEMM's span on the device's real-time counter: one per timed
+    launch, positive, inside the launch's events and the host's wall time,
+    and the work counters unchanged by it."""
+    import time
+
+    import torch
+
+    A = torch.rand(2048, 2048, device="cuda")
+    gpu_lib.estimate(A, A, path="bf16")
+    torch.cuda.synchronize()
+    gpu_lib.timing_reset()
+    gpu_lib.timing_enable(True)
+    try:
+        t0 = time.perf_counter()
+        for _ in range(3):
+            gpu_lib.estimate(A, A, path="bf16")
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        ev_ms, ev_n = gpu_lib.timing_read("mt_pfamily_gemm_bf16")
+        sp_ms, sp_n = gpu_lib.timing_span("mt_pfamily_gemm_bf16")
+        work = gpu_lib.timing_work("mt_pfamily_gemm_bf16")
+        none_ms, none_n = gpu_lib.timing_span("mt_rowmax")  # counts no work, records no span
+    finally:
+        gpu_lib.timing_enable(False)
+        gpu_lib.timing_reset()
+    print(f"span {sp_ms:.4f} ms, events {ev_ms:.4f} ms, wall {wall_ms:.3f} ms", flush=True)
+    assert ev_n == 3 and sp_n == 3
+    assert 0 < sp_ms <= ev_ms + 0.005 and sp_ms < wall_ms
+    assert work >= 3 * 2.0 * 2048 ** 3  # at least one segment per launch
+    assert none_n == 0 and none_ms == 0.0
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (70, 33, 130), (3, 200, 64, 90)])
 def test_exact_kernel_matches_oracle(gpu_lib, shape):
     """The exact (max, x) product kernel (Alg. 2) against the oracle."""
