@@ -177,7 +177,19 @@ def run_legs(mt, torch, np, sections=None):
         c1 = config(1)
         A1, B1 = torch.from_numpy(c1["A"]).cuda(), torch.from_numpy(c1["B"]).cuda()
         ms = time_call(lambda: mt.estimate(A1, B1, P=c1["P"], path="fp64"), 20, torch)
-        legs["product_256_fp64"] = {"ms": ms, "ops_per_s": 256.0 ** 3 / (ms / 1e3), "P": c1["P"]}
+        # the product runs as one kernel (the small-product path); its span
+        # on the device clock beside the whole call as Python issues it
+        mt.timing_reset()
+        mt.timing_enable(True)
+        time_call(lambda: mt.estimate(A1, B1, P=c1["P"], path="fp64"), 20, torch)
+        kms, kn = mt.timing_span("mt_small_product_f64")
+        klaunch = mt.timing_read("mt_")[1]
+        mt.timing_enable(False)
+        mt.timing_reset()
+        legs["product_256_fp64"] = {"ms": ms, "ops_per_s": 256.0 ** 3 / (ms / 1e3), "P": c1["P"],
+                                    "kernel_ms": kms / kn if kn else None,
+                                    "launches_per_call": klaunch / 21.0,
+                                    "kernel": "mt_small_product_f64 (one launch per product)"}
 
     if want("apsp2048"):
         c2 = config(2)

@@ -517,6 +517,24 @@ int32_t maxtimes_tail_threshold(void);
 mt_status maxtimes_set_search_start(int32_t entry);
 int32_t maxtimes_search_start(void);
 
+/*
+ * Small products (Alg. 5 with the scaled call H' of Sec. 2.1, FP64 path):
+ * maxtimes_estimate (and its _noalloc form) computes a product with
+ * b * m * k * n <= max_work multiply-adds, options at most MT_FLAG_CLAMP and
+ * MT_FLAG_NORM_CORRECT, b <= 65535 and m <= 2^21 in one kernel: each
+ * workgroup takes the maxima of its 32 rows of A and 32 columns of B, then
+ * forms S_p = A'^p B'^p for its 32 x 32 outputs in FP64 from the largest p
+ * down and stops once each output has its p (the general path's seven to
+ * fourteen launches cost more than such a product's arithmetic).  Same
+ * results as the general path up to the order of the FP64 sums; the
+ * workspace argument is checked as for the general path and not used.
+ * max_work = 0 sends every product down the general path; the default is
+ * 2^25.  MT_ERR_INVALID_ARG for a negative limit.  Process-wide; not
+ * synchronised with calls in flight on other threads.
+ */
+mt_status maxtimes_set_small_product_limit(int64_t max_work);
+int64_t maxtimes_small_product_limit(void);
+
 /* Library version string. */
 const char* maxtimes_version(void);
 

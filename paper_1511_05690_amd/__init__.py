@@ -24,6 +24,7 @@ __all__ = [
     "MaxTimesError", "load_library", "library_path", "estimate", "estimate_backward", "apsp",
     "workspace_size", "workspace_map", "backward_workspace_size", "apsp_workspace_size", "exact", "timing_enable",
     "timing_reset", "timing_read", "timing_work", "timing_span", "set_tail_threshold", "tail_threshold",
+    "set_small_product_limit", "small_product_limit",
     "set_search_start", "search_start", "apsp_exact_rows", "apsp_affine_correct", "maxconv", "maxconv_exact",
     "maxconv_workspace_size", "xy_topk", "xy_topk_workspace_size", "XY_FAMILY", "pfamily", "PSTAR_NONE", "PATHS",
 ]
@@ -122,6 +123,8 @@ def load_library():
         "maxtimes_tail_threshold": [],
         "maxtimes_set_search_start": [ctypes.c_int32],
         "maxtimes_search_start": [],
+        "maxtimes_set_small_product_limit": [i64],
+        "maxtimes_small_product_limit": [],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -130,6 +133,7 @@ def load_library():
     for name in ("maxtimes_status_string", "maxtimes_last_error", "maxtimes_version"):
         f = getattr(lib, name)
         f.restype = ctypes.c_char_p
+    lib.maxtimes_small_product_limit.restype = ctypes.c_int64
     lib.maxtimes_status_string.argtypes = [ctypes.c_int]
     lib.maxtimes_last_error.argtypes = []
     lib.maxtimes_version.argtypes = []
@@ -573,6 +577,16 @@ def set_search_start(entry):
 
 def search_start():
     return int(load_library().maxtimes_search_start())
+
+
+def set_small_product_limit(max_work):
+    """FP64-path products with b m k n <= ``max_work`` (and no projection,
+    balancing or domain check) run as one kernel; 0: never.  Process-wide."""
+    _check(load_library().maxtimes_set_small_product_limit(int(max_work)))
+
+
+def small_product_limit():
+    return int(load_library().maxtimes_small_product_limit())
 
 
 def timing_work(prefix):

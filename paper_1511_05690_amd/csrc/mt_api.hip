@@ -348,6 +348,11 @@ struct Layout {
 // A tile with at most this many undecided entries hands them to the sparse
 // tail (0 disables it).  512 of a 256 x 256 BF16 tile is 0.8 %.
 std::atomic<int32_t> g_tail_max{512};
+// Products with b m k n up to this many multiply-adds take the one-kernel
+// FP64 path (mt_small.hip) when their options allow it; 0: never.
+constexpr int64_t kSmallProductDefault = (int64_t)1 << 25;
+std::atomic<int64_t> g_small_limit{kSmallProductDefault};
+
 // Forward search start: a plan index, or kStartAuto (the pilot chooses).
 constexpr int32_t kStartAuto = -1;
 std::atomic<int32_t> g_start_entry{kStartAuto};
@@ -723,6 +728,24 @@ mt_status estimate_impl(const void* A, const void* B, mt_dtype dtype, int64_t b,
     hipStream_t st = (hipStream_t)stream;
     uint8_t* ws = (uint8_t*)workspace;
     const int f64 = dtype == MT_F64;
+    // small FP64-path products without projections, balancing or the
+    // domain check: one kernel (maxima, powers, ring products, selection)
+    const uint32_t small_ok = MT_FLAG_CLAMP | MT_FLAG_NORM_CORRECT;
+    if (!f.bf16 && k > 0 && !(f.flags & ~small_ok) && b <= 65535 && (m + 31) / 32 <= 65535 &&
+        (double)b * m * k * n <= (double)g_small_limit.load()) {
+        SmallSpec sp;
+        memset(&sp, 0, sizeof sp);
+        const RootSpec rsp = root_spec(f, k, EPI_PLAIN, (f.flags & MT_FLAG_CLAMP) ? 1 : 0);
+        sp.n = f.n;
+        for (int q = 0; q < f.n; ++q) {
+            sp.p[q] = f.p[q];
+            sp.corr[q] = rsp.corr[q];
+        }
+        sp.tau = f.tau;
+        sp.clamp = rsp.clamp;
+        MT_TRY(launch_small_product_f64(A, B, f64, b, m, k, n, sp, C, f64, p_star, st), "small product (FP64)");
+        return MT_OK;
+    }
     int32_t* flag = (int32_t*)(ws + L.hdr);
     // everything the kernels expect at zero is cleared by kernels of the
     // call itself (the header: domain flag, tail count, p* histogram), so a
@@ -1297,6 +1320,15 @@ mt_status maxtimes_set_search_start(int32_t entry) {
 }
 
 int32_t maxtimes_search_start(void) { return g_start_entry.load(); }
+
+mt_status maxtimes_set_small_product_limit(int64_t max_work) {
+    g_last_error.clear();
+    if (max_work < 0) return fail(MT_ERR_INVALID_ARG, "small-product limit %lld is negative", (long long)max_work);
+    g_small_limit.store(max_work);
+    return MT_OK;
+}
+
+int64_t maxtimes_small_product_limit(void) { return g_small_limit.load(); }
 
 mt_status maxtimes_timing_enable(int on) {
     std::lock_guard<std::mutex> lk(g_tmu);

@@ -232,6 +232,18 @@ struct RootSpec {
     int32_t clamp;
     int32_t r1;     // r = 1 projection from S (at p*) and S2 (at the family's next smaller p)
 };
+// The one-kernel FP64-path estimate of small products (mt_small.hip): the
+// family (ascending), its norm corrections, tau and the clamp to 1.
+struct SmallSpec {
+    int32_t n;
+    int32_t p[MT_MAX_P];
+    double corr[MT_MAX_P];
+    double tau;
+    int32_t clamp;
+};
+hipError_t launch_small_product_f64(const void* A, const void* B, int in_f64, int64_t b, int64_t m, int64_t k,
+                                    int64_t n, const SmallSpec& spec, void* C, int out_f64, uint8_t* pstar,
+                                    hipStream_t st);
 // r = 2 projection over an S stack (plane t holds S at the t-th smallest of
 // the family's p and the added 3q): per family index fi, the stack plane of
 // its p (plane), of the next smaller family p (lo, -1 if none) and of q,

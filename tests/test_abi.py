@@ -201,6 +201,23 @@ def test_search_start_validation():
         mt.set_search_start(old)
 
 
+def test_small_product_limit_validation():
+    """Products with b m k n up to the limit (default 2^25) take the
+    one-kernel FP64 path; 0 turns it off, a negative limit is rejected."""
+    assert mt.small_product_limit() == 1 << 25
+    old = mt.small_product_limit()
+    try:
+        with pytest.raises(mt.MaxTimesError) as e:
+            mt.set_small_product_limit(-1)
+        assert e.value.status == 1
+        mt.set_small_product_limit(0)
+        assert mt.small_product_limit() == 0
+        mt.set_small_product_limit(1 << 40)
+        assert mt.small_product_limit() == 1 << 40
+    finally:
+        mt.set_small_product_limit(old)
+
+
 def test_bf16_inner_dimension_limit():
     """The BF16 path contracts at most 2^23 terms per entry; the FP64 path
     keeps the general 2^24 limit."""

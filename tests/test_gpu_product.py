@@ -21,8 +21,24 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
+# "fp64" takes the one-kernel path for products of at most 2^25
+# multiply-adds (most below), "fp64_general" the general one (planes, MFMA
+# GEMM, sparse tail, root pass) with the one-kernel path turned off
+PATHS = ["fp64", "fp64_general", "bf16"]
+
+
+def _real(path):
+    return "fp64" if path.startswith("fp64") else path
+
+
 def _run(mt, A, B, P, path, **kw):
-    C, ps = mt.estimate(_dev(A), _dev(B), P=P, path=path, return_pstar=True, **kw)
+    old = mt.small_product_limit()
+    if path == "fp64_general":
+        mt.set_small_product_limit(0)
+    try:
+        C, ps = mt.estimate(_dev(A), _dev(B), P=P, path=_real(path), return_pstar=True, **kw)
+    finally:
+        mt.set_small_product_limit(old)
     return C.cpu().numpy(), ps.cpu().numpy()
 
 
@@ -30,21 +46,21 @@ SHAPES = [(1, 1, 1), (5, 7, 3), (64, 64, 64), (300, 77, 130), (257, 513, 255), (
 
 
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_uniform_parity(gpu_lib, shape, path):
     m, k, n = shape
     print(f"[parity] uniform {path} {shape}", flush=True)
     A, B = uniform_product(m, k, n, seed=m * 7 + k * 3 + n)
-    dt = np.float64 if path == "fp64" else np.float32
+    dt = np.float64 if path.startswith("fp64") else np.float32
     A, B = A.astype(dt), B.astype(dt)
     C, ps = _run(gpu_lib, A, B, P64, path)
-    ref = oracle.pnorm_estimate(A, B, P64, TAU[path])
-    st = compare_estimate(C, ps, ref, P64, path)
+    ref = oracle.pnorm_estimate(A, B, P64, TAU[_real(path)])
+    st = compare_estimate(C, ps, ref, P64, _real(path))
     assert st["flips"] == 0
 
 
 @pytest.mark.parametrize("shape", [(200, 300, 100), (512, 512, 512), (129, 2050, 67)])
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_lognormal_parity(gpu_lib, shape, path):
     """Large dynamic range: p* spreads over the family and flips at tau
     occur; the band rule arbitrates them."""
@@ -52,41 +68,41 @@ def test_lognormal_parity(gpu_lib, shape, path):
     print(f"[parity] lognormal {path} {shape}", flush=True)
     A, B = lognormal_product(m, k, n, seed=100 + m)
     C, ps = _run(gpu_lib, A, B, P128, path)
-    ref = oracle.pnorm_estimate(A, B, P128, TAU[path])
-    st = compare_estimate(C, ps, ref, P128, path)
+    ref = oracle.pnorm_estimate(A, B, P128, TAU[_real(path)])
+    st = compare_estimate(C, ps, ref, P128, _real(path))
     print(st, flush=True)
     assert len(np.unique(ps)) >= 2
 
 
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_batched_parity(gpu_lib, path):
     A, B = uniform_product(70, 90, 40, seed=5, batch=3)
-    dt = np.float64 if path == "fp64" else np.float32
+    dt = np.float64 if path.startswith("fp64") else np.float32
     A, B = A.astype(dt), B.astype(dt)
     print(f"[parity] batched {path}", flush=True)
     C, ps = _run(gpu_lib, A, B, P64, path)
-    ref = oracle.pnorm_estimate(A, B, P64, TAU[path])
-    compare_estimate(C, ps, ref, P64, path)
+    ref = oracle.pnorm_estimate(A, B, P64, TAU[_real(path)])
+    compare_estimate(C, ps, ref, P64, _real(path))
 
 
 @pytest.mark.parametrize("P", [[1], [2], [3, 5, 7], [16], [1, 2, 4, 8, 16, 32, 64, 128, 256, 512]])
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_other_families(gpu_lib, P, path):
     """Single p, non-power-of-two p and a long family."""
     A, B = lognormal_product(96, 160, 80, seed=len(P) + P[-1], sigma=1.0)
-    if path == "fp64":
+    if path.startswith("fp64"):
         A, B = A.astype(np.float64), B.astype(np.float64)
     print(f"[parity] family {P} {path}", flush=True)
     C, ps = _run(gpu_lib, A, B, P, path)
-    ref = oracle.pnorm_estimate(A, B, P, TAU[path])
-    compare_estimate(C, ps, ref, P, path)
+    ref = oracle.pnorm_estimate(A, B, P, TAU[_real(path)])
+    compare_estimate(C, ps, ref, P, _real(path))
 
 
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_closed_forms_on_gpu(gpu_lib, path):
     """All-ones: C = k^(1/p_max); one-hot rows: C exact; P = {1}: A @ B."""
-    dt = np.float64 if path == "fp64" else np.float32
-    tol = 1e-12 if path == "fp64" else 2e-3
+    dt = np.float64 if path.startswith("fp64") else np.float32
+    tol = 1e-12 if path.startswith("fp64") else 2e-3
     k = 300
     C, ps = _run(gpu_lib, np.ones((40, k), dt), np.ones((k, 50), dt), P64, path)
     np.testing.assert_allclose(C, k ** (1 / 64), rtol=tol)
@@ -100,14 +116,14 @@ def test_closed_forms_on_gpu(gpu_lib, path):
     A = rng.random((50, 70)).astype(dt)
     B = rng.random((70, 30)).astype(dt)
     C, _ = _run(gpu_lib, A, B, [1], path)
-    np.testing.assert_allclose(C, A.astype(np.float64) @ B.astype(np.float64), rtol=1e-12 if path == "fp64" else 5e-5)
+    np.testing.assert_allclose(C, A.astype(np.float64) @ B.astype(np.float64), rtol=1e-12 if path.startswith("fp64") else 5e-5)
 
 
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_zero_rows_and_empty_inner(gpu_lib, path):
     import torch
 
-    dt = np.float64 if path == "fp64" else np.float32
+    dt = np.float64 if path.startswith("fp64") else np.float32
     A, B = uniform_product(33, 20, 17, seed=9)
     A, B = A.astype(dt), B.astype(dt)
     A[4] = 0
@@ -117,18 +133,18 @@ def test_zero_rows_and_empty_inner(gpu_lib, path):
     assert (ps[4] == 255).all() and (ps[:, 3] == 255).all()
     Ce, pe = gpu_lib.estimate(torch.zeros((5, 0), dtype=torch.float32, device="cuda"),
                               torch.zeros((0, 6), dtype=torch.float32, device="cuda"),
-                              P=P64, path=path, return_pstar=True)
+                              P=P64, path=_real(path), return_pstar=True)
     assert (Ce.cpu().numpy() == 0).all() and (pe.cpu().numpy() == 255).all()
 
 
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_norm_correct_and_clamp(gpu_lib, path):
     A, B = uniform_product(80, 120, 60, seed=11)
-    dt = np.float64 if path == "fp64" else np.float32
+    dt = np.float64 if path.startswith("fp64") else np.float32
     A, B = A.astype(dt), B.astype(dt)
     C, ps = _run(gpu_lib, A, B, P64, path, norm_correct=True)
-    ref = oracle.pnorm_estimate(A, B, P64, TAU[path], norm_correct=True)
-    compare_estimate(C, ps, ref, P64, path, norm_k=120)
+    ref = oracle.pnorm_estimate(A, B, P64, TAU[_real(path)], norm_correct=True)
+    compare_estimate(C, ps, ref, P64, _real(path), norm_k=120)
     C2, _ = _run(gpu_lib, A * 3, B, P64, path, clamp=True)
     assert C2.max() <= 1.0
 
@@ -149,7 +165,7 @@ def test_validate_flag_reports_domain_errors(gpu_lib):
     gpu_lib.estimate(A, A, validate=True)
 
 
-@pytest.mark.parametrize("path", ["fp64", "bf16"])
+@pytest.mark.parametrize("path", PATHS)
 def test_deterministic(gpu_lib, path):
     A, B = lognormal_product(300, 700, 260, seed=13)
     C1, p1 = _run(gpu_lib, A, B, P128, path)
