@@ -24,3 +24,13 @@ def gpu_lib():
 
     mt.load_library()
     return mt
+
+
+@pytest.fixture(scope="module")
+def general_path(gpu_lib):
+    """Products take the general path (planes, MFMA GEMM, sparse tail) even
+    where the one-kernel small-product path would serve them."""
+    old = gpu_lib.small_product_limit()
+    gpu_lib.set_small_product_limit(0)
+    yield gpu_lib
+    gpu_lib.set_small_product_limit(old)

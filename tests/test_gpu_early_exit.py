@@ -11,7 +11,9 @@ import pytest
 import oracle
 from parity import TAU, compare_estimate
 
-pytestmark = pytest.mark.gpu
+# these cases exercise the general path (planes, MFMA GEMM, sparse tail,
+# search start), also at sizes the one-kernel small-product path would take
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("general_path")]
 
 P128 = [1, 2, 4, 8, 16, 32, 64, 128]
 SHAPE = (300, 257, 290)

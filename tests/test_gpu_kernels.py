@@ -20,7 +20,9 @@ import pytest
 
 from workloads import lognormal_product, uniform_product
 
-pytestmark = pytest.mark.gpu
+# these cases exercise the general path (planes, MFMA GEMM, sparse tail,
+# search start), also at sizes the one-kernel small-product path would take
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("general_path")]
 
 
 def _bf16_rne(f32):

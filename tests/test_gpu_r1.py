@@ -13,7 +13,9 @@ import oracle
 from parity import TAU, compare_estimate
 from workloads import er_graph, lognormal_product, rgg_graph, uniform_product
 
-pytestmark = pytest.mark.gpu
+# these cases exercise the general path (planes, MFMA GEMM, sparse tail,
+# search start), also at sizes the one-kernel small-product path would take
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("general_path")]
 
 P64 = [1, 2, 4, 8, 16, 32, 64]
 P128 = P64 + [128]

@@ -20,7 +20,9 @@ import oracle
 from parity import TAU, compare_estimate
 from workloads import crossed_product, lognormal_product, rgg_graph, er_graph
 
-pytestmark = pytest.mark.gpu
+# these cases exercise the general path (planes, MFMA GEMM, sparse tail,
+# search start), also at sizes the one-kernel small-product path would take
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("general_path")]
 
 P128 = [1, 2, 4, 8, 16, 32, 64, 128]
 P512 = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512]
