@@ -125,7 +125,7 @@ template <class C, int MODE, typename TO, bool R1>
 struct SelectEpi {
     static constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
     static constexpr int NDEC = (WT_M * WT_N * 16 + 31) / 32;
-    static constexpr int STG = 32 * 33;  // floats of one wave's staging tile
+    static constexpr int STG = 16 * 64;  // floats of one wave's staging tile (rolled walk)
     // row and column scales: FP32 mantissas, then int exponents
     static constexpr int LDS_BYTES = (C::BM + C::BN) * 8;
     static_assert(C::NW * STG * 4 <= C::BUF_BYTES, "staging must fit in one pipeline buffer");
@@ -144,6 +144,11 @@ struct SelectEpi {
     int lr0, lc0;
     int64_t out_lane;
     int32_t rows_left, cols_left, diag_off;
+
+    // Row offset, from this lane's first row lr0, of accumulator element q
+    // of sub-tile row i (the 32 x 32 MFMA layout: element q of lane l is row
+    // (q / 4) * 8 + (l / 32) * 4 + q % 4, column l % 32 of the sub-tile).
+    static __device__ __forceinline__ int roff_of(int i, int q) { return i * 32 + (q >> 2) * 8 + (q & 3); }
 
     static constexpr bool kAllActive = true;
     static constexpr bool kCanStop = true;
@@ -189,7 +194,7 @@ struct SelectEpi {
                     if ((dec >> q) & 1u) continue;
                     TailEntry te;
                     te.bi = t.bi;
-                    te.i = (int32_t)(t.row0 + lr0 + i * 32 + 2 * q);
+                    te.i = (int32_t)(t.row0 + lr0 + roff_of(i, q));
                     te.j = (int32_t)(t.col0 + lc0 + j * 32);
                     if ((pnd >> q) & 1u) {
                         te.state = R1 ? kTailR1 : kTailRise;
@@ -223,10 +228,10 @@ struct SelectEpi {
             rs[i] = sp.m;
             res[i] = sp.e;
         }
-        // Tile (i, j) of this wave is staged through LDS as a 32 x 32 block;
-        // lane l then handles rows 2q + l/32 (q = 0..15) of column l%32, so
-        // lanes 0-31 and 32-63 store two consecutive row runs.
-        lr0 = t.wm * WT_M * 32 + (t.lane >> 5);
+        // Lane l handles the accumulator elements it holds: column l % 32 of
+        // each 32 x 32 sub-tile and rows roff_of(i, q) from lr0 (lanes 0-31
+        // and 32-63 store two row runs 4 apart).
+        lr0 = t.wm * WT_M * 32 + (t.lane >> 5) * 4;
         lc0 = t.wn * WT_N * 32 + (t.lane & 31);
         out_lane = ((int64_t)t.bi * m + t.row0 + lr0) * n + t.col0 + lc0;
         rows_left = (int32_t)min<int64_t>(m - (t.row0 + lr0), 1 << 30);
@@ -244,19 +249,19 @@ struct SelectEpi {
                 uint32_t bits = 0u;
 #pragma unroll
                 for (int q = 0; q < 16; ++q)
-                    if (!(j * 32 < cols_left && i * 32 + 2 * q < rows_left)) bits |= 1u << q;
+                    if (!(j * 32 < cols_left && roff_of(i, q) < rows_left)) bits |= 1u << q;
                 decided[tix >> 1] |= bits << ((tix & 1) * 16);
             }
     }
 
-    // Walk the (i, j) sub-tiles of this wave: acc[i][j] is staged through
-    // LDS (stg, one wave's tile) and f(roff, j, q, S, mask, dec, pnd) sees
-    // each entry of this lane (row offset roff in the tile, bit `mask` of the
-    // sub-tile's decided / pending words).  A sub-tile whose entries all have
-    // a bit of `skip` set is passed over.  Unrolled: the hot path (every
-    // entry of a top-down search).
+    // Walk the (i, j) sub-tiles of this wave: f(roff, j, S, mask, dec, pnd)
+    // sees each entry of this lane straight from its accumulator register
+    // (row offset roff from lr0, bit `mask` of the sub-tile's decided /
+    // pending words).  A sub-tile whose entries all have a bit of `skip` set
+    // is passed over.  Unrolled: the hot path (every entry of a top-down
+    // search).
     template <class F>
-    __device__ void each_unrolled(f32x16 (&acc)[WT_M][WT_N], float* stg, int lane, bool skip_pending, F&& f) {
+    __device__ void each_unrolled(f32x16 (&acc)[WT_M][WT_N], float*, int, bool skip_pending, F&& f) {
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
 #pragma unroll
@@ -267,21 +272,22 @@ struct SelectEpi {
                 const int sh = (tix & 1) * 16;
                 const uint32_t skip = skip_pending ? (dec | pnd) : dec;
                 if (__all(((skip >> sh) & 0xFFFFu) == 0xFFFFu)) continue;
+                // the sub-tile's 16 values in a local array that the
+                // partly unrolled walk indexes by register (a fully unrolled
+                // walk is too large and puts the accumulators in scratch)
+                float vals[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    stg[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * 33 + (lane & 31)] = acc[i][j][r];
-                __builtin_amdgcn_wave_barrier();
+                for (int q = 0; q < 16; ++q) vals[q] = acc[i][j][q];
 #pragma unroll 2
-                for (int q = 0; q < 16; ++q)
-                    f(i * 32 + 2 * q, j, stg[(2 * q + (lane >> 5)) * 33 + (lane & 31)], 1u << (sh + q), dec, pnd);
+                for (int q = 0; q < 16; ++q) f(roff_of(i, q), j, vals[q], 1u << (sh + q), dec, pnd);
                 decided[tix >> 1] = dec;
                 pending[tix >> 1] = pnd;
-                __builtin_amdgcn_wave_barrier();
             }
     }
-    // The same with the sub-tile loop rolled (the per-entry code appears once):
-    // for the entries of a search that does not start at the largest p,
-    // which run once or a few times per tile.
+    // The same with the sub-tile loop rolled (the per-entry code appears
+    // once; the sub-tile is copied to LDS, stg, so that the rolled loop can
+    // index it): for the entries of a search that does not start at the
+    // largest p, which run once or a few times per tile.
     template <class F>
     __device__ void each_rolled(f32x16 (&acc)[WT_M][WT_N], float* stg, int lane, F&& f) {
 #pragma unroll 1
@@ -302,13 +308,11 @@ struct SelectEpi {
                 for (int jj = 0; jj < WT_N; ++jj)
                     if (ii * WT_N + jj == tix) {
 #pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            stg[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * 33 + (lane & 31)] = acc[ii][jj][r];
+                        for (int r = 0; r < 16; ++r) stg[r * 64 + lane] = acc[ii][jj][r];
                     }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
-            for (int q = 0; q < 16; ++q)
-                f(i * 32 + 2 * q, j, stg[(2 * q + (lane >> 5)) * 33 + (lane & 31)], 1u << (sh + q), dec, pnd);
+            for (int q = 0; q < 16; ++q) f(roff_of(i, q), j, stg[q * 64 + lane], 1u << (sh + q), dec, pnd);
 #pragma unroll
             for (int w = 0; w < NDEC; ++w)
                 if (w == (tix >> 1)) {
