@@ -137,10 +137,10 @@ struct SelectEpi {
     // r = 1 projection: entries whose p* was found at the previous p and
     // whose S_{p*} is parked in `out` until S at this (next smaller) p is known
     uint32_t pending[NDEC];
-    float* rs;  // mantissas of the row scales (BM), then of the column scales (BN)
-    float* cs;
-    int* res;   // their exponents
-    int* ces;
+    // row scales of the tile (BM), then its column scales (BN), each as
+    // (FP32 mantissa bits, exponent): one 8-byte LDS read per scale
+    int2* rsc;
+    int2* csc;
     int lr0, lc0;
     int64_t out_lane;
     int32_t rows_left, cols_left, diag_off;
@@ -211,10 +211,8 @@ struct SelectEpi {
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
         m = g.rows;
         n = g.cols;
-        rs = (float*)lds;
-        cs = rs + C::BM;
-        res = (int*)(rs + C::BM + C::BN);
-        ces = res + C::BM;
+        rsc = (int2*)lds;
+        csc = rsc + C::BM;
         // Row / column scales of this tile (1 where absent or padding).
         for (int i = tid; i < C::BM + C::BN; i += C::THREADS) {
             double v = 1.0;
@@ -225,8 +223,7 @@ struct SelectEpi {
                 if (a.c && cc < n) v = a.c[(int64_t)t.bi * n + cc];
             }
             const ScaleSplit sp = split_scale(v);
-            rs[i] = sp.m;
-            res[i] = sp.e;
+            rsc[i] = make_int2(__float_as_int(sp.m), sp.e);
         }
         // Lane l handles the accumulator elements it holds: column l % 32 of
         // each 32 x 32 sub-tile and rows roff_of(i, q) from lr0 (lanes 0-31
@@ -323,11 +320,68 @@ struct SelectEpi {
         }
     }
 
+    // The walk of the search going down (every entry of a top-down search:
+    // the hot path).  Per sub-tile the decisions are bit masks: `stab` the
+    // entries stable at this p, `cand` those decided here (stable, or any at
+    // the smallest p, and neither decided nor parked).  The output of element
+    // q is formed when some lane decides its entry q and stored under the
+    // mask, so the lanes do not branch one by one.
+    __device__ void down_walk(f32x16 (&acc)[WT_M][WT_N], bool last, float tau_f, float inv_p, bool p_is_1,
+                              float corr, uint8_t pcode, TO* out, uint8_t* ps) {
+        float cm[WT_N];
+        int ce[WT_N];
+#pragma unroll
+        for (int j = 0; j < WT_N; ++j) {
+            const int2 cv = csc[lc0 + j * 32];
+            cm[j] = __int_as_float(cv.x);
+            ce[j] = cv.y;
+        }
+#pragma unroll
+        for (int i = 0; i < WT_M; ++i)
+#pragma unroll
+            for (int j = 0; j < WT_N; ++j) {
+                const int tix = i * WT_N + j;
+                const int sh = (tix & 1) * 16;
+                const uint32_t busy = ((decided[tix >> 1] | pending[tix >> 1]) >> sh) & 0xFFFFu;
+                if (__all(busy == 0xFFFFu)) continue;
+                // the sub-tile's values in a local array that the partly
+                // unrolled loop below indexes by register
+                float vals[16];
+                uint32_t stab = 0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    vals[q] = acc[i][j][q];
+                    stab |= (vals[q] >= tau_f ? 1u : 0u) << q;
+                }
+                const uint32_t cand = (last ? 0xFFFFu : stab) & ~busy;
+                if (!__any(cand != 0)) continue;
+                decided[tix >> 1] |= cand << sh;
+#pragma unroll 2
+                for (int q = 0; q < 16; ++q) {
+                    const bool take = (cand >> q) & 1u;
+                    if (!__any(take)) continue;
+                    const int roff = roff_of(i, q);
+                    const int2 rv = rsc[lr0 + roff];
+                    const float S = vals[q];
+                    const float v = __int_as_float(rv.x) * cm[j] * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
+                    TO w = scale_out<TO>(v, rv.y + ce[j]);
+                    if (MODE == EPI_APSP_X || a.clamp) w = w < TO(1) ? w : TO(1);
+                    if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) w = TO(1);
+                    if (take) {
+                        const int64_t o = (int64_t)roff * n + j * 32;
+                        out[o] = w;
+                        if (ps) ps[o] = ((stab >> q) & 1u) ? pcode : (uint8_t)MT_PSTAR_NONE;
+                    }
+                }
+            }
+    }
+
     // Final output of entry (roff, j) from its ring result S at a p with
     // root factor inv_p (p_is_1: no root) and norm correction corr.
     __device__ void put(TO* out, int roff, int j, int64_t o, float S, bool p_is_1, float inv_p, float corr) {
-        const float v = rs[lr0 + roff] * cs[lc0 + j * 32] * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
-        TO w = scale_out<TO>(v, res[lr0 + roff] + ces[lc0 + j * 32]);
+        const int2 rv = rsc[lr0 + roff], cv = csc[lc0 + j * 32];
+        const float v = __int_as_float(rv.x) * __int_as_float(cv.x) * (p_is_1 ? S : root_f32(S, inv_p)) * corr;
+        TO w = scale_out<TO>(v, rv.y + cv.y);
         if (MODE == EPI_APSP_X || a.clamp) w = w < TO(1) ? w : TO(1);
         if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) w = TO(1);
         out[o] = w;
@@ -383,15 +437,7 @@ struct SelectEpi {
         } else if (e > s || s == 0) {
             // going down: decide entries stable here (or at the smallest p);
             // entries parked at the start wait
-            each_unrolled(acc, stg, lane, true,
-                          [&](int roff, int j, float S, uint32_t mask, uint32_t& dec, uint32_t& pnd) {
-                              const bool stable = S >= tau_f;
-                              if (((dec | pnd) & mask) || !(stable || last)) return;
-                              const int64_t o = (int64_t)roff * n + j * 32;
-                              dec |= mask;
-                              put(out, roff, j, o, S, p_is_1, inv_p, corr);
-                              if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
-                          });
+            down_walk(acc, last, tau_f, inv_p, p_is_1, corr, pcode, out, ps);
         } else if (e == s) {
             // the start: an entry stable here whose S does not rule out the
             // next larger p (S_q <= S^(q/p)) parks S in `out`
