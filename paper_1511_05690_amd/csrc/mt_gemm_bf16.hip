@@ -320,14 +320,18 @@ struct SelectEpi {
         }
     }
 
-    // The walk of the search going down (every entry of a top-down search:
-    // the hot path).  Per sub-tile the decisions are bit masks: `stab` the
-    // entries stable at this p, `cand` those decided here (stable, or any at
-    // the smallest p, and neither decided nor parked).  The output of element
-    // q is formed when some lane decides its entry q and stored under the
-    // mask, so the lanes do not branch one by one.
+    // The walk of the search at its start and going down (every entry of
+    // a search passes here: the hot path).  Per sub-tile the decisions are
+    // bit masks: `stab` the entries stable at this p, `act` those acted on
+    // here (stable, or any at the smallest p, and neither decided nor
+    // parked).  At the start (`start`, a search that did not begin at the
+    // largest p) an acted-on entry that is stable with S >= rise_thr may be
+    // stable at a larger p too: it parks S in `out` (`park`) instead of being
+    // decided.  The output of element q is formed when some lane acts on its
+    // entry q and stored under the mask, so the lanes do not branch one by
+    // one.
     __device__ void down_walk(f32x16 (&acc)[WT_M][WT_N], bool last, float tau_f, float inv_p, bool p_is_1,
-                              float corr, uint8_t pcode, TO* out, uint8_t* ps) {
+                              float corr, uint8_t pcode, TO* out, uint8_t* ps, bool start, float rise_thr) {
         float cm[WT_N];
         int ce[WT_N];
 #pragma unroll
@@ -347,18 +351,21 @@ struct SelectEpi {
                 // the sub-tile's values in a local array that the partly
                 // unrolled loop below indexes by register
                 float vals[16];
-                uint32_t stab = 0;
+                uint32_t stab = 0, rise = 0;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     vals[q] = acc[i][j][q];
                     stab |= (vals[q] >= tau_f ? 1u : 0u) << q;
+                    rise |= (vals[q] >= rise_thr ? 1u : 0u) << q;
                 }
-                const uint32_t cand = (last ? 0xFFFFu : stab) & ~busy;
-                if (!__any(cand != 0)) continue;
-                decided[tix >> 1] |= cand << sh;
+                const uint32_t act = (last ? 0xFFFFu : stab) & ~busy;
+                if (!__any(act != 0)) continue;
+                const uint32_t park = start ? (act & stab & rise) : 0u;
+                decided[tix >> 1] |= (act & ~park) << sh;
+                pending[tix >> 1] |= park << sh;
 #pragma unroll 2
                 for (int q = 0; q < 16; ++q) {
-                    const bool take = (cand >> q) & 1u;
+                    const bool take = (act >> q) & 1u;
                     if (!__any(take)) continue;
                     const int roff = roff_of(i, q);
                     const int2 rv = rsc[lr0 + roff];
@@ -367,6 +374,7 @@ struct SelectEpi {
                     TO w = scale_out<TO>(v, rv.y + ce[j]);
                     if (MODE == EPI_APSP_X || a.clamp) w = w < TO(1) ? w : TO(1);
                     if (MODE == EPI_APSP_X && roff - j * 32 == diag_off) w = TO(1);
+                    if ((park >> q) & 1u) w = (TO)S;  // parked: S waits in `out`
                     if (take) {
                         const int64_t o = (int64_t)roff * n + j * 32;
                         out[o] = w;
@@ -437,24 +445,11 @@ struct SelectEpi {
         } else if (e > s || s == 0) {
             // going down: decide entries stable here (or at the smallest p);
             // entries parked at the start wait
-            down_walk(acc, last, tau_f, inv_p, p_is_1, corr, pcode, out, ps);
+            down_walk(acc, last, tau_f, inv_p, p_is_1, corr, pcode, out, ps, false, 0.f);
         } else if (e == s) {
             // the start: an entry stable here whose S does not rule out the
             // next larger p (S_q <= S^(q/p)) parks S in `out`
-            const float rise_thr = plan.e[e].rise_thr_f;
-            each_rolled(acc, stg, lane, [&](int roff, int j, float S, uint32_t mask, uint32_t& dec, uint32_t& pnd) {
-                const bool stable = S >= tau_f;
-                if ((dec & mask) || !(stable || last)) return;
-                const int64_t o = (int64_t)roff * n + j * 32;
-                if (ps) ps[o] = stable ? pcode : (uint8_t)MT_PSTAR_NONE;
-                if (stable && S >= rise_thr) {
-                    out[o] = (TO)S;
-                    pnd |= mask;
-                    return;
-                }
-                dec |= mask;
-                put(out, roff, j, o, S, p_is_1, inv_p, corr);
-            });
+            down_walk(acc, last, tau_f, inv_p, p_is_1, corr, pcode, out, ps, true, plan.e[e].rise_thr_f);
         } else {
             // going up: only parked entries are left, their S from plan
             // entry e + 1 waits in `out`
