@@ -238,26 +238,36 @@ __device__ inline T ipow(T x, int p) {
 // optional; a zero scale gives 0), the scaled input of Sec. 2.1's H'.
 // Every thread produces 8 consecutive plane columns (one 16-byte BF16 chunk)
 // of two plane rows.
+// A workgroup covers PlaneTile::T plane rows x PlaneTile::U plane columns:
+// through an LDS transpose (FP32 sources kTrRows x kTrCols, FP64 64 x 64),
+// or 16 rows x 256 columns straight from the rows (512 contiguous bytes per
+// row and BF16 plane written).
+constexpr int kTrRows = 64, kTrCols = 64;
+template <typename TS, bool kTranspose>
+struct PlaneTile {
+    static constexpr int T = kTranspose ? (sizeof(TS) == 4 ? kTrRows : 64) : 16;
+    static constexpr int U = kTranspose ? (sizeof(TS) == 4 ? kTrCols : 64) : 256;
+    static constexpr int CHUNKS = U / 8;  // 8-column chunks per plane row
+    static constexpr int TASKS = T * CHUNKS;
+    static_assert(TASKS % kThreads == 0, "whole tasks per thread");
+};
+
 template <typename TS, bool kBf16, bool kTranspose>
 __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
     const TS* __restrict__ src, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
     const double* __restrict__ scale_rows, const double* __restrict__ scale_cols,
     const double* __restrict__ col_mul, PlaneSpec spec, void* __restrict__ planes) {
-    __shared__ TS tile[64][64 + 1];
+    using PT = PlaneTile<TS, kTranspose>;
+    __shared__ TS tile[kTranspose ? PT::T : 1][kTranspose ? PT::U + 1 : 1];
     const int64_t bi = blockIdx.z;
-    // A workgroup covers kPlaneRows x kPlaneCols of a plane: 64 x 64 through
-    // an LDS transpose, or 16 rows x 256 columns straight from the rows (512
-    // contiguous bytes per row and BF16 plane written).
-    constexpr int kPlaneRows = kTranspose ? 64 : 16;
-    constexpr int kChunkShift = kTranspose ? 3 : 5;  // log2 of the 8-column chunks per row
-    const int64_t t0 = (int64_t)blockIdx.y * kPlaneRows;      // plane row
-    const int64_t u0 = (int64_t)blockIdx.x * (8 << kChunkShift);  // plane column
+    const int64_t t0 = (int64_t)blockIdx.y * PT::T;  // plane row
+    const int64_t u0 = (int64_t)blockIdx.x * PT::U;  // plane column
     const TS* s = src + bi * rows * cols;
 
     if (kTranspose) {
-        // src[u][t]: read 64 (u) x 64 (t) coalesced along t.
-        for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
-            const int uu = e >> 6, tt = e & 63;
+        // src[u][t]: read U (u) x T (t) coalesced along t.
+        for (int e = threadIdx.x; e < PT::T * PT::U; e += kThreads) {
+            const int uu = e / PT::T, tt = e % PT::T;
             const int64_t u = u0 + uu, t = t0 + tt;
             tile[tt][uu] = (u < cols && t < rows) ? s[u * rows + t] : TS(0);
         }
@@ -266,9 +276,9 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
 
     typedef typename std::conditional<kBf16, float, double>::type TC;
     const int64_t plane_elems = rows_pad * cols_pad;
-    for (int rep = 0; rep < 2; ++rep) {
-        const int task = threadIdx.x + rep * kThreads;  // 0..511
-        const int tt = task >> kChunkShift, ch = task & ((1 << kChunkShift) - 1);
+    for (int rep = 0; rep < PT::TASKS / kThreads; ++rep) {
+        const int task = threadIdx.x + rep * kThreads;
+        const int tt = task / PT::CHUNKS, ch = task % PT::CHUNKS;
         const int64_t t = t0 + tt;
         const int64_t u = u0 + ch * 8;
         if (t >= rows_pad || u >= cols_pad) continue;
@@ -614,14 +624,13 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
                                const PlaneSpec& spec, int bf16, void* planes, hipStream_t st,
                                const double* col_mul) {
     if (rows_pad <= 0 || cols_pad <= 0) return hipSuccess;
-    // 64 x 64 tiles through LDS for the transposed operand, 16 x 256 otherwise
-    const dim3 grid = transpose
-        ? dim3((unsigned)((cols_pad + 63) / 64), (unsigned)((rows_pad + 63) / 64), (unsigned)b)
-        : dim3((unsigned)((cols_pad + 255) / 256), (unsigned)((rows_pad + 15) / 16), (unsigned)b);
-#define MT_PLANES(TS, BF, TR)                                                                   \
-    hipLaunchKernelGGL((mt_power_planes_kernel<TS, BF, TR>), grid, dim3(kThreads), 0, st,      \
-                       (const TS*)src, rows, cols, rows_pad, cols_pad, scale_rows, scale_cols, col_mul, spec,  \
-                       planes)
+#define MT_PLANES(TS, BF, TR)                                                                    \
+    hipLaunchKernelGGL((mt_power_planes_kernel<TS, BF, TR>),                                    \
+                       dim3((unsigned)((cols_pad + PlaneTile<TS, TR>::U - 1) / PlaneTile<TS, TR>::U), \
+                            (unsigned)((rows_pad + PlaneTile<TS, TR>::T - 1) / PlaneTile<TS, TR>::T), \
+                            (unsigned)b),                                                       \
+                       dim3(kThreads), 0, st, (const TS*)src, rows, cols, rows_pad, cols_pad,   \
+                       scale_rows, scale_cols, col_mul, spec, planes)
     timing_before(bf16 ? "mt_power_planes_bf16" : "mt_power_planes_f64", st);
     if (src_f64) {
         if (bf16) {
