@@ -64,17 +64,35 @@ def _estimate(col, P, tau):
     return 0.0, -1
 
 
-def norm_queue(x, y, P, k, tau=TAU_FFT):
-    """Algorithm E of Sec. 2.3 on one pair of lists (x and y may differ in
-    length here).  Returns dict values (k, additive space), diag (k, m*),
-    sigma (|P| x (n + m - 1), before any pop)."""
+def ring_results(x, y, P):
+    """The ring results of Sec. 2.3 for one pair of lists: sigma (|P| x
+    (n + m - 1)), sigma^(p) = x'^p * y'^p by direct convolution, with the
+    scale-backs max x and max y."""
     P = [int(p) for p in P]
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     mx, my = x.max(), y.max()
     xs = np.exp(x - mx)
     ys = np.exp(y - my)
-    sigma = np.stack([np.convolve(xs ** p, ys ** p) for p in P])
+    return np.stack([np.convolve(xs ** p, ys ** p) for p in P]), mx, my
+
+
+def norm_queue(x, y, P, k, tau=TAU_FFT):
+    """Algorithm E of Sec. 2.3 on one pair of lists (x and y may differ in
+    length here).  Returns dict values (k, additive space), diag (k, m*),
+    sigma (|P| x (n + m - 1), before any pop)."""
+    sigma, mx, my = ring_results(x, y, P)
+    return queue_pops(sigma, mx, my, P, k, tau)
+
+
+def queue_pops(sigma, mx, my, P, k, tau=TAU_FFT):
+    """The k pops of algorithm E (Sec. 2.3) from given ring results sigma
+    (|P| x L) of lists whose maxima were mx and my: the same steps as
+    norm_queue, on whatever ring results the caller holds (the tests feed
+    it FFT-rounded ones to find how deep a pop sequence is insensitive to
+    the ring results' rounding)."""
+    P = [int(p) for p in P]
+    sigma = np.asarray(sigma, dtype=np.float64)
     work = sigma.copy()
     L = work.shape[1]
     psi = np.zeros(L)

@@ -9,11 +9,16 @@ on some inputs (the accumulation of error Sec. 3 reports), so the whole pop
 sequence (values within 1e-6, diagonals and indices exactly) is compared on
 inputs and depths whose sequence does not depend on rounding (checked on the
 CPU by running the oracle's algorithm on numpy FFT ring results of three
-lengths, which give the same sequence): uniform lists on [0, 1] to rank 128.
+lengths, which give the same sequence; `test_oracle_xy_topk.py`): uniform
+lists on [0, 1] to rank 128.
 Elsewhere the FFT's absolute rounding of small ring results leaves residuals
 above tau after a diagonal is popped, whose roots then compete with the true
 values (near one-hot lists show it within a few ranks), so there the first
-pop is compared.  The value tolerance covers
+pop is compared.  (That numpy's FFT at three lengths gives the same
+sequence is necessary, not sufficient: on normal lists, n = 1024, whose
+first 15 ranks are the same under numpy's three FFTs, the GPU's coarser
+FFT rounding re-popped a diagonal at rank 13; `xy_robust`.)  The value
+tolerance covers
 the FFT rounding of a ring result near tau divided by p* (the numpy FFT run
 differs from the direct one by up to 6e-9 on these inputs).  On any input the first pop,
 the largest diagonal estimate, is compared.

@@ -32,9 +32,11 @@ pair is accurate):
 import itertools
 
 import numpy as np
+import pytest
 
 import oracle
-from oracle.xy_topk import exact_topk_xy, norm_queue, xy_topk_estimate
+from oracle.xy_topk import exact_topk_xy, norm_queue, queue_pops, ring_results, xy_topk_estimate
+from xy_robust import fft_ring_results, robust_depth
 
 # 24 powers up to 4096, as in Sec. 3 (|P| = 24, p*_max = 4096)
 P24 = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
@@ -219,3 +221,44 @@ def test_paired_exhausted_queue_reports_nothing_more():
     assert r["values"][0] == 0.25 + -1.5 and r["i"][0] == 0 and r["j"][0] == 0
     assert r["accepted"].tolist() == [True, False, False]
     assert np.isneginf(r["values"][1:]).all() and (r["i"][1:] == -1).all()
+
+
+def test_queue_pops_from_ring_results_is_the_queue():
+    """Splitting the queue from its ring results changes nothing: the pops
+    from ring_results equal norm_queue, and FFT ring results (numpy, exact
+    up to rounding) agree with the direct convolution to rounding."""
+    rng = np.random.default_rng(9650)
+    x, y = rng.normal(0, 1, 300), rng.uniform(0, 2, 300)
+    sigma, mx, my = ring_results(x, y, P24)
+    a = norm_queue(x, y, P24, 20)
+    b = queue_pops(sigma, mx, my, P24, 20)
+    np.testing.assert_array_equal(a["diag"], b["diag"])
+    np.testing.assert_array_equal(a["values"], b["values"])
+    sf, mxf, myf = fft_ring_results(x, y, P24, 1024)
+    assert (mxf, myf) == (mx, my)
+    bound = 1e-12 * np.linalg.norm(sigma, axis=1, keepdims=True)
+    assert (np.abs(sf - sigma) <= bound).all()
+
+
+@pytest.mark.parametrize("n,seed", [(1024, 9600), (1024, 9601), (2048, 9700), (3000, 9801), (8192, 9800)])
+def test_uniform_unit_lists_are_rounding_robust(n, seed):
+    """The premise of the GPU's whole-sequence comparison on uniform [0, 1]
+    lists: their top 128 (diagonals of both runs, values within 1e-6) is the
+    same whichever of three FFT lengths computes the ring results."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 1, n)
+    y = rng.uniform(0, 1, n)
+    assert robust_depth(x, y, P24, 128) == 128
+
+
+def test_robust_depth_is_short_where_ghosts_appear():
+    """A near one-hot x leaves FFT residuals above tau once the dominant
+    diagonal terms are popped (reading 20): the depth stops early there,
+    and it never exceeds k."""
+    rng = np.random.default_rng(9651)
+    n = 512
+    x = np.full(n, -60.0)
+    x[17] = 2.0
+    y = rng.uniform(0, 3, n)
+    d = robust_depth(x, y, P24, 64)
+    assert 1 <= d < 64
