@@ -491,7 +491,7 @@ BwdLayout backward_layout(const Family& f, int64_t b, int64_t m, int64_t k, int6
 mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64_t m, int64_t k,
                       int64_t n, const Family& f, const PlaneSpec& ps, const Geom& g,
                       const Layout& L, uint8_t* ws, bool scale, int mode, int clamp, void* out,
-                      int out_f64, uint8_t* pstar, hipStream_t st) {
+                      int out_f64, uint8_t* pstar, hipStream_t st, bool fuse_rowmax = false) {
     double* r = scale ? (double*)(ws + L.r) : nullptr;
     double* c = scale ? (double*)(ws + L.c) : nullptr;
     void* ap = ws + L.ap;
@@ -500,8 +500,15 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     const bool bal = scale && (f.flags & MT_FLAG_BALANCE);
     const double* d = bal ? (const double*)(ws + L.bal + 2 * align_up((size_t)(b * k) * 8)) : nullptr;
     const double* dinv = bal ? (const double*)(ws + L.bal + 3 * align_up((size_t)(b * k) * 8)) : nullptr;
-    MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps, f.bf16, ap, st, d),
-           "power planes (A)");
+    if (fuse_rowmax) {
+        // r and the planes of A in one pass (the row maxima were not taken)
+        MT_TRY(launch_rowmax_planes((const float*)A, b, m, k, g.mp, g.kp, r, (int32_t*)(ws + L.hdr), ps, f.bf16,
+                                    ap, st),
+               "row max and power planes (A)");
+    } else {
+        MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps, f.bf16, ap, st, d),
+               "power planes (A)");
+    }
     MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, nullptr, ps, f.bf16, bp, st, dinv),
            "power planes (B)");
     const FamilyPlan plan = family_plan(f, ps, k);
@@ -751,6 +758,7 @@ mt_status estimate_impl(const void* A, const void* B, mt_dtype dtype, int64_t b,
     // call itself (the header: domain flag, tail count, p* histogram), so a
     // workspace that holds an earlier call's contents is fine
     MT_TRY(launch_fill_zero_u32(ws + L.hdr, sizeof(WsHeader) / 4, st), "clear header");
+    bool fuse_rowmax = false;
     if ((f.flags & MT_FLAG_BALANCE) && k > 0) {
         // inner-index balancing: a_k = max_i A_ik, b_k = max_j B_kj,
         // d_k = sqrt(b_k / a_k); then r_i = max_k A_ik d_k, c_j = max_k B_kj / d_k
@@ -765,14 +773,17 @@ mt_status estimate_impl(const void* A, const void* B, mt_dtype dtype, int64_t b,
         MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st, d, m), "row max");
         MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st, dinv), "column max");
     } else {
-        MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
+        // FP32 rows that fit one workgroup take their maxima in the plane
+        // pass of A (unless the domain check must come before the planes)
+        fuse_rowmax = !f64 && !(f.flags & MT_FLAG_VALIDATE) && g.kp <= kFusedRowMaxK && b <= 65535;
+        if (!fuse_rowmax) MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
         MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st), "column max");
     }
     if (f.flags & MT_FLAG_VALIDATE) {
         if ((s = read_domain_flag(ws + L.hdr, st)) != MT_OK) return s;
     }
     return run_product(A, B, f64, b, m, k, n, f, ps, g, L, ws, true, EPI_PLAIN,
-                       (f.flags & MT_FLAG_CLAMP) ? 1 : 0, C, f64, p_star, st);
+                       (f.flags & MT_FLAG_CLAMP) ? 1 : 0, C, f64, p_star, st, fuse_rowmax);
 }
 
 }  // namespace

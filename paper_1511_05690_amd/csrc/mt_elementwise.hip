@@ -238,6 +238,55 @@ __device__ inline T ipow(T x, int p) {
 // optional; a zero scale gives 0), the scaled input of Sec. 2.1's H'.
 // Every thread produces 8 consecutive plane columns (one 16-byte BF16 chunk)
 // of two plane rows.
+// Powers of one 8-element chunk of scaled values x (plane row position
+// `pos` = t * cols_pad + u) to every plane of the family: squaring where p
+// doubles the previous power, binary powering otherwise; BF16 planes take
+// hi = RNE(power) and, for a split p, lo = RNE(power - hi) in the next plane.
+template <typename TC, bool kBf16>
+__device__ __forceinline__ void write_power_chunk(const TC (&x)[8], const PlaneSpec& spec, void* __restrict__ planes,
+                                                  int64_t bi, int64_t plane_elems, int64_t pos) {
+    TC pw[8];
+    int prev = 0;
+    for (int q = 0; q < spec.n_p; ++q) {
+        const int p = spec.p[q];
+        if (prev > 0 && p == 2 * prev) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pw[i] = pw[i] * pw[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pw[i] = ipow(x[i], p);
+        }
+        prev = p;
+        const int64_t pl = spec.first_plane[q];
+        const int64_t off = (bi * spec.n_planes + pl) * plane_elems + pos;
+        if (kBf16) {
+            uint16_t* base = (uint16_t*)planes;
+            u32x4 hi, lo;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float f0 = (float)pw[2 * i], f1 = (float)pw[2 * i + 1];
+                const uint32_t h = bf16x2_rne(f0, f1);
+                hi[i] = h;
+                if (spec.split[q])
+                    lo[i] = bf16x2_rne(f0 - __uint_as_float(h << 16), f1 - __uint_as_float(h & 0xFFFF0000u));
+            }
+            // streaming stores: the planes are read back only by the GEMM,
+            // long after (measured: the GEMM 1.5 % faster, the planes even)
+            __builtin_nontemporal_store(hi, (u32x4*)(base + off));
+            if (spec.split[q]) __builtin_nontemporal_store(lo, (u32x4*)(base + off + plane_elems));
+        } else {
+            double* base = (double*)planes;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                double2 v2;
+                v2.x = (double)pw[i];
+                v2.y = (double)pw[i + 1];
+                *(double2*)(base + off + i) = v2;
+            }
+        }
+    }
+}
+
 // A workgroup covers PlaneTile::T plane rows x PlaneTile::U plane columns:
 // through an LDS transpose (FP32 sources kTrRows x kTrCols, FP64 64 x 64),
 // or 16 rows x 256 columns straight from the rows (512 contiguous bytes per
@@ -331,47 +380,88 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
                 x[i] = (TC)v;
             }
         }
-        TC pw[8];
-        int prev = 0;
-        for (int q = 0; q < spec.n_p; ++q) {
-            const int p = spec.p[q];
-            if (prev > 0 && p == 2 * prev) {
+        write_power_chunk<TC, kBf16>(x, spec, planes, bi, plane_elems, t * cols_pad + u);
+    }
+}
+
+// Row maxima and power planes of a row-major FP32 operand in one pass, for
+// rows of at most kFusedRowMaxK padded inner elements: one workgroup per
+// plane row holds the row in registers (kFusedChunks chunks of 8 per thread),
+// takes r = max_k A_ik (Sec. 2.1 scaling; the domain check of the row-max
+// kernel included), then writes the planes of A / r with the plane kernel's
+// arithmetic (the FP64 reciprocal of r for whole 8-element chunks of rows
+// whose length allows 16-byte loads, a division otherwise).  Padding rows
+// and columns get zeros; r is written for the real rows.
+constexpr int kFusedChunks = (int)(kFusedRowMaxK / 8 / kThreads);
+template <bool kBf16>
+__global__ __launch_bounds__(kThreads) void mt_rowmax_planes_kernel(const float* __restrict__ A, int64_t rows,
+                                                                   int64_t cols, int64_t rows_pad,
+                                                                   int64_t cols_pad, double* __restrict__ r,
+                                                                   int32_t* __restrict__ flag, PlaneSpec spec,
+                                                                   void* __restrict__ planes) {
+    __shared__ float wmax[kThreads / 64];
+    const int64_t t = blockIdx.x;  // plane row
+    const int64_t bi = blockIdx.y;
+    const bool real_row = t < rows;
+    const float* s = A + (bi * rows + (real_row ? t : 0)) * cols;
+    const bool vec_row = (cols & 3) == 0 && ((uintptr_t)s % 16) == 0;
+    float v[kFusedChunks][8];
+    float mx = 0.f;
+    bool bad = false;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) pw[i] = pw[i] * pw[i];
-            } else {
+    for (int c = 0; c < kFusedChunks; ++c) {
+        const int64_t u = ((int64_t)c * kThreads + threadIdx.x) * 8;
+        if (real_row && vec_row && u + 8 <= cols) {
+            typedef float vec4 __attribute__((ext_vector_type(4)));
+            const vec4 a0 = *(const vec4*)(s + u);
+            const vec4 a1 = *(const vec4*)(s + u + 4);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) pw[i] = ipow(x[i], p);
+            for (int i = 0; i < 4; ++i) {
+                v[c][i] = a0[i];
+                v[c][4 + i] = a1[i];
             }
-            prev = p;
-            const int64_t pl = spec.first_plane[q];
-            if (kBf16) {
-                uint16_t* base = (uint16_t*)planes;
-                u32x4 hi, lo;
+        } else {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float f0 = (float)pw[2 * i], f1 = (float)pw[2 * i + 1];
-                    const uint32_t h = bf16x2_rne(f0, f1);
-                    hi[i] = h;
-                    if (spec.split[q])
-                        lo[i] = bf16x2_rne(f0 - __uint_as_float(h << 16), f1 - __uint_as_float(h & 0xFFFF0000u));
-                }
-                const int64_t off = ((bi * spec.n_planes + pl) * plane_elems) + t * cols_pad + u;
-                // streaming stores: the planes are read back only by the GEMM,
-                // long after (measured: the GEMM 1.5 % faster, the planes even)
-                __builtin_nontemporal_store(hi, (u32x4*)(base + off));
-                if (spec.split[q]) __builtin_nontemporal_store(lo, (u32x4*)(base + off + plane_elems));
-            } else {
-                double* base = (double*)planes;
-                const int64_t off = ((bi * spec.n_planes + pl) * plane_elems) + t * cols_pad + u;
+            for (int i = 0; i < 8; ++i) v[c][i] = (real_row && u + i < cols) ? s[u + i] : 0.f;
+        }
 #pragma unroll
-                for (int i = 0; i < 8; i += 2) {
-                    double2 v2;
-                    v2.x = (double)pw[i];
-                    v2.y = (double)pw[i + 1];
-                    *(double2*)(base + off + i) = v2;
-                }
+        for (int i = 0; i < 8; ++i) {
+            bad |= bad_value(v[c][i]);
+            mx = fmaxf(mx, v[c][i]);
+        }
+    }
+    // the row's maximum (exact in FP32) over the workgroup
+    for (int d = 32; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = wmax[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
+    const double sc = (double)mx;
+    if (real_row && threadIdx.x == 0) r[bi * rows + t] = sc;
+    if (bad) atomicOr(flag, 1);
+
+    typedef typename std::conditional<kBf16, float, double>::type TC;
+    const int64_t plane_elems = rows_pad * cols_pad;
+    const bool zero_row = !real_row || sc == 0.0;
+    const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+#pragma unroll
+    for (int c = 0; c < kFusedChunks; ++c) {
+        const int64_t u = ((int64_t)c * kThreads + threadIdx.x) * 8;
+        if (u >= cols_pad) continue;
+        TC x[8];
+        if (!zero_row && sc >= DBL_MIN && u + 8 <= cols && (cols & 3) == 0) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = (TC)((double)v[c][i] * inv);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                double y = 0.0;
+                if (!zero_row && u + i < cols) y = sc > 0.0 ? (double)v[c][i] / sc : 0.0;
+                x[i] = (TC)y;
             }
         }
+        write_power_chunk<TC, kBf16>(x, spec, planes, bi, plane_elems, t * cols_pad + u);
     }
 }
 
@@ -646,6 +736,23 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
         }
     }
 #undef MT_PLANES
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowmax_planes(const float* A, int64_t b, int64_t rows, int64_t cols, int64_t rows_pad,
+                                int64_t cols_pad, double* r, int32_t* flag, const PlaneSpec& spec, int bf16,
+                                void* planes, hipStream_t st) {
+    if (rows_pad <= 0 || cols_pad <= 0 || b <= 0) return hipSuccess;
+    if (cols_pad > kFusedRowMaxK || cols > cols_pad || rows_pad > 0x7fffffff || b > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)rows_pad, (unsigned)b);
+    timing_before(bf16 ? "mt_power_planes_bf16" : "mt_power_planes_f64", st);
+    if (bf16)
+        hipLaunchKernelGGL(mt_rowmax_planes_kernel<true>, grid, dim3(kThreads), 0, st, A, rows, cols, rows_pad,
+                           cols_pad, r, flag, spec, planes);
+    else
+        hipLaunchKernelGGL(mt_rowmax_planes_kernel<false>, grid, dim3(kThreads), 0, st, A, rows, cols, rows_pad,
+                           cols_pad, r, flag, spec, planes);
     timing_after(st);
     return hipGetLastError();
 }
