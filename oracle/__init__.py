@@ -1,4 +1,4 @@
-"""CPU oracle for the p-norm (max, x) product estimate and its APSP driver.
+"""CPU oracle for the p-norm (max, x) product estimate and its APSP by repeated squaring.
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the ``cpu_baseline`` leg of ``bench.py`` may import, call, link or execute

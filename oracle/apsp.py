@@ -67,13 +67,13 @@ def apsp_by_squaring(W, s, T, product):
 
 
 def apsp_exact_squaring(W, s=1.0, T=None):
-    """The same driver with the exact product of Alg. 2 (Alg. 1 after the
+    """The same squaring loop with the exact product of Alg. 2 (Alg. 1 after the
     transform).  Equals Floyd-Warshall when T >= ceil(log2 n)."""
     return apsp_by_squaring(W, s, T, exact_maxtimes)
 
 
 def apsp_estimate(W, s, P, tau, T=None, projection=None):
-    """APSP estimate: the driver with the p-norm product (Alg. 5) at each
+    """APSP estimate: the repeated squaring with the p-norm product (Alg. 5) at each
     squaring (projection "r1": the r = 1 projection of Sec. 1 in place of
     the plain root).  Returns dict D, X, pstar_idx_last (p* index of the
     last squaring)."""

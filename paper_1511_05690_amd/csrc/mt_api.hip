@@ -1,6 +1,6 @@
 // C ABI of libmaxtimes (include/maxtimes.h): argument checks, workspace
 // layout, the launch sequence of the p-norm (max, x) estimate (Alg. 5 with
-// the scaled ring call H' of Sec. 2.1) and of the APSP driver (Sec. 2.2),
+// the scaled ring call H' of Sec. 2.1) and of the APSP squaring loop (Sec. 2.2),
 // and per-kernel event timing.  Host code only; kernels live in
 // mt_elementwise.hip, mt_gemm_bf16.hip, mt_gemm_f64.hip and mt_backward.hip.
 #include <hip/hip_runtime.h>

@@ -1,4 +1,4 @@
-"""GPU parity of the APSP estimate (Sec. 2.2) with the oracle's driver, and
+"""GPU parity of the APSP estimate (Sec. 2.2) with the oracle's squaring loop, and
 properties at full size (reachability, zero diagonal, the one-sided bound
 against exact distances)."""
 

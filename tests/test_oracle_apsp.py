@@ -1,5 +1,5 @@
 """Pins of the oracle's APSP pieces (CPU only): Floyd-Warshall and Dijkstra
-against scipy's csgraph (a library routine), the squaring driver with the
+against scipy's csgraph (a library routine), the squaring loop with the
 exact product against Floyd-Warshall, hop-limited brute force, closed forms
 for short chains, and the one-sided bound of the estimate."""
 
@@ -48,7 +48,7 @@ def test_exact_squaring_equals_floyd_warshall(n):
 
 
 def test_squaring_count_limits_hops():
-    """After T squarings the driver covers paths of at most 2^T hops: with
+    """After T squarings the squaring loop covers paths of at most 2^T hops: with
     T = 1, brute-force min over one intermediate vertex."""
     W = er_graph(12, 0.3, 10.0, seed=50).astype(np.float64)
     D1, _ = oracle.apsp_exact_squaring(W, s=0.5, T=1)
