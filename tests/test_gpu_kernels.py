@@ -90,6 +90,8 @@ CASES = [
     ("uniform", 2, 100, 70, 50),      # k % 4 != 0: every A chunk divides
     ("lognormal", 1, 257, 204, 129),  # a ragged last chunk, denormal powers
     ("lognormal", 2, 64, 256, 300),
+    ("lognormal", 1, 5, 8192, 40),    # the longest rows whose maxima the plane pass takes
+    ("uniform", 1, 6, 8200, 33),      # one chunk longer: separate maxima, k % 4 != 0
 ]
 
 
