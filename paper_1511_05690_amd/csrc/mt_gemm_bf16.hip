@@ -95,8 +95,9 @@ struct GemmGeom {
 };
 
 // WAVES_M x WAVES_N waves, each owning WT_M x WT_N MFMA tiles of 32 x 32.
-template <int WAVES_M, int WAVES_N, int WT_M_, int WT_N_>
+template <int WAVES_M, int WAVES_N, int WT_M_, int WT_N_, int MINW_ = 1>
 struct Cfg {
+    static constexpr int MINW = MINW_;  // waves per SIMD the kernel must allow
     static constexpr int NW = WAVES_M * WAVES_N;
     static constexpr int THREADS = 64 * NW;
     static constexpr int WT_M = WT_M_, WT_N = WT_N_;
@@ -552,44 +553,57 @@ struct AdjointEpi {
                           uint8_t*) {
         const int pm1 = plan.e[e].p - 1;
         const TM* src = (const TM*)a.M + lane_off;
+        // one sub-tile at a time (a rolled loop keeps one sub-tile's inputs
+        // and powers live, not all of them)
+#pragma unroll 1
+        for (int tix = 0; tix < WT_M * WT_N; ++tix) {
+            const int i = tix / WT_N, j = tix % WT_N;
+            f32x16 av{};
 #pragma unroll
-        for (int i = 0; i < WT_M; ++i)
+            for (int ii = 0; ii < WT_M; ++ii)
 #pragma unroll
-            for (int j = 0; j < WT_N; ++j) {
-                const bool col_ok = j * 32 < cols_left;
-                const float cinv = cs[lc0 + j * 32];
-                const int cexp = ces[lc0 + j * 32];
-                float x[16];
+                for (int jj = 0; jj < WT_N; ++jj)
+                    if (ii * WT_N + jj == tix) av = acc[ii][jj];
+            const bool col_ok = j * 32 < cols_left;
+            const float cinv = cs[lc0 + j * 32];
+            const int cexp = ces[lc0 + j * 32];
+            float x[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int roff = i * 32 + (r >> 2) * 8 + (r & 3);
-                    float v = 0.f;
-                    if (col_ok && roff < rows_left) {
-                        const int ex = -(res[lr0 + roff] + cexp);
-                        const TM mv = src[(int64_t)roff * cols + j * 32];
-                        if constexpr (sizeof(TM) == 8)
-                            v = (float)__builtin_amdgcn_ldexp(mv, ex);
-                        else
-                            v = __builtin_amdgcn_ldexpf(mv, ex);
-                        v = v * rs[lr0 + roff] * cinv;
-                    }
-                    x[r] = v;
+            for (int r = 0; r < 16; ++r) {
+                const int roff = i * 32 + (r >> 2) * 8 + (r & 3);
+                float v = 0.f;
+                if (col_ok && roff < rows_left) {
+                    const int ex = -(res[lr0 + roff] + cexp);
+                    const TM mv = src[(int64_t)roff * cols + j * 32];
+                    if constexpr (sizeof(TM) == 8)
+                        v = (float)__builtin_amdgcn_ldexp(mv, ex);
+                    else
+                        v = __builtin_amdgcn_ldexpf(mv, ex);
+                    v = v * rs[lr0 + roff] * cinv;
                 }
-                // x^(p-1) by binary powering (p uniform); 0^0 = 1
-                float pw[16];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) pw[r] = 1.f;
-                for (int ex = pm1; ex; ex >>= 1) {
-                    if (ex & 1) {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) pw[r] *= x[r];
-                    }
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) x[r] *= x[r];
-                }
-#pragma unroll
-                for (int r = 0; r < 16; ++r) tot[i][j][r] += pw[r] * acc[i][j][r];
+                x[r] = v;
             }
+            // x^(p-1) by binary powering (p uniform); 0^0 = 1
+            float pw[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) pw[r] = 1.f;
+            for (int ex = pm1; ex; ex >>= 1) {
+                if (ex & 1) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) pw[r] *= x[r];
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) x[r] *= x[r];
+            }
+#pragma unroll
+            for (int ii = 0; ii < WT_M; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < WT_N; ++jj)
+                    if (ii * WT_N + jj == tix) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) tot[ii][jj][r] += pw[r] * av[r];
+                    }
+        }
     }
 
     __device__ void finish(const TileCtx& t) {
@@ -630,7 +644,7 @@ struct AdjointEpi {
 
 // ------------------------------------------------------------ the main loop
 template <class C, class Epi>
-__global__ __launch_bounds__(C::THREADS, 1) void mt_pfamily_gemm_bf16_kernel(GemmGeom g,
+__global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kernel(GemmGeom g,
                                                                             FamilyPlan plan,
                                                                             typename Epi::Args args) {
     constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
@@ -1215,9 +1229,12 @@ hipError_t launch_gemm(const GemmGeom& g, int64_t b, const FamilyPlan& plan,
 
 // Forward: 8 waves (2 per SIMD) in 2 x 4, each 128 x 64 -> 256 x 256 tiles.
 using FwdCfg = Cfg<2, 4, 4, 2>;
-// Adjoint: 8 waves in 2 x 4, each 64 x 32 -> 128 x 128 tiles (accumulator
-// plus running sum fit the two-waves-per-SIMD register budget).
-using AdjCfg = Cfg<2, 4, 2, 1>;
+// Adjoint: 8 waves in 2 x 4, each 64 x 32 -> 128 x 128 tiles, held to 128
+// registers (4 waves per SIMD) so that two workgroups share a CU and one's
+// loads and barriers overlap the other's MFMAs (the batched 512^3 products
+// have short K loops); the accumulator plus running sum fit that budget with
+// the epilogue walking one sub-tile at a time.
+using AdjCfg = Cfg<2, 4, 2, 1, 4>;
 static_assert(FwdCfg::BM == kBf16BM && FwdCfg::BN == kBf16BN, "forward tile");
 static_assert(AdjCfg::BM == kAdjBM && AdjCfg::BN == kAdjBM, "adjoint tile");
 
