@@ -387,6 +387,22 @@ def run_legs(mt, torch, np, sections=None):
                    "ops_per_s": c5["T"] * float(n5) ** 3 / (ms / 1e3),
                    "vs_exact_64_sources": apsp_errors(D5[si], ex5, c5["s"], torch),
                    "exact_rows": {"sources": len(src5), "bellman_ford_rounds": rounds5}}
+            if path == "bf16":
+                # the squarings' GEMM on the device clock, with the MFMA work
+                # its launches executed (one more call with per-launch timing)
+                mt.timing_reset()
+                mt.timing_enable(True)
+                mt.apsp(W5, s=c5["s"], P=c5["P"], path=path, n_squarings=c5["T"], out_dtype=torch.float64,
+                        projection=proj)
+                torch.cuda.synchronize()
+                g_ms, g_n = mt.timing_span("mt_pfamily_gemm_bf16")
+                g_work = mt.timing_work("mt_pfamily_gemm_bf16")
+                mt.timing_enable(False)
+                mt.timing_reset()
+                if g_n:
+                    leg["gemm"] = {"launches": g_n, "ms_per_launch": g_ms / g_n, "flop_per_launch": g_work / g_n,
+                                   "tflops": g_work / (g_ms / 1e3) / 1e12,
+                                   "frac_of_bf16_peak": g_work / (g_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS}
             Dc = D5.clone()
             ab = mt.apsp_affine_correct(Dc, src5, ex5)
             leg["affine_64_sources"] = dict(apsp_errors(Dc[si], ex5, c5["s"], torch),
