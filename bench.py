@@ -133,6 +133,9 @@ def hbm_kernels(kern_ms, n, P, path, in_bytes=4):
         plane_bytes = 2 * (n2 * in_bytes + n2 * 2 * planes)  # both operands
     else:
         plane_bytes = 2 * (n2 * in_bytes + n2 * 8 * len(P))
+    if "mt_colmax" not in kern_ms:
+        # B's column maxima ran inside the plane launches (one more read of B)
+        plane_bytes += n2 * in_bytes
     algo = {
         "mt_rowmax": n2 * in_bytes,
         "mt_colmax": n2 * in_bytes,

@@ -501,10 +501,11 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     const double* d = bal ? (const double*)(ws + L.bal + 2 * align_up((size_t)(b * k) * 8)) : nullptr;
     const double* dinv = bal ? (const double*)(ws + L.bal + 3 * align_up((size_t)(b * k) * 8)) : nullptr;
     if (fuse_rowmax) {
-        // r and the planes of A in one pass (the row maxima were not taken)
-        MT_TRY(launch_rowmax_planes((const float*)A, b, m, k, g.mp, g.kp, r, (int32_t*)(ws + L.hdr), ps, f.bf16,
-                                    ap, st),
-               "row max and power planes (A)");
+        // r and the planes of A in one pass, with c taken by the same launch
+        // (neither maximum was taken before)
+        MT_TRY(launch_rowmax_planes_colmax((const float*)A, (const float*)B, b, m, k, g.mp, g.kp, n, r, c,
+                                           (int32_t*)(ws + L.hdr), ps, f.bf16, ap, st),
+               "row and column max, power planes (A)");
     } else {
         MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps, f.bf16, ap, st, d),
                "power planes (A)");
@@ -774,10 +775,14 @@ mt_status estimate_impl(const void* A, const void* B, mt_dtype dtype, int64_t b,
         MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st, dinv), "column max");
     } else {
         // FP32 rows that fit one workgroup take their maxima in the plane
-        // pass of A (unless the domain check must come before the planes)
-        fuse_rowmax = !f64 && !(f.flags & MT_FLAG_VALIDATE) && g.kp <= kFusedRowMaxK && b <= 65535;
-        if (!fuse_rowmax) MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
-        MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st), "column max");
+        // pass of A, and B's column maxima run in the same launch (unless the
+        // domain check must come before the planes)
+        fuse_rowmax = !f64 && !(f.flags & MT_FLAG_VALIDATE) && g.kp <= kFusedRowMaxK && b <= 65535 && k > 0 &&
+                      n > 0 && g.mp * b >= ((n + 1023) / 1024) * ((k + 63) / 64) * b;
+        if (!fuse_rowmax) {
+            MT_TRY(launch_rowmax(A, f64, b * m, k, (double*)(ws + L.r), flag, st), "row max");
+            MT_TRY(launch_colmax(B, f64, b, k, n, (double*)(ws + L.c), flag, st), "column max");
+        }
     }
     if (f.flags & MT_FLAG_VALIDATE) {
         if ((s = read_domain_flag(ws + L.hdr, st)) != MT_OK) return s;

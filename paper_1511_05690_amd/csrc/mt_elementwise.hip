@@ -160,15 +160,14 @@ __global__ __launch_bounds__(kThreads) void mt_rowmax_kernel(const T* __restrict
 // maximum): each thread owns kColVec consecutive columns (one 16-byte load
 // per row when n allows it), 64 rows per block, combined with an integer
 // atomic max on the bit pattern (exact for >= 0).
-template <typename T, bool kMul = false>
-__global__ __launch_bounds__(kThreads) void mt_colmax_kernel(const T* __restrict__ B, int64_t k,
-                                                             int64_t n, double* __restrict__ c,
-                                                             int32_t* __restrict__ flag,
-                                                             const double* __restrict__ mul = nullptr) {
+template <typename T, bool kMul>
+__device__ __forceinline__ void colmax_block(const T* __restrict__ B, int64_t k, int64_t n, double* __restrict__ c,
+                                             int32_t* __restrict__ flag, const double* __restrict__ mul,
+                                             int64_t bx, int64_t by, int64_t bz) {
     constexpr int V = 16 / sizeof(T);
-    const int64_t j0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * V;
-    const int64_t k0 = (int64_t)blockIdx.y * 64;
-    const int64_t bi = blockIdx.z;
+    const int64_t j0 = (bx * kThreads + threadIdx.x) * V;
+    const int64_t k0 = by * 64;
+    const int64_t bi = bz;
     if (j0 >= n) return;
     const T* bb = B + bi * k * n + j0;
     double mx[V];
@@ -205,6 +204,14 @@ __global__ __launch_bounds__(kThreads) void mt_colmax_kernel(const T* __restrict
     for (int q = 0; q < V; ++q)
         if (j0 + q < n && (mx[q] > 0.0 || mx[q] != mx[q]))
             atomicMax((unsigned long long*)(c + bi * n + j0 + q), (unsigned long long)__double_as_longlong(mx[q]));
+}
+
+template <typename T, bool kMul = false>
+__global__ __launch_bounds__(kThreads) void mt_colmax_kernel(const T* __restrict__ B, int64_t k,
+                                                             int64_t n, double* __restrict__ c,
+                                                             int32_t* __restrict__ flag,
+                                                             const double* __restrict__ mul = nullptr) {
+    colmax_block<T, kMul>(B, k, n, c, flag, mul, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Inner-index balancing: d = sqrt(b / a) per inner index (a = largest entry
@@ -394,14 +401,11 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
 // and columns get zeros; r is written for the real rows.
 constexpr int kFusedChunks = (int)(kFusedRowMaxK / 8 / kThreads);
 template <bool kBf16>
-__global__ __launch_bounds__(kThreads) void mt_rowmax_planes_kernel(const float* __restrict__ A, int64_t rows,
-                                                                   int64_t cols, int64_t rows_pad,
-                                                                   int64_t cols_pad, double* __restrict__ r,
-                                                                   int32_t* __restrict__ flag, PlaneSpec spec,
-                                                                   void* __restrict__ planes) {
-    __shared__ float wmax[kThreads / 64];
-    const int64_t t = blockIdx.x;  // plane row
-    const int64_t bi = blockIdx.y;
+__device__ __forceinline__ void rowmax_planes_block(const float* __restrict__ A, int64_t rows, int64_t cols,
+                                                    int64_t rows_pad, int64_t cols_pad, double* __restrict__ r,
+                                                    int32_t* __restrict__ flag, const PlaneSpec& spec,
+                                                    void* __restrict__ planes, int64_t t, int64_t bi,
+                                                    float* wmax) {
     const bool real_row = t < rows;
     const float* s = A + (bi * rows + (real_row ? t : 0)) * cols;
     const bool vec_row = (cols & 3) == 0 && ((uintptr_t)s % 16) == 0;
@@ -463,6 +467,47 @@ __global__ __launch_bounds__(kThreads) void mt_rowmax_planes_kernel(const float*
         }
         write_power_chunk<TC, kBf16>(x, spec, planes, bi, plane_elems, t * cols_pad + u);
     }
+}
+
+template <bool kBf16>
+__global__ __launch_bounds__(kThreads) void mt_rowmax_planes_kernel(const float* __restrict__ A, int64_t rows,
+                                                                   int64_t cols, int64_t rows_pad,
+                                                                   int64_t cols_pad, double* __restrict__ r,
+                                                                   int32_t* __restrict__ flag, PlaneSpec spec,
+                                                                   void* __restrict__ planes) {
+    __shared__ float wmax[kThreads / 64];
+    rowmax_planes_block<kBf16>(A, rows, cols, rows_pad, cols_pad, r, flag, spec, planes, blockIdx.x, blockIdx.y,
+                               wmax);
+}
+
+// The same pass with B's column maxima in the same launch: its column-max
+// blocks are interleaved with the plane-row blocks (one every ratio + 1 while
+// both last), so the two HBM-bound passes share the GPU instead of running
+// one after the other.  c must be zero before the launch.
+template <bool kBf16>
+__global__ __launch_bounds__(kThreads) void mt_rowmax_planes_colmax_kernel(
+    const float* __restrict__ A, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
+    double* __restrict__ r, int32_t* __restrict__ flag, PlaneSpec spec, void* __restrict__ planes,
+    const float* __restrict__ B, int64_t kb, int64_t nb, double* __restrict__ c, int64_t na, int64_t nc,
+    int64_t ratio, int64_t cgx, int64_t cgy) {
+    __shared__ float wmax[kThreads / 64];
+    const int64_t id = blockIdx.x;
+    const int64_t span = nc * (ratio + 1);
+    int64_t a_idx, c_idx = -1;
+    if (id < span) {
+        const int64_t g = id / (ratio + 1), pos = id - g * (ratio + 1);
+        if (pos == ratio) c_idx = g;
+        a_idx = g * ratio + pos;
+    } else {
+        a_idx = nc * ratio + (id - span);
+    }
+    if (c_idx >= 0) {
+        colmax_block<float, false>(B, kb, nb, c, flag, nullptr, c_idx % cgx, (c_idx / cgx) % cgy, c_idx / (cgx * cgy));
+        return;
+    }
+    if (a_idx < na)
+        rowmax_planes_block<kBf16>(A, rows, cols, rows_pad, cols_pad, r, flag, spec, planes, a_idx % rows_pad,
+                                   a_idx / rows_pad, wmax);
 }
 
 // X = exp(-s W) in FP64; +inf -> 0; diagonal -> 1.
@@ -753,6 +798,34 @@ hipError_t launch_rowmax_planes(const float* A, int64_t b, int64_t rows, int64_t
     else
         hipLaunchKernelGGL(mt_rowmax_planes_kernel<false>, grid, dim3(kThreads), 0, st, A, rows, cols, rows_pad,
                            cols_pad, r, flag, spec, planes);
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowmax_planes_colmax(const float* A, const float* B, int64_t b, int64_t rows, int64_t cols,
+                                       int64_t rows_pad, int64_t cols_pad, int64_t nb, double* r, double* c,
+                                       int32_t* flag, const PlaneSpec& spec, int bf16, void* planes,
+                                       hipStream_t st) {
+    if (rows_pad <= 0 || cols_pad <= 0 || b <= 0 || nb <= 0 || cols <= 0)
+        return hipErrorInvalidValue;
+    if (cols_pad > kFusedRowMaxK || cols > cols_pad) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_zero_u32(c, b * nb * 2, st);
+    if (e != hipSuccess) return e;
+    // B is b x cols x nb (its inner index runs over A's columns)
+    const int64_t cgx = (nb + (int64_t)kThreads * 4 - 1) / ((int64_t)kThreads * 4);
+    const int64_t cgy = (cols + 63) / 64;
+    const int64_t na = rows_pad * b, nc = cgx * cgy * b;
+    if (na < nc || na + nc > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t ratio = na / nc;
+    timing_before(bf16 ? "mt_power_planes_bf16" : "mt_power_planes_f64", st);
+    if (bf16)
+        hipLaunchKernelGGL(mt_rowmax_planes_colmax_kernel<true>, dim3((unsigned)(na + nc)), dim3(kThreads), 0, st,
+                           A, rows, cols, rows_pad, cols_pad, r, flag, spec, planes, B, cols, nb, c, na, nc, ratio,
+                           cgx, cgy);
+    else
+        hipLaunchKernelGGL(mt_rowmax_planes_colmax_kernel<false>, dim3((unsigned)(na + nc)), dim3(kThreads), 0, st,
+                           A, rows, cols, rows_pad, cols_pad, r, flag, spec, planes, B, cols, nb, c, na, nc, ratio,
+                           cgx, cgy);
     timing_after(st);
     return hipGetLastError();
 }

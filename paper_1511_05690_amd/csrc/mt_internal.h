@@ -217,6 +217,12 @@ constexpr int64_t kFusedRowMaxK = 8192;
 hipError_t launch_rowmax_planes(const float* A, int64_t b, int64_t rows, int64_t cols, int64_t rows_pad,
                                 int64_t cols_pad, double* r, int32_t* flag, const PlaneSpec& spec, int bf16,
                                 void* planes, hipStream_t st);
+// The same with the column maxima c of B (FP32, b x cols x nb) taken in the
+// same launch (c is cleared first): the two passes share the GPU.
+hipError_t launch_rowmax_planes_colmax(const float* A, const float* B, int64_t b, int64_t rows, int64_t cols,
+                                       int64_t rows_pad, int64_t cols_pad, int64_t nb, double* r, double* c,
+                                       int32_t* flag, const PlaneSpec& spec, int bf16, void* planes,
+                                       hipStream_t st);
 hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int64_t b,
                                int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
                                const double* scale_rows, const double* scale_cols,
