@@ -469,21 +469,11 @@ __device__ __forceinline__ void rowmax_planes_block(const float* __restrict__ A,
     }
 }
 
-template <bool kBf16>
-__global__ __launch_bounds__(kThreads) void mt_rowmax_planes_kernel(const float* __restrict__ A, int64_t rows,
-                                                                   int64_t cols, int64_t rows_pad,
-                                                                   int64_t cols_pad, double* __restrict__ r,
-                                                                   int32_t* __restrict__ flag, PlaneSpec spec,
-                                                                   void* __restrict__ planes) {
-    __shared__ float wmax[kThreads / 64];
-    rowmax_planes_block<kBf16>(A, rows, cols, rows_pad, cols_pad, r, flag, spec, planes, blockIdx.x, blockIdx.y,
-                               wmax);
-}
-
-// The same pass with B's column maxima in the same launch: its column-max
-// blocks are interleaved with the plane-row blocks (one every ratio + 1 while
-// both last), so the two HBM-bound passes share the GPU instead of running
-// one after the other.  c must be zero before the launch.
+// The row-max and plane pass of A with B's column maxima in the same
+// launch: the column-max blocks are interleaved with the plane-row blocks
+// (one every ratio + 1 while both last), so the two HBM-bound passes share
+// the GPU instead of running one after the other.  c must be zero before
+// the launch.
 template <bool kBf16>
 __global__ __launch_bounds__(kThreads) void mt_rowmax_planes_colmax_kernel(
     const float* __restrict__ A, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
@@ -781,23 +771,6 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
         }
     }
 #undef MT_PLANES
-    timing_after(st);
-    return hipGetLastError();
-}
-
-hipError_t launch_rowmax_planes(const float* A, int64_t b, int64_t rows, int64_t cols, int64_t rows_pad,
-                                int64_t cols_pad, double* r, int32_t* flag, const PlaneSpec& spec, int bf16,
-                                void* planes, hipStream_t st) {
-    if (rows_pad <= 0 || cols_pad <= 0 || b <= 0) return hipSuccess;
-    if (cols_pad > kFusedRowMaxK || cols > cols_pad || rows_pad > 0x7fffffff || b > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)rows_pad, (unsigned)b);
-    timing_before(bf16 ? "mt_power_planes_bf16" : "mt_power_planes_f64", st);
-    if (bf16)
-        hipLaunchKernelGGL(mt_rowmax_planes_kernel<true>, grid, dim3(kThreads), 0, st, A, rows, cols, rows_pad,
-                           cols_pad, r, flag, spec, planes);
-    else
-        hipLaunchKernelGGL(mt_rowmax_planes_kernel<false>, grid, dim3(kThreads), 0, st, A, rows, cols, rows_pad,
-                           cols_pad, r, flag, spec, planes);
     timing_after(st);
     return hipGetLastError();
 }

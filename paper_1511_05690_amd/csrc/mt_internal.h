@@ -209,16 +209,14 @@ struct PlaneSpec {
     int32_t first_plane[MT_MAX_P];  // plane index of power q (hi plane if split)
     int32_t n_planes;
 };
-// Row maxima r of a row-major FP32 operand (b x rows x cols) and its power
+// Row maxima r of a row-major FP32 operand A (b x rows x cols) and its power
 // planes in one pass, the same values as launch_rowmax followed by
 // launch_power_planes (untransposed, no column scales or multipliers), for
-// cols_pad <= kFusedRowMaxK.
+// cols_pad <= kFusedRowMaxK; with the column maxima c of B (FP32,
+// b x cols x nb) taken in the same launch (c is cleared first), so the two
+// passes share the GPU.  Needs at least as many plane rows (b rows_pad) as
+// column-max blocks.
 constexpr int64_t kFusedRowMaxK = 8192;
-hipError_t launch_rowmax_planes(const float* A, int64_t b, int64_t rows, int64_t cols, int64_t rows_pad,
-                                int64_t cols_pad, double* r, int32_t* flag, const PlaneSpec& spec, int bf16,
-                                void* planes, hipStream_t st);
-// The same with the column maxima c of B (FP32, b x cols x nb) taken in the
-// same launch (c is cleared first): the two passes share the GPU.
 hipError_t launch_rowmax_planes_colmax(const float* A, const float* B, int64_t b, int64_t rows, int64_t cols,
                                        int64_t rows_pad, int64_t cols_pad, int64_t nb, double* r, double* c,
                                        int32_t* flag, const PlaneSpec& spec, int bf16, void* planes,
