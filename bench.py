@@ -123,13 +123,16 @@ def cpu_baseline(A, B, P, tau, rows):
     }
 
 
-def hbm_kernels(kern_ms, n, P, path, in_bytes=4):
+def hbm_kernels(kern_ms, n, P, path, in_bytes=4, deferred=False):
     """Achieved HBM rate of the bandwidth-bound kernels of one step, from
     their algorithmic bytes (each input read once, each output written once)
-    and the in-process launch times (ms per step)."""
+    and the in-process launch times (ms per step).  deferred: the plane
+    launches write no planes of the two smallest p (they are written later,
+    and only if some entry needs them)."""
     n2 = float(n) * n
     if path == "bf16":
-        planes = sum(2 if p <= 4 else 1 for p in P)
+        written = sorted(P)[2:] if deferred else P
+        planes = sum(2 if p <= 4 else 1 for p in written)
         plane_bytes = 2 * (n2 * in_bytes + n2 * 2 * planes)  # both operands
     else:
         plane_bytes = 2 * (n2 * in_bytes + n2 * 8 * len(P))
@@ -528,17 +531,21 @@ def main():
         gemm_ms, gemm_n = mt.timing_span(kname)
         gemm_work = mt.timing_work(kname)
         kern = {}
-        for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_pilot", "mt_pfamily_gemm", "mt_tail",
-                   "mt_select_root", "mt_fill"):
+        for kn in ("mt_rowmax", "mt_colmax", "mt_power_planes", "mt_planes_if", "mt_pilot", "mt_pfamily_gemm",
+                   "mt_rerun_gemm", "mt_tail", "mt_select_root", "mt_fill"):
             t, c = mt.timing_read(kn)
             if c:
                 kern[kn] = round(t / steps, 4)
         if gemm_n:
             kern["mt_pfamily_gemm"] = round(gemm_ms / steps, 4)  # device clock, as above
+        # deferred planes: work of the tiles that ran again (0: no entry
+        # needed the planes of the two smallest p)
+        rerun_work = mt.timing_work("mt_rerun_gemm") if path == "bf16" else 0.0
         mt.timing_reset()
         res[path] = {"ms_per_step": ms, "wall_s": wall, "gemm_ms": gemm_ms / max(gemm_n, 1),
                      "gemm_event_ms": gemm_ev_ms / max(gemm_ev_n, 1),
                      "gemm_launches": gemm_n, "gemm_flop": gemm_work / max(gemm_n, 1),
+                     "rerun_flop_per_step": rerun_work / steps,
                      "kernel_ms_per_step": kern, "C": holder["C"]}
         del ws
         log(f"[bench] {path}: {ms:.3f} ms/step, GEMM {gemm_ms / max(gemm_n, 1):.3f} ms on the device clock "
@@ -598,6 +605,9 @@ def main():
     rp_ms = trace_from_profile(TRACE_SUMMARY, GEMM_SRC, "mt_pfamily_gemm_bf16") if main_path == "bf16" else None
 
     value = ops / (bf["ms_per_step"] / 1e3)
+    # the planes of the two smallest p wait until some entry needs them
+    # (BF16 plain products the pilot steers, families of five or more p)
+    deferred = main_path == "bf16" and mt.deferred_planes() and len(P) >= 5
     out = {
         "metric": METRIC,
         "value": value,
@@ -632,7 +642,9 @@ def main():
             "frac_at_rocprof_avg": (flop / (rp_ms / 1e3) / 1e12 / peak) if rp_ms else None,
         },
         "kernel_ms_per_step": bf["kernel_ms_per_step"],
-        "hbm_kernels": hbm_kernels(bf["kernel_ms_per_step"], n, P, main_path),
+        "hbm_kernels": hbm_kernels(bf["kernel_ms_per_step"], n, P, main_path, deferred=deferred),
+        "deferred_planes": {"on": deferred, "rerun_flop_per_step": bf.get("rerun_flop_per_step", 0.0),
+                            "late_planes_ms_per_step": bf["kernel_ms_per_step"].get("mt_planes_if", 0.0)},
         "max_rel_err_vs_exact": errs,
         "exact_valu": {"rows": len(rows), "ms": exact_ms,
                        "ops_per_s": len(rows) * float(n) * n / (exact_ms / 1e3)},

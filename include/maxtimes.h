@@ -518,6 +518,27 @@ mt_status maxtimes_set_search_start(int32_t entry);
 int32_t maxtimes_search_start(void);
 
 /*
+ * Deferred planes (BF16 path, plain products whose search start the pilot
+ * chooses, families of at least five p).  Most products need no p below the
+ * third smallest: an entry that reaches the smallest two has no stable p
+ * above them, where Sec. 1 puts p* at the largest stable p.  With on = 1, the
+ * default, the power planes of the two smallest p are not written with the
+ * others.  They are written before the GEMM when the pilot's sampled entries
+ * include one that is unstable at every larger p; otherwise a GEMM tile or a
+ * sparse-tail entry that reaches them marks its tile, and after the GEMM the
+ * planes are written and the marked tiles run their whole search again,
+ * densely, without the sparse tail (three extra launches per product, which
+ * return at once when nothing is marked).  Results: the same selection rule on the
+ * same planes; a tile that ran again sums its entries on the MFMA instead of
+ * the tail kernel, which changes the order of the FP32 sums.  The workspace
+ * holds 4 bytes per output tile for the marks either way.  on = 0 writes
+ * every plane up front.  MT_ERR_INVALID_ARG for other values.  Process-wide;
+ * not synchronised with calls in flight on other threads.
+ */
+mt_status maxtimes_set_deferred_planes(int32_t on);
+int32_t maxtimes_deferred_planes(void);
+
+/*
  * Small products (Alg. 5 with the scaled call H' of Sec. 2.1, FP64 path):
  * maxtimes_estimate (and its _noalloc form) computes a product with
  * b * m * k * n <= max_work multiply-adds, options at most MT_FLAG_CLAMP and

@@ -123,6 +123,8 @@ def load_library():
         "maxtimes_tail_threshold": [],
         "maxtimes_set_search_start": [ctypes.c_int32],
         "maxtimes_search_start": [],
+        "maxtimes_set_deferred_planes": [ctypes.c_int32],
+        "maxtimes_deferred_planes": [],
         "maxtimes_set_small_product_limit": [i64],
         "maxtimes_small_product_limit": [],
     }
@@ -577,6 +579,18 @@ def set_search_start(entry):
 
 def search_start():
     return int(load_library().maxtimes_search_start())
+
+
+def set_deferred_planes(on):
+    """BF16 plain products steered by the pilot: write the power planes of
+    the two smallest p only once some entry needs them (True, the default),
+    running again the tiles that reached them first; False writes every plane
+    up front.  Process-wide."""
+    _check(load_library().maxtimes_set_deferred_planes(1 if on else 0))
+
+
+def deferred_planes():
+    return bool(load_library().maxtimes_deferred_planes())
 
 
 def set_small_product_limit(max_work):

@@ -217,6 +217,7 @@ PlaneSpec plane_spec(const Family& f) {
         pl += s.split[q] ? 2 : 1;
     }
     s.n_planes = pl;
+    s.write_mask = 0xFFFFFFFFu;
     return s;
 }
 
@@ -340,7 +341,7 @@ Geom product_geom(const Family& f, int64_t b, int64_t m, int64_t k, int64_t n) {
 }
 
 struct Layout {
-    size_t hdr, r, c, bal, ap, bp, s, s2, code, tail, tail_sorted, tail_bucket, pilot, x, total;
+    size_t hdr, r, c, bal, ap, bp, s, s2, code, tail, tail_sorted, tail_bucket, pilot, missed, x, total;
     int32_t tail_max;  // sparse-tail threshold the layout was sized for (0: no tail)
     int32_t tail_shift, tail_buckets;  // row buckets of the tail sort
 };
@@ -356,6 +357,9 @@ std::atomic<int64_t> g_small_limit{kSmallProductDefault};
 // Forward search start: a plan index, or kStartAuto (the pilot chooses).
 constexpr int32_t kStartAuto = -1;
 std::atomic<int32_t> g_start_entry{kStartAuto};
+
+// Deferred planes of the two smallest p on the BF16 path (on by default).
+std::atomic<int32_t> g_defer_planes{1};
 
 // The pilot runs for products of at least this many output entries (below,
 // its fixed cost is not worth it and the search starts at the largest p).
@@ -409,6 +413,9 @@ Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64
     off += f.n > 1 ? align_up((size_t)kPilotKParts * f.n * kMaxPilotSide * kMaxPilotSide * (f.bf16 ? 4 : 8)) +
                          align_up(sizeof(PilotCounts))
                    : 0;
+    // deferred planes: one word per output tile (BF16 path with the tail)
+    L.missed = off;
+    off += f.bf16 && L.tail_max > 0 ? align_up((size_t)tiles * 4) : 0;
     L.x = off;
     off += align_up(x_bytes);
     L.total = off;
@@ -500,19 +507,41 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     const bool bal = scale && (f.flags & MT_FLAG_BALANCE);
     const double* d = bal ? (const double*)(ws + L.bal + 2 * align_up((size_t)(b * k) * 8)) : nullptr;
     const double* dinv = bal ? (const double*)(ws + L.bal + 3 * align_up((size_t)(b * k) * 8)) : nullptr;
+    const FamilyPlan plan = family_plan(f, ps, k);
+    WsHeader* hdr = (WsHeader*)(ws + L.hdr);
+    // The pilot chooses where the search starts (below: products large
+    // enough, the tail on, no r = 1 projection).
+    const int32_t s0 = g_start_entry.load();
+    const bool pilot = !plan.r1 && s0 == kStartAuto && L.tail_max > 0 && f.n > 2 && k >= 256 &&
+                       b * m * n >= kPilotMinOutputs;
+    // Deferred planes (BF16 plain products the pilot steers): the planes of
+    // the two smallest p are written only once some entry needs them, which
+    // the pilot's sample tells before the GEMM, or a tile or tail entry that
+    // reaches them tells after it (those tiles then run again).
+    const bool defer = pilot && f.bf16 && mode == EPI_PLAIN && !(f.flags & MT_FLAG_PROJECT_R2) && plan.n >= 5 &&
+                       g_defer_planes.load() != 0;
+    const int32_t n_eval = defer ? plan.n - 2 : plan.n;
+    PlaneSpec ps_now = ps, ps_late = ps;
+    if (defer) {
+        uint32_t late = 0;
+        for (int q = 0; q < ps.n_p; ++q)
+            for (int e = n_eval; e < plan.n; ++e)
+                if (plan.e[e].a_plane[0] == ps.first_plane[q]) late |= 1u << q;
+        ps_now.write_mask = ~late;
+        ps_late.write_mask = late;
+    }
     if (fuse_rowmax) {
         // r and the planes of A in one pass, with c taken by the same launch
         // (neither maximum was taken before)
         MT_TRY(launch_rowmax_planes_colmax((const float*)A, (const float*)B, b, m, k, g.mp, g.kp, n, r, c,
-                                           (int32_t*)(ws + L.hdr), ps, f.bf16, ap, st),
+                                           (int32_t*)(ws + L.hdr), ps_now, f.bf16, ap, st),
                "row and column max, power planes (A)");
     } else {
-        MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps, f.bf16, ap, st, d),
+        MT_TRY(launch_power_planes(A, in_f64, 0, b, m, k, g.mp, g.kp, r, nullptr, ps_now, f.bf16, ap, st, d),
                "power planes (A)");
     }
-    MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, nullptr, ps, f.bf16, bp, st, dinv),
+    MT_TRY(launch_power_planes(B, in_f64, 1, b, n, k, g.np, g.kp, c, nullptr, ps_now, f.bf16, bp, st, dinv),
            "power planes (B)");
-    const FamilyPlan plan = family_plan(f, ps, k);
     EpiArgs epi;
     memset(&epi, 0, sizeof epi);
     epi.r = r;
@@ -533,9 +562,7 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
         return MT_OK;
     }
     if (!plan.r1) {
-        WsHeader* hdr = (WsHeader*)(ws + L.hdr);
-        const int32_t s0 = g_start_entry.load();
-        if (s0 == kStartAuto && L.tail_max > 0 && f.n > 2 && k >= 256 && b * m * n >= kPilotMinOutputs) {
+        if (pilot) {
             PilotArgs pa;
             memset(&pa, 0, sizeof pa);
             pa.X = ap;
@@ -559,7 +586,14 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
             pa.kappa = 1.0f / 250.0f;
             pa.part = ws + L.pilot;
             pa.counts = ws + L.pilot + align_up((size_t)kPilotKParts * f.n * kMaxPilotSide * kMaxPilotSide * (f.bf16 ? 4 : 8));
+            pa.n_eval = n_eval;
+            pa.low_need = defer ? &hdr->low_need : nullptr;
+            pa.low_missed = defer ? &hdr->low_missed : nullptr;
             MT_TRY(launch_choose_start(pa, plan, &hdr->start, f.bf16 ? 0 : 1, st), "p search start (pilot)");
+            if (defer)
+                MT_TRY(launch_planes_if(&hdr->low_need, A, B, in_f64, b, m, n, k, g.mp, g.np, g.kp, r, c, d, dinv,
+                                        ps_late, ap, bp, st),
+                       "deferred planes (the pilot's sample needs them)");
         } else {
             const int32_t s1 = s0 < 0 ? 0 : (s0 < f.n ? s0 : f.n - 1);
             MT_TRY(launch_fill_u32(&hdr->start, (uint32_t)s1, 1, st), "p search start");
@@ -567,7 +601,6 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
         epi.start = &hdr->start;
     }
     if (L.tail_max > 0 && k > 0) {
-        WsHeader* hdr = (WsHeader*)(ws + L.hdr);
         MT_TRY(launch_fill_zero_u32(&hdr->tail_count, 1, st), "clear tail count");
         epi.tail = (TailEntry*)(ws + L.tail);
         epi.tail_count = &hdr->tail_count;
@@ -583,9 +616,26 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
         epi.out = out;
         epi.out_f64 = out_f64;
         epi.pstar = pstar;
+        if (defer) {
+            epi.low_need = &hdr->low_need;
+            epi.low_missed = &hdr->low_missed;
+            epi.missed_tile = (uint32_t*)(ws + L.missed);
+            epi.n_eval = n_eval;
+        }
         MT_TRY(launch_pfamily_gemm_bf16((const uint16_t*)ap, (const uint16_t*)bp, b, m, n, g.mp, g.np,
                                         g.kp, ps.n_planes, plan, epi, st),
                "p-family GEMM (BF16)");
+        if (defer) {
+            // tiles or tail entries that reached the deferred planes: write
+            // them, then run those tiles again (each launch returns at once
+            // when nothing was missed)
+            MT_TRY(launch_planes_if(&hdr->low_missed, A, B, in_f64, b, m, n, k, g.mp, g.np, g.kp, r, c, d, dinv,
+                                    ps_late, ap, bp, st),
+                   "deferred planes (after a miss)");
+            MT_TRY(launch_rerun_gemm_bf16((const uint16_t*)ap, (const uint16_t*)bp, b, m, n, g.mp, g.np, g.kp,
+                                          ps.n_planes, plan, epi, st),
+                   "p-family GEMM (BF16, tiles run again)");
+        }
     } else {
         epi.mode = EPI_PLAIN;
         epi.out = ws + L.s;
@@ -970,6 +1020,7 @@ mt_status maxtimes_estimate_backward(const void* A, const void* B, const void* G
         ps.first_plane[q] = f.bf16 ? 2 * q : q;
     }
     ps.n_planes = f.bf16 ? 2 * f.n : f.n;
+    ps.write_mask = 0xFFFFFFFFu;
     FamilyPlan plan;
     memset(&plan, 0, sizeof plan);
     plan.n = f.n;
@@ -1337,6 +1388,15 @@ mt_status maxtimes_set_search_start(int32_t entry) {
 
 int32_t maxtimes_search_start(void) { return g_start_entry.load(); }
 
+mt_status maxtimes_set_deferred_planes(int32_t on) {
+    g_last_error.clear();
+    if (on != 0 && on != 1) return fail(MT_ERR_INVALID_ARG, "deferred planes switch %d is not 0 or 1", on);
+    g_defer_planes.store(on);
+    return MT_OK;
+}
+
+int32_t maxtimes_deferred_planes(void) { return g_defer_planes.load(); }
+
 mt_status maxtimes_set_small_product_limit(int64_t max_work) {
     g_last_error.clear();
     if (max_work < 0) return fail(MT_ERR_INVALID_ARG, "small-product limit %lld is negative", (long long)max_work);
@@ -1353,6 +1413,17 @@ mt_status maxtimes_timing_enable(int on) {
         hipEvent_t e = nullptr;
         if (hipEventCreate(&e) != hipSuccess) break;
         g_event_pool.push_back(e);
+    }
+    if (g_timing && !g_work) {
+        // the timing slots' address and their first clearing (a synchronous
+        // copy) here, not inside the first timed launch that counts work,
+        // whose pair of events would otherwise hold that copy and the wait
+        // for everything queued before it
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(timing_work_counters)) == hipSuccess) {
+            g_work = (unsigned long long*)p;
+            if (clear_work_slots(kWorkSlots) != hipSuccess) g_work = nullptr;
+        }
     }
     return MT_OK;
 }

@@ -264,6 +264,9 @@ __device__ __forceinline__ void write_power_chunk(const TC (&x)[8], const PlaneS
             for (int i = 0; i < 8; ++i) pw[i] = ipow(x[i], p);
         }
         prev = p;
+        // powers whose planes are not wanted are still formed: the next
+        // power may square them
+        if (!((spec.write_mask >> q) & 1u)) continue;
         const int64_t pl = spec.first_plane[q];
         const int64_t off = (bi * spec.n_planes + pl) * plane_elems + pos;
         if (kBf16) {
@@ -308,16 +311,19 @@ struct PlaneTile {
     static_assert(TASKS % kThreads == 0, "whole tasks per thread");
 };
 
+// The workgroup of plane tile (bx, by) of batch item bz.
 template <typename TS, bool kBf16, bool kTranspose>
-__global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
-    const TS* __restrict__ src, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
-    const double* __restrict__ scale_rows, const double* __restrict__ scale_cols,
-    const double* __restrict__ col_mul, PlaneSpec spec, void* __restrict__ planes) {
+__device__ __forceinline__ void power_planes_block(const TS* __restrict__ src, int64_t rows, int64_t cols,
+                                                   int64_t rows_pad, int64_t cols_pad,
+                                                   const double* __restrict__ scale_rows,
+                                                   const double* __restrict__ scale_cols,
+                                                   const double* __restrict__ col_mul, const PlaneSpec& spec,
+                                                   void* __restrict__ planes, int64_t bx, int64_t by, int64_t bz) {
     using PT = PlaneTile<TS, kTranspose>;
     __shared__ TS tile[kTranspose ? PT::T : 1][kTranspose ? PT::U + 1 : 1];
-    const int64_t bi = blockIdx.z;
-    const int64_t t0 = (int64_t)blockIdx.y * PT::T;  // plane row
-    const int64_t u0 = (int64_t)blockIdx.x * PT::U;  // plane column
+    const int64_t bi = bz;
+    const int64_t t0 = by * PT::T;  // plane row
+    const int64_t u0 = bx * PT::U;  // plane column
     const TS* s = src + bi * rows * cols;
 
     if (kTranspose) {
@@ -388,6 +394,46 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
             }
         }
         write_power_chunk<TC, kBf16>(x, spec, planes, bi, plane_elems, t * cols_pad + u);
+    }
+}
+
+template <typename TS, bool kBf16, bool kTranspose>
+__global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
+    const TS* __restrict__ src, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
+    const double* __restrict__ scale_rows, const double* __restrict__ scale_cols,
+    const double* __restrict__ col_mul, PlaneSpec spec, void* __restrict__ planes) {
+    power_planes_block<TS, kBf16, kTranspose>(src, rows, cols, rows_pad, cols_pad, scale_rows, scale_cols,
+                                              col_mul, spec, planes, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Both operands' planes of spec.write_mask (BF16), only when *cond is set: A's
+// untransposed plane tiles first, then B's transposed ones, a fixed grid
+// striding over them.
+struct PlanesIfOperand {
+    const void* src;
+    int64_t rows, cols, rows_pad, cols_pad;
+    const double* scale_rows;
+    const double* col_mul;
+    void* planes;
+    int64_t gx, gy, blocks;  // plane tiles along columns, along rows, in all
+};
+template <typename TS>
+__global__ __launch_bounds__(kThreads) void mt_planes_if_kernel(const int32_t* __restrict__ cond, PlanesIfOperand a,
+                                                                PlanesIfOperand b, PlaneSpec spec) {
+    if (*cond == 0) return;
+    for (int64_t v = blockIdx.x; v < a.blocks + b.blocks; v += gridDim.x) {
+        if (v < a.blocks) {
+            power_planes_block<TS, true, false>((const TS*)a.src, a.rows, a.cols, a.rows_pad, a.cols_pad,
+                                                a.scale_rows, nullptr, a.col_mul, spec, a.planes, v % a.gx,
+                                                (v / a.gx) % a.gy, v / (a.gx * a.gy));
+        } else {
+            const int64_t w = v - a.blocks;
+            power_planes_block<TS, true, true>((const TS*)b.src, b.rows, b.cols, b.rows_pad, b.cols_pad,
+                                               b.scale_rows, nullptr, b.col_mul, spec, b.planes, w % b.gx,
+                                               (w / b.gx) % b.gy, w / (b.gx * b.gy));
+        }
+        // the transposed tile in LDS is refilled by the next iteration
+        __syncthreads();
     }
 }
 
@@ -771,6 +817,48 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
         }
     }
 #undef MT_PLANES
+    timing_after(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_planes_if(const int32_t* cond, const void* A, const void* B, int src_f64, int64_t b, int64_t m,
+                            int64_t n, int64_t k, int64_t mp, int64_t np, int64_t kp, const double* r,
+                            const double* c, const double* a_mul, const double* b_mul, const PlaneSpec& spec,
+                            void* a_planes, void* b_planes, hipStream_t st) {
+    if (b <= 0 || mp <= 0 || np <= 0 || kp <= 0) return hipSuccess;
+    auto operand = [&](const void* src, int64_t rows, int64_t rows_pad, const double* sc, const double* mul,
+                       void* planes, int64_t tile_t, int64_t tile_u) {
+        PlanesIfOperand o;
+        o.src = src;
+        o.rows = rows;
+        o.cols = k;
+        o.rows_pad = rows_pad;
+        o.cols_pad = kp;
+        o.scale_rows = sc;
+        o.col_mul = mul;
+        o.planes = planes;
+        o.gx = (kp + tile_u - 1) / tile_u;
+        o.gy = (rows_pad + tile_t - 1) / tile_t;
+        o.blocks = o.gx * o.gy * b;
+        return o;
+    };
+    timing_before("mt_planes_if", st);
+    // an idle launch (cond clear) costs one short wave per workgroup: a
+    // fixed grid of a few workgroups per CU, striding when the planes are due
+    auto launch = [&](auto tag) {
+        using TS = decltype(tag);
+        const PlanesIfOperand oa =
+            operand(A, m, mp, r, a_mul, a_planes, PlaneTile<TS, false>::T, PlaneTile<TS, false>::U);
+        const PlanesIfOperand ob =
+            operand(B, n, np, c, b_mul, b_planes, PlaneTile<TS, true>::T, PlaneTile<TS, true>::U);
+        const int64_t total = oa.blocks + ob.blocks;
+        hipLaunchKernelGGL(mt_planes_if_kernel<TS>, dim3((unsigned)(total < 2048 ? total : 2048)), dim3(kThreads),
+                           0, st, cond, oa, ob, spec);
+    };
+    if (src_f64)
+        launch(double{});
+    else
+        launch(float{});
     timing_after(st);
     return hipGetLastError();
 }

@@ -122,7 +122,7 @@ struct TileCtx {
 };
 
 // ------------------------------------------------------------ selection epilogue
-template <class C, int MODE, typename TO, bool R1>
+template <class C, int MODE, typename TO, bool R1, bool RERUN = false>
 struct SelectEpi {
     static constexpr int WT_M = C::WT_M, WT_N = C::WT_N;
     static constexpr int NDEC = (WT_M * WT_N * 16 + 31) / 32;
@@ -145,6 +145,7 @@ struct SelectEpi {
     int lr0, lc0;
     int64_t out_lane;
     int32_t rows_left, cols_left, diag_off;
+    int32_t n_eval;  // plan entries whose planes this launch may read
 
     // Row offset, from this lane's first row lr0, of accumulator element q
     // of sub-tile row i (the 32 x 32 MFMA layout: element q of lane l is row
@@ -154,6 +155,16 @@ struct SelectEpi {
     static constexpr bool kAllActive = true;
     static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
+    // Deferred planes: plan entry e's planes are not written (yet).  The
+    // rerun launch runs only the tiles marked for it, with every plane
+    // written, densely to the end.
+    __device__ bool deferred(int e) const { return e >= n_eval; }
+    static __device__ bool skip_tile(const Args& a, int64_t tile) { return RERUN && a.missed_tile[tile] == 0u; }
+    __device__ void record_tile(int64_t tile, bool missed) const {
+        if (RERUN || a.missed_tile == nullptr) return;
+        a.missed_tile[tile] = missed ? 1u : 0u;
+        if (missed) *a.low_missed = 1;
+    }
 
     // Entries of this lane without a final output yet: `open` ones have no
     // stable p so far; `parked` ones are stable at the p the search started
@@ -177,7 +188,7 @@ struct SelectEpi {
         }
     }
     __device__ int32_t start_index() const { return (!R1 && a.start) ? *a.start : 0; }
-    __device__ bool can_hand_over(int total) const { return a.tail != nullptr && total <= a.tail_max; }
+    __device__ bool can_hand_over(int total) const { return !RERUN && a.tail != nullptr && total <= a.tail_max; }
     __device__ uint32_t* tail_counter() const { return a.tail_count; }
     // Write this lane's undecided entries to the sparse-tail list from `pos`
     // on, after plan entry e of a search that started at plan entry s.
@@ -212,6 +223,8 @@ struct SelectEpi {
     __device__ void setup(const TileCtx& t, const GemmGeom& g, uint8_t* lds, int tid) {
         m = g.rows;
         n = g.cols;
+        n_eval = MT_MAX_P;
+        if (!RERUN && a.low_need != nullptr && __builtin_amdgcn_readfirstlane(*a.low_need) == 0) n_eval = a.n_eval;
         rsc = (int2*)lds;
         csc = rsc + C::BM;
         // Row / column scales of this tile (1 where absent or padding).
@@ -508,6 +521,9 @@ struct AdjointEpi {
     static constexpr bool kAllActive = false;
     static constexpr bool kCanStop = false;
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
+    __device__ bool deferred(int) const { return false; }
+    static __device__ bool skip_tile(const Args&, int64_t) { return false; }
+    __device__ void record_tile(int64_t, bool) const {}
     __device__ void counts(int& open, int& parked) const { open = parked = 0; }
     __device__ int32_t start_index() const { return 0; }
     __device__ bool can_hand_over(int) const { return false; }
@@ -684,6 +700,8 @@ __global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kern
     const int tn = in_g / gsz;
     t.row0 = (int64_t)tm * C::BM;
     t.col0 = (int64_t)tn * C::BN;
+    const int64_t tile_id = (int64_t)t.bi * per_batch + (int64_t)tm * g.tiles_n + tn;
+    if (Epi::skip_tile(args, tile_id)) return;
 
     Epi epi;
     epi.a = args;
@@ -805,8 +823,16 @@ __global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kern
 
     int buf = 0;
     int64_t kunits = 0;  // executed MFMA work in units of BM x BN x 1 products
+    bool missed = false;
     for (int ai = 0; ai < nact; ++ai) {
         const int e = entry_of(ai);
+        // a p whose planes are deferred and not written: the tile runs again
+        // once they are (no load is in flight here; the prefetched step of
+        // this entry is unused)
+        if (epi.deferred(e)) {
+            missed = true;
+            break;
+        }
         f32x16 acc[WT_M][WT_N];
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
@@ -969,6 +995,7 @@ __global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kern
         }
     }
     epi.finish(t);
+    if (tid == 0) epi.record_tile(tile_id, missed);
     if (g.work) {
         // timed launch: the work, and the end once every wave is done
         __syncthreads();
@@ -1071,6 +1098,10 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
     const int64_t w1 = min<int64_t>(w0 + run, (int64_t)count);
     TO* out = (TO*)a.out;
     const float tau_f = plan.tau_f;
+    // deferred planes not written: an entry that reaches them marks its tile
+    // for the rerun launch instead
+    int n_eval = MT_MAX_P;
+    if (a.low_need != nullptr && __builtin_amdgcn_readfirstlane(*a.low_need) == 0) n_eval = a.n_eval;
     for (int64_t w = w0; w < w1;) {
         TailEntry te[G];
         te[0] = a.tail_sorted[w];
@@ -1162,6 +1193,17 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
                     any_act |= act[q];
                 }
                 if (!any_live) break;
+                if (e >= n_eval) {
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+                        if (live[q] && lane == 0) {
+                            const int64_t tile = ((int64_t)te[q].bi * g.tiles_m + te[q].i / kBf16BM) * g.tiles_n +
+                                                 te[q].j / kBf16BN;
+                            a.missed_tile[tile] = 1u;
+                            *a.low_missed = 1;
+                        }
+                    break;
+                }
                 if (!any_act) continue;
                 const PlanEntry& pe = plan.e[e];
                 tail_dot_group_bf16<G>(xr, yr, act, pe, g, lane, S);
@@ -1280,9 +1322,28 @@ hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int6
     if (epi.mode == EPI_APSP_X) {
         if (epi.out_f64) MT_SEL2(EPI_APSP_X, double) else MT_SEL2(EPI_APSP_X, float)
     }
+    if (epi.low_need != nullptr) {
+        // deferred planes (plain products, no r = 1 projection)
+        if (plan.r1 || epi.mode != EPI_PLAIN || !epi.tail) return hipErrorInvalidValue;
+        if (epi.out_f64) MT_SEL(EPI_PLAIN, double, false) else MT_SEL(EPI_PLAIN, float, false)
+    }
     if (epi.out_f64) MT_SEL2(EPI_PLAIN, double) else MT_SEL2(EPI_PLAIN, float)
 #undef MT_SEL2
 #undef MT_SEL
+}
+
+hipError_t launch_rerun_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m, int64_t n,
+                                  int64_t mp, int64_t np, int64_t kp, int32_t n_planes, const FamilyPlan& plan,
+                                  const EpiArgs& epi, hipStream_t st) {
+    if (epi.missed_tile == nullptr || plan.r1 || epi.mode != EPI_PLAIN) return hipErrorInvalidValue;
+    const GemmGeom g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, kBf16BM, kBf16BN);
+    // a launch of its own name: the forward GEMM's timing and work stay apart
+    // (a tile that is not marked adds no work and ends no span)
+    if (epi.out_f64)
+        return launch_gemm<FwdCfg, SelectEpi<FwdCfg, EPI_PLAIN, double, false, true>>(g, b, plan, epi,
+                                                                                      "mt_rerun_gemm_bf16", st);
+    return launch_gemm<FwdCfg, SelectEpi<FwdCfg, EPI_PLAIN, float, false, true>>(g, b, plan, epi,
+                                                                                "mt_rerun_gemm_bf16", st);
 }
 
 hipError_t launch_adjoint_gemm_bf16(const uint16_t* Xp, const uint16_t* Yp, int64_t b, int64_t rows,

@@ -35,7 +35,9 @@ struct WsHeader {
     int32_t domain_flag;
     uint32_t tail_count;
     int32_t start;       // plan index the forward's p search starts at
-    int32_t pad[5];
+    int32_t low_missed;  // deferred planes: some tile or tail entry reached them unwritten
+    int32_t low_need;    // deferred planes: the pilot saw sampled entries that need them
+    int32_t pad[3];
     int32_t hist[MT_MAX_P + 1];
 };
 
@@ -110,6 +112,16 @@ struct EpiArgs {
     int32_t tail_shift;
     int32_t tail_buckets;
     int64_t stack_stride;  // EPI_STORE_ALL: elements per plane of the S stack (b m n)
+    // Deferred planes (BF16 forward): the planes of plan entries n_eval and
+    // below are written only when *low_need is set before the GEMM.  Without
+    // them a tile that reaches such an entry, or a tail entry that does,
+    // stops, marks its tile in missed_tile and sets *low_missed; the planes
+    // are then written and the marked tiles run again from the start, densely
+    // (the rerun launch).  low_need null: every plane is written.
+    const int32_t* low_need;
+    int32_t* low_missed;
+    uint32_t* missed_tile;  // b x tiles_m x tiles_n: 1 where the tile must run again
+    int32_t n_eval;         // plan entries whose planes are always written
 };
 constexpr int64_t kTailBuckets = 65536;
 
@@ -155,6 +167,12 @@ struct PilotArgs {
     float kappa;           // one tail dot product in dense tile-entry units
     void* part;            // kparts x n x kMaxPilotSide^2 partial sums (float or double)
     void* counts;          // PilotCounts
+    // plan entries whose planes exist (n: all); the sampled entries with no
+    // stable p among them set *low_need (nullable; *low_missed is cleared
+    // with it) and count as undecided to the last entry
+    int32_t n_eval;
+    int32_t* low_need;
+    int32_t* low_missed;
 };
 // Counts over the sampled entries: es_hist[e] of e* = e (the first stable
 // plan entry, the last if none); stop[s][u]: waiting at start s and decided
@@ -208,6 +226,7 @@ struct PlaneSpec {
     int32_t split[MT_MAX_P];
     int32_t first_plane[MT_MAX_P];  // plane index of power q (hi plane if split)
     int32_t n_planes;
+    uint32_t write_mask;            // bit q: the planes of power q are written
 };
 // Row maxima r of a row-major FP32 operand A (b x rows x cols) and its power
 // planes in one pass, the same values as launch_rowmax followed by
@@ -226,11 +245,24 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
                                const double* scale_rows, const double* scale_cols,
                                const PlaneSpec& spec, int bf16, void* planes, hipStream_t st,
                                const double* col_mul = nullptr);
+// The planes of spec.write_mask for both operands in one launch (A untransposed
+// as launch_power_planes with transpose 0, B transposed as with transpose 1),
+// only when *cond is nonzero on the device (else every workgroup returns at
+// once): the deferred planes, written once some entry needs them.
+hipError_t launch_planes_if(const int32_t* cond, const void* A, const void* B, int src_f64, int64_t b, int64_t m,
+                            int64_t n, int64_t k, int64_t mp, int64_t np, int64_t kp, const double* r,
+                            const double* c, const double* a_mul, const double* b_mul, const PlaneSpec& spec,
+                            void* a_planes, void* b_planes, hipStream_t st);
 
 // Fused p-family GEMM + selection epilogue.
 hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m,
                                     int64_t n, int64_t mp, int64_t np, int64_t kp, int32_t n_planes,
                                     const FamilyPlan& plan, const EpiArgs& epi, hipStream_t st);
+// The rerun launch of deferred planes: the tiles marked in epi.missed_tile
+// again from the start, every plane written, without the sparse tail.
+hipError_t launch_rerun_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m, int64_t n,
+                                  int64_t mp, int64_t np, int64_t kp, int32_t n_planes, const FamilyPlan& plan,
+                                  const EpiArgs& epi, hipStream_t st);
 hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b, int64_t m,
                                    int64_t n, int64_t mp, int64_t np, int64_t kp, int32_t n_planes,
                                    int bm, const FamilyPlan& plan, const EpiArgs& epi,

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kPilotThreads) void pilot_count_kernel(PilotArgs pa
 #pragma unroll
     for (int e = MT_MAX_P - 1; e >= 0; --e) {
         T v = 0;
-        if (e < n && in) {
+        if (e < pa.n_eval && in) {
             T pv[kMaxPilotKParts];
 #pragma unroll
             for (int kp = 0; kp < kMaxPilotKParts; ++kp)
@@ -378,12 +378,21 @@ __global__ __launch_bounds__(64) void pilot_choose_kernel(PilotArgs pa, FamilyPl
     if (s == 0) {
         int best = 0;
         float best_cost = cost[0];
-        for (int x = 1; x < n; ++x)
+        // a start on deferred planes is not an option
+        for (int x = 1; x < pa.n_eval; ++x)
             if (cost[x] < best_cost * 0.98f) {  // a start further down must save at least 2 %
                 best_cost = cost[x];
                 best = x;
             }
         *start = best;
+        if (pa.low_need != nullptr) {
+            // sampled entries with no stable p among the evaluated plan
+            // entries (e* counted at the last entry) need the deferred planes
+            int need = 0;
+            for (int e = pa.n_eval; e < n; ++e) need |= sc.es_hist[e];
+            *pa.low_need = need != 0 ? 1 : 0;
+            *pa.low_missed = 0;
+        }
     }
 }
 
@@ -391,10 +400,19 @@ __global__ __launch_bounds__(64) void pilot_choose_kernel(PilotArgs pa, FamilyPl
 
 hipError_t launch_choose_start(const PilotArgs& pa, const FamilyPlan& plan, int32_t* start, int f64,
                                hipStream_t st) {
-    if (plan.n < 2 || pa.nr <= 0 || pa.nc <= 0) return launch_fill_u32(start, 0u, 1, st);
+    if (plan.n < 2 || pa.nr <= 0 || pa.nc <= 0) {
+        // no pilot: the search starts at the largest p, every plane is due
+        if (pa.low_need != nullptr) {
+            hipError_t e = launch_fill_u32(pa.low_need, 1u, 1, st);
+            if (e == hipSuccess) e = launch_fill_zero_u32(pa.low_missed, 1, st);
+            if (e != hipSuccess) return e;
+        }
+        return launch_fill_u32(start, 0u, 1, st);
+    }
     hipError_t e = launch_fill_zero_u32(pa.counts, sizeof(PilotCounts) / 4, st);
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)((pa.nr + kPilotRows - 1) / kPilotRows), (unsigned)plan.n, (unsigned)pa.kparts);
+    if (pa.n_eval < 1 || pa.n_eval > plan.n) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((pa.nr + kPilotRows - 1) / kPilotRows), (unsigned)pa.n_eval, (unsigned)pa.kparts);
     const dim3 cgrid((unsigned)((pa.nr * pa.nc + kPilotThreads - 1) / kPilotThreads));
     timing_before("mt_pilot", st);
     if (f64) {
@@ -402,7 +420,7 @@ hipError_t launch_choose_start(const PilotArgs& pa, const FamilyPlan& plan, int3
         hipLaunchKernelGGL(pilot_count_kernel<true>, cgrid, dim3(kPilotThreads), 0, st, pa, plan);
         hipLaunchKernelGGL(pilot_choose_kernel<true>, dim3(1), dim3(64), 0, st, pa, plan, start);
     } else {
-        hipLaunchKernelGGL(pilot_mfma_bf16_kernel, dim3(4, (unsigned)plan.n, (unsigned)pa.kparts), dim3(64), 0, st, pa, plan);
+        hipLaunchKernelGGL(pilot_mfma_bf16_kernel, dim3(4, (unsigned)pa.n_eval, (unsigned)pa.kparts), dim3(64), 0, st, pa, plan);
         hipLaunchKernelGGL(pilot_count_kernel<false>, cgrid, dim3(kPilotThreads), 0, st, pa, plan);
         hipLaunchKernelGGL(pilot_choose_kernel<false>, dim3(1), dim3(64), 0, st, pa, plan, start);
     }
