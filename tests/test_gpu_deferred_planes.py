@@ -16,13 +16,15 @@ Checks, on 2048 x 512 x 2048 products (large enough for the pilot, whose
   and rows whose every term is about 1e-10 after scaling, p* = 2): tiles
   reach them in the GEMM (three such rows in a tile, 768 undecided entries,
   more than the tail takes) and in the tail (one such row); those tiles run
-  again and every row of them matches the oracle, and the other tiles are
-  bit-equal to the all-planes run;
+  again, the special rows and other rows of them match the oracle, and the
+  other tiles are bit-equal to the all-planes run;
 * every row needs them: the pilot sees it, the planes are written before
   the GEMM and no tile runs again;
 * the same rare rows with inner-index balancing (which lifts most entries
   of the crossed rows to p* = 4, leaving some at 2) and with FP64 inputs
-  (the late planes take the balancing factors and the FP64 reader)."""
+  (the late planes take the balancing factors and the FP64 reader);
+* two batch items of a ragged product, only the second with such rows: the
+  marks index the batch item and partial tiles."""
 
 import numpy as np
 import pytest
@@ -147,3 +149,37 @@ def test_every_row_needs_late_planes(knobs):
     rows = np.arange(3, M, 173)
     ref = oracle.pnorm_estimate_rows(A, B, P128, TAU["bf16"], rows)
     compare_estimate(C1[rows], p1[rows], ref, P128, "bf16")
+
+
+def test_rare_rows_batched_ragged(knobs):
+    """Two batch items of a ragged 2000 x 520 x 2100 product (partial tiles,
+    a padded inner length): only the second has rows that need the late
+    planes, so only its tiles with them run again; the tile marks index the
+    batch item."""
+    m, k, n = 2000, 520, 2100
+    sampled = set(((2 * np.arange(64) + 1) * m) // 128)
+    A0, B0 = lognormal_product(m, k, n, seed=4301)
+    A1, B1 = lognormal_product(m, k, n, seed=4302)
+    h = k // 2
+    B1[:h, :] *= 1e-10
+    crossed, zero = (700, 1990), (1010, 1011, 1012)
+    for i in crossed:
+        A1[i, h:] *= 1e-12
+    for i in zero:
+        A1[i, :] = 0
+    assert not (set(crossed) | set(zero)) & sampled
+    A, B = np.stack([A0, A1]), np.stack([B0, B1])
+    print("[deferred] batched ragged rare rows", flush=True)
+    C1, p1, w1 = _run(knobs, A, B, True)
+    C0, p0, w0 = _run(knobs, A, B, False)
+    assert w0 == 0.0 and w1 > 0.0
+    special = np.zeros((2, m), dtype=bool)
+    for i in crossed + zero:
+        special[1, (i // 256) * 256:(i // 256 + 1) * 256] = True
+    np.testing.assert_array_equal(p1[~special], p0[~special])
+    np.testing.assert_array_equal(C1[~special].view(np.uint32), C0[~special].view(np.uint32))
+    for bi, rows in ((0, [3, 1000, 1999]), (1, sorted(crossed + zero + (699, 1013, 1500)))):
+        rows = np.array(rows)
+        ref = oracle.pnorm_estimate_rows(A[bi], B[bi], P128, TAU["bf16"], rows)
+        compare_estimate(C1[bi][rows], p1[bi][rows], ref, P128, "bf16")
+    assert (C1[1][list(zero)] == 0).all()
