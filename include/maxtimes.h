@@ -487,7 +487,10 @@ mt_status maxtimes_timing_span(const char* prefix, double* total_ms, int64_t* la
  * to a second kernel that runs the remaining p for each of them alone (one
  * dot product of a plane row of A'^p and of B'^p per p, FP32 accumulation on
  * the BF16 path, FP64 on the FP64 path) and stops.  Results equal the dense
- * path's up to the order of the FP32 / FP64 summation.  0 disables it; the
+ * path's up to the order of the FP32 / FP64 summation; on the BF16 path an
+ * entry that goes up from p to 2p (both without the hi/lo split) takes S_2p
+ * from the same dot product, each term squared, so its 2p terms are rounded
+ * as squares of BF16 p-th powers instead of BF16 2p-th powers.  0 disables it; the
  * default is 512.  The workspace sizes grow by 32 bytes x max_entries per
  * output tile (the list and its copy sorted by row), so query them after
  * changing the threshold (a workspace sized before is reported too small).  Process-wide; not synchronised with calls

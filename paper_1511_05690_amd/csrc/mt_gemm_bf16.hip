@@ -1019,12 +1019,15 @@ __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w 
 // S_p of up to G entries of one row at once (act: which take part): each
 // chunk of the row's X plane is loaded once for all of them.  Lane l sums the
 // 8-element chunks l, l + 64, ... in order, as tail_dot_bf16 does.
-template <int G>
+// SQ (an unsplit p only): S2 gets the sum of the squared terms, S_2p formed
+// from the planes of p, for an entry that rises from p to 2p.
+template <int G, bool SQ = false>
 __device__ void tail_dot_group_bf16(const uint16_t* xr, const uint16_t* const (&yr)[G], const bool (&act)[G],
-                                    const PlanEntry& pe, const GemmGeom& g, int lane, float (&S)[G]) {
-    float acc[G];
+                                    const PlanEntry& pe, const GemmGeom& g, int lane, float (&S)[G],
+                                    float (&S2)[G]) {
+    float acc[G], acc2[G];
 #pragma unroll
-    for (int q = 0; q < G; ++q) acc[q] = 0.f;
+    for (int q = 0; q < G; ++q) acc[q] = acc2[q] = 0.f;
     if (pe.nseg == 3) {
         const uint16_t* xh = xr + (int64_t)pe.a_plane[0] * g.x_plane_elems;
         const uint16_t* xl = xr + (int64_t)pe.a_plane[2] * g.x_plane_elems;
@@ -1067,8 +1070,17 @@ __device__ void tail_dot_group_bf16(const uint16_t* xr, const uint16_t* const (&
                 if (act[q]) {
 #pragma unroll
                     for (int h = 0; h < 4; ++h) {
-                        acc[q] += bf16_lo(vx[h]) * bf16_lo(vy[q][h]);
-                        acc[q] += bf16_hi(vx[h]) * bf16_hi(vy[q][h]);
+                        const float x0 = bf16_lo(vx[h]), y0 = bf16_lo(vy[q][h]);
+                        const float x1 = bf16_hi(vx[h]), y1 = bf16_hi(vy[q][h]);
+                        acc[q] = __builtin_fmaf(x0, y0, acc[q]);
+                        acc[q] = __builtin_fmaf(x1, y1, acc[q]);
+                        if (SQ) {
+                            // the term of the doubled power: the square of
+                            // this term (a BF16 x BF16 product is exact in FP32)
+                            const float t0 = x0 * y0, t1 = x1 * y1;
+                            acc2[q] = __builtin_fmaf(t0, t0, acc2[q]);
+                            acc2[q] = __builtin_fmaf(t1, t1, acc2[q]);
+                        }
                     }
                 }
         }
@@ -1078,6 +1090,11 @@ __device__ void tail_dot_group_bf16(const uint16_t* xr, const uint16_t* const (&
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) acc[q] += __shfl_xor(acc[q], d);
         S[q] = acc[q];
+        if (SQ) {
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) acc2[q] += __shfl_xor(acc2[q], d);
+            S2[q] = acc2[q];
+        }
     }
 }
 
@@ -1140,30 +1157,58 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
         };
         if (!R1 && state == kTailRise) {
             // stable at e_next + 1 (S parked): go up while a larger p may be
-            // stable too
+            // stable too.  Where the next larger p doubles this one (both
+            // unsplit), its S comes from the same plane rows, each term
+            // squared: one pass decides both, and the planes of the larger p
+            // are not read.  nxt: the plan entry each entry runs next.
             int e = e_first[0];
+            int nxt[G];
 #pragma unroll
-            for (int q = 1; q < G; ++q)
+            for (int q = 0; q < G; ++q) {
+                nxt[q] = e_first[q];
                 if (live[q] && e_first[q] > e) e = e_first[q];
+            }
             for (; e >= 0; --e) {
                 bool any_live = false, any_act = false;
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
-                    act[q] = live[q] && e <= e_first[q];
+                    act[q] = live[q] && e == nxt[q];
                     any_live |= live[q];
                     any_act |= act[q];
                 }
                 if (!any_live) break;
                 if (!any_act) continue;
                 const PlanEntry& pe = plan.e[e];
-                tail_dot_group_bf16<G>(xr, yr, act, pe, g, lane, S);
+                const bool paired = e > 0 && pe.nseg == 1 && plan.e[e - 1].nseg == 1 && plan.e[e - 1].p == 2 * pe.p;
+                float S2[G];
+                if (paired)
+                    tail_dot_group_bf16<G, true>(xr, yr, act, pe, g, lane, S, S2);
+                else
+                    tail_dot_group_bf16<G, false>(xr, yr, act, pe, g, lane, S, S2);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
                     if (!act[q]) continue;
                     const bool stable = S[q] >= tau_f;
                     if (stable && lane == 0 && a.pstar) a.pstar[o[q]] = (uint8_t)pe.pidx;
                     if (stable && e > 0 && S[q] >= pe.rise_thr_f) {
-                        Sh[q] = S[q];
+                        if (!paired) {
+                            Sh[q] = S[q];
+                            nxt[q] = e - 1;
+                            continue;
+                        }
+                        // the doubled p, plan entry e - 1, from the squared terms
+                        const PlanEntry& pu = plan.e[e - 1];
+                        const bool stable_u = S2[q] >= tau_f;
+                        if (stable_u && lane == 0 && a.pstar) a.pstar[o[q]] = (uint8_t)pu.pidx;
+                        if (stable_u && e - 1 > 0 && S2[q] >= pu.rise_thr_f) {
+                            Sh[q] = S2[q];
+                            nxt[q] = e - 2;
+                            continue;
+                        }
+                        if (stable_u)
+                            put(q, root_f32(S2[q], pu.inv_p) * pu.corr);
+                        else
+                            put(q, (pe.p == 1 ? S[q] : root_f32(S[q], pe.inv_p)) * pe.corr);
                         continue;
                     }
                     if (stable) {
@@ -1206,7 +1251,8 @@ __global__ __launch_bounds__(256) void mt_tail_bf16_kernel(GemmGeom g, FamilyPla
                 }
                 if (!any_act) continue;
                 const PlanEntry& pe = plan.e[e];
-                tail_dot_group_bf16<G>(xr, yr, act, pe, g, lane, S);
+                float S2[G];
+                tail_dot_group_bf16<G, false>(xr, yr, act, pe, g, lane, S, S2);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
                     if (!act[q]) continue;
