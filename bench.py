@@ -127,15 +127,17 @@ def hbm_kernels(kern_ms, n, P, path, in_bytes=4, deferred=False):
     """Achieved HBM rate of the bandwidth-bound kernels of one step, from
     their algorithmic bytes (each input read once, each output written once)
     and the in-process launch times (ms per step).  deferred: the plane
-    launches write no planes of the two smallest p (they are written later,
-    and only if some entry needs them)."""
+    launches write no planes of the two smallest p (BF16 path) or of all but
+    the three largest p (FP64 path); those are written later, and only if some
+    entry needs them."""
     n2 = float(n) * n
     if path == "bf16":
         written = sorted(P)[2:] if deferred else P
         planes = sum(2 if p <= 4 else 1 for p in written)
         plane_bytes = 2 * (n2 * in_bytes + n2 * 2 * planes)  # both operands
     else:
-        plane_bytes = 2 * (n2 * in_bytes + n2 * 8 * len(P))
+        written = sorted(P)[-3:] if deferred else P
+        plane_bytes = 2 * (n2 * in_bytes + n2 * 8 * len(written))
     if "mt_colmax" not in kern_ms:
         # B's column maxima ran inside the plane launches (one more read of B)
         plane_bytes += n2 * in_bytes
@@ -540,7 +542,7 @@ def main():
             kern["mt_pfamily_gemm"] = round(gemm_ms / steps, 4)  # device clock, as above
         # deferred planes: work of the tiles that ran again (0: no entry
         # needed the planes of the two smallest p)
-        rerun_work = mt.timing_work("mt_rerun_gemm") if path == "bf16" else 0.0
+        rerun_work = mt.timing_work("mt_rerun_gemm")
         mt.timing_reset()
         res[path] = {"ms_per_step": ms, "wall_s": wall, "gemm_ms": gemm_ms / max(gemm_n, 1),
                      "gemm_event_ms": gemm_ev_ms / max(gemm_ev_n, 1),
@@ -605,9 +607,9 @@ def main():
     rp_ms = trace_from_profile(TRACE_SUMMARY, GEMM_SRC, "mt_pfamily_gemm_bf16") if main_path == "bf16" else None
 
     value = ops / (bf["ms_per_step"] / 1e3)
-    # the planes of the two smallest p wait until some entry needs them
-    # (BF16 plain products the pilot steers, families of five or more p)
-    deferred = main_path == "bf16" and mt.deferred_planes() and len(P) >= 5
+    # the planes of the smaller p wait until some entry needs them (plain
+    # products the pilot steers, families of five or more p)
+    deferred = bool(mt.deferred_planes()) and len(P) >= 5
     out = {
         "metric": METRIC,
         "value": value,
@@ -663,7 +665,8 @@ def main():
             "gemm_tflops": f["gemm_flop"] / (f["gemm_ms"] / 1e3) / 1e12,
             "gemm_frac_of_fp64_peak": f["gemm_flop"] / (f["gemm_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
             "kernel_ms_per_step": f["kernel_ms_per_step"],
-            "hbm_kernels": hbm_kernels(f["kernel_ms_per_step"], n, P, "fp64"),
+            "hbm_kernels": hbm_kernels(f["kernel_ms_per_step"], n, P, "fp64", deferred=deferred),
+            "rerun_flop_per_step": f.get("rerun_flop_per_step", 0.0),
         }
         out["bf16_over_fp64"] = value / fval
 

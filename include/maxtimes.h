@@ -521,22 +521,26 @@ mt_status maxtimes_set_search_start(int32_t entry);
 int32_t maxtimes_search_start(void);
 
 /*
- * Deferred planes (BF16 path, plain products whose search start the pilot
- * chooses, families of at least five p).  Most products need no p below the
- * third smallest: an entry that reaches the smallest two has no stable p
- * above them, where Sec. 1 puts p* at the largest stable p.  With on = 1, the
- * default, the power planes of the two smallest p are not written with the
- * others.  They are written before the GEMM when the pilot's sampled entries
- * include one that is unstable at every larger p; otherwise a GEMM tile or a
- * sparse-tail entry that reaches them marks its tile, and after the GEMM the
- * planes are written and the marked tiles run their whole search again,
- * densely, without the sparse tail (three extra launches per product, which
- * return at once when nothing is marked).  Results: the same selection rule on the
- * same planes; a tile that ran again sums its entries on the MFMA instead of
- * the tail kernel, which changes the order of the FP32 sums.  The workspace
- * holds 4 bytes per output tile for the marks either way.  on = 0 writes
- * every plane up front.  MT_ERR_INVALID_ARG for other values.  Process-wide;
- * not synchronised with calls in flight on other threads.
+ * Deferred planes (plain products whose search start the pilot chooses,
+ * families of at least five p).  p* is the largest stable p (Sec. 1), so an
+ * entry needs the planes of a smaller p only if it is unstable at every
+ * larger one.  With on = 1, the default, the power planes of the two
+ * smallest p (BF16 path), or of all but the three largest p (FP64 path, whose
+ * tiny tau puts p* near the largest p), are not written with the others.
+ * They are written before the GEMM when the pilot's sampled entries include
+ * one that is unstable at every p whose planes were written; otherwise a
+ * GEMM tile or a sparse-tail entry that reaches them marks its tile, and
+ * after the GEMM those planes are written for the rows of A and the columns
+ * of B of the marked tiles, and the marked tiles run their whole search
+ * again, densely, without the sparse tail (three extra launches per
+ * product, which return at once when nothing is marked).  The workspace's
+ * deferred planes then hold data only where a tile needed them.
+ * Results: the same selection rule on the same planes; a tile that ran
+ * again sums its entries on the MFMA instead of the tail kernel, which
+ * changes the order of the sums.  The workspace holds 4 bytes per output
+ * tile for the marks either way.  on = 0 writes every plane up front.
+ * MT_ERR_INVALID_ARG for other values.  Process-wide; not synchronised with
+ * calls in flight on other threads.
  */
 mt_status maxtimes_set_deferred_planes(int32_t on);
 int32_t maxtimes_deferred_planes(void);

@@ -582,10 +582,11 @@ def search_start():
 
 
 def set_deferred_planes(on):
-    """BF16 plain products steered by the pilot: write the power planes of
-    the two smallest p only once some entry needs them (True, the default),
-    running again the tiles that reached them first; False writes every plane
-    up front.  Process-wide."""
+    """Plain products steered by the pilot: write the power planes of the
+    two smallest p (BF16 path; FP64 path: all but the three largest p) only
+    once some entry needs them (True, the default), running again the tiles
+    that reached them first; False writes every plane up front.
+    Process-wide."""
     _check(load_library().maxtimes_set_deferred_planes(1 if on else 0))
 
 

@@ -413,9 +413,9 @@ Layout product_layout(const Family& f, const PlaneSpec& ps, const Geom& g, int64
     off += f.n > 1 ? align_up((size_t)kPilotKParts * f.n * kMaxPilotSide * kMaxPilotSide * (f.bf16 ? 4 : 8)) +
                          align_up(sizeof(PilotCounts))
                    : 0;
-    // deferred planes: one word per output tile (BF16 path with the tail)
+    // deferred planes: one word per output tile (with the tail)
     L.missed = off;
-    off += f.bf16 && L.tail_max > 0 ? align_up((size_t)tiles * 4) : 0;
+    off += L.tail_max > 0 ? align_up((size_t)tiles * 4) : 0;
     L.x = off;
     off += align_up(x_bytes);
     L.total = off;
@@ -514,13 +514,16 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
     const int32_t s0 = g_start_entry.load();
     const bool pilot = !plan.r1 && s0 == kStartAuto && L.tail_max > 0 && f.n > 2 && k >= 256 &&
                        b * m * n >= kPilotMinOutputs;
-    // Deferred planes (BF16 plain products the pilot steers): the planes of
-    // the two smallest p are written only once some entry needs them, which
-    // the pilot's sample tells before the GEMM, or a tile or tail entry that
-    // reaches them tells after it (those tiles then run again).
-    const bool defer = pilot && f.bf16 && mode == EPI_PLAIN && !(f.flags & MT_FLAG_PROJECT_R2) && plan.n >= 5 &&
+    // Deferred planes (plain products the pilot steers): the planes of the
+    // smaller p are written only once some entry needs them, which the
+    // pilot's sample tells before the GEMM, or a tile or tail entry that
+    // reaches them tells after it (those tiles then run again, after the
+    // planes of their rows are written).  BF16 path: the two smallest p;
+    // FP64 path, whose tau puts p* near the largest p: all but the three
+    // largest.
+    const bool defer = pilot && mode == EPI_PLAIN && !(f.flags & MT_FLAG_PROJECT_R2) && plan.n >= 5 &&
                        g_defer_planes.load() != 0;
-    const int32_t n_eval = defer ? plan.n - 2 : plan.n;
+    const int32_t n_eval = defer ? (f.bf16 ? plan.n - 2 : 3) : plan.n;
     PlaneSpec ps_now = ps, ps_late = ps;
     if (defer) {
         uint32_t late = 0;
@@ -591,8 +594,8 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
             pa.low_missed = defer ? &hdr->low_missed : nullptr;
             MT_TRY(launch_choose_start(pa, plan, &hdr->start, f.bf16 ? 0 : 1, st), "p search start (pilot)");
             if (defer)
-                MT_TRY(launch_planes_if(&hdr->low_need, A, B, in_f64, b, m, n, k, g.mp, g.np, g.kp, r, c, d, dinv,
-                                        ps_late, ap, bp, st),
+                MT_TRY(launch_planes_if(&hdr->low_need, A, B, in_f64, f.bf16, b, m, n, k, g.mp, g.np, g.kp, r, c,
+                                        d, dinv, ps_late, ap, bp, st),
                        "deferred planes (the pilot's sample needs them)");
         } else {
             const int32_t s1 = s0 < 0 ? 0 : (s0 < f.n ? s0 : f.n - 1);
@@ -629,9 +632,9 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
             // tiles or tail entries that reached the deferred planes: write
             // them, then run those tiles again (each launch returns at once
             // when nothing was missed)
-            MT_TRY(launch_planes_if(&hdr->low_missed, A, B, in_f64, b, m, n, k, g.mp, g.np, g.kp, r, c, d, dinv,
-                                    ps_late, ap, bp, st),
-                   "deferred planes (after a miss)");
+            MT_TRY(launch_planes_if(&hdr->low_missed, A, B, in_f64, f.bf16, b, m, n, k, g.mp, g.np, g.kp, r, c,
+                                    d, dinv, ps_late, ap, bp, st, epi.missed_tile, g.bm),
+                   "deferred planes (after a miss: the marked tiles' rows)");
             MT_TRY(launch_rerun_gemm_bf16((const uint16_t*)ap, (const uint16_t*)bp, b, m, n, g.mp, g.np, g.kp,
                                           ps.n_planes, plan, epi, st),
                    "p-family GEMM (BF16, tiles run again)");
@@ -642,9 +645,23 @@ mt_status run_product(const void* A, const void* B, int in_f64, int64_t b, int64
         epi.out2 = (f.flags & MT_FLAG_PROJECT_R1) ? ws + L.s2 : nullptr;
         epi.out_f64 = 1;
         epi.pstar = ws + L.code;
+        if (defer) {
+            epi.low_need = &hdr->low_need;
+            epi.low_missed = &hdr->low_missed;
+            epi.missed_tile = (uint32_t*)(ws + L.missed);
+            epi.n_eval = n_eval;
+        }
         MT_TRY(launch_pfamily_gemm_f64((const double*)ap, (const double*)bp, b, m, n, g.mp, g.np, g.kp,
                                        ps.n_planes, g.bm, plan, epi, st),
                "p-family GEMM (FP64)");
+        if (defer) {
+            MT_TRY(launch_planes_if(&hdr->low_missed, A, B, in_f64, f.bf16, b, m, n, k, g.mp, g.np, g.kp, r, c,
+                                    d, dinv, ps_late, ap, bp, st, epi.missed_tile, g.bm),
+                   "deferred planes (after a miss: the marked tiles' rows)");
+            MT_TRY(launch_rerun_gemm_f64((const double*)ap, (const double*)bp, b, m, n, g.mp, g.np, g.kp,
+                                         ps.n_planes, g.bm, plan, epi, st),
+                   "p-family GEMM (FP64, tiles run again)");
+        }
         const RootSpec rsp = root_spec(f, k, mode, clamp);
         MT_TRY(launch_select_root_f64((const double*)(ws + L.s), (const double*)(ws + L.s2), ws + L.code, b, m,
                                       n, r, c, rsp, out, out_f64, pstar, st),

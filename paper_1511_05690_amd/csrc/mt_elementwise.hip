@@ -406,9 +406,9 @@ __global__ __launch_bounds__(kThreads) void mt_power_planes_kernel(
                                               col_mul, spec, planes, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// Both operands' planes of spec.write_mask (BF16), only when *cond is set: A's
-// untransposed plane tiles first, then B's transposed ones, a fixed grid
-// striding over them.
+// Both operands' planes of spec.write_mask (BF16 or FP64), only when *cond is
+// set: A's untransposed plane tiles first, then B's transposed ones, a fixed
+// grid striding over them.
 struct PlanesIfOperand {
     const void* src;
     int64_t rows, cols, rows_pad, cols_pad;
@@ -417,20 +417,40 @@ struct PlanesIfOperand {
     void* planes;
     int64_t gx, gy, blocks;  // plane tiles along columns, along rows, in all
 };
-template <typename TS>
+// With marks (b x tiles_m x tiles_n output tiles of side tile_bm, nonzero:
+// the tile runs again), only the plane rows of marked tiles are written: A's
+// rows of a tile row with a marked tile, B's of a tile column with one.
+struct PlanesIfMarks {
+    const uint32_t* marks;  // null: every plane row
+    int64_t tiles_m, tiles_n, tile_bm;
+};
+template <typename TS, bool kBf16>
 __global__ __launch_bounds__(kThreads) void mt_planes_if_kernel(const int32_t* __restrict__ cond, PlanesIfOperand a,
-                                                                PlanesIfOperand b, PlaneSpec spec) {
+                                                                PlanesIfOperand b, PlaneSpec spec, PlanesIfMarks mk) {
     if (*cond == 0) return;
     for (int64_t v = blockIdx.x; v < a.blocks + b.blocks; v += gridDim.x) {
-        if (v < a.blocks) {
-            power_planes_block<TS, true, false>((const TS*)a.src, a.rows, a.cols, a.rows_pad, a.cols_pad,
-                                                a.scale_rows, nullptr, a.col_mul, spec, a.planes, v % a.gx,
-                                                (v / a.gx) % a.gy, v / (a.gx * a.gy));
+        const bool is_a = v < a.blocks;
+        const int64_t w = is_a ? v : v - a.blocks;
+        const PlanesIfOperand& o = is_a ? a : b;
+        const int64_t bx = w % o.gx, by = (w / o.gx) % o.gy, bz = w / (o.gx * o.gy);
+        if (mk.marks != nullptr) {
+            // plane rows by * T.. of this block lie in one tile row (A) or
+            // tile column (B): any marked tile along it?
+            const int64_t tr = by * (is_a ? PlaneTile<TS, false>::T : PlaneTile<TS, true>::T) / mk.tile_bm;
+            const int64_t len = is_a ? mk.tiles_n : mk.tiles_m;
+            int hit = 0;
+            for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+                const int64_t tm = is_a ? tr : i, tn = is_a ? i : tr;
+                hit |= mk.marks[(bz * mk.tiles_m + tm) * mk.tiles_n + tn] != 0u;
+            }
+            if (!__syncthreads_or(hit)) continue;
+        }
+        if (is_a) {
+            power_planes_block<TS, kBf16, false>((const TS*)a.src, a.rows, a.cols, a.rows_pad, a.cols_pad,
+                                                 a.scale_rows, nullptr, a.col_mul, spec, a.planes, bx, by, bz);
         } else {
-            const int64_t w = v - a.blocks;
-            power_planes_block<TS, true, true>((const TS*)b.src, b.rows, b.cols, b.rows_pad, b.cols_pad,
-                                               b.scale_rows, nullptr, b.col_mul, spec, b.planes, w % b.gx,
-                                               (w / b.gx) % b.gy, w / (b.gx * b.gy));
+            power_planes_block<TS, kBf16, true>((const TS*)b.src, b.rows, b.cols, b.rows_pad, b.cols_pad,
+                                                b.scale_rows, nullptr, b.col_mul, spec, b.planes, bx, by, bz);
         }
         // the transposed tile in LDS is refilled by the next iteration
         __syncthreads();
@@ -821,11 +841,19 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
     return hipGetLastError();
 }
 
-hipError_t launch_planes_if(const int32_t* cond, const void* A, const void* B, int src_f64, int64_t b, int64_t m,
-                            int64_t n, int64_t k, int64_t mp, int64_t np, int64_t kp, const double* r,
+hipError_t launch_planes_if(const int32_t* cond, const void* A, const void* B, int src_f64, int bf16, int64_t b,
+                            int64_t m, int64_t n, int64_t k, int64_t mp, int64_t np, int64_t kp, const double* r,
                             const double* c, const double* a_mul, const double* b_mul, const PlaneSpec& spec,
-                            void* a_planes, void* b_planes, hipStream_t st) {
+                            void* a_planes, void* b_planes, hipStream_t st, const uint32_t* marks,
+                            int64_t tile_bm) {
     if (b <= 0 || mp <= 0 || np <= 0 || kp <= 0) return hipSuccess;
+    PlanesIfMarks mk;
+    mk.marks = marks;
+    mk.tile_bm = tile_bm;
+    mk.tiles_m = marks ? mp / tile_bm : 0;
+    mk.tiles_n = marks ? np / tile_bm : 0;
+    // a marked plane row block lies in one tile row or column
+    if (marks && (tile_bm <= 0 || mp % tile_bm || np % tile_bm || tile_bm % 64)) return hipErrorInvalidValue;
     auto operand = [&](const void* src, int64_t rows, int64_t rows_pad, const double* sc, const double* mul,
                        void* planes, int64_t tile_t, int64_t tile_u) {
         PlanesIfOperand o;
@@ -852,8 +880,12 @@ hipError_t launch_planes_if(const int32_t* cond, const void* A, const void* B, i
         const PlanesIfOperand ob =
             operand(B, n, np, c, b_mul, b_planes, PlaneTile<TS, true>::T, PlaneTile<TS, true>::U);
         const int64_t total = oa.blocks + ob.blocks;
-        hipLaunchKernelGGL(mt_planes_if_kernel<TS>, dim3((unsigned)(total < 2048 ? total : 2048)), dim3(kThreads),
-                           0, st, cond, oa, ob, spec);
+        const dim3 grid((unsigned)(total < 2048 ? total : 2048));
+        if (bf16)
+            hipLaunchKernelGGL((mt_planes_if_kernel<TS, true>), grid, dim3(kThreads), 0, st, cond, oa, ob, spec, mk);
+        else
+            hipLaunchKernelGGL((mt_planes_if_kernel<TS, false>), grid, dim3(kThreads), 0, st, cond, oa, ob, spec,
+                               mk);
     };
     if (src_f64)
         launch(double{});

@@ -39,6 +39,7 @@ struct GemmGeomF64 {
     int64_t kp;
     int64_t rows, cols;
     int32_t tiles_m, tiles_n;
+    int32_t bm;                // output tile side
     unsigned long long* work;  // if set: MFMA flops executed, summed over workgroups
 };
 
@@ -58,7 +59,7 @@ struct TileCtx {
 };
 
 // ------------------------------------------------------------ selection record
-template <class C, bool R1>
+template <class C, bool R1, bool RERUN = false>
 struct RecordEpi {
     static constexpr int WT = C::WT;
     static constexpr int NDEC = (WT * WT * 4 + 31) / 32;
@@ -74,9 +75,21 @@ struct RecordEpi {
     int lr0, lc0;
     int64_t out_lane;
     int32_t rows_left, cols_left;
+    int32_t n_eval;  // plan entries whose planes this launch may read
 
     static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
+    // Deferred planes: the planes of plan entries n_eval and below are not
+    // written (yet), so the way down ends above them.  The rerun launch runs
+    // only the tiles marked for it, with every plane written, densely to the
+    // end.
+    __device__ int down_end(const FamilyPlan& plan) const { return min(plan.n, n_eval); }
+    static __device__ bool skip_tile(const Args& a, int64_t tile) { return RERUN && a.missed_tile[tile] == 0u; }
+    __device__ void record_tile(int64_t tile, bool missed) const {
+        if (RERUN || a.missed_tile == nullptr) return;
+        a.missed_tile[tile] = missed ? 1u : 0u;
+        if (missed) *a.low_missed = 1;
+    }
 
     // Entries of this lane without their final record yet: `open` ones have
     // no stable p so far, `parked` ones wait for the way up (with the r = 1
@@ -97,7 +110,7 @@ struct RecordEpi {
         }
     }
     __device__ int32_t start_index() const { return (!R1 && a.start) ? *a.start : 0; }
-    __device__ bool can_hand_over(int total) const { return a.tail != nullptr && total <= a.tail_max; }
+    __device__ bool can_hand_over(int total) const { return !RERUN && a.tail != nullptr && total <= a.tail_max; }
     __device__ uint32_t* tail_counter() const { return a.tail_count; }
     // Write this lane's undecided entries to the sparse-tail list from `pos`
     // on, after plan entry e of a search that started at plan entry s.
@@ -130,6 +143,8 @@ struct RecordEpi {
 
     __device__ void setup(const TileCtx& t, const GemmGeomF64& g, uint8_t*, int) {
         n = g.cols;
+        n_eval = MT_MAX_P;
+        if (!RERUN && a.low_need != nullptr && __builtin_amdgcn_readfirstlane(*a.low_need) == 0) n_eval = a.n_eval;
 #pragma unroll
         for (int i = 0; i < NDEC; ++i) decided[i] = pending[i] = 0u;
         // Entry (i, j, r) of this lane: tile row wm*WT*16 + i*16 + l/16 + 4r,
@@ -252,6 +267,9 @@ struct StoreAllEpi {
     int32_t rows_left, cols_left;
 
     __device__ bool active(int, const FamilyPlan&) const { return true; }
+    __device__ int down_end(const FamilyPlan& plan) const { return plan.n; }
+    static __device__ bool skip_tile(const Args&, int64_t) { return false; }
+    __device__ void record_tile(int64_t, bool) const {}
     __device__ void counts(int& open, int& parked) const { open = parked = 0; }
     __device__ int32_t start_index() const { return 0; }
     __device__ bool can_hand_over(int) const { return false; }
@@ -295,6 +313,9 @@ struct AdjointEpiF64 {
     AdjArgs a;
     int64_t rows, cols;
     f64x4 tot[WT][WT];
+    __device__ int down_end(const FamilyPlan& plan) const { return plan.n; }
+    static __device__ bool skip_tile(const Args&, int64_t) { return false; }
+    __device__ void record_tile(int64_t, bool) const {}
     double* rs;
     double* cs;
     int* res;
@@ -441,18 +462,23 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
     const int tn = in_g / gsz;
     t.row0 = (int64_t)tm * C::BM;
     t.col0 = (int64_t)tn * C::BM;
+    const int64_t tile_id = (int64_t)t.bi * per_batch + (int64_t)tm * g.tiles_n + tn;
+    if (Epi::skip_tile(args, tile_id)) return;
 
     Epi epi;
     epi.a = args;
     epi.setup(t, g, smem + C::PIPE_BYTES, tid);
+    if (tid == 0) epi.record_tile(tile_id, false);
     // The p search starts at plan entry e0 (0: the largest p), goes down to
     // the smallest p and then up from e0 - 1 to the largest; s_act holds the
     // active plan entries in that order.
     const int e0_req = __builtin_amdgcn_readfirstlane(epi.start_index());
     const int e0 = e0_req < 0 ? 0 : (e0_req >= plan.n ? plan.n - 1 : e0_req);
+    // deferred planes not written: the way down ends above them
+    const int e_end = epi.down_end(plan);
     if (tid == 0) {
         int na = 0;
-        for (int e = e0; e < plan.n; ++e)
+        for (int e = e0; e < e_end; ++e)
             if (epi.active(e, plan)) s_act[1 + na++] = e;
         for (int e = e0 - 1; e >= 0; --e)
             if (epi.active(e, plan)) s_act[1 + na++] = e;
@@ -595,10 +621,15 @@ __global__ __launch_bounds__(kThreads, 2) void mt_pfamily_gemm_f64_kernel(GemmGe
                 epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), e, e0, t);
                 break;
             }
+            // deferred planes: entries still open after the way down (which
+            // ends above the deferred p) and not handed to the tail need
+            // those p; the tile runs again once their planes are written
+            // (what it records meanwhile is overwritten then)
+            if (e_end < plan.n && e == e_end - 1 && open > 0 && tid == 0) epi.record_tile(tile_id, true);
             // going down with nothing open left: only the entries parked at
             // the start wait, for larger p; skip to the way up (plan entry
             // e0 - 1) and reload its first K step in place of the prefetched one
-            const int n_down = plan.n - e0;
+            const int n_down = e_end - e0;
             if (open == 0 && e >= e0 && e0 > 0 && ai + 1 < n_down) {
                 ai = n_down - 1;  // ++ai below -> first entry of the way up
                 la_ = n_down;
@@ -672,6 +703,10 @@ __global__ __launch_bounds__(256) void mt_tail_f64_kernel(GemmGeomF64 g, FamilyP
     const int64_t w1 = min<int64_t>(w0 + run, (int64_t)count);
     double* out = (double*)a.out;
     double* out2 = (double*)a.out2;
+    // deferred planes not written: an entry that reaches them marks its tile
+    // for the rerun launch instead
+    int n_eval = MT_MAX_P;
+    if (a.low_need != nullptr && __builtin_amdgcn_readfirstlane(*a.low_need) == 0) n_eval = a.n_eval;
     for (int64_t w = w0; w < w1; ++w) {
         const TailEntry te = a.tail_sorted[w];
         const int64_t o = ((int64_t)te.bi * g.rows + te.i) * g.cols + te.j;
@@ -694,6 +729,13 @@ __global__ __launch_bounds__(256) void mt_tail_f64_kernel(GemmGeomF64 g, FamilyP
         }
         bool pend = R1 && te.state == kTailR1;
         for (int e = te.e_next; e < plan.n; ++e) {
+            if (e >= n_eval) {
+                if (lane == 0) {
+                    a.missed_tile[((int64_t)te.bi * g.tiles_m + te.i / g.bm) * g.tiles_n + te.j / g.bm] = 1u;
+                    *a.low_missed = 1;
+                }
+                break;
+            }
             const PlanEntry& pe = plan.e[e];
             const double acc = tail_dot_f64(xr, yr, pe, g, lane);
             if (R1 && pend) {
@@ -754,6 +796,7 @@ GemmGeomF64 make_geom(const double* X, const double* Y, int64_t rows, int64_t co
     g.cols = cols;
     g.tiles_m = (int32_t)(rows_pad / bm);
     g.tiles_n = (int32_t)(cols_pad / bm);
+    g.bm = bm;
     g.work = nullptr;
     return g;
 }
@@ -793,6 +836,19 @@ hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b
         hipLaunchKernelGGL(mt_tail_f64_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, g, plan, epi);
     timing_after(st);
     return hipGetLastError();
+}
+
+hipError_t launch_rerun_gemm_f64(const double* Ap, const double* Bp, int64_t b, int64_t m, int64_t n, int64_t mp,
+                                 int64_t np, int64_t kp, int32_t n_planes, int bm, const FamilyPlan& plan,
+                                 const EpiArgs& epi, hipStream_t st) {
+    if (epi.missed_tile == nullptr || plan.r1 || epi.mode != EPI_PLAIN) return hipErrorInvalidValue;
+    const GemmGeomF64 g = make_geom(Ap, Bp, m, n, mp, np, kp, n_planes, n_planes, bm);
+    // a launch of its own name: the forward GEMM's timing and work stay apart
+    // (a tile that is not marked adds no work and ends no span)
+    const char* name = "mt_rerun_gemm_f64";
+    if (bm == 128) return launch_gemm<CfgF64<4>, RecordEpi<CfgF64<4>, false, true>>(g, b, plan, epi, name, st);
+    if (bm == 64) return launch_gemm<CfgF64<2>, RecordEpi<CfgF64<2>, false, true>>(g, b, plan, epi, name, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_adjoint_gemm_f64(const double* Xp, const double* Yp, int64_t b, int64_t rows,

@@ -246,13 +246,17 @@ hipError_t launch_power_planes(const void* src, int src_f64, int transpose, int6
                                const PlaneSpec& spec, int bf16, void* planes, hipStream_t st,
                                const double* col_mul = nullptr);
 // The planes of spec.write_mask for both operands in one launch (A untransposed
-// as launch_power_planes with transpose 0, B transposed as with transpose 1),
-// only when *cond is nonzero on the device (else every workgroup returns at
-// once): the deferred planes, written once some entry needs them.
-hipError_t launch_planes_if(const int32_t* cond, const void* A, const void* B, int src_f64, int64_t b, int64_t m,
-                            int64_t n, int64_t k, int64_t mp, int64_t np, int64_t kp, const double* r,
+// as launch_power_planes with transpose 0, B transposed as with transpose 1;
+// BF16 or FP64 planes), only when *cond is nonzero on the device (else every
+// workgroup returns at once): the deferred planes, written once some entry
+// needs them.  With marks (one word per output tile of side tile_bm, a
+// multiple of 64 dividing mp and np), only the plane rows of the tile rows
+// (A) and tile columns (B) that hold a marked tile.
+hipError_t launch_planes_if(const int32_t* cond, const void* A, const void* B, int src_f64, int bf16, int64_t b,
+                            int64_t m, int64_t n, int64_t k, int64_t mp, int64_t np, int64_t kp, const double* r,
                             const double* c, const double* a_mul, const double* b_mul, const PlaneSpec& spec,
-                            void* a_planes, void* b_planes, hipStream_t st);
+                            void* a_planes, void* b_planes, hipStream_t st, const uint32_t* marks = nullptr,
+                            int64_t tile_bm = 0);
 
 // Fused p-family GEMM + selection epilogue.
 hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m,
@@ -263,6 +267,10 @@ hipError_t launch_pfamily_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int6
 hipError_t launch_rerun_gemm_bf16(const uint16_t* Ap, const uint16_t* Bp, int64_t b, int64_t m, int64_t n,
                                   int64_t mp, int64_t np, int64_t kp, int32_t n_planes, const FamilyPlan& plan,
                                   const EpiArgs& epi, hipStream_t st);
+// The same for the FP64 path (bm: the forward launch's tile side).
+hipError_t launch_rerun_gemm_f64(const double* Ap, const double* Bp, int64_t b, int64_t m, int64_t n, int64_t mp,
+                                 int64_t np, int64_t kp, int32_t n_planes, int bm, const FamilyPlan& plan,
+                                 const EpiArgs& epi, hipStream_t st);
 hipError_t launch_pfamily_gemm_f64(const double* Ap, const double* Bp, int64_t b, int64_t m,
                                    int64_t n, int64_t mp, int64_t np, int64_t kp, int32_t n_planes,
                                    int bm, const FamilyPlan& plan, const EpiArgs& epi,

@@ -24,7 +24,11 @@ Checks, on 2048 x 512 x 2048 products (large enough for the pilot, whose
   of the crossed rows to p* = 4, leaving some at 2) and with FP64 inputs
   (the late planes take the balancing factors and the FP64 reader);
 * two batch items of a ragged product, only the second with such rows: the
-  marks index the batch item and partial tiles."""
+  marks index the batch item and partial tiles;
+* the FP64 path, which defers all but the three largest p (64 x 64 tiles at
+  this size): no entry below p = 32 (bit-equal, nothing runs again); zero
+  rows and rows with p* = 16 off the sample, reached in the tail and, eleven
+  such rows in one tile, in the GEMM; every row at p* = 16."""
 
 import numpy as np
 import pytest
@@ -78,14 +82,14 @@ def _rare(A, B):
     return A, B
 
 
-def _run(mt, A, B, on, balance=False):
+def _run(mt, A, B, on, balance=False, path="bf16"):
     """(C, p*, work of the tiles that ran again) with deferral on or off."""
     import torch
 
     mt.set_deferred_planes(on)
     mt.timing_reset()
     mt.timing_enable(True)
-    C, ps = mt.estimate(_dev(A), _dev(B), P=P128, path="bf16", return_pstar=True, balance=balance)
+    C, ps = mt.estimate(_dev(A), _dev(B), P=P128, path=path, return_pstar=True, balance=balance)
     torch.cuda.synchronize()
     rerun = mt.timing_work("mt_rerun_gemm")
     mt.timing_enable(False)
@@ -183,3 +187,44 @@ def test_rare_rows_batched_ragged(knobs):
         ref = oracle.pnorm_estimate_rows(A[bi], B[bi], P128, TAU["bf16"], rows)
         compare_estimate(C1[bi][rows], p1[bi][rows], ref, P128, "bf16")
     assert (C1[1][list(zero)] == 0).all()
+
+
+@pytest.mark.parametrize("case", ["none", "rare", "every"])
+def test_fp64_path(knobs, case):
+    """FP64 path (tau 1e-290): the planes of p <= 16 are deferred.  Crossed
+    terms of about 1e-10 underflow at p >= 32 and are stable at p = 16."""
+    A, B = lognormal_product(M, K, N, seed=4203 if case == "every" else 4201)
+    A, B = A.astype(np.float64), B.astype(np.float64)
+    h = K // 2
+    crossed, zero = (1000,) + tuple(range(1500, 1511)), (5, 300, 301, 302)
+    if case == "rare":
+        B[:h] *= 1e-10
+        for i in crossed:
+            A[i, h:] *= 1e-12
+        for i in zero:
+            A[i] = 0
+        assert not (set(crossed) | set(zero)) & _sampled_rows()
+    elif case == "every":
+        B[:h] *= 1e-10
+        A[:, h:] *= 1e-12
+    print(f"[deferred] fp64 {case}", flush=True)
+    C1, p1, w1 = _run(knobs, A, B, True, path="fp64")
+    C0, p0, w0 = _run(knobs, A, B, False, path="fp64")
+    assert w0 == 0.0
+    special = np.zeros(M, dtype=bool)
+    if case == "rare":
+        for i in crossed + zero:
+            special[(i // 64) * 64:(i // 64 + 1) * 64] = True
+        assert w1 > 0.0
+        assert (p1[list(crossed)] == 4).mean() > 0.99  # p* = 16
+        assert (C1[list(zero)] == 0).all()
+    else:
+        assert w1 == 0.0
+    if case != "every":
+        np.testing.assert_array_equal(p1[~special], p0[~special])
+        np.testing.assert_array_equal(C1[~special].view(np.uint64), C0[~special].view(np.uint64))
+    else:
+        assert (p1 == 4).mean() > 0.99
+    rows = np.array(sorted({3, 741, 1300, 2047} | (set(crossed) | set(zero) | {299, 1499} if case == "rare" else set())))
+    ref = oracle.pnorm_estimate_rows(A, B, P128, TAU["fp64"], rows)
+    compare_estimate(C1[rows], p1[rows], ref, P128, "fp64")
