@@ -358,7 +358,7 @@ std::atomic<int64_t> g_small_limit{kSmallProductDefault};
 constexpr int32_t kStartAuto = -1;
 std::atomic<int32_t> g_start_entry{kStartAuto};
 
-// Deferred planes of the two smallest p on the BF16 path (on by default).
+// Deferred planes of the smaller p (on by default).
 std::atomic<int32_t> g_defer_planes{1};
 
 // The pilot runs for products of at least this many output entries (below,

@@ -112,12 +112,13 @@ struct EpiArgs {
     int32_t tail_shift;
     int32_t tail_buckets;
     int64_t stack_stride;  // EPI_STORE_ALL: elements per plane of the S stack (b m n)
-    // Deferred planes (BF16 forward): the planes of plan entries n_eval and
-    // below are written only when *low_need is set before the GEMM.  Without
-    // them a tile that reaches such an entry, or a tail entry that does,
-    // stops, marks its tile in missed_tile and sets *low_missed; the planes
-    // are then written and the marked tiles run again from the start, densely
-    // (the rerun launch).  low_need null: every plane is written.
+    // Deferred planes (the forward GEMMs): the planes of plan entries n_eval
+    // and beyond are written before the GEMM only when *low_need is set.
+    // Without them a tile that needs such an entry, or a tail entry that
+    // reaches one, marks its tile in missed_tile and sets *low_missed; the
+    // planes of the marked tiles' rows are then written and those tiles run
+    // again from the start, densely (the rerun launch).  low_need null:
+    // every plane is written.
     const int32_t* low_need;
     int32_t* low_missed;
     uint32_t* missed_tile;  // b x tiles_m x tiles_n: 1 where the tile must run again
