@@ -29,6 +29,10 @@
 //            owns, where the p* test runs.
 // Indices decided at a larger p keep their S; a workgroup stops once every
 // index of its pairs is decided, and the roots are taken once per index.
+// When every index still open has at most kDirectTerms terms (they sit at
+// the ends of the output, where few products meet), the workgroup finishes
+// them by direct sums of x'^p y'^p for the remaining p instead of further
+// transforms.
 //
 // Global path (n + m - 1 <= 16384): the same passes through two buffers in
 // the workspace, one thread per butterfly, kernel boundaries between passes,
@@ -421,6 +425,19 @@ __device__ __forceinline__ void convolve_pair(double2 (&v)[16], int tl, double2*
     }
 }
 
+// An open index with at most this many terms is finished by direct sums.
+constexpr int kDirectTerms = 64;
+
+// x^p for p >= 1 by binary powering (p uniform)
+__device__ __forceinline__ double pow_int(double x, int p) {
+    double r = 1.0;
+    for (; p; p >>= 1) {
+        if (p & 1) r *= x;
+        x *= x;
+    }
+    return r;
+}
+
 template <typename T, int LOGN>
 __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __restrict__ x,
                                                                   const T* __restrict__ y, int64_t b, int64_t n,
@@ -487,7 +504,7 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
         convolve_pair<LOGN>(v, tl, buf, pt);
         // p* test: the first stable p from the top decides an index; the
         // smallest p decides what is left (its S, no p stable)
-        int open = 0;
+        int open = 0, open_far = 0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int t = tl + i * TP;
@@ -496,12 +513,47 @@ __global__ __launch_bounds__(kConvThreads, 2) void mt_maxconv_kernel(const T* __
             const bool stable = S >= spec.tau;
             const bool dec = live && (stable || q == 0);
             open |= live && !dec;
+            // terms of index t: x[j] y[t - j] for max(0, t - m + 1) <= j <= min(t, n - 1)
+            const int nterms = min(t, (int)n - 1) - max(0, t - (int)m + 1) + 1;
+            open_far |= live && !dec && nterms > kDirectTerms;
             s_sel[i] = dec ? S : s_sel[i];
             const uint32_t code = stable ? (uint32_t)q : (uint32_t)MT_PSTAR_NONE;
             q_sel[i / 4] = dec ? (q_sel[i / 4] & ~(0xffu << (8 * (i % 4)))) | (code << (8 * (i % 4))) : q_sel[i / 4];
             decided |= dec ? 1u << i : 0u;
         }
         if (!__syncthreads_or(open)) break;
+        if (!__syncthreads_or(open_far)) {
+            // every open index has few terms: its S for the remaining p as a
+            // direct sum (the exact S the transforms approximate), the same
+            // selection.  x' and y' go to the pair's LDS buffer first (free
+            // after the barrier above; n + m - 1 <= N doubles fit in it).
+            double* sx = (double*)buf;
+            double* sy = sx + n;
+            for (int j = tl; j < (int)n; j += TP) sx[j] = active ? (double)xi[j] * ix : 0.0;
+            for (int j = tl; j < (int)m; j += TP) sy[j] = active ? (double)yi[j] * iy : 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int t = tl + i * TP;
+                if (!(active && t < L && !(decided & (1u << i)))) continue;
+                const int j0 = max(0, t - (int)m + 1), j1 = min(t, (int)n - 1);
+                for (int qq = q - 1; qq >= 0; --qq) {
+                    const int pp = spec.p[qq];
+                    double S = 0.0;
+                    for (int j = j0; j <= j1; ++j) S = fma(pow_int(sx[j], pp), pow_int(sy[t - j], pp), S);
+                    const bool stable = S >= spec.tau;
+                    if (!(stable || qq == 0)) continue;
+                    s_sel[i] = S;
+                    const uint32_t code = stable ? (uint32_t)qq : (uint32_t)MT_PSTAR_NONE;
+                    q_sel[i / 4] = (q_sel[i / 4] & ~(0xffu << (8 * (i % 4)))) | (code << (8 * (i % 4)));
+                    decided |= 1u << i;
+                    break;
+                }
+            }
+            // the roots below reuse the buffer
+            __syncthreads();
+            break;
+        }
     }
     // roots, once per index: the selected S goes to the thread's own LDS
     // positions, then one index at a time (the buffer is free after the loop's
