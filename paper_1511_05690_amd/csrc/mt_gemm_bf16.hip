@@ -155,10 +155,11 @@ struct SelectEpi {
     static constexpr bool kAllActive = true;
     static constexpr bool kCanStop = true;
     __device__ bool active(int, const FamilyPlan&) const { return true; }
-    // Deferred planes: plan entry e's planes are not written (yet).  The
-    // rerun launch runs only the tiles marked for it, with every plane
-    // written, densely to the end.
-    __device__ bool deferred(int e) const { return e >= n_eval; }
+    // Deferred planes: the planes of plan entries n_eval and beyond are not
+    // written (yet), so the way down ends above them.  The rerun launch runs
+    // only the tiles marked for it, with every plane written, densely to the
+    // end.
+    __device__ int down_end(const FamilyPlan& plan) const { return min(plan.n, n_eval); }
     static __device__ bool skip_tile(const Args& a, int64_t tile) { return RERUN && a.missed_tile[tile] == 0u; }
     __device__ void record_tile(int64_t tile, bool missed) const {
         if (RERUN || a.missed_tile == nullptr) return;
@@ -521,7 +522,7 @@ struct AdjointEpi {
     static constexpr bool kAllActive = false;
     static constexpr bool kCanStop = false;
     __device__ bool active(int e, const FamilyPlan& plan) const { return a.hist[plan.e[e].pidx] > 0; }
-    __device__ bool deferred(int) const { return false; }
+    __device__ int down_end(const FamilyPlan& plan) const { return plan.n; }
     static __device__ bool skip_tile(const Args&, int64_t) { return false; }
     __device__ void record_tile(int64_t, bool) const {}
     __device__ void counts(int& open, int& parked) const { open = parked = 0; }
@@ -744,7 +745,9 @@ __global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kern
     const int32_t rd_split = (lane & 31) * 64 + (((lane >> 5) ^ ((lane >> 2) & 3)) * 16);
 
     __syncthreads();
-    const int nact = Epi::kAllActive ? plan.n : __builtin_amdgcn_readfirstlane(s_act[0]);
+    // (deferred planes: the way down ends above them, plan entry e_end)
+    const int e_end = epi.down_end(plan);
+    const int nact = Epi::kAllActive ? e_end : __builtin_amdgcn_readfirstlane(s_act[0]);
     // The p search starts at plan entry s (0: the largest p), goes down to
     // the smallest p and then up from s - 1 to the largest (forward only).
     int s0 = Epi::kAllActive ? __builtin_amdgcn_readfirstlane(epi.start_index()) : 0;
@@ -823,16 +826,9 @@ __global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kern
 
     int buf = 0;
     int64_t kunits = 0;  // executed MFMA work in units of BM x BN x 1 products
-    bool missed = false;
+    if (tid == 0) epi.record_tile(tile_id, false);
     for (int ai = 0; ai < nact; ++ai) {
         const int e = entry_of(ai);
-        // a p whose planes are deferred and not written: the tile runs again
-        // once they are (no load is in flight here; the prefetched step of
-        // this entry is unused)
-        if (epi.deferred(e)) {
-            missed = true;
-            break;
-        }
         f32x16 acc[WT_M][WT_N];
 #pragma unroll
         for (int i = 0; i < WT_M; ++i)
@@ -977,6 +973,11 @@ __global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kern
                 epi.hand_over(s_tail_base + (uint32_t)(wave_pre + lane_pre), e, s, t);
                 break;
             }
+            // deferred planes: entries still open after the way down (which
+            // ends above the deferred p) and not handed to the tail need
+            // those p; the tile runs again once their planes are written
+            // (what it stores meanwhile is overwritten then)
+            if (e_end < plan.n && e == e_end - 1 && open > 0 && tid == 0) epi.record_tile(tile_id, true);
             // Going down with nothing open left: only the entries parked at
             // the start wait, for larger p.  Skip to the way up (plan entry
             // s - 1): reload its first K step in place of the prefetched one.
@@ -995,7 +996,6 @@ __global__ __launch_bounds__(C::THREADS, C::MINW) void mt_pfamily_gemm_bf16_kern
         }
     }
     epi.finish(t);
-    if (tid == 0) epi.record_tile(tile_id, missed);
     if (g.work) {
         // timed launch: the work, and the end once every wave is done
         __syncthreads();
