@@ -228,3 +228,23 @@ def test_fp64_path(knobs, case):
     rows = np.array(sorted({3, 741, 1300, 2047} | (set(crossed) | set(zero) | {299, 1499} if case == "rare" else set())))
     ref = oracle.pnorm_estimate_rows(A, B, P128, TAU["fp64"], rows)
     compare_estimate(C1[rows], p1[rows], ref, P128, "fp64")
+
+
+def test_rare_rows_noalloc(knobs):
+    """The entry point without a workspace keeps the marks and flags in its
+    static scratch: the same C and p* as the workspace call, twice in a row
+    (the second call finds the first call's marks and clears them)."""
+    import torch
+
+    if knobs.workspace_size(1, M, K, N, P128, path="bf16") > knobs.NOALLOC_SCRATCH_BYTES:
+        pytest.skip("the product does not fit the static scratch")
+    A, B = _rare(*lognormal_product(M, K, N, seed=4201))
+    knobs.set_deferred_planes(True)
+    dA, dB = _dev(A), _dev(B)
+    C0, p0 = knobs.estimate(dA, dB, P=P128, path="bf16", return_pstar=True)
+    for rep in range(2):
+        print(f"[deferred] noalloc call {rep}", flush=True)
+        C1, p1 = knobs.estimate_noalloc(dA, dB, P=P128, path="bf16")
+        torch.cuda.synchronize()
+        assert torch.equal(p0, p1)
+        assert torch.equal(C0, C1)
